@@ -1,0 +1,288 @@
+"""Pins of the CPU oracle's forward pass against facts fixed by the paper's
+equations and by mathematics, independent of the oracle's own code:
+
+* single isotropic Gaussian on the optical axis: closed form of Eq. 1 + the
+  perspective splat + Eq. 2-3 (one Gaussian: weight = alpha);
+* off-axis anisotropic projection: the splat covariance equals J Sigma_c J^T
+  with J obtained by central differences of the pinhole projection;
+* discretisation scale: the sum of alpha over pixels equals the Gaussian
+  integral o * 2 pi sqrt(det Sigma');
+* two Gaussians: C = c1 a1 + c2 a2 (1 - a1), depth order decides the roles,
+  equal keys are broken by the lower index;
+* blending invariants of Eqs. 2-3;
+* an independent numpy brute force (no culling) on tiny scenes.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2504_19409_amd import scenegen as sg
+
+
+def _single(z, s, o, rgb, feat, W=48, H=40, f=40.0, x=0.0, y=0.0, q=(1, 0, 0, 0)):
+    params = dict(means=np.array([[x], [y], [z]], np.float64),
+                  log_scales=np.log(np.array(s, np.float64)).reshape(3, 1),
+                  quats=np.array(q, np.float64).reshape(4, 1),
+                  logit_opacity=np.array([math.log(o / (1 - o))]),
+                  rgb=np.array(rgb, np.float64).reshape(3, 1),
+                  feat=np.array(feat, np.float64).reshape(1, -1))
+    camera = dict(width=W, height=H, fx=f, fy=f, cx=W / 2, cy=H / 2,
+                  viewmat=sg.identity_viewmat())
+    return params, camera
+
+
+def test_single_isotropic_closed_form(oracle_lib):
+    z, s, o = 2.5, 0.1, 0.7
+    rgb, feat = (0.2, 0.5, 0.9), (1.5, -2.0, 0.25)
+    W, H, f = 48, 40, 40.0
+    p, c = _single(z, (s, s, s), o, rgb, feat, W, H, f)
+    out = oracle_lib.render(p, c)
+    var = (f * s / z) ** 2 + 0.3
+    ys, xs = np.mgrid[0:H, 0:W]
+    r2 = (xs + 0.5 - W / 2) ** 2 + (ys + 0.5 - H / 2) ** 2
+    alpha = o * np.exp(-r2 / (2 * var))
+    alpha = np.where(alpha >= 1 / 255, alpha, 0.0)
+    np.testing.assert_allclose(out["alpha"], alpha, rtol=1e-12, atol=1e-15)
+    for k in range(3):
+        np.testing.assert_allclose(out["rgb"][k], rgb[k] * alpha, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(out["depth"], z * alpha, rtol=1e-12, atol=1e-15)
+    for k in range(3):
+        np.testing.assert_allclose(out["feat"][k], feat[k] * alpha, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(out["T"], 1 - alpha, rtol=1e-12)
+
+
+def test_alpha_clamp_single(oracle_lib):
+    # opacity 0.999 exceeds alpha_max at the centre: alpha clamps to 0.99
+    # odd image size: the principal point is a pixel centre
+    p, c = _single(2.0, (0.2, 0.2, 0.2), 0.999, (1, 1, 1), (1,), W=17, H=17, f=20.0)
+    out = oracle_lib.render(p, c)
+    assert abs(out["alpha"][8, 8] - 0.99) < 1e-15
+    assert out["alpha"][8, 9] < 0.99
+
+
+def _fd_jacobian(mc, f, cx, cy, h=1e-6):
+    def proj(m):
+        return np.array([f * m[0] / m[2] + cx, f * m[1] / m[2] + cy])
+    J = np.zeros((2, 3))
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = h
+        J[:, k] = (proj(mc + e) - proj(mc - e)) / (2 * h)
+    return J
+
+
+def _rot_from_quat_sandwich(q):
+    q = np.asarray(q, float) / np.linalg.norm(q)
+    w, v = q[0], q[1:]
+    R = np.zeros((3, 3))
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = 1.0
+        # Rodrigues form of the sandwich product q e q*
+        R[:, k] = e * (w * w - v @ v) + 2 * v * (v @ e) + 2 * w * np.cross(v, e)
+    return R
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_offaxis_anisotropic_projection(oracle_lib, seed):
+    rng = np.random.default_rng(100 + seed)
+    W, H, f = 64, 48, 60.0
+    q = rng.normal(size=4)
+    s = np.exp(rng.normal(-1.5, 0.4, size=3))
+    m = np.array([rng.uniform(-0.6, 0.6), rng.uniform(-0.4, 0.4), rng.uniform(2, 4)])
+    # a rotated, translated camera
+    vm, _ = sg.perturbed_viewmat(rng, sg.identity_viewmat(), 0.05, 7.0)
+    params = dict(means=m.reshape(3, 1), log_scales=np.log(s).reshape(3, 1),
+                  quats=q.reshape(4, 1), logit_opacity=np.array([0.5]),
+                  rgb=np.ones((3, 1)), feat=np.zeros((1, 1)))
+    cam = dict(width=W, height=H, fx=f, fy=f, cx=W / 2, cy=H / 2, viewmat=vm)
+    pr = oracle_lib.project(params, cam)
+    assert pr["valid"][0] == 1
+    V = vm.astype(np.float64)
+    Rv, tv = V[:, :3], V[:, 3]
+    mc = Rv @ m + tv
+    Rq = _rot_from_quat_sandwich(q)
+    Sig = Rq @ np.diag(s**2) @ Rq.T
+    J = _fd_jacobian(mc, f, W / 2, H / 2)
+    S2 = J @ (Rv @ Sig @ Rv.T) @ J.T + 0.3 * np.eye(2)
+    np.testing.assert_allclose([pr["sig_a"][0], pr["sig_b"][0], pr["sig_c"][0]],
+                               [S2[0, 0], S2[0, 1], S2[1, 1]], rtol=1e-7)
+    K = np.linalg.inv(S2)
+    np.testing.assert_allclose([pr["conic_a"][0], pr["conic_b"][0], pr["conic_c"][0]],
+                               [K[0, 0], K[0, 1], K[1, 1]], rtol=1e-7)
+    np.testing.assert_allclose([pr["u"][0], pr["v"][0]],
+                               [f * mc[0] / mc[2] + W / 2, f * mc[1] / mc[2] + H / 2],
+                               rtol=1e-12)
+    assert pr["depth"][0] == pytest.approx(mc[2], rel=1e-14)
+
+
+def test_gaussian_integral(oracle_lib):
+    # a well-resolved, unclamped Gaussian: sum_p alpha(p) = o 2 pi sqrt(det Sigma')
+    o = 0.6
+    p, c = _single(2.0, (0.2, 0.12, 0.3), o, (1, 1, 1), (0,), W=96, H=96, f=60.0,
+                   q=(0.9, 0.2, -0.3, 0.1))
+    st = oracle_lib.default_settings(alpha_min=1e-14)
+    out = oracle_lib.render(p, c, st)
+    pr = oracle_lib.project(p, c, st)
+    det = pr["sig_a"][0] * pr["sig_c"][0] - pr["sig_b"][0] ** 2
+    assert out["alpha"].sum() == pytest.approx(o * 2 * math.pi * math.sqrt(det), rel=1e-9)
+
+
+def _two(z1, z2, o1=0.6, o2=0.5, c1=(1, 0, 0), c2=(0, 1, 0)):
+    params = dict(means=np.array([[0.0, 0.0], [0.0, 0.0], [z1, z2]]),
+                  log_scales=np.log(np.full((3, 2), 0.15)),
+                  quats=np.array([[1.0, 1.0], [0, 0], [0, 0], [0, 0]]),
+                  logit_opacity=np.log(np.array([o1 / (1 - o1), o2 / (1 - o2)])),
+                  rgb=np.array([c1, c2], float).T, feat=np.array([[1.0], [2.0]]))
+    camera = dict(width=8, height=8, fx=20.0, fy=20.0, cx=4.0, cy=4.0,
+                  viewmat=sg.identity_viewmat())
+    return params, camera
+
+
+def _alpha_at_center_pixel(o, z, f=20.0, s=0.15):
+    var = (f * s / z) ** 2 + 0.3
+    return o * math.exp(-(0.5 ** 2 + 0.5 ** 2) / (2 * var))
+
+
+def test_two_gaussian_closed_form_and_order(oracle_lib):
+    p, c = _two(2.0, 3.0)
+    out = oracle_lib.render(p, c)
+    a1 = _alpha_at_center_pixel(0.6, 2.0)
+    a2 = _alpha_at_center_pixel(0.5, 3.0)
+    px = (4, 4)  # pixel whose centre is (4.5, 4.5)
+    assert out["rgb"][0][px] == pytest.approx(a1, rel=1e-12)
+    assert out["rgb"][1][px] == pytest.approx(a2 * (1 - a1), rel=1e-12)
+    assert out["depth"][px] == pytest.approx(2.0 * a1 + 3.0 * a2 * (1 - a1), rel=1e-12)
+    assert out["alpha"][px] == pytest.approx(1 - (1 - a1) * (1 - a2), rel=1e-12)
+    # swapping the depths swaps the roles
+    p, c = _two(3.0, 2.0)
+    out = oracle_lib.render(p, c)
+    b1 = _alpha_at_center_pixel(0.6, 3.0)
+    b2 = _alpha_at_center_pixel(0.5, 2.0)
+    assert out["rgb"][1][px] == pytest.approx(b2, rel=1e-12)
+    assert out["rgb"][0][px] == pytest.approx(b1 * (1 - b2), rel=1e-12)
+    # equal depth: the lower index is in front
+    p, c = _two(2.0, 2.0)
+    out = oracle_lib.render(p, c)
+    e1 = _alpha_at_center_pixel(0.6, 2.0)
+    e2 = _alpha_at_center_pixel(0.5, 2.0)
+    assert out["rgb"][0][px] == pytest.approx(e1, rel=1e-12)
+    assert out["rgb"][1][px] == pytest.approx(e2 * (1 - e1), rel=1e-12)
+
+
+def test_saturation_stop(oracle_lib):
+    # six equal on-axis Gaussians: at the centre pixel each has alpha = o, so
+    # T after k contributors is (1 - o)^k; blending stops before the one that
+    # would take T below 1e-4 (o = sigmoid(3): (1-o)^3 = 1.06e-4, (1-o)^4 < 1e-4)
+    n = 6
+    params = dict(means=np.stack([np.zeros(n), np.zeros(n), 2.0 + 0.1 * np.arange(n)]),
+                  log_scales=np.log(np.full((3, n), 0.3)),
+                  quats=np.tile(np.array([[1.0], [0], [0], [0]]), (1, n)),
+                  logit_opacity=np.full(n, 3.0), rgb=np.ones((3, n)),
+                  feat=np.ones((n, 1)))
+    camera = dict(width=5, height=5, fx=10.0, fy=10.0, cx=2.5, cy=2.5,
+                  viewmat=sg.identity_viewmat())
+    out = oracle_lib.render(params, camera)
+    o = 1 / (1 + math.exp(-3.0))
+    assert out["n"][2, 2] == 3
+    assert out["T"][2, 2] == pytest.approx((1 - o) ** 3, rel=1e-12)
+    assert out["T"].min() >= 1e-4
+
+
+def _tiny_scene(seed, P=48, W=32, H=24, f=30.0, C=5, perturb=True):
+    rng = np.random.default_rng(seed)
+    vm = sg.identity_viewmat()
+    if perturb:
+        vm, _ = sg.perturbed_viewmat(rng, vm, 0.05, 5.0)
+    sc = sg.make_scene(P, W, H, f, f, W / 2, H / 2, C, seed=seed, viewmat=vm)
+    # larger splats than the default distribution so pixels see many overlaps
+    sc.log_scales += 1.2
+    return sc
+
+
+@pytest.mark.parametrize("seed", [3, 4, 5, 6])
+def test_brute_force_equality(oracle_lib, seed):
+    from oracle import brute
+    sc = _tiny_scene(seed)
+    p, c = oracle_lib.scene_dicts(sc)
+    o = oracle_lib.render(p, c)
+    b = brute.render(p, c)
+    assert o["n"].max() > 3
+    for k in ["rgb", "depth", "alpha", "feat", "T"]:
+        np.testing.assert_allclose(o[k], b[k], rtol=1e-11, atol=1e-13)
+
+
+def test_brute_force_equality_features_off(oracle_lib):
+    from oracle import brute
+    sc = _tiny_scene(9)
+    p, c = oracle_lib.scene_dicts(sc)
+    o = oracle_lib.render(p, c, oracle_lib.default_settings(render_features=False))
+    b = brute.render(p, c, render_features=False)
+    assert np.all(o["feat"] == 0)
+    for k in ["rgb", "depth", "alpha", "T"]:
+        np.testing.assert_allclose(o[k], b[k], rtol=1e-11, atol=1e-13)
+
+
+def test_blending_invariants(oracle_lib):
+    sc, _ = sg.workload_scene("tiny")
+    p, c = oracle_lib.scene_dicts(sc)
+    out = oracle_lib.render(p, c)
+    A = out["alpha"]
+    assert np.all(A >= 0) and np.all(A < 1)
+    assert np.all(out["T"] >= 1e-4)
+    np.testing.assert_allclose(A, 1 - out["T"], rtol=0, atol=1e-15)
+    assert out["rgb"].min() >= 0 and out["rgb"].max() <= 1
+    # constant colour 1 => rendered colour equals accumulated opacity (sum w = A)
+    p1 = dict(p, rgb=np.ones_like(p["rgb"]))
+    o1 = oracle_lib.render(p1, c)
+    for k in range(3):
+        np.testing.assert_allclose(o1["rgb"][k], A, rtol=1e-12, atol=1e-15)
+    # constant feature => F = f A;  F is linear in f
+    C = p["feat"].shape[1]
+    fc = np.tile(np.linspace(-1, 2, C), (p["feat"].shape[0], 1))
+    o2 = oracle_lib.render(dict(p, feat=fc), c)
+    for k in range(C):
+        np.testing.assert_allclose(o2["feat"][k], fc[0, k] * A, rtol=1e-11, atol=1e-14)
+    rng = np.random.default_rng(0)
+    f1, f2 = rng.normal(size=p["feat"].shape), rng.normal(size=p["feat"].shape)
+    oa = oracle_lib.render(dict(p, feat=f1), c)["feat"]
+    ob = oracle_lib.render(dict(p, feat=f2), c)["feat"]
+    oab = oracle_lib.render(dict(p, feat=2.0 * f1 - 3.0 * f2), c)["feat"]
+    np.testing.assert_allclose(oab, 2.0 * oa - 3.0 * ob, rtol=1e-10, atol=1e-12)
+    # flag off => F = 0, geometry outputs unchanged
+    o3 = oracle_lib.render(p, c, oracle_lib.default_settings(render_features=False))
+    assert np.all(o3["feat"] == 0)
+    for k in ["rgb", "depth", "alpha"]:
+        assert np.array_equal(o3[k], out[k])
+
+
+def test_constant_depth_gives_depth_times_alpha(oracle_lib):
+    rng = np.random.default_rng(11)
+    P, W, H, f = 60, 24, 20, 25.0
+    z = 3.0
+    u, v = rng.uniform(0, W, P), rng.uniform(0, H, P)
+    means = np.stack([(u - W / 2) * z / f, (v - H / 2) * z / f, np.full(P, z)])
+    q = rng.normal(size=(4, P))
+    params = dict(means=means, log_scales=rng.normal(-1.5, 0.3, (3, P)), quats=q,
+                  logit_opacity=rng.normal(size=P), rgb=rng.random((3, P)),
+                  feat=np.zeros((P, 1)))
+    cam = dict(width=W, height=H, fx=f, fy=f, cx=W / 2, cy=H / 2,
+               viewmat=sg.identity_viewmat())
+    out = oracle_lib.render(params, cam)
+    np.testing.assert_allclose(out["depth"], z * out["alpha"], rtol=1e-12, atol=1e-14)
+
+
+def test_culling_rules(oracle_lib):
+    # behind the near plane, outside the guard band, zero quaternion, tiny opacity
+    params = dict(means=np.array([[0.0, 5.0, 0.0, 0.0, 0.0], [0, 0, 0, 0, 0],
+                                  [0.1, 2.0, 2.0, 2.0, 2.0]]),
+                  log_scales=np.full((3, 5), -1.0),
+                  quats=np.array([[1.0, 1, 0, 1, 1], [0, 0, 0, 0, 0], [0, 0, 0, 0, 0],
+                                  [0, 0, 0, 0, 0]]),
+                  logit_opacity=np.array([0.0, 0.0, 0.0, -9.0, 0.0]),
+                  rgb=np.ones((3, 5)), feat=np.ones((5, 1)))
+    cam = dict(width=16, height=16, fx=16.0, fy=16.0, cx=8.0, cy=8.0,
+               viewmat=sg.identity_viewmat())
+    pr = oracle_lib.project(params, cam)
+    assert list(pr["valid"]) == [0, 0, 0, 0, 1]
