@@ -1,0 +1,237 @@
+/*
+ * gsff.h -- C ABI of the MI355X (gfx950) feature-field Gaussian rasterizer.
+ *
+ * The library renders, for one pinhole camera, the RGB image, the depth image,
+ * the accumulated opacity and an N-channel feature map of a set of 3D Gaussians
+ * by front-to-back alpha blending (GSFF-SLAM, Sec. 3.1, Eqs. 1-3), and returns
+ * the gradients of the outputs with respect to every Gaussian parameter and the
+ * SE(3) camera pose (Sec. 3.2, Eq. 4).  The feature map's gradient reaches only
+ * the feature embeddings, never the means, covariances, opacities or pose
+ * (Sec. 3.1, last paragraph), and a flag turns feature rendering and its
+ * gradient off altogether (same paragraph).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Array pointers are DEVICE pointers to caller-owned memory unless stated.
+ *    The library never allocates or frees device memory and keeps no pointer
+ *    after a call returns.  All scratch lives in a caller-allocated workspace
+ *    of gsff_workspace_size() bytes (256-byte aligned).
+ *  - `stream` is a hipStream_t (passed as void*); all work is enqueued on it
+ *    and the call returns without waiting.  Nothing inside the forward or
+ *    backward synchronises host and device, so sequences of calls can be
+ *    captured into a HIP graph.  Only gsff_read_status() waits.
+ *  - Layouts: per-Gaussian vectors are planar [k, P] (component-major);
+ *    features are row-major [P, C]; images are planar [k, H, W].
+ *  - Calls are thread-compatible: the library holds no mutable global state.
+ *  - Return value: GSFF_OK, or GSFF_ERR_INVALID_ARGUMENT (NULL pointer, bad
+ *    size, workspace too small, unsupported size combination),
+ *    GSFF_ERR_UNSUPPORTED (dtype / channel combination not built), or
+ *    GSFF_ERR_HIP (a launch failed; gsff_last_error() has the text).
+ *  - Conditions found on the device (too many tile pairs for the workspace)
+ *    are not returned: they set bits of a status word inside the workspace that
+ *    gsff_read_status() reports.  On overflow the affected frame renders as
+ *    empty (zero images, T = 1) rather than reading out of bounds.
+ */
+#ifndef GSFF_H
+#define GSFF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gsff_status;
+#define GSFF_OK 0
+#define GSFF_ERR_INVALID_ARGUMENT (-1)
+#define GSFF_ERR_UNSUPPORTED (-2)
+#define GSFF_ERR_HIP (-3)
+
+/* status-word bits set by the device */
+#define GSFF_FLAG_PAIR_OVERFLOW 1u
+
+/* payload / output element types */
+#define GSFF_DTYPE_F32 0
+#define GSFF_DTYPE_BF16 1
+#define GSFF_DTYPE_F16 2
+
+/* largest channel count composited in one pass; wider payloads are rendered in
+ * channel chunks of this size that recompute the blending weights */
+#define GSFF_MAX_CHANNELS_PER_PASS 64
+
+/* Screen tiles are GSFF_TILE x GSFF_TILE pixels. */
+#define GSFF_TILE 16
+
+/* Rendering constants the paper does not print (it inherits them from the
+ * 3D Gaussian splatting rasterizer it builds on, Sec. 3.1).  Defaults from
+ * gsff_default_settings(): near 0.2, guard 1.3, dilation 0.3,
+ * alpha_min 1/255, alpha_max 0.99, t_min 1e-4, render_features 1. */
+typedef struct gsff_settings {
+  float near_plane;       /* Gaussians with camera z <= near_plane are culled     */
+  float guard;            /* cull |x/z| > guard*W/(2fx) or |y/z| > guard*H/(2fy)  */
+  float dilation;         /* added to both diagonal entries of the 2D covariance */
+  float alpha_min;        /* per-pixel alpha below this is skipped               */
+  float alpha_max;        /* per-pixel alpha is clamped to this                  */
+  float t_min;            /* blending stops before T would fall below this       */
+  int32_t render_features;/* 0: feature map is zero and receives no gradient     */
+  int32_t reserved;
+} gsff_settings;
+
+/* Pinhole camera.  viewmat is a DEVICE pointer to 12 floats, the row-major
+ * 3x4 world-to-camera transform [R | t] = T_CW (x right, y down, z forward).
+ * Pixel (px, py) is sampled at (px + 1/2, py + 1/2). */
+typedef struct gsff_camera {
+  int32_t width, height;
+  float fx, fy, cx, cy;
+  const float* viewmat;
+} gsff_camera;
+
+/* Gaussian set G_i = {mean, quaternion, scale, opacity, colour, feature}
+ * (Sec. 3.1).  Raw optimisation parameters: scale = exp(log_scales),
+ * opacity = sigmoid(logit_opacity); the activations are fused into the
+ * kernels.  Quaternions (w, x, y, z) need not be normalised.  rgb is a
+ * view-independent colour.  feat is [P, C] in feat_dtype (NULL iff C == 0). */
+typedef struct gsff_gaussians {
+  int64_t P;
+  int32_t C;
+  int32_t feat_dtype;          /* GSFF_DTYPE_F32 / BF16 / F16 */
+  const float* means;          /* [3, P] */
+  const float* log_scales;     /* [3, P] */
+  const float* quats;          /* [4, P] */
+  const float* logit_opacity;  /* [P]    */
+  const float* rgb;            /* [3, P] */
+  const void* feat;            /* [P, C] */
+} gsff_gaussians;
+
+/* Gradient outputs, FP32, same layouts as the parameters.  Any pointer may be
+ * NULL to skip that output.  pose is [6] = (rho, theta): the gradient w.r.t.
+ * the left perturbation T_CW <- Exp(delta) T_CW at delta = 0 (Eq. 4),
+ * summed over Gaussians in FP64.  feat is FP32 even for a BF16/FP16 payload. */
+typedef struct gsff_grads {
+  float* means;          /* [3, P] */
+  float* log_scales;     /* [3, P] */
+  float* quats;          /* [4, P] */
+  float* logit_opacity;  /* [P]    */
+  float* rgb;            /* [3, P] */
+  float* feat;           /* [P, C] */
+  float* pose;           /* [6]    */
+} gsff_grads;
+
+/* Where each workspace region starts (byte offsets from the workspace base)
+ * and how big it is; used by tests to inspect intermediate stages. */
+typedef struct gsff_ws_layout {
+  uint64_t status;      /* uint32[4]: flags, pair count, reserved x2            */
+  uint64_t records;     /* float4[3][P]: (u,v,A,B) (C,o,z,valid) (r,g,b,-)     */
+  uint64_t rects;       /* uint16[4][P]: tile rect x0,y0,x1,y1 (inclusive); empty => x0>x1 */
+  uint64_t depth_keys;  /* uint32[P]: sorted depth keys (float bits)           */
+  uint64_t depth_ids;   /* uint32[P]: Gaussian index in depth order            */
+  uint64_t pair_keys;   /* uint32[max_pairs]: (tile << rank_bits) | depth rank */
+  uint64_t tile_ranges; /* uint32[2][ntiles]: [start, end) into pair_keys      */
+  uint64_t pix_T;       /* float[H*W]: final transmittance                     */
+  uint64_t pix_end;     /* uint32[H*W]: 1 + list position of last contributor  */
+  uint64_t grad2d;      /* float[P][10]: du dv dA dB dC do dr dg db dz         */
+  uint64_t total_bytes;
+  int32_t rank_bits;    /* bits of the depth rank inside a pair key            */
+  int32_t tiles_x, tiles_y;
+  int32_t reserved;
+} gsff_ws_layout;
+
+/* Library version (host only, no device work). */
+gsff_status gsff_version(int32_t* major, int32_t* minor);
+
+/* Text of the last GSFF_ERR_HIP / argument error raised on this thread. */
+const char* gsff_last_error(void);
+
+/* Fill *st with the defaults listed above (host only). */
+gsff_status gsff_default_settings(gsff_settings* st);
+
+/* Workspace bytes for P Gaussians, a pair capacity of max_pairs
+ * (Gaussian-tile overlaps), and a width x height image (host only).
+ * Requires ceil(log2(max(P,2))) + ceil(log2(tiles)) <= 32. */
+gsff_status gsff_workspace_size(int64_t P, int64_t max_pairs, int32_t width,
+                                int32_t height, size_t* bytes);
+
+/* Region offsets of a workspace for these sizes (host only). */
+gsff_status gsff_workspace_layout(int64_t P, int64_t max_pairs, int32_t width,
+                                  int32_t height, gsff_ws_layout* out);
+
+/* Forward render (Sec. 3.1, Eqs. 1-3): preprocess, depth sort, tile binning,
+ * tile sort, tile ranges and front-to-back compositing, all on `stream`.
+ * Outputs (caller-owned, device): out_rgb [3,H,W] f32, out_depth [H,W] f32
+ * (sum of w_i z_i, not normalised), out_alpha [H,W] f32 (= 1 - T_final),
+ * out_feat [C,H,W] in out_feat_dtype (F32 or BF16; may be NULL when C == 0
+ * or features are off -- when non-NULL and features are off it is zeroed).
+ * The workspace keeps what the backward needs; leave it untouched between
+ * the forward and the backward of the same frame. */
+gsff_status gsff_forward(const gsff_gaussians* g, const gsff_camera* cam,
+                         const gsff_settings* st, void* ws, size_t ws_bytes,
+                         int64_t max_pairs, float* out_rgb, float* out_depth,
+                         float* out_alpha, void* out_feat, int32_t out_feat_dtype,
+                         void* stream);
+
+/* Backward (Sec. 3.1 last paragraph; Sec. 3.2, Eq. 4) of the forward that
+ * last used `ws`.  Upstream gradients g_rgb [3,H,W], g_depth [H,W],
+ * g_alpha [H,W] (f32, none NULL) and g_feat [C,H,W] f32 (NULL = zero).
+ * Geometry gradients (means, scales, rotations, opacities, colours, pose)
+ * come only from g_rgb / g_depth / g_alpha; g_feat only reaches out->feat.
+ * accumulate = 0 overwrites the outputs, 1 adds to them (multi-view).
+ * With every geometry pointer NULL only the feature gradient is computed. */
+gsff_status gsff_backward(const gsff_gaussians* g, const gsff_camera* cam,
+                          const gsff_settings* st, void* ws, size_t ws_bytes,
+                          int64_t max_pairs, const float* g_rgb, const float* g_depth,
+                          const float* g_alpha, const float* g_feat,
+                          const gsff_grads* out, int32_t accumulate, void* stream);
+
+/* Stage entry points: the forward is exactly preprocess, sort_depth, bin,
+ * sort_tiles, tile_ranges, composite_fwd in this order; the backward is
+ * composite_bwd then preprocess_bwd.  Same arguments and conventions as the
+ * two calls above; exposed for stage-by-stage testing and timing. */
+gsff_status gsff_preprocess(const gsff_gaussians* g, const gsff_camera* cam,
+                            const gsff_settings* st, void* ws, size_t ws_bytes,
+                            int64_t max_pairs, void* stream);
+gsff_status gsff_sort_depth(const gsff_gaussians* g, const gsff_camera* cam,
+                            const gsff_settings* st, void* ws, size_t ws_bytes,
+                            int64_t max_pairs, void* stream);
+gsff_status gsff_bin(const gsff_gaussians* g, const gsff_camera* cam,
+                     const gsff_settings* st, void* ws, size_t ws_bytes,
+                     int64_t max_pairs, void* stream);
+gsff_status gsff_sort_tiles(const gsff_gaussians* g, const gsff_camera* cam,
+                            const gsff_settings* st, void* ws, size_t ws_bytes,
+                            int64_t max_pairs, void* stream);
+gsff_status gsff_tile_ranges(const gsff_gaussians* g, const gsff_camera* cam,
+                             const gsff_settings* st, void* ws, size_t ws_bytes,
+                             int64_t max_pairs, void* stream);
+gsff_status gsff_composite_fwd(const gsff_gaussians* g, const gsff_camera* cam,
+                               const gsff_settings* st, void* ws, size_t ws_bytes,
+                               int64_t max_pairs, float* out_rgb, float* out_depth,
+                               float* out_alpha, void* out_feat, int32_t out_feat_dtype,
+                               void* stream);
+gsff_status gsff_composite_bwd(const gsff_gaussians* g, const gsff_camera* cam,
+                               const gsff_settings* st, void* ws, size_t ws_bytes,
+                               int64_t max_pairs, const float* g_rgb,
+                               const float* g_depth, const float* g_alpha,
+                               const float* g_feat, const gsff_grads* out,
+                               int32_t accumulate, void* stream);
+gsff_status gsff_preprocess_bwd(const gsff_gaussians* g, const gsff_camera* cam,
+                                const gsff_settings* st, void* ws, size_t ws_bytes,
+                                int64_t max_pairs, const gsff_grads* out,
+                                int32_t accumulate, void* stream);
+
+/* L1 loss of one output group (the tracking / mapping / semantic losses,
+ * Eqs. 5, 8 and 11, are weighted L1 terms): grad[i] = scale * sign(x[i] - y[i])
+ * (0 where equal) and, if loss != NULL, *loss += scale * sum |x - y| (FP32
+ * atomics).  n elements, device pointers. */
+gsff_status gsff_l1_grad(const float* x, const float* y, int64_t n, float scale,
+                         float* grad, float* loss, void* stream);
+
+/* Wait for `stream`, then copy the workspace status word (which starts at
+ * byte 0 of every workspace) to the host: *flags receives the GSFF_FLAG_*
+ * bits and *n_pairs the number of tile pairs the last forward needed (even
+ * when it exceeded max_pairs).  Host pointers; either may be NULL. */
+gsff_status gsff_read_status(const void* ws, uint32_t* flags, int64_t* n_pairs, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GSFF_H */

@@ -1,0 +1,139 @@
+"""ctypes declarations of the C ABI in include/gsff.h (argument marshalling
+only; every step of the computation runs in the HIP library)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgsff.so")
+
+OK = 0
+ERR_INVALID_ARGUMENT = -1
+ERR_UNSUPPORTED = -2
+ERR_HIP = -3
+FLAG_PAIR_OVERFLOW = 1
+DTYPE_F32, DTYPE_BF16, DTYPE_F16 = 0, 1, 2
+TILE = 16
+MAX_CHANNELS_PER_PASS = 64
+
+_vp = ctypes.c_void_p
+
+
+class Settings(ctypes.Structure):
+    _fields_ = [("near_plane", ctypes.c_float), ("guard", ctypes.c_float),
+                ("dilation", ctypes.c_float), ("alpha_min", ctypes.c_float),
+                ("alpha_max", ctypes.c_float), ("t_min", ctypes.c_float),
+                ("render_features", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("fx", ctypes.c_float), ("fy", ctypes.c_float),
+                ("cx", ctypes.c_float), ("cy", ctypes.c_float), ("viewmat", _vp)]
+
+
+class Gaussians(ctypes.Structure):
+    _fields_ = [("P", ctypes.c_int64), ("C", ctypes.c_int32), ("feat_dtype", ctypes.c_int32),
+                ("means", _vp), ("log_scales", _vp), ("quats", _vp), ("logit_opacity", _vp),
+                ("rgb", _vp), ("feat", _vp)]
+
+
+class Grads(ctypes.Structure):
+    _fields_ = [("means", _vp), ("log_scales", _vp), ("quats", _vp), ("logit_opacity", _vp),
+                ("rgb", _vp), ("feat", _vp), ("pose", _vp)]
+
+
+class WsLayout(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_uint64), ("records", ctypes.c_uint64),
+                ("rects", ctypes.c_uint64), ("depth_keys", ctypes.c_uint64),
+                ("depth_ids", ctypes.c_uint64), ("pair_keys", ctypes.c_uint64),
+                ("tile_ranges", ctypes.c_uint64), ("pix_T", ctypes.c_uint64),
+                ("pix_end", ctypes.c_uint64), ("grad2d", ctypes.c_uint64),
+                ("total_bytes", ctypes.c_uint64), ("rank_bits", ctypes.c_int32),
+                ("tiles_x", ctypes.c_int32), ("tiles_y", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+_G, _C, _S, _R = (ctypes.POINTER(Gaussians), ctypes.POINTER(Camera), ctypes.POINTER(Settings),
+                  ctypes.POINTER(Grads))
+_i64, _i32, _f32, _sz = ctypes.c_int64, ctypes.c_int32, ctypes.c_float, ctypes.c_size_t
+
+# name -> (restype, argtypes); the header's full list of entry points
+SIGNATURES = {
+    "gsff_version": (_i32, [ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    "gsff_last_error": (ctypes.c_char_p, []),
+    "gsff_default_settings": (_i32, [_S]),
+    "gsff_workspace_size": (_i32, [_i64, _i64, _i32, _i32, ctypes.POINTER(_sz)]),
+    "gsff_workspace_layout": (_i32, [_i64, _i64, _i32, _i32, ctypes.POINTER(WsLayout)]),
+    "gsff_forward": (_i32, [_G, _C, _S, _vp, _sz, _i64, _vp, _vp, _vp, _vp, _i32, _vp]),
+    "gsff_backward": (_i32, [_G, _C, _S, _vp, _sz, _i64, _vp, _vp, _vp, _vp, _R, _i32, _vp]),
+    "gsff_preprocess": (_i32, [_G, _C, _S, _vp, _sz, _i64, _vp]),
+    "gsff_sort_depth": (_i32, [_G, _C, _S, _vp, _sz, _i64, _vp]),
+    "gsff_bin": (_i32, [_G, _C, _S, _vp, _sz, _i64, _vp]),
+    "gsff_sort_tiles": (_i32, [_G, _C, _S, _vp, _sz, _i64, _vp]),
+    "gsff_tile_ranges": (_i32, [_G, _C, _S, _vp, _sz, _i64, _vp]),
+    "gsff_composite_fwd": (_i32, [_G, _C, _S, _vp, _sz, _i64, _vp, _vp, _vp, _vp, _i32, _vp]),
+    "gsff_composite_bwd": (_i32, [_G, _C, _S, _vp, _sz, _i64, _vp, _vp, _vp, _vp, _R, _i32,
+                                  _vp]),
+    "gsff_preprocess_bwd": (_i32, [_G, _C, _S, _vp, _sz, _i64, _R, _i32, _vp]),
+    "gsff_l1_grad": (_i32, [_vp, _vp, _i64, _f32, _vp, _vp, _vp]),
+    "gsff_read_status": (_i32, [_vp, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(_i64),
+                                _vp]),
+    "gsff_decoder_forward": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _i32, _i64, _vp]),
+    "gsff_decoder_train_step": (_i32, [_vp] * 6 + [_i64, _f32, _vp, _vp, _vp, _vp, _vp, _vp,
+                                                   _vp, _sz, _vp]),
+    "gsff_decoder_workspace_size": (_i32, [_i64, ctypes.POINTER(_sz)]),
+}
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libgsff.so.  Raises if it is missing: there is no fallback."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is not built; run paper_2504_19409_amd/build.py "
+                "(or __graft_entry__.build()) first")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            if hasattr(L, name):
+                f = getattr(L, name)
+                f.restype = res
+                f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class GsffError(RuntimeError):
+    pass
+
+
+def check(rc: int, what: str):
+    if rc != OK:
+        msg = load().gsff_last_error()
+        raise GsffError(f"{what} failed ({rc}): {msg.decode() if msg else ''}")
+
+
+def default_settings(**kw) -> Settings:
+    s = Settings()
+    check(load().gsff_default_settings(ctypes.byref(s)), "gsff_default_settings")
+    for k, v in kw.items():
+        setattr(s, k, v)
+    return s
+
+
+def workspace_size(P, max_pairs, width, height) -> int:
+    n = _sz(0)
+    check(load().gsff_workspace_size(P, max_pairs, width, height, ctypes.byref(n)),
+          "gsff_workspace_size")
+    return int(n.value)
+
+
+def workspace_layout(P, max_pairs, width, height) -> WsLayout:
+    lay = WsLayout()
+    check(load().gsff_workspace_layout(P, max_pairs, width, height, ctypes.byref(lay)),
+          "gsff_workspace_layout")
+    return lay

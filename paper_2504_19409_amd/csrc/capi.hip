@@ -1,0 +1,363 @@
+// Host side of the C ABI declared in include/gsff.h: argument checks,
+// workspace layout, and the launch sequence of every stage.  No allocation,
+// no host/device synchronisation (except gsff_read_status).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "gsff_internal.h"
+
+namespace gsff {
+
+static thread_local std::string g_last_error;
+
+static gsff_status fail(gsff_status code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+static gsff_status hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return GSFF_OK;
+  return fail(GSFF_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool compute_layout(int64_t P, int64_t max_pairs, int32_t W, int32_t H, Layout* L) {
+  if (P < 0 || max_pairs < 0 || W <= 0 || H <= 0) return false;
+  if (P > (int64_t)0x7FFFFFFF || max_pairs > (int64_t)0xFFFFFFFEu) return false;
+  Layout l;
+  l.P = P;
+  l.max_pairs = max_pairs;
+  l.W = W;
+  l.H = H;
+  l.tiles_x = (W + kTile - 1) / kTile;
+  l.tiles_y = (H + kTile - 1) / kTile;
+  if (l.tiles_x > 65535 || l.tiles_y > 65535) return false;
+  l.ntiles = l.tiles_x * l.tiles_y;
+  l.rank_bits = ceil_log2((uint64_t)(P < 2 ? 2 : P));
+  l.tile_bits = ceil_log2((uint64_t)l.ntiles);
+  if (l.rank_bits + l.tile_bits > 32) return false;
+  l.depth_chunks = (P + kRadixChunk - 1) / kRadixChunk;
+  l.pair_chunks = (max_pairs + kRadixChunk - 1) / kRadixChunk;
+  l.scan_blocks = (P + kScanBlock - 1) / kScanBlock;
+  l.pose_blocks = (P + kPoseBlock - 1) / kPoseBlock;
+  const uint64_t HW = (uint64_t)W * H;
+  const uint64_t A = 256;
+  uint64_t o = 0;
+  auto take = [&](uint64_t bytes) {
+    const uint64_t at = o;
+    o = align_up(o + bytes, A);
+    return at;
+  };
+  l.status = take(16);
+  l.records = take(48ull * P);
+  l.rects = take(8ull * P);
+  l.dkeys_a = take(4ull * P);
+  l.dkeys_b = take(4ull * P);
+  l.dids_a = take(4ull * P);
+  l.dids_b = take(4ull * P);
+  l.offsets = take(4ull * (P + 1));
+  l.pkeys_a = take(4ull * max_pairs);
+  l.pkeys_b = take(4ull * max_pairs);
+  l.tile_ranges = take(8ull * l.ntiles);
+  l.pix_T = take(4ull * HW);
+  l.pix_end = take(4ull * HW);
+  l.grad2d = take(40ull * P);
+  const int64_t chunks = l.depth_chunks > l.pair_chunks ? l.depth_chunks : l.pair_chunks;
+  l.hist = take(4ull * 256 * (uint64_t)(chunks > 0 ? chunks : 1));
+  l.hist_tot = take(4ull * 256);
+  l.scan_part = take(4ull * (uint64_t)(l.scan_blocks + 1));
+  l.pose_part = take(8ull * 6 * (uint64_t)(l.pose_blocks + 1));
+  l.total = o;
+  *L = l;
+  return true;
+}
+
+WsView make_view(void* ws, const Layout& L) {
+  char* b = (char*)ws;
+  WsView w;
+  w.status = (uint32_t*)(b + L.status);
+  w.rec = (float4*)(b + L.records);
+  w.rects = (ushort4*)(b + L.rects);
+  w.dkeys_a = (uint32_t*)(b + L.dkeys_a);
+  w.dkeys_b = (uint32_t*)(b + L.dkeys_b);
+  w.dids_a = (uint32_t*)(b + L.dids_a);
+  w.dids_b = (uint32_t*)(b + L.dids_b);
+  w.offsets = (uint32_t*)(b + L.offsets);
+  w.pkeys_a = (uint32_t*)(b + L.pkeys_a);
+  w.pkeys_b = (uint32_t*)(b + L.pkeys_b);
+  w.tile_ranges = (uint2*)(b + L.tile_ranges);
+  w.pix_T = (float*)(b + L.pix_T);
+  w.pix_end = (uint32_t*)(b + L.pix_end);
+  w.grad2d = (float*)(b + L.grad2d);
+  w.hist = (uint32_t*)(b + L.hist);
+  w.hist_tot = (uint32_t*)(b + L.hist_tot);
+  w.scan_part = (uint32_t*)(b + L.scan_part);
+  w.pose_part = (double*)(b + L.pose_part);
+  return w;
+}
+
+namespace {
+
+struct Ctx {
+  Layout L;
+  WsView w;
+  DevGaussians g;
+  DevCamera cam;
+  DevSettings st;
+  hipStream_t s;
+};
+
+gsff_status check_common(const gsff_gaussians* g, const gsff_camera* cam, const gsff_settings* st,
+                         void* ws, size_t ws_bytes, int64_t max_pairs, void* stream, Ctx* c) {
+  if (!g || !cam || !st) return fail(GSFF_ERR_INVALID_ARGUMENT, "NULL gaussians/camera/settings");
+  if (g->P < 0) return fail(GSFF_ERR_INVALID_ARGUMENT, "P < 0");
+  if (g->C < 0 || g->C > 4096) return fail(GSFF_ERR_INVALID_ARGUMENT, "C out of range [0, 4096]");
+  if (g->feat_dtype != GSFF_DTYPE_F32 && g->feat_dtype != GSFF_DTYPE_BF16 &&
+      g->feat_dtype != GSFF_DTYPE_F16)
+    return fail(GSFF_ERR_UNSUPPORTED, "feature dtype");
+  if (g->P > 0 && (!g->means || !g->log_scales || !g->quats || !g->logit_opacity || !g->rgb))
+    return fail(GSFF_ERR_INVALID_ARGUMENT, "NULL Gaussian parameter pointer");
+  if (g->P > 0 && g->C > 0 && !g->feat)
+    return fail(GSFF_ERR_INVALID_ARGUMENT, "C > 0 but feat is NULL");
+  if (cam->width <= 0 || cam->height <= 0) return fail(GSFF_ERR_INVALID_ARGUMENT, "image size");
+  if (!(cam->fx > 0.f) || !(cam->fy > 0.f) || !std::isfinite(cam->cx) || !std::isfinite(cam->cy))
+    return fail(GSFF_ERR_INVALID_ARGUMENT, "intrinsics");
+  if (!cam->viewmat) return fail(GSFF_ERR_INVALID_ARGUMENT, "NULL viewmat");
+  if (!(st->alpha_min > 0.f) || !(st->alpha_max <= 1.f) || !(st->alpha_min < st->alpha_max) ||
+      !(st->t_min > 0.f) || !(st->t_min < 1.f) || !(st->dilation >= 0.f) || !(st->guard > 0.f) ||
+      !std::isfinite(st->near_plane))
+    return fail(GSFF_ERR_INVALID_ARGUMENT, "settings out of range");
+  if (!ws) return fail(GSFF_ERR_INVALID_ARGUMENT, "NULL workspace");
+  if (((uintptr_t)ws & 255u) != 0) return fail(GSFF_ERR_INVALID_ARGUMENT, "workspace not 256-byte aligned");
+  if (!compute_layout(g->P, max_pairs, cam->width, cam->height, &c->L))
+    return fail(GSFF_ERR_INVALID_ARGUMENT,
+                "sizes not representable (P, max_pairs, image, or rank+tile bits > 32)");
+  if (ws_bytes < c->L.total) return fail(GSFF_ERR_INVALID_ARGUMENT, "workspace too small");
+  c->w = make_view(ws, c->L);
+  c->g = DevGaussians{g->P, g->C, g->feat_dtype, g->means, g->log_scales, g->quats,
+                      g->logit_opacity, g->rgb, g->feat};
+  c->cam = DevCamera{cam->width, cam->height, cam->fx, cam->fy, cam->cx, cam->cy, cam->viewmat};
+  c->st = DevSettings{st->near_plane, st->guard, st->dilation, st->alpha_min,
+                      st->alpha_max, st->t_min, st->render_features ? 1 : 0};
+  c->s = (hipStream_t)stream;
+  return GSFF_OK;
+}
+
+gsff_status check_outputs(const Ctx& c, float* out_rgb, float* out_depth, float* out_alpha,
+                          void* out_feat, int32_t out_feat_dtype) {
+  if (!out_rgb || !out_depth || !out_alpha) return fail(GSFF_ERR_INVALID_ARGUMENT, "NULL output image");
+  if (out_feat_dtype != GSFF_DTYPE_F32 && out_feat_dtype != GSFF_DTYPE_BF16)
+    return fail(GSFF_ERR_UNSUPPORTED, "output feature dtype");
+  if (c.st.render_features && c.g.C > 0 && !out_feat)
+    return fail(GSFF_ERR_INVALID_ARGUMENT, "features on but out_feat is NULL");
+  return GSFF_OK;
+}
+
+bool any_geometry(const gsff_grads* o) {
+  return o->means || o->log_scales || o->quats || o->logit_opacity || o->rgb || o->pose;
+}
+
+}  // namespace
+}  // namespace gsff
+
+using namespace gsff;
+
+extern "C" {
+
+gsff_status gsff_version(int32_t* major, int32_t* minor) {
+  if (!major || !minor) return fail(GSFF_ERR_INVALID_ARGUMENT, "NULL version pointer");
+  *major = 0;
+  *minor = 1;
+  return GSFF_OK;
+}
+
+const char* gsff_last_error(void) { return g_last_error.c_str(); }
+
+gsff_status gsff_default_settings(gsff_settings* st) {
+  if (!st) return fail(GSFF_ERR_INVALID_ARGUMENT, "NULL settings");
+  st->near_plane = 0.2f;
+  st->guard = 1.3f;
+  st->dilation = 0.3f;
+  st->alpha_min = 1.0f / 255.0f;
+  st->alpha_max = 0.99f;
+  st->t_min = 1e-4f;
+  st->render_features = 1;
+  st->reserved = 0;
+  return GSFF_OK;
+}
+
+gsff_status gsff_workspace_size(int64_t P, int64_t max_pairs, int32_t width, int32_t height,
+                                size_t* bytes) {
+  if (!bytes) return fail(GSFF_ERR_INVALID_ARGUMENT, "NULL bytes");
+  Layout L;
+  if (!compute_layout(P, max_pairs, width, height, &L))
+    return fail(GSFF_ERR_INVALID_ARGUMENT, "sizes not representable");
+  *bytes = (size_t)L.total;
+  return GSFF_OK;
+}
+
+gsff_status gsff_workspace_layout(int64_t P, int64_t max_pairs, int32_t width, int32_t height,
+                                  gsff_ws_layout* out) {
+  if (!out) return fail(GSFF_ERR_INVALID_ARGUMENT, "NULL layout");
+  Layout L;
+  if (!compute_layout(P, max_pairs, width, height, &L))
+    return fail(GSFF_ERR_INVALID_ARGUMENT, "sizes not representable");
+  out->status = L.status;
+  out->records = L.records;
+  out->rects = L.rects;
+  out->depth_keys = L.dkeys_a;
+  out->depth_ids = L.dids_a;
+  out->pair_keys = L.pkeys_a;
+  out->tile_ranges = L.tile_ranges;
+  out->pix_T = L.pix_T;
+  out->pix_end = L.pix_end;
+  out->grad2d = L.grad2d;
+  out->total_bytes = L.total;
+  out->rank_bits = L.rank_bits;
+  out->tiles_x = L.tiles_x;
+  out->tiles_y = L.tiles_y;
+  out->reserved = 0;
+  return GSFF_OK;
+}
+
+#define GSFF_PRELUDE                                                                \
+  Ctx c;                                                                            \
+  {                                                                                 \
+    gsff_status rc_ = check_common(g, cam, st, ws, ws_bytes, max_pairs, stream, &c); \
+    if (rc_ != GSFF_OK) return rc_;                                                 \
+  }
+
+gsff_status gsff_preprocess(const gsff_gaussians* g, const gsff_camera* cam,
+                            const gsff_settings* st, void* ws, size_t ws_bytes,
+                            int64_t max_pairs, void* stream) {
+  GSFF_PRELUDE
+  return hip_check(launch_preprocess(c.g, c.cam, c.st, c.L, c.w, c.s), "preprocess");
+}
+
+gsff_status gsff_sort_depth(const gsff_gaussians* g, const gsff_camera* cam,
+                            const gsff_settings* st, void* ws, size_t ws_bytes,
+                            int64_t max_pairs, void* stream) {
+  GSFF_PRELUDE
+  return hip_check(launch_sort_depth(c.L, c.w, c.s), "sort_depth");
+}
+
+gsff_status gsff_bin(const gsff_gaussians* g, const gsff_camera* cam, const gsff_settings* st,
+                     void* ws, size_t ws_bytes, int64_t max_pairs, void* stream) {
+  GSFF_PRELUDE
+  return hip_check(launch_bin(c.L, c.w, c.s), "bin");
+}
+
+gsff_status gsff_sort_tiles(const gsff_gaussians* g, const gsff_camera* cam,
+                            const gsff_settings* st, void* ws, size_t ws_bytes,
+                            int64_t max_pairs, void* stream) {
+  GSFF_PRELUDE
+  return hip_check(launch_sort_tiles(c.L, c.w, c.s), "sort_tiles");
+}
+
+gsff_status gsff_tile_ranges(const gsff_gaussians* g, const gsff_camera* cam,
+                             const gsff_settings* st, void* ws, size_t ws_bytes,
+                             int64_t max_pairs, void* stream) {
+  GSFF_PRELUDE
+  return hip_check(launch_tile_ranges(c.L, c.w, c.s), "tile_ranges");
+}
+
+gsff_status gsff_composite_fwd(const gsff_gaussians* g, const gsff_camera* cam,
+                               const gsff_settings* st, void* ws, size_t ws_bytes,
+                               int64_t max_pairs, float* out_rgb, float* out_depth,
+                               float* out_alpha, void* out_feat, int32_t out_feat_dtype,
+                               void* stream) {
+  GSFF_PRELUDE
+  gsff_status rc = check_outputs(c, out_rgb, out_depth, out_alpha, out_feat, out_feat_dtype);
+  if (rc != GSFF_OK) return rc;
+  return hip_check(launch_composite_fwd(c.g, c.st, c.L, c.w, out_rgb, out_depth, out_alpha,
+                                        out_feat, out_feat_dtype, c.s),
+                   "composite_fwd");
+}
+
+gsff_status gsff_forward(const gsff_gaussians* g, const gsff_camera* cam, const gsff_settings* st,
+                         void* ws, size_t ws_bytes, int64_t max_pairs, float* out_rgb,
+                         float* out_depth, float* out_alpha, void* out_feat,
+                         int32_t out_feat_dtype, void* stream) {
+  GSFF_PRELUDE
+  gsff_status rc = check_outputs(c, out_rgb, out_depth, out_alpha, out_feat, out_feat_dtype);
+  if (rc != GSFF_OK) return rc;
+  if ((rc = hip_check(launch_preprocess(c.g, c.cam, c.st, c.L, c.w, c.s), "preprocess")) != GSFF_OK)
+    return rc;
+  if ((rc = hip_check(launch_sort_depth(c.L, c.w, c.s), "sort_depth")) != GSFF_OK) return rc;
+  if ((rc = hip_check(launch_bin(c.L, c.w, c.s), "bin")) != GSFF_OK) return rc;
+  if ((rc = hip_check(launch_sort_tiles(c.L, c.w, c.s), "sort_tiles")) != GSFF_OK) return rc;
+  if ((rc = hip_check(launch_tile_ranges(c.L, c.w, c.s), "tile_ranges")) != GSFF_OK) return rc;
+  return hip_check(launch_composite_fwd(c.g, c.st, c.L, c.w, out_rgb, out_depth, out_alpha,
+                                        out_feat, out_feat_dtype, c.s),
+                   "composite_fwd");
+}
+
+gsff_status gsff_composite_bwd(const gsff_gaussians* g, const gsff_camera* cam,
+                               const gsff_settings* st, void* ws, size_t ws_bytes,
+                               int64_t max_pairs, const float* g_rgb, const float* g_depth,
+                               const float* g_alpha, const float* g_feat, const gsff_grads* out,
+                               int32_t accumulate, void* stream) {
+  GSFF_PRELUDE
+  if (!out) return fail(GSFF_ERR_INVALID_ARGUMENT, "NULL grads");
+  const bool geo = any_geometry(out);
+  if (geo && (!g_rgb || !g_depth || !g_alpha))
+    return fail(GSFF_ERR_INVALID_ARGUMENT, "NULL upstream gradient");
+  if (out->feat && g->C == 0) return fail(GSFF_ERR_INVALID_ARGUMENT, "feat grad with C == 0");
+  return hip_check(launch_composite_bwd(c.g, c.st, c.L, c.w, g_rgb, g_depth, g_alpha, g_feat, geo,
+                                        out->feat, accumulate, c.s),
+                   "composite_bwd");
+}
+
+gsff_status gsff_preprocess_bwd(const gsff_gaussians* g, const gsff_camera* cam,
+                                const gsff_settings* st, void* ws, size_t ws_bytes,
+                                int64_t max_pairs, const gsff_grads* out, int32_t accumulate,
+                                void* stream) {
+  GSFF_PRELUDE
+  if (!out) return fail(GSFF_ERR_INVALID_ARGUMENT, "NULL grads");
+  if (!any_geometry(out)) return GSFF_OK;
+  return hip_check(launch_preprocess_bwd(c.g, c.cam, c.st, c.L, c.w, *out, accumulate, c.s),
+                   "preprocess_bwd");
+}
+
+gsff_status gsff_backward(const gsff_gaussians* g, const gsff_camera* cam,
+                          const gsff_settings* st, void* ws, size_t ws_bytes, int64_t max_pairs,
+                          const float* g_rgb, const float* g_depth, const float* g_alpha,
+                          const float* g_feat, const gsff_grads* out, int32_t accumulate,
+                          void* stream) {
+  GSFF_PRELUDE
+  if (!out) return fail(GSFF_ERR_INVALID_ARGUMENT, "NULL grads");
+  const bool geo = any_geometry(out);
+  if (geo && (!g_rgb || !g_depth || !g_alpha))
+    return fail(GSFF_ERR_INVALID_ARGUMENT, "NULL upstream gradient");
+  if (out->feat && g->C == 0) return fail(GSFF_ERR_INVALID_ARGUMENT, "feat grad with C == 0");
+  gsff_status rc = hip_check(launch_composite_bwd(c.g, c.st, c.L, c.w, g_rgb, g_depth, g_alpha,
+                                                  g_feat, geo, out->feat, accumulate, c.s),
+                             "composite_bwd");
+  if (rc != GSFF_OK || !geo) return rc;
+  return hip_check(launch_preprocess_bwd(c.g, c.cam, c.st, c.L, c.w, *out, accumulate, c.s),
+                   "preprocess_bwd");
+}
+
+gsff_status gsff_l1_grad(const float* x, const float* y, int64_t n, float scale, float* grad,
+                         float* loss, void* stream) {
+  if (n < 0) return fail(GSFF_ERR_INVALID_ARGUMENT, "n < 0");
+  if (n > 0 && (!x || !y || !grad)) return fail(GSFF_ERR_INVALID_ARGUMENT, "NULL pointer");
+  return hip_check(launch_l1_grad(x, y, n, scale, grad, loss, (hipStream_t)stream), "l1_grad");
+}
+
+gsff_status gsff_read_status(const void* ws, uint32_t* flags, int64_t* n_pairs, void* stream) {
+  if (!ws) return fail(GSFF_ERR_INVALID_ARGUMENT, "NULL workspace");
+  gsff_status rc = hip_check(hipStreamSynchronize((hipStream_t)stream), "stream sync");
+  if (rc != GSFF_OK) return rc;
+  uint32_t h[4];
+  rc = hip_check(hipMemcpy(h, ws, sizeof(h), hipMemcpyDeviceToHost), "status copy");
+  if (rc != GSFF_OK) return rc;
+  if (flags) *flags = h[0];
+  if (n_pairs) *n_pairs = (int64_t)h[1];
+  return GSFF_OK;
+}
+
+}  // extern "C"

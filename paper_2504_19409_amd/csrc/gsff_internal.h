@@ -1,0 +1,115 @@
+// Internal declarations shared by the HIP translation units of libgsff:
+// workspace layout, device-side views, and the host launchers each .hip file
+// provides to the C ABI in capi.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/gsff.h"
+
+namespace gsff {
+
+constexpr int kTile = GSFF_TILE;           // 16x16 pixel screen tiles
+constexpr int kBlock = kTile * kTile;      // one thread per pixel of a tile
+constexpr int kRadixIpt = 16;              // keys per lane in a radix chunk
+constexpr int kRadixChunk = 64 * kRadixIpt;  // keys per wave chunk
+constexpr int kScanBlock = 1024;           // elements per block in the count scan
+constexpr int kPoseBlock = 256;            // Gaussians per preprocess-adjoint block
+
+inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+inline int ceil_log2(uint64_t v) {
+  int b = 0;
+  while ((uint64_t(1) << b) < v) ++b;
+  return b;
+}
+
+// Byte offsets of every workspace region; computed identically on the host
+// for gsff_workspace_size / gsff_workspace_layout and for every launch.
+struct Layout {
+  int64_t P = 0, max_pairs = 0;
+  int32_t W = 0, H = 0, tiles_x = 0, tiles_y = 0, ntiles = 0;
+  int32_t rank_bits = 0, tile_bits = 0;
+  int64_t depth_chunks = 0, pair_chunks = 0, scan_blocks = 0, pose_blocks = 0;
+  uint64_t status = 0, records = 0, rects = 0, dkeys_a = 0, dkeys_b = 0, dids_a = 0,
+           dids_b = 0, offsets = 0, pkeys_a = 0, pkeys_b = 0, tile_ranges = 0, pix_T = 0,
+           pix_end = 0, grad2d = 0, hist = 0, hist_tot = 0, scan_part = 0, pose_part = 0,
+           total = 0;
+};
+
+// Returns false if the sizes are not representable (key bits, negative sizes).
+bool compute_layout(int64_t P, int64_t max_pairs, int32_t W, int32_t H, Layout* L);
+
+// Device-side view of a workspace.
+struct WsView {
+  uint32_t* status;      // [0] flags, [1] pair count
+  float4* rec;           // [3][P]
+  ushort4* rects;        // [P]
+  uint32_t* dkeys_a;     // [P]  depth keys (sorted result lands here)
+  uint32_t* dkeys_b;
+  uint32_t* dids_a;      // [P]  Gaussian ids in depth order
+  uint32_t* dids_b;
+  uint32_t* offsets;     // [P+1] exclusive scan of tile counts in depth order
+  uint32_t* pkeys_a;     // [max_pairs] pair keys (sorted result lands here)
+  uint32_t* pkeys_b;
+  uint2* tile_ranges;    // [ntiles]
+  float* pix_T;          // [H*W]
+  uint32_t* pix_end;     // [H*W]
+  float* grad2d;         // [P][10]
+  uint32_t* hist;        // radix chunk histograms [bins][chunks]
+  uint32_t* hist_tot;    // radix digit totals [256]
+  uint32_t* scan_part;   // count-scan block partials
+  double* pose_part;     // [pose_blocks][6]
+};
+
+WsView make_view(void* ws, const Layout& L);
+
+// Device copy of the settings with derived constants.
+struct DevSettings {
+  float near_plane, guard, dilation, alpha_min, alpha_max, t_min;
+  int32_t render_features;
+};
+
+struct DevCamera {
+  int32_t W, H;
+  float fx, fy, cx, cy;
+  const float* viewmat;
+};
+
+struct DevGaussians {
+  int64_t P;
+  int32_t C;
+  int32_t feat_dtype;
+  const float* means;
+  const float* log_scales;
+  const float* quats;
+  const float* logit;
+  const float* rgb;
+  const void* feat;
+};
+
+// ---- host launchers (each returns the first HIP error, or hipSuccess) ----
+hipError_t launch_preprocess(const DevGaussians& g, const DevCamera& cam,
+                             const DevSettings& st, const Layout& L, const WsView& w,
+                             hipStream_t s);
+hipError_t launch_sort_depth(const Layout& L, const WsView& w, hipStream_t s);
+hipError_t launch_bin(const Layout& L, const WsView& w, hipStream_t s);
+hipError_t launch_sort_tiles(const Layout& L, const WsView& w, hipStream_t s);
+hipError_t launch_tile_ranges(const Layout& L, const WsView& w, hipStream_t s);
+hipError_t launch_composite_fwd(const DevGaussians& g, const DevSettings& st,
+                                const Layout& L, const WsView& w, float* out_rgb,
+                                float* out_depth, float* out_alpha, void* out_feat,
+                                int32_t out_feat_dtype, hipStream_t s);
+hipError_t launch_composite_bwd(const DevGaussians& g, const DevSettings& st,
+                                const Layout& L, const WsView& w, const float* g_rgb,
+                                const float* g_depth, const float* g_alpha,
+                                const float* g_feat, bool geometry, float* d_feat,
+                                int32_t accumulate, hipStream_t s);
+hipError_t launch_preprocess_bwd(const DevGaussians& g, const DevCamera& cam,
+                                 const DevSettings& st, const Layout& L, const WsView& w,
+                                 const gsff_grads& out, int32_t accumulate, hipStream_t s);
+hipError_t launch_l1_grad(const float* x, const float* y, int64_t n, float scale,
+                          float* grad, float* loss, hipStream_t s);
+
+}  // namespace gsff

@@ -1,0 +1,241 @@
+// Preprocess (projection, culling, support rectangle, depth key) and its
+// adjoint with the Lie-algebra pose gradient (Sec. 3.1 Eq. 1; Sec. 3.2 Eq. 4).
+//
+// One thread per Gaussian, planar [k, P] loads so every wave reads whole
+// cache lines; the adjoint recomputes the forward quantities instead of
+// storing them.
+#include <hip/hip_runtime.h>
+
+#include "gsff_internal.h"
+#include "project.h"
+
+namespace gsff {
+
+// Support rectangle margin in pixels: the FP32 bound is widened by this much
+// so that no pixel whose alpha reaches alpha_min in exact arithmetic is left
+// outside a Gaussian's tiles by rounding.
+constexpr float kRectMargin = 0.05f;
+
+__global__ __launch_bounds__(256) void k_preprocess(DevGaussians g, DevCamera cam,
+                                                    DevSettings st, WsView w) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    w.status[0] = 0u;
+    w.status[1] = 0u;
+  }
+  const int64_t P = g.P;
+  if (i >= P) return;
+  float V[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) V[k] = cam.viewmat[k];
+  const Proj p = project_gaussian(g, cam, st, V, i);
+  ushort4 rect = make_ushort4(1, 1, 0, 0);  // empty: x0 > x1
+  float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0;
+  if (p.valid) {
+    // exact half-widths of { alpha >= alpha_min } = { d^T K d <= 2 ln(o/alpha_min) }
+    const float k2 = 2.f * logf(p.o / st.alpha_min);
+    const float rx = sqrtf(fmaxf(k2, 0.f) * p.a);
+    const float ry = sqrtf(fmaxf(k2, 0.f) * p.c);
+    // pixel px is covered when |px + 1/2 - u| <= rx
+    float fx0 = ceilf(p.u - rx - 0.5f - kRectMargin);
+    float fx1 = floorf(p.u + rx - 0.5f + kRectMargin);
+    float fy0 = ceilf(p.v - ry - 0.5f - kRectMargin);
+    float fy1 = floorf(p.v + ry - 0.5f + kRectMargin);
+    fx0 = fmaxf(fx0, 0.f);
+    fy0 = fmaxf(fy0, 0.f);
+    fx1 = fminf(fx1, (float)(cam.W - 1));
+    fy1 = fminf(fy1, (float)(cam.H - 1));
+    if (fx0 <= fx1 && fy0 <= fy1) {
+      rect = make_ushort4((unsigned short)((int)fx0 / kTile), (unsigned short)((int)fy0 / kTile),
+                          (unsigned short)((int)fx1 / kTile), (unsigned short)((int)fy1 / kTile));
+    }
+    r0 = make_float4(p.u, p.v, p.A, p.B);
+    r1 = make_float4(p.Cc, p.o, p.z, 1.f);
+  }
+  const float4 r2 = make_float4(g.rgb[i], g.rgb[P + i], g.rgb[2 * P + i], 0.f);
+  w.rec[i] = r0;
+  w.rec[P + i] = r1;
+  w.rec[2 * P + i] = r2;
+  w.rects[i] = rect;
+  // culled Gaussians keep the largest key and an empty rectangle
+  w.dkeys_a[i] = (p.valid && rect.x <= rect.z) ? p.key : 0xFFFFFFFFu;
+  w.dids_a[i] = (uint32_t)i;
+}
+
+// Adjoint of project_gaussian followed by the pose terms of Eq. 4.
+__global__ __launch_bounds__(kPoseBlock) void k_preprocess_bwd(DevGaussians g, DevCamera cam,
+                                                               DevSettings st, WsView w,
+                                                               gsff_grads out, int accumulate) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t P = g.P;
+  float V[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) V[k] = cam.viewmat[k];
+  float pose[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (i < P) {
+    const Proj p = project_gaussian(g, cam, st, V, i);
+    const float* d = w.grad2d + i * 10;
+    float dmean[3] = {0.f, 0.f, 0.f}, dls[3] = {0.f, 0.f, 0.f}, dq[4] = {0.f, 0.f, 0.f, 0.f};
+    float dlogit = 0.f;
+    const float drgb[3] = {d[6], d[7], d[8]};
+    if (p.valid) {
+      const float du = d[0], dv = d[1], dA = d[2], dB = d[3], dC = d[4], dop = d[5], dz = d[9];
+      dlogit = dop * p.o * (1.f - p.o);
+      // conic -> 2D covariance: G = -K Gk K with Gk = [[dA, dB/2], [dB/2, dC]]
+      const float hB = 0.5f * dB;
+      const float k00 = p.A * dA + p.B * hB, k01 = p.A * hB + p.B * dC;
+      const float k10 = p.B * dA + p.Cc * hB, k11 = p.B * hB + p.Cc * dC;
+      const float G00 = -(k00 * p.A + k01 * p.B);
+      const float G01 = -(k00 * p.B + k01 * p.Cc);
+      const float G11 = -(k10 * p.B + k11 * p.Cc);
+      // Sigma' = TM TM^T:  dTM = 2 G TM
+      float dTM[6];
+      for (int k = 0; k < 3; ++k) {
+        dTM[k] = 2.f * (G00 * p.TM[k] + G01 * p.TM[3 + k]);
+        dTM[3 + k] = 2.f * (G01 * p.TM[k] + G11 * p.TM[3 + k]);
+      }
+      // TM[r][k] = sum_l T[r][l] Rq[l][k] s_k
+      float T[6];
+      for (int k = 0; k < 3; ++k) {
+        T[k] = p.J00 * V[k] + p.J02 * V[8 + k];
+        T[3 + k] = p.J11 * V[4 + k] + p.J12 * V[8 + k];
+      }
+      float dM[9];  // d/d(Rq S)
+      for (int l = 0; l < 3; ++l)
+        for (int k = 0; k < 3; ++k) dM[3 * l + k] = T[l] * dTM[k] + T[3 + l] * dTM[3 + k];
+      float dT[6];  // d/dT = dTM (Rq S)^T
+      for (int r = 0; r < 2; ++r)
+        for (int l = 0; l < 3; ++l) {
+          float acc = 0.f;
+          for (int k = 0; k < 3; ++k) acc += dTM[3 * r + k] * p.Rq[3 * l + k] * p.s[k];
+          dT[3 * r + l] = acc;
+        }
+      float dRq[9];
+      for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) dRq[3 * r + k] = dM[3 * r + k] * p.s[k];
+      for (int k = 0; k < 3; ++k) {
+        const float ds = dM[k] * p.Rq[k] + dM[3 + k] * p.Rq[3 + k] + dM[6 + k] * p.Rq[6 + k];
+        dls[k] = ds * p.s[k];
+      }
+      const float qw = p.q[0], qx = p.q[1], qy = p.q[2], qz = p.q[3];
+      const float* Gq = dRq;
+      float dqn[4];
+      dqn[0] = 2.f * (-qz * Gq[1] + qy * Gq[2] + qz * Gq[3] - qx * Gq[5] - qy * Gq[6] + qx * Gq[7]);
+      dqn[1] = 2.f * (qy * Gq[1] + qz * Gq[2] + qy * Gq[3] - 2.f * qx * Gq[4] - qw * Gq[5] +
+                      qz * Gq[6] + qw * Gq[7] - 2.f * qx * Gq[8]);
+      dqn[2] = 2.f * (-2.f * qy * Gq[0] + qx * Gq[1] + qw * Gq[2] + qx * Gq[3] + qz * Gq[5] -
+                      qw * Gq[6] + qz * Gq[7] - 2.f * qy * Gq[8]);
+      dqn[3] = 2.f * (-2.f * qz * Gq[0] - qw * Gq[1] + qx * Gq[2] + qw * Gq[3] - 2.f * qz * Gq[4] +
+                      qy * Gq[5] + qx * Gq[6] + qy * Gq[7]);
+      const float qd = qw * dqn[0] + qx * dqn[1] + qy * dqn[2] + qz * dqn[3];
+      for (int k = 0; k < 4; ++k) dq[k] = (dqn[k] - p.q[k] * qd) * p.qinv;
+      // T = J R:  dJ = dT R^T (only J00, J02, J11, J12 vary),  dR = J^T dT
+      const float dJ00 = dT[0] * V[0] + dT[1] * V[1] + dT[2] * V[2];
+      const float dJ02 = dT[0] * V[8] + dT[1] * V[9] + dT[2] * V[10];
+      const float dJ11 = dT[3] * V[4] + dT[4] * V[5] + dT[5] * V[6];
+      const float dJ12 = dT[3] * V[8] + dT[4] * V[9] + dT[5] * V[10];
+      float dR[9];
+      for (int l = 0; l < 3; ++l) {
+        dR[l] = p.J00 * dT[l];
+        dR[3 + l] = p.J11 * dT[3 + l];
+        dR[6 + l] = p.J02 * dT[l] + p.J12 * dT[3 + l];
+      }
+      // camera-space mean: image position, Jacobian, blended depth
+      const float rz = 1.f / p.z, rz2 = rz * rz, rz3 = rz2 * rz;
+      float gm0 = du * cam.fx * rz + dJ02 * (-cam.fx * rz2);
+      float gm1 = dv * cam.fy * rz + dJ12 * (-cam.fy * rz2);
+      float gm2 = du * (-cam.fx * p.x * rz2) + dv * (-cam.fy * p.y * rz2) +
+                  dJ00 * (-cam.fx * rz2) + dJ02 * (2.f * cam.fx * p.x * rz3) +
+                  dJ11 * (-cam.fy * rz2) + dJ12 * (2.f * cam.fy * p.y * rz3) + dz;
+      // world mean: R^T gm
+      for (int k = 0; k < 3; ++k) dmean[k] = V[k] * gm0 + V[4 + k] * gm1 + V[8 + k] * gm2;
+      // pose, left perturbation (Eq. 4): rho += gm, theta += mc x gm + sum_k R[:,k] x dR[:,k]
+      pose[0] = gm0;
+      pose[1] = gm1;
+      pose[2] = gm2;
+      pose[3] = p.y * gm2 - p.z * gm1;
+      pose[4] = p.z * gm0 - p.x * gm2;
+      pose[5] = p.x * gm1 - p.y * gm0;
+      for (int k = 0; k < 3; ++k) {
+        const float c0 = V[k], c1 = V[4 + k], c2 = V[8 + k];
+        const float e0 = dR[k], e1 = dR[3 + k], e2 = dR[6 + k];
+        pose[3] += c1 * e2 - c2 * e1;
+        pose[4] += c2 * e0 - c0 * e2;
+        pose[5] += c0 * e1 - c1 * e0;
+      }
+    }
+    if (accumulate) {
+      if (out.means)
+        for (int k = 0; k < 3; ++k) out.means[k * P + i] += dmean[k];
+      if (out.log_scales)
+        for (int k = 0; k < 3; ++k) out.log_scales[k * P + i] += dls[k];
+      if (out.quats)
+        for (int k = 0; k < 4; ++k) out.quats[k * P + i] += dq[k];
+      if (out.logit_opacity) out.logit_opacity[i] += dlogit;
+      if (out.rgb)
+        for (int k = 0; k < 3; ++k) out.rgb[k * P + i] += drgb[k];
+    } else {
+      if (out.means)
+        for (int k = 0; k < 3; ++k) out.means[k * P + i] = dmean[k];
+      if (out.log_scales)
+        for (int k = 0; k < 3; ++k) out.log_scales[k * P + i] = dls[k];
+      if (out.quats)
+        for (int k = 0; k < 4; ++k) out.quats[k * P + i] = dq[k];
+      if (out.logit_opacity) out.logit_opacity[i] = dlogit;
+      if (out.rgb)
+        for (int k = 0; k < 3; ++k) out.rgb[k * P + i] = drgb[k];
+    }
+  }
+  if (!out.pose) return;
+  // block reduction of the six pose terms in FP64 (fixed order)
+  __shared__ double s_red[kPoseBlock / 64][6];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int k = 0; k < 6; ++k) {
+    double v = (double)pose[k];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) s_red[wv][k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    double acc = 0.0;
+    for (int j = 0; j < kPoseBlock / 64; ++j) acc += s_red[j][threadIdx.x];
+    w.pose_part[blockIdx.x * 6 + threadIdx.x] = acc;
+  }
+}
+
+// Sum the per-block pose partials in block order (deterministic).
+__global__ __launch_bounds__(64) void k_pose_final(const double* part, int nblocks, float* pose,
+                                                   int accumulate) {
+  const int lane = threadIdx.x;
+  for (int k = 0; k < 6; ++k) {
+    double acc = 0.0;
+    for (int b = lane; b < nblocks; b += 64) acc += part[b * 6 + k];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) pose[k] = accumulate ? pose[k] + (float)acc : (float)acc;
+  }
+}
+
+hipError_t launch_preprocess(const DevGaussians& g, const DevCamera& cam, const DevSettings& st,
+                             const Layout& L, const WsView& w, hipStream_t s) {
+  const int64_t blocks = g.P > 0 ? (g.P + 255) / 256 : 1;
+  hipLaunchKernelGGL(k_preprocess, dim3((unsigned)blocks), dim3(256), 0, s, g, cam, st, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_preprocess_bwd(const DevGaussians& g, const DevCamera& cam,
+                                 const DevSettings& st, const Layout& L, const WsView& w,
+                                 const gsff_grads& out, int32_t accumulate, hipStream_t s) {
+  if (g.P > 0) {
+    hipLaunchKernelGGL(k_preprocess_bwd, dim3((unsigned)L.pose_blocks), dim3(kPoseBlock), 0, s,
+                       g, cam, st, w, out, (int)accumulate);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (out.pose) {
+    hipLaunchKernelGGL(k_pose_final, dim3(1), dim3(64), 0, s, w.pose_part,
+                       (int)(g.P > 0 ? L.pose_blocks : 0), out.pose, (int)accumulate);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace gsff

@@ -1,0 +1,336 @@
+// Depth sort, tile binning and tile sort (Sec. 3.1: the projected Gaussians
+// are sorted by depth and blended front to back, per screen tile).
+//
+// Order of work:
+//   1. LSD radix sort of the P depth keys (float32 bits of camera z, culled
+//      Gaussians keyed 0xFFFFFFFF), values = Gaussian ids.  Stable, so equal
+//      keys keep index order.
+//   2. Tile counts in depth-rank order, exclusive scan, and emission of one
+//      32-bit pair key (tile << rank_bits | rank) per (Gaussian, tile): the
+//      pair array comes out in global depth order.
+//   3. Stable LSD radix sort of the pair keys on the tile bits only; within a
+//      tile the depth order of step 2 survives.
+//   4. Per-tile [start, end) by binary search in the sorted pair keys.
+//
+// Radix passes: every wave owns a chunk of kRadixChunk consecutive keys.
+//   hist    : per-chunk digit histogram (LDS atomics) -> hist[digit][chunk]
+//   rowscan : one block per digit, exclusive scan along the chunk axis,
+//             digit totals -> hist_tot
+//   scatter : each wave walks its chunk in order; lanes with equal digits find
+//             each other with one ballot per digit bit, take their rank among
+//             lower lanes, and write to base + running count (stable).
+#include <hip/hip_runtime.h>
+
+#include "gsff_internal.h"
+
+namespace gsff {
+
+__device__ __forceinline__ uint64_t lanemask_lt(int lane) {
+  return (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Inclusive wave scan (wave64) of a 32-bit value.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t t = __shfl_up(v, off, 64);
+    if (lane >= off) v += t;
+  }
+  return v;
+}
+
+// Exclusive block scan (256 threads).  Returns the exclusive prefix; *total
+// receives the block sum.  Uses s_tmp[4].
+__device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t* s_tmp,
+                                                       uint32_t* total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint32_t inc = wave_incl_scan(v, lane);
+  if (lane == 63) s_tmp[wv] = inc;
+  __syncthreads();
+  uint32_t base = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t t = s_tmp[k];
+    if (k < wv) base += t;
+    tot += t;
+  }
+  __syncthreads();
+  *total = tot;
+  return base + inc - v;
+}
+
+// ---------------------------------------------------------------- radix ----
+
+__global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__ keys,
+                                                    const uint32_t* __restrict__ n_dev,
+                                                    uint32_t n_static, int shift, int nbits,
+                                                    uint32_t* __restrict__ hist, int nchunks) {
+  __shared__ uint32_t s_hist[4][256];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int chunk = blockIdx.x * 4 + wv;
+  const uint32_t n = n_dev ? *n_dev : n_static;
+  const uint32_t nbins = 1u << nbits, mask = nbins - 1u;
+  for (uint32_t d = lane; d < nbins; d += 64) s_hist[wv][d] = 0u;
+  __syncthreads();
+  if (chunk < nchunks) {
+    const uint64_t base = (uint64_t)chunk * kRadixChunk;
+#pragma unroll
+    for (int it = 0; it < kRadixIpt; ++it) {
+      const uint64_t idx = base + (uint64_t)it * 64 + lane;
+      if (idx < n) atomicAdd(&s_hist[wv][(keys[idx] >> shift) & mask], 1u);
+    }
+  }
+  __syncthreads();
+  if (chunk < nchunks)
+    for (uint32_t d = lane; d < nbins; d += 64) hist[(uint64_t)d * nchunks + chunk] = s_hist[wv][d];
+}
+
+__global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t* __restrict__ hist, int nchunks,
+                                                       uint32_t* __restrict__ hist_tot) {
+  __shared__ uint32_t s_tmp[4];
+  const int d = blockIdx.x;
+  uint32_t* row = hist + (uint64_t)d * nchunks;
+  uint32_t carry = 0;
+  for (int b = 0; b < nchunks; b += 256) {
+    const int i = b + threadIdx.x;
+    const uint32_t v = (i < nchunks) ? row[i] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan256(v, s_tmp, &tot);
+    if (i < nchunks) row[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) hist_tot[d] = carry;
+}
+
+template <bool HasVals>
+__global__ __launch_bounds__(256) void k_radix_scatter(
+    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
+    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
+    const uint32_t* __restrict__ n_dev, uint32_t n_static, int shift, int nbits,
+    const uint32_t* __restrict__ hist, const uint32_t* __restrict__ hist_tot, int nchunks,
+    uint32_t cap) {
+  __shared__ uint32_t s_base[256];
+  __shared__ uint32_t s_cnt[4][256];
+  __shared__ uint32_t s_tmp[4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int chunk = blockIdx.x * 4 + wv;
+  const uint32_t n = n_dev ? *n_dev : n_static;
+  const uint32_t nbins = 1u << nbits, mask = nbins - 1u;
+  // digit bases: exclusive scan of the digit totals (nbins <= 256)
+  {
+    const uint32_t v = (threadIdx.x < nbins) ? hist_tot[threadIdx.x] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan256(v, s_tmp, &tot);
+    s_base[threadIdx.x] = ex;
+  }
+  __syncthreads();
+  if (chunk >= nchunks) return;  // whole wave; no barrier follows
+  for (uint32_t d = lane; d < nbins; d += 64)
+    s_cnt[wv][d] = s_base[d] + hist[(uint64_t)d * nchunks + chunk];
+  const uint64_t base = (uint64_t)chunk * kRadixChunk;
+  uint32_t k[kRadixIpt];
+  uint32_t v[kRadixIpt];
+#pragma unroll
+  for (int it = 0; it < kRadixIpt; ++it) {
+    const uint64_t idx = base + (uint64_t)it * 64 + lane;
+    k[it] = (idx < n) ? keys_in[idx] : 0u;
+    if (HasVals) v[it] = (idx < n) ? vals_in[idx] : 0u;
+  }
+  const uint64_t lt = lanemask_lt(lane);
+#pragma unroll
+  for (int it = 0; it < kRadixIpt; ++it) {
+    const uint64_t idx = base + (uint64_t)it * 64 + lane;
+    const bool valid = idx < n;
+    const uint32_t d = (k[it] >> shift) & mask;
+    uint64_t peers = __ballot(valid);
+    for (int b = 0; b < nbits; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t m = __ballot(bit);
+      peers &= bit ? m : ~m;
+    }
+    const uint32_t rank = (uint32_t)__popcll(peers & lt);
+    const uint32_t start = s_cnt[wv][d];
+    if (valid && start + rank < cap) {  // cap: output capacity, never exceeded
+      keys_out[start + rank] = k[it];
+      if (HasVals) vals_out[start + rank] = v[it];
+    }
+    // the lowest lane of each digit group advances the running count
+    if (valid && (peers & lt) == 0ull) s_cnt[wv][d] = start + (uint32_t)__popcll(peers);
+  }
+}
+
+static hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
+                             uint32_t* vout, const uint32_t* n_dev, uint32_t n_static,
+                             int shift, int nbits, int nchunks, uint32_t cap, const WsView& w,
+                             hipStream_t s) {
+  const unsigned blocks = (unsigned)((nchunks + 3) / 4);
+  hipLaunchKernelGGL(k_radix_hist, dim3(blocks), dim3(256), 0, s, kin, n_dev, n_static, shift,
+                     nbits, w.hist, nchunks);
+  hipLaunchKernelGGL(k_radix_rowscan, dim3(1u << nbits), dim3(256), 0, s, w.hist, nchunks,
+                     w.hist_tot);
+  if (vin)
+    hipLaunchKernelGGL(k_radix_scatter<true>, dim3(blocks), dim3(256), 0, s, kin, vin, kout, vout,
+                       n_dev, n_static, shift, nbits, w.hist, w.hist_tot, nchunks, cap);
+  else
+    hipLaunchKernelGGL(k_radix_scatter<false>, dim3(blocks), dim3(256), 0, s, kin, nullptr, kout,
+                       nullptr, n_dev, n_static, shift, nbits, w.hist, w.hist_tot, nchunks, cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort_depth(const Layout& L, const WsView& w, hipStream_t s) {
+  if (L.P == 0) return hipSuccess;
+  uint32_t* ka = w.dkeys_a;
+  uint32_t* kb = w.dkeys_b;
+  uint32_t* va = w.dids_a;
+  uint32_t* vb = w.dids_b;
+  for (int pass = 0; pass < 4; ++pass) {
+    hipError_t e = radix_pass(ka, va, kb, vb, nullptr, (uint32_t)L.P, pass * 8, 8,
+                              (int)L.depth_chunks, (uint32_t)L.P, w, s);
+    if (e != hipSuccess) return e;
+    uint32_t* t = ka;
+    ka = kb;
+    kb = t;
+    t = va;
+    va = vb;
+    vb = t;
+  }
+  return hipSuccess;  // four passes: the result is back in dkeys_a / dids_a
+}
+
+hipError_t launch_sort_tiles(const Layout& L, const WsView& w, hipStream_t s) {
+  if (L.P == 0 || L.tile_bits == 0 || L.max_pairs == 0) return hipSuccess;
+  const int n1 = (L.tile_bits + 1) / 2, n2 = L.tile_bits - n1;
+  hipError_t e = radix_pass(w.pkeys_a, nullptr, w.pkeys_b, nullptr, w.status + 2, 0u,
+                            L.rank_bits, n1, (int)L.pair_chunks, (uint32_t)L.max_pairs, w, s);
+  if (e != hipSuccess) return e;
+  // second pass (possibly 0 bits: a stable copy) brings the keys back to pkeys_a
+  return radix_pass(w.pkeys_b, nullptr, w.pkeys_a, nullptr, w.status + 2, 0u,
+                    L.rank_bits + n1, n2, (int)L.pair_chunks, (uint32_t)L.max_pairs, w, s);
+}
+
+// ------------------------------------------------------------- binning ----
+
+// rectangle of the Gaussian at depth rank r (empty if the stored id is not valid)
+__device__ __forceinline__ ushort4 ranked_rect(const WsView& w, int64_t r, int64_t P) {
+  const uint32_t gid = w.dids_a[r];
+  return gid < (uint32_t)P ? w.rects[gid] : make_ushort4(1, 1, 0, 0);
+}
+
+__device__ __forceinline__ uint32_t rect_count(ushort4 r) {
+  if (r.x > r.z || r.y > r.w) return 0u;
+  return (uint32_t)(r.z - r.x + 1) * (uint32_t)(r.w - r.y + 1);
+}
+
+// per-block sums of tile counts, ranks in depth order
+__global__ __launch_bounds__(256) void k_count_reduce(WsView w, int64_t P) {
+  __shared__ uint32_t s_tmp[4];
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock;
+  uint32_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < kScanBlock / 256; ++k) {
+    const int64_t r = base + k * 256 + threadIdx.x;
+    if (r < P) sum += rect_count(ranked_rect(w, r, P));
+  }
+  uint32_t tot;
+  block_excl_scan256(sum, s_tmp, &tot);
+  if (threadIdx.x == 0) w.scan_part[blockIdx.x] = tot;
+}
+
+// one block: exclusive scan of the block sums; pair count and overflow flag
+__global__ __launch_bounds__(1024) void k_count_top(WsView w, int nblocks, uint64_t max_pairs) {
+  __shared__ uint64_t s_w[16];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint64_t carry = 0;
+  for (int b = 0; b < nblocks; b += 1024) {
+    const int i = b + threadIdx.x;
+    uint64_t v = (i < nblocks) ? (uint64_t)w.scan_part[i] : 0ull;
+    uint64_t inc = v;
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint64_t t = __shfl_up(inc, off, 64);
+      if (lane >= off) inc += t;
+    }
+    if (lane == 63) s_w[wv] = inc;
+    __syncthreads();
+    uint64_t pre = 0, tot = 0;
+    for (int k = 0; k < 16; ++k) {
+      if (k < wv) pre += s_w[k];
+      tot += s_w[k];
+    }
+    __syncthreads();
+    if (i < nblocks) w.scan_part[i] = (uint32_t)(carry + pre + inc - v);
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    const bool over = carry > max_pairs;
+    if (over) w.status[0] |= GSFF_FLAG_PAIR_OVERFLOW;
+    w.status[1] = (uint32_t)(carry > 0xFFFFFFFFull ? 0xFFFFFFFFull : carry);
+    w.status[2] = over ? 0u : (uint32_t)carry;  // pairs the later stages use
+  }
+}
+
+// offsets and pair emission: key = (tile << rank_bits) | rank
+__global__ __launch_bounds__(256) void k_emit(WsView w, int64_t P, int tiles_x, int rank_bits) {
+  __shared__ uint32_t s_tmp[4];
+  const bool ok = w.status[2] != 0u || w.status[1] == 0u;
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock;
+  uint32_t carry = w.scan_part[blockIdx.x];
+  for (int k = 0; k < kScanBlock / 256; ++k) {
+    const int64_t r = base + k * 256 + threadIdx.x;
+    ushort4 rc = make_ushort4(1, 1, 0, 0);
+    if (r < P) rc = ranked_rect(w, r, P);
+    const uint32_t cnt = rect_count(rc);
+    uint32_t tot;
+    const uint32_t off = carry + block_excl_scan256(cnt, s_tmp, &tot);
+    carry += tot;
+    if (r < P) w.offsets[r] = off;
+    if (ok && cnt) {
+      uint32_t o = off;
+      for (int ty = rc.y; ty <= rc.w; ++ty)
+        for (int tx = rc.x; tx <= rc.z; ++tx)
+          w.pkeys_a[o++] = ((uint32_t)(ty * tiles_x + tx) << rank_bits) | (uint32_t)r;
+    }
+  }
+}
+
+hipError_t launch_bin(const Layout& L, const WsView& w, hipStream_t s) {
+  if (L.P == 0) {
+    return hipSuccess;  // status was zeroed by the preprocess kernel
+  }
+  hipLaunchKernelGGL(k_count_reduce, dim3((unsigned)L.scan_blocks), dim3(256), 0, s, w, L.P);
+  hipLaunchKernelGGL(k_count_top, dim3(1), dim3(1024), 0, s, w, (int)L.scan_blocks,
+                     (uint64_t)L.max_pairs);
+  hipLaunchKernelGGL(k_emit, dim3((unsigned)L.scan_blocks), dim3(256), 0, s, w, L.P, L.tiles_x,
+                     L.rank_bits);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- ranges -----
+
+__device__ __forceinline__ uint32_t lower_bound_u64(const uint32_t* a, uint32_t n, uint64_t key) {
+  uint32_t lo = 0, hi = n;
+  while (lo < hi) {
+    const uint32_t mid = lo + ((hi - lo) >> 1);
+    if ((uint64_t)a[mid] < key)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void k_tile_ranges(WsView w, int ntiles, int rank_bits) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntiles) return;
+  const uint32_t n = w.status[2];
+  const uint32_t a = lower_bound_u64(w.pkeys_a, n, (uint64_t)t << rank_bits);
+  const uint32_t b = lower_bound_u64(w.pkeys_a, n, (uint64_t)(t + 1) << rank_bits);
+  w.tile_ranges[t] = make_uint2(a, b);
+}
+
+hipError_t launch_tile_ranges(const Layout& L, const WsView& w, hipStream_t s) {
+  hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)((L.ntiles + 255) / 256)), dim3(256), 0, s, w,
+                     L.ntiles, L.rank_bits);
+  return hipGetLastError();
+}
+
+}  // namespace gsff
