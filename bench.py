@@ -1,0 +1,275 @@
+"""Throughput of one forward+backward render iteration of the feature-field
+Gaussian rasterizer on one MI355X.
+
+Workload (the tracking/mapping frame): 200,000 Gaussians drawn uniformly in
+the camera frustum at 1-5 m, 640x480 pinhole camera (fx = fy = 525), RGB +
+depth + accumulated opacity + 16-channel FP32 features, camera pose perturbed
+by 1 cm / 1 degree from the pose the target images were rendered at.
+
+One step = preprocess -> depth sort -> tile binning -> tile sort -> tile
+ranges -> compositing -> L1 loss gradients of the four output groups ->
+compositing adjoint -> preprocess adjoint + pose reduction, all in libgsff
+kernels on one stream, inputs resident in HBM.
+
+Prints one JSON line (see the keys below); ``--gpus`` above 1 is refused: this
+build runs on a single GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP32_VALU_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, TFLOP/s (packed FMA)
+
+STAGES = ["preprocess", "sort_depth", "bin", "sort_tiles", "tile_ranges", "composite_fwd",
+          "l1", "composite_bwd", "preprocess_bwd"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="wall-clock budget of the CPU oracle sample")
+    ap.add_argument("--no-graph", action="store_true", help="time eager launches only")
+    return ap.parse_args()
+
+
+def build_problem(torch):
+    from paper_2504_19409_amd import scenegen as sg
+    from paper_2504_19409_amd.rasterizer import CameraSpec, Frame
+    scene, _ = sg.workload_scene("frame")
+    cam = scene.camera
+    spec = CameraSpec(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    dev = dict(means=t(scene.means), log_scales=t(scene.log_scales), quats=t(scene.quats),
+               logit_opacity=t(scene.logit_opacity), rgb=t(scene.rgb), feat=t(scene.feat))
+    # targets: this library's render of the same scene at the unperturbed pose
+    ident = t(sg.identity_viewmat())
+    f0 = Frame(dev["means"], dev["log_scales"], dev["quats"], dev["logit_opacity"], dev["rgb"],
+               dev["feat"], ident, spec)
+    targets = [o.clone() for o in f0.forward()]
+    # pair capacity from one sizing pass at the perturbed pose
+    vm = t(cam.viewmat)
+    f1 = Frame(dev["means"], dev["log_scales"], dev["quats"], dev["logit_opacity"], dev["rgb"],
+               dev["feat"], vm, spec)
+    f1.forward()
+    flags, n = f1.read_status()
+    assert flags == 0, "pair overflow while sizing"
+    fr = Frame(dev["means"], dev["log_scales"], dev["quats"], dev["logit_opacity"], dev["rgb"],
+               dev["feat"], vm, spec, max_pairs=int(n * 1.05) + 4096)
+    return scene, fr, targets, n
+
+
+class Step:
+    """One forward+backward iteration issued stage by stage."""
+
+    def __init__(self, torch, fr, targets):
+        from paper_2504_19409_amd.rasterizer import l1_grad
+        self.torch, self.fr, self.targets, self.l1 = torch, fr, targets, l1_grad
+        self.outs = fr.alloc_outputs()
+        self.ups = [torch.empty_like(o) for o in self.outs]
+        self.loss = torch.zeros(1, device="cuda")
+        self.grads = fr.make_grads()
+
+    def run(self, events=None):
+        fr = self.fr
+        rec = (lambda i: events[i].record()) if events is not None else (lambda i: None)
+        rec(0)
+        fr.call_stage("gsff_preprocess")
+        rec(1)
+        fr.call_stage("gsff_sort_depth")
+        rec(2)
+        fr.call_stage("gsff_bin")
+        rec(3)
+        fr.call_stage("gsff_sort_tiles")
+        rec(4)
+        fr.call_stage("gsff_tile_ranges")
+        rec(5)
+        fr.composite_fwd(self.outs)
+        rec(6)
+        self.loss.zero_()
+        for o, tg, u in zip(self.outs, self.targets, self.ups):
+            self.l1(o, tg, 1.0 / o.numel(), u, self.loss)
+        rec(7)
+        fr.composite_bwd(*self.ups, self.grads)
+        rec(8)
+        fr.preprocess_bwd(self.grads)
+        rec(9)
+
+
+def algorithmic_work(scene, n_pairs, torch):
+    """Per-stage algorithmic bytes (HBM) and the compositing evaluation counts
+    from the oracle's exact work counts (pairs with support, alpha
+    evaluations up to each pixel's stop, contributing pairs)."""
+    import oracle
+    oracle.build(force=False)
+    p, c = oracle.scene_dicts(scene)
+    wc = oracle.work_counts(p, c, 16)
+    P, C = scene.P, scene.C
+    HW = scene.camera.width * scene.camera.height
+    return wc, dict(P=P, C=C, HW=HW, n_pairs=n_pairs)
+
+
+def cpu_baseline(scene, budget_s):
+    """The FP64 oracle (single-threaded C++) on whole frames of the same
+    workload: forward + backward with an L1-shaped upstream, repeated until the
+    time budget is spent."""
+    import oracle
+    from paper_2504_19409_amd import scenegen as sg
+    oracle.build(force=False)
+    p, c = oracle.scene_dicts(scene)
+    rng = np.random.default_rng(0)
+    W, H, C = scene.camera.width, scene.camera.height, scene.C
+    gr, gd, ga, gf = sg.upstream_signs(rng, W, H, C)
+    g = dict(g_rgb=gr, g_depth=gd, g_alpha=ga, g_feat=gf)
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.render(p, c)
+        oracle.backward(p, c, g)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    return dict(value=n / el, unit="it/s", cores=1, kind="oracle",
+                sample=f"{n} full 640x480 / 200k-Gaussian / 16-ch frames, forward + backward, "
+                       f"FP64 single-threaded C++ oracle, {el:.1f} s")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(2)
+    scene, fr, targets, n_pairs = build_problem(torch)
+    step = Step(torch, fr, targets)
+    log(f"pairs {n_pairs}, workspace {fr.ws_bytes / 1e6:.1f} MB")
+    for _ in range(args.warmup):
+        step.run()
+    torch.cuda.synchronize()
+
+    # eager, with per-stage events
+    K = args.steps
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(10)] for _ in range(K)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(K):
+        step.run(ev[k])
+    torch.cuda.synchronize()
+    eager_ms = (time.perf_counter() - t0) / K * 1e3
+    stage_ms = {s: float(np.mean([ev[k][i].elapsed_time(ev[k][i + 1]) for k in range(K)]))
+                for i, s in enumerate(STAGES)}
+    log("eager ms/step %.4f" % eager_ms)
+    for s in STAGES:
+        log(f"  {s:16s} {stage_ms[s] * 1e3:9.1f} us")
+
+    # the same step replayed from a HIP graph (launch overhead removed)
+    graph_ms = None
+    if not args.no_graph:
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            step.run()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        ref = [g.clone() for g in step.grads.values()]
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            step.run()
+        torch.cuda.synchronize()
+        for _ in range(3):
+            g.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(step.grads.values(), ref):
+            d = (a - b).norm() / max(b.norm(), 1e-30)
+            assert float(d) < 1e-4, "graph replay differs from eager"
+        for _ in range(args.warmup):
+            g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(K):
+            g.replay()
+        torch.cuda.synchronize()
+        graph_ms = (time.perf_counter() - t0) / K * 1e3
+        log("graph ms/step %.4f" % graph_ms)
+
+    ms = min(eager_ms, graph_ms) if graph_ms else eager_ms
+    value = 1e3 / ms
+
+    wc, sizes = algorithmic_work(scene, n_pairs, torch)
+    dom = max(STAGES, key=lambda s: stage_ms[s])
+    roof = roofline_for(dom, stage_ms[dom], wc, sizes)
+    out = {
+        "metric": "fwd+bwd render iterations/sec at 640x480, 200k Gaussians, 16-ch features",
+        "value": round(value, 2), "unit": "it/s", "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "tracking/mapping frame: 200k Gaussians, 640x480, fx=fy=525, "
+                               "RGB+depth+alpha+16-ch FP32 features, pose perturbed 1 cm/1 deg",
+                   "gaussians": scene.P, "width": 640, "height": 480, "channels": 16,
+                   "timing": "graph replay" if graph_ms and graph_ms < eager_ms else "eager",
+                   "eager_ms": round(eager_ms, 4),
+                   "graph_ms": round(graph_ms, 4) if graph_ms else None,
+                   "stage_us": {s: round(v * 1e3, 1) for s, v in stage_ms.items()},
+                   "pairs": n_pairs, "work": wc},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(scene, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def roofline_for(stage, ms, wc, sz):
+    """Roofline entry of the dominant stage: algorithmic work per launch over the
+    measured average launch time.  Work per unit is stated in the design notes."""
+    P, C, HW, M = sz["P"], sz["C"], sz["HW"], sz["n_pairs"]
+    sec = ms * 1e-3
+    if stage in ("composite_fwd", "composite_bwd"):
+        # FP32 VALU work: flops per alpha evaluation (evaluations up to each
+        # pixel's stop) plus per contributing pair
+        if stage == "composite_fwd":
+            flops = wc["evals"] * 15 + wc["contribs"] * (2 * (4 + C) + 4)
+        else:
+            flops = wc["evals"] * 15 + wc["contribs"] * (60 + 2 * C)
+        achieved = flops / sec / 1e12
+        return {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VALU_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP32_VALU_PEAK_TFLOPS, 4),
+                "traffic": None, "stage": stage, "work_flops": flops}
+    bytes_ = {
+        "preprocess": P * (44 + 12) + P * (48 + 8 + 8),
+        "sort_depth": 4 * P * 8 * 3,
+        "bin": P * 8 * 2 + M * 4,
+        "sort_tiles": 2 * M * 4 * 3,
+        "tile_ranges": 8 * 1200,
+        "l1": HW * (5 + C) * 4 * 3,
+        "preprocess_bwd": P * (44 + 40) + P * 56,
+    }[stage]
+    achieved = bytes_ / sec / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "stage": stage}
+
+
+if __name__ == "__main__":
+    main()

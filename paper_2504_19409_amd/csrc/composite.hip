@@ -53,6 +53,12 @@ __device__ __forceinline__ void store_out(uint16_t* p, int64_t i, float v) {
   p[i] = (uint16_t)(u >> 16);
 }
 
+// A tile's [start, end) limited to the pair buffer.
+__device__ __forceinline__ uint2 clamp_range(uint2 r, uint32_t max_pairs) {
+  const uint32_t e = min(r.y, max_pairs);
+  return make_uint2(min(r.x, e), e);
+}
+
 // Gaussian id of sorted pair `idx`; returns P (an out-of-range marker) if
 // the stored rank or id is not a valid index, so no gather can leave the
 // record arrays.
@@ -105,7 +111,8 @@ __device__ __forceinline__ AlphaEval eval_alpha(const float4 r0, const float4 r1
 template <int CP, typename FT, typename OT>
 __global__ __launch_bounds__(kBlock) void k_composite_fwd(
     DevSettings st, int64_t P, int C, int c0, int W, int H, int tiles_x, int ntiles,
-    int rank_bits, WsView w, const FT* __restrict__ feat, float* __restrict__ out_rgb,
+    int rank_bits, uint32_t max_pairs, WsView w, const FT* __restrict__ feat,
+    float* __restrict__ out_rgb,
     float* __restrict__ out_depth, float* __restrict__ out_alpha, OT* __restrict__ out_feat,
     int write_geo) {
   constexpr int CPs = CP > 0 ? CP : 1;
@@ -118,7 +125,7 @@ __global__ __launch_bounds__(kBlock) void k_composite_fwd(
   const int py = ty * kTile + (threadIdx.x / kTile);
   const bool inside = px < W && py < H;
   const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
-  const uint2 range = w.tile_ranges[tile];
+  const uint2 range = clamp_range(w.tile_ranges[tile], max_pairs);
   const uint32_t rmask = (rank_bits >= 32) ? 0xFFFFFFFFu : ((1u << rank_bits) - 1u);
   const int cn = CP > 0 ? min(CP, C - c0) : 0;
 
@@ -197,7 +204,7 @@ static void launch_fwd_t(const DevSettings& st, const DevGaussians& g, const Lay
                          float* out_alpha, void* out_feat, int write_geo, hipStream_t s) {
   const int grid = ((L.ntiles + kNumXcd - 1) / kNumXcd) * kNumXcd;
   hipLaunchKernelGGL((k_composite_fwd<CP, FT, OT>), dim3(grid), dim3(kBlock), 0, s, st, g.P, g.C,
-                     c0, L.W, L.H, L.tiles_x, L.ntiles, L.rank_bits, w,
+                     c0, L.W, L.H, L.tiles_x, L.ntiles, L.rank_bits, (uint32_t)L.max_pairs, w,
                      (const FT*)g.feat, out_rgb, out_depth, out_alpha, (OT*)out_feat, write_geo);
 }
 
@@ -274,40 +281,82 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
-// GEO: compute the geometry adjoint (10 image-space values per Gaussian);
-// CP: feature channels whose gradient is accumulated (0 = none).
+// v + (v from the lane given by a DPP permutation inside each row of 16)
+template <int CTRL>
+__device__ __forceinline__ float dpp_add(float v) {
+  return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// Sum over the 16 lanes of a DPP row, result in every lane of the row:
+// butterflies over lane^1, lane^2 (quad permutes), then the half-row and
+// row mirrors, each pairing a lane with one in the other half it has not
+// combined with yet.
+__device__ __forceinline__ float row16_allreduce(float v) {
+  v = dpp_add<0xB1>(v);   // quad_perm [1,0,3,2]
+  v = dpp_add<0x4E>(v);   // quad_perm [2,3,0,1]
+  v = dpp_add<0x141>(v);  // row_half_mirror
+  v = dpp_add<0x140>(v);  // row_mirror
+  return v;
+}
+
+constexpr int kBwdNB = 16;          // Gaussians per batch (one per DPP row in the contraction)
+constexpr int kBwdStride = 272;     // LDS row stride of the per-pixel products (bank spread)
+
+// The per-pixel adjoint of a tile, as a contraction.
+//
+// Phase A (one thread per pixel, back to front over a batch of kBwdNB
+// Gaussians): recover T, and store the blending weight w_ip and
+// dL/dpower_ip (zero where the pixel does not use Gaussian i or alpha is
+// clamped) in LDS.
+// Phase B (thread = (Gaussian i, pixel column)): every per-Gaussian gradient is
+// a sum over the tile's pixels of one of these two values times a per-pixel
+// constant:
+//   colour / depth / feature : sum_p w_ip g_k(p)
+//   image-space mean, conic  : sums of dL/dpower_ip times 1, x, y, x^2, xy, y^2
+//                              (tile-local pixel coordinates), from which
+//                              du, dv, dA, dB, dC follow in closed form
+//   opacity                  : sum_p dL/dpower_ip / o_i  (d alpha/d o = G,
+//                              d alpha/d power = o G)
+// so each column accumulates its 16 pixels and one DPP row reduction
+// completes the sum.  Geometry terms come only from the colour, depth and
+// opacity upstream; the feature upstream only enters the feature sums.
 template <int CP, bool GEO>
 __global__ __launch_bounds__(kBlock) void k_composite_bwd(
     DevSettings st, int64_t P, int C, int c0, int W, int H, int tiles_x, int ntiles,
-    int rank_bits, WsView w, const float* __restrict__ g_rgb, const float* __restrict__ g_depth,
-    const float* __restrict__ g_alpha, const float* __restrict__ g_feat,
-    float* __restrict__ d_feat) {
-  constexpr int NG = (GEO ? 10 : 0) + CP;
-  constexpr int NGs = NG > 0 ? NG : 1;
-  constexpr int CPs = CP > 0 ? CP : 1;
-  __shared__ float4 s_r0[kBwdBatch], s_r1[kBwdBatch], s_r2[kBwdBatch];
-  __shared__ uint32_t s_gid[kBwdBatch];
-  __shared__ float s_grad[kBwdBatch][NGs];
+    int rank_bits, uint32_t max_pairs, WsView w, const float* __restrict__ g_rgb,
+    const float* __restrict__ g_depth, const float* __restrict__ g_alpha,
+    const float* __restrict__ g_feat, float* __restrict__ d_feat) {
+  constexpr int NL = (GEO ? 4 : 0) + CP;   // linear channels: r, g, b, depth, features
+  constexpr int NLs = NL > 0 ? NL : 1;
+  constexpr int NM = GEO ? 6 : 0;          // moments of dL/dpower
+  constexpr int NO = NL + NM;
+  constexpr int NF = (GEO ? 10 : 0) + CP;  // outputs per Gaussian
+  constexpr int NOs = NO > 0 ? NO : 1;
+  __shared__ float4 s_r0[kBwdNB], s_r1[kBwdNB], s_r2[kBwdNB];
+  __shared__ uint32_t s_gid[kBwdNB];
+  __shared__ int s_any[kBwdNB];
+  __shared__ float s_w[kBwdNB][kBwdStride];
+  __shared__ float s_dp[GEO ? kBwdNB : 1][kBwdStride];
+  __shared__ float s_gl[NLs][kBlock];
   __shared__ uint32_t s_end;
   const int tile = xcd_tile(blockIdx.x, ntiles);
   if (tile >= ntiles) return;
   const int tx = tile % tiles_x, ty = tile / tiles_x;
-  const int px = tx * kTile + (threadIdx.x & (kTile - 1));
-  const int py = ty * kTile + (threadIdx.x / kTile);
+  const int tid = threadIdx.x;
+  const int px = tx * kTile + (tid & (kTile - 1));
+  const int py = ty * kTile + (tid / kTile);
   const bool inside = px < W && py < H;
   const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
-  const uint2 range = w.tile_ranges[tile];
+  const uint2 range = clamp_range(w.tile_ranges[tile], max_pairs);
   const uint32_t rmask = (rank_bits >= 32) ? 0xFFFFFFFFu : ((1u << rank_bits) - 1u);
   const int cn = CP > 0 ? min(CP, C - c0) : 0;
   const int64_t HW = (int64_t)W * H;
   const int64_t p = (int64_t)py * W + px;
 
+  // per-pixel state and upstream gradients
   float T = 1.f, Tfin = 1.f;
   uint32_t pend = range.x;
   float gr = 0.f, gg = 0.f, gb = 0.f, gd = 0.f, ga = 0.f;
-  float gf[CPs];
-#pragma unroll
-  for (int c = 0; c < CPs; ++c) gf[c] = 0.f;
   if (inside) {
     Tfin = w.pix_T[p];
     T = Tfin;
@@ -319,91 +368,145 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd(
       gd = g_depth[p];
       ga = g_alpha[p];
     }
-#pragma unroll
-    for (int c = 0; c < CP; ++c) gf[c] = (c < cn) ? g_feat[(int64_t)(c0 + c) * HW + p] : 0.f;
   }
-  if (threadIdx.x == 0) s_end = range.x;
+  if (GEO) {
+    s_gl[0][tid] = gr;
+    s_gl[1][tid] = gg;
+    s_gl[2][tid] = gb;
+    s_gl[3][tid] = gd;
+  }
+#pragma unroll
+  for (int c = 0; c < CP; ++c)
+    s_gl[(GEO ? 4 : 0) + c][tid] =
+        (inside && c < cn) ? g_feat[(int64_t)(c0 + c) * HW + p] : 0.f;
+  if (tid == 0) s_end = range.x;
   __syncthreads();
   if (inside && pend > range.x) atomicMax(&s_end, pend);
   __syncthreads();
   const uint32_t blk_end = min(s_end, range.y);
-  const int lane = threadIdx.x & 63;
-  float S_r = 0.f, S_g = 0.f, S_b = 0.f, S_d = 0.f;  // suffix sums behind the current Gaussian
+  float S_r = 0.f, S_g = 0.f, S_b = 0.f, S_d = 0.f;  // sums over the contributors behind
+
+  // phase-B role of this thread
+  const int bj = tid >> 4;          // Gaussian slot in the batch (one DPP row)
+  const int bq = tid & 15;          // pixel column of the tile
+  const float xl = (float)bq + 0.5f - 0.5f * kTile;  // tile-local x of the column
+  const float tcx = (float)(tx * kTile) + 0.5f * kTile, tcy = (float)(ty * kTile) + 0.5f * kTile;
 
   for (uint32_t b1 = blk_end; b1 > range.x;) {
-    const uint32_t b0 = (b1 - range.x > (uint32_t)kBwdBatch) ? b1 - kBwdBatch : range.x;
-    const uint32_t n = b1 - b0;
+    const uint32_t b0 = (b1 - range.x > (uint32_t)kBwdNB) ? b1 - kBwdNB : range.x;
+    const int n = (int)(b1 - b0);
     __syncthreads();  // previous batch fully consumed
-    if (threadIdx.x < n) {
-      const uint32_t gid = pair_gid(w, b0 + threadIdx.x, rmask, P);
-      s_gid[threadIdx.x] = gid;
-      load_record(w, gid, P, s_r0[threadIdx.x], s_r1[threadIdx.x], s_r2[threadIdx.x]);
+    if (tid < n) {
+      const uint32_t gid = pair_gid(w, b0 + tid, rmask, P);
+      s_gid[tid] = gid;
+      load_record(w, gid, P, s_r0[tid], s_r1[tid], s_r2[tid]);
     }
-    for (int e = threadIdx.x; e < kBwdBatch * NGs; e += kBlock) (&s_grad[0][0])[e] = 0.f;
+    if (tid < kBwdNB) s_any[tid] = 0;
     __syncthreads();
-    for (int jj = (int)n - 1; jj >= 0; --jj) {
+    // ---- phase A: per-pixel products, back to front
+    for (int jj = n - 1; jj >= 0; --jj) {
       const uint32_t j = b0 + (uint32_t)jj;
       const float4 r0 = s_r0[jj], r1 = s_r1[jj];
-      bool contrib = inside && j < pend;
-      AlphaEval e;
-      e.alpha = 0.f;
-      if (contrib) {
-        e = eval_alpha(r0, r1, pxc, pyc, st.alpha_max);
-        contrib = e.alpha >= st.alpha_min;
-      }
-      if (__ballot(contrib) == 0ull) continue;  // nothing for this wave
-      float gv[NGs];
-#pragma unroll
-      for (int k = 0; k < NGs; ++k) gv[k] = 0.f;
-      if (contrib) {
-        const float om = 1.f - e.alpha;
-        const float inv = 1.f / om;
-        const float Tb = T * inv;  // transmittance in front of this Gaussian
-        const float wgt = e.alpha * Tb;
-        if (GEO) {
-          const float4 r2 = s_r2[jj];
-          const float dal = Tb * (gr * r2.x + gg * r2.y + gb * r2.z + gd * r1.z) -
-                            (gr * S_r + gg * S_g + gb * S_b + gd * S_d) * inv + ga * Tfin * inv;
-          S_r += wgt * r2.x;
-          S_g += wgt * r2.y;
-          S_b += wgt * r2.z;
-          S_d += wgt * r1.z;
-          if (e.oG < st.alpha_max) {
-            const float dpow = dal * e.oG;
-            gv[0] = -dpow * (r0.z * e.dx + r0.w * e.dy);
-            gv[1] = -dpow * (r0.w * e.dx + r1.x * e.dy);
-            gv[2] = -0.5f * dpow * e.dx * e.dx;
-            gv[3] = -dpow * e.dx * e.dy;
-            gv[4] = -0.5f * dpow * e.dy * e.dy;
-            gv[5] = dal * e.G;
+      float wv = 0.f, dp = 0.f;
+      if (inside && j < pend) {
+        const AlphaEval e = eval_alpha(r0, r1, pxc, pyc, st.alpha_max);
+        if (e.alpha >= st.alpha_min) {
+          const float inv = 1.f / (1.f - e.alpha);
+          const float Tb = T * inv;  // transmittance in front of this Gaussian
+          wv = e.alpha * Tb;
+          if constexpr (GEO) {
+            const float4 r2 = s_r2[jj];
+            const float dal = Tb * (gr * r2.x + gg * r2.y + gb * r2.z + gd * r1.z) -
+                              (gr * S_r + gg * S_g + gb * S_b + gd * S_d) * inv + ga * Tfin * inv;
+            S_r += wv * r2.x;
+            S_g += wv * r2.y;
+            S_b += wv * r2.z;
+            S_d += wv * r1.z;
+            dp = (e.oG < st.alpha_max) ? dal * e.oG : 0.f;
           }
-          gv[6] = wgt * gr;
-          gv[7] = wgt * gg;
-          gv[8] = wgt * gb;
-          gv[9] = wgt * gd;
+          T = Tb;
+          s_any[jj] = 1;
         }
-#pragma unroll
-        for (int c = 0; c < CP; ++c) gv[(GEO ? 10 : 0) + c] = wgt * gf[c];
-        T = Tb;
       }
-#pragma unroll
-      for (int k = 0; k < NG; ++k) {
-        const float v = wave_sum(gv[k]);
-        if (lane == 0 && v != 0.f) atomicAdd(&s_grad[jj][k], v);
-      }
+      s_w[jj][tid] = wv;
+      if (GEO) s_dp[jj][tid] = dp;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < (int)n * NG; e += kBlock) {
-      const int jj = e / NGs, k = e % NGs;
-      const float v = s_grad[jj][k];
-      if (v == 0.f) continue;
-      const uint32_t gid = s_gid[jj];
-      if (gid >= (uint32_t)P) continue;
-      if (GEO && k < 10)
-        unsafeAtomicAdd(&w.grad2d[(int64_t)gid * 10 + k], v);
-      else {
-        const int c = k - (GEO ? 10 : 0);
-        if (c < cn) unsafeAtomicAdd(&d_feat[(int64_t)gid * C + c0 + c], v);
+    // ---- phase B: contraction over the tile's pixels, one column per lane
+    const bool wave_active =
+        __ballot(bj < n && s_any[bj] != 0) != 0ull;  // uniform per wave: skip idle waves
+    if (!wave_active) {
+      b1 = b0;
+      continue;
+    }
+    float acc[NOs];
+#pragma unroll
+    for (int k = 0; k < NO; ++k) acc[k] = 0.f;
+    if (bj < n && s_any[bj]) {
+#pragma unroll 4
+      for (int i = 0; i < kTile; ++i) {
+        const int pp = i * kTile + bq;
+        const float wv = s_w[bj][pp];
+#pragma unroll
+        for (int k = 0; k < NL; ++k) acc[k] += wv * s_gl[k][pp];
+        if constexpr (GEO) {
+          const float dp = s_dp[bj][pp];
+          const float yl = (float)i + 0.5f - 0.5f * kTile;
+          const float dx = dp * xl, dy = dp * yl;
+          acc[NL + 0] += dp;
+          acc[NL + 1] += dx;
+          acc[NL + 2] += dy;
+          acc[NL + 3] += dx * xl;
+          acc[NL + 4] += dx * yl;
+          acc[NL + 5] += dy * yl;
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NO; ++k) acc[k] = row16_allreduce(acc[k]);
+    // ---- phase C: per-Gaussian outputs, spread over the 16 lanes of the row
+    if (bj < n && s_any[bj]) {
+      const uint32_t gid = s_gid[bj];
+      if (gid < (uint32_t)P) {
+        float geo[10];
+        if constexpr (GEO) {
+          const float4 r0 = s_r0[bj], r1 = s_r1[bj];
+          const float ud = r0.x - tcx, vd = r0.y - tcy;  // mean relative to the tile centre
+          const float M0 = acc[NL], M1 = acc[NL + 1], M2 = acc[NL + 2];
+          const float M3 = acc[NL + 3], M4 = acc[NL + 4], M5 = acc[NL + 5];
+          // sums of dL/dpower times (u - x_p), (v - y_p) and their products
+          const float Sx = ud * M0 - M1, Sy = vd * M0 - M2;
+          const float Sxx = ud * ud * M0 - 2.f * ud * M1 + M3;
+          const float Sxy = ud * vd * M0 - ud * M2 - vd * M1 + M4;
+          const float Syy = vd * vd * M0 - 2.f * vd * M2 + M5;
+          geo[0] = -(r0.z * Sx + r0.w * Sy);
+          geo[1] = -(r0.w * Sx + r1.x * Sy);
+          geo[2] = -0.5f * Sxx;
+          geo[3] = -Sxy;
+          geo[4] = -0.5f * Syy;
+          geo[5] = r1.y > 0.f ? M0 / r1.y : 0.f;
+          geo[6] = acc[0];
+          geo[7] = acc[1];
+          geo[8] = acc[2];
+          geo[9] = acc[3];
+        }
+#pragma unroll
+        for (int f0 = 0; f0 < NF; f0 += 16) {
+          const int f = f0 + bq;
+          if (f >= NF) break;
+          if (GEO && f < 10) {  // geometry slots exist only when GEO
+            float v = 0.f;
+#pragma unroll
+            for (int k = 0; k < 10; ++k) v = (k == f) ? geo[k] : v;
+            if (v != 0.f) unsafeAtomicAdd(&w.grad2d[(int64_t)gid * 10 + f], v);
+          } else {
+            const int c = f - (GEO ? 10 : 0);
+            float v = 0.f;
+#pragma unroll
+            for (int k = 0; k < CP; ++k) v = (k == c) ? acc[(GEO ? 4 : 0) + k] : v;
+            if (c < cn && v != 0.f) unsafeAtomicAdd(&d_feat[(int64_t)gid * C + c0 + c], v);
+          }
+        }
       }
     }
     b1 = b0;
@@ -417,7 +520,8 @@ static void launch_bwd_t(const DevSettings& st, const DevGaussians& g, const Lay
                          hipStream_t s) {
   const int grid = ((L.ntiles + kNumXcd - 1) / kNumXcd) * kNumXcd;
   hipLaunchKernelGGL((k_composite_bwd<CP, GEO>), dim3(grid), dim3(kBlock), 0, s, st, g.P, g.C, c0,
-                     L.W, L.H, L.tiles_x, L.ntiles, L.rank_bits, w, g_rgb, g_depth, g_alpha,
+                     L.W, L.H, L.tiles_x, L.ntiles, L.rank_bits, (uint32_t)L.max_pairs, w, g_rgb,
+                     g_depth, g_alpha,
                      g_feat, d_feat);
 }
 
@@ -475,24 +579,31 @@ __global__ __launch_bounds__(256) void k_l1_grad(const float* __restrict__ x,
                                                  const float* __restrict__ y, int64_t n,
                                                  float scale, float* __restrict__ grad,
                                                  float* __restrict__ loss) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ float s_part[4];
   float l = 0.f;
-  if (i < n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
     const float d = x[i] - y[i];
     grad[i] = d > 0.f ? scale : (d < 0.f ? -scale : 0.f);
-    l = fabsf(d) * scale;
+    l += fabsf(d);
   }
-  if (loss) {
-    l = wave_sum(l);
-    if ((threadIdx.x & 63) == 0 && l != 0.f) unsafeAtomicAdd(loss, l);
+  if (!loss) return;  // uniform
+  l = wave_sum(l);
+  if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = l;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const float t = (s_part[0] + s_part[1]) + (s_part[2] + s_part[3]);
+    if (t != 0.f) unsafeAtomicAdd(loss, t * scale);
   }
 }
 
 hipError_t launch_l1_grad(const float* x, const float* y, int64_t n, float scale, float* grad,
                           float* loss, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_l1_grad, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, y, n, scale,
-                     grad, loss);
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 512) blocks = 512;  // grid-stride: few atomics on the loss scalar
+  hipLaunchKernelGGL(k_l1_grad, dim3((unsigned)blocks), dim3(256), 0, s, x, y, n, scale, grad,
+                     loss);
   return hipGetLastError();
 }
 

@@ -19,9 +19,11 @@ constexpr float kRectMargin = 0.05f;
 __global__ __launch_bounds__(256) void k_preprocess(DevGaussians g, DevCamera cam,
                                                     DevSettings st, WsView w) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) {
+  if (i == 0) {  // the whole status word: later stages read the pair count from it
     w.status[0] = 0u;
     w.status[1] = 0u;
+    w.status[2] = 0u;
+    w.status[3] = 0u;
   }
   const int64_t P = g.P;
   if (i >= P) return;

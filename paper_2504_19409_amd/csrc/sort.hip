@@ -64,11 +64,12 @@ __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t* s_t
 __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__ keys,
                                                     const uint32_t* __restrict__ n_dev,
                                                     uint32_t n_static, int shift, int nbits,
-                                                    uint32_t* __restrict__ hist, int nchunks) {
+                                                    uint32_t* __restrict__ hist, int nchunks,
+                                                    uint32_t cap) {
   __shared__ uint32_t s_hist[4][256];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int chunk = blockIdx.x * 4 + wv;
-  const uint32_t n = n_dev ? *n_dev : n_static;
+  const uint32_t n = min(n_dev ? *n_dev : n_static, cap);  // never past the key buffer
   const uint32_t nbins = 1u << nbits, mask = nbins - 1u;
   for (uint32_t d = lane; d < nbins; d += 64) s_hist[wv][d] = 0u;
   __syncthreads();
@@ -114,7 +115,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(
   __shared__ uint32_t s_tmp[4];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int chunk = blockIdx.x * 4 + wv;
-  const uint32_t n = n_dev ? *n_dev : n_static;
+  const uint32_t n = min(n_dev ? *n_dev : n_static, cap);  // never past either buffer
   const uint32_t nbins = 1u << nbits, mask = nbins - 1u;
   // digit bases: exclusive scan of the digit totals (nbins <= 256)
   {
@@ -165,7 +166,7 @@ static hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t*
                              hipStream_t s) {
   const unsigned blocks = (unsigned)((nchunks + 3) / 4);
   hipLaunchKernelGGL(k_radix_hist, dim3(blocks), dim3(256), 0, s, kin, n_dev, n_static, shift,
-                     nbits, w.hist, nchunks);
+                     nbits, w.hist, nchunks, cap);
   hipLaunchKernelGGL(k_radix_rowscan, dim3(1u << nbits), dim3(256), 0, s, w.hist, nchunks,
                      w.hist_tot);
   if (vin)
@@ -268,11 +269,16 @@ __global__ __launch_bounds__(1024) void k_count_top(WsView w, int nblocks, uint6
   }
 }
 
-// offsets and pair emission: key = (tile << rank_bits) | rank
-__global__ __launch_bounds__(256) void k_emit(WsView w, int64_t P, int tiles_x, int rank_bits) {
+// Offsets and pair emission: key = (tile << rank_bits) | rank.  After the
+// block scan every lane holds the offset, count and rectangle of its own rank;
+// each wave then walks its 64 ranks in order, broadcasting one rank's values
+// with readlane, and all lanes write consecutive keys of that rank's run.
+__global__ __launch_bounds__(256) void k_emit(WsView w, int64_t P, int tiles_x, int rank_bits,
+                                              uint32_t max_pairs) {
   __shared__ uint32_t s_tmp[4];
-  const bool ok = w.status[2] != 0u || w.status[1] == 0u;
+  const bool ok = (w.status[2] != 0u || w.status[1] == 0u) && w.status[2] <= max_pairs;
   const int64_t base = (int64_t)blockIdx.x * kScanBlock;
+  const int lane = threadIdx.x & 63;
   uint32_t carry = w.scan_part[blockIdx.x];
   for (int k = 0; k < kScanBlock / 256; ++k) {
     const int64_t r = base + k * 256 + threadIdx.x;
@@ -283,11 +289,21 @@ __global__ __launch_bounds__(256) void k_emit(WsView w, int64_t P, int tiles_x, 
     const uint32_t off = carry + block_excl_scan256(cnt, s_tmp, &tot);
     carry += tot;
     if (r < P) w.offsets[r] = off;
-    if (ok && cnt) {
-      uint32_t o = off;
-      for (int ty = rc.y; ty <= rc.w; ++ty)
-        for (int tx = rc.x; tx <= rc.z; ++tx)
-          w.pkeys_a[o++] = ((uint32_t)(ty * tiles_x + tx) << rank_bits) | (uint32_t)r;
+    if (!ok) continue;
+    const uint32_t x0 = rc.x, y0 = rc.y, wd = (uint32_t)(rc.z - rc.x) + 1u;
+    const uint32_t rank0 = (uint32_t)(r - lane);
+    for (int src = 0; src < 64; ++src) {
+      const uint32_t n = __builtin_amdgcn_readlane(cnt, src);
+      if (n == 0u) continue;  // uniform
+      const uint32_t o = __builtin_amdgcn_readlane(off, src);
+      const uint32_t bx = __builtin_amdgcn_readlane(x0, src);
+      const uint32_t by = __builtin_amdgcn_readlane(y0, src);
+      const uint32_t bw = __builtin_amdgcn_readlane(wd, src);
+      const uint32_t rk = rank0 + (uint32_t)src;
+      for (uint32_t j = lane; j < n; j += 64) {
+        const uint32_t ty = by + j / bw, tx = bx + j % bw;
+        w.pkeys_a[o + j] = ((ty * (uint32_t)tiles_x + tx) << rank_bits) | rk;
+      }
     }
   }
 }
@@ -300,7 +316,7 @@ hipError_t launch_bin(const Layout& L, const WsView& w, hipStream_t s) {
   hipLaunchKernelGGL(k_count_top, dim3(1), dim3(1024), 0, s, w, (int)L.scan_blocks,
                      (uint64_t)L.max_pairs);
   hipLaunchKernelGGL(k_emit, dim3((unsigned)L.scan_blocks), dim3(256), 0, s, w, L.P, L.tiles_x,
-                     L.rank_bits);
+                     L.rank_bits, (uint32_t)L.max_pairs);
   return hipGetLastError();
 }
 
@@ -318,10 +334,11 @@ __device__ __forceinline__ uint32_t lower_bound_u64(const uint32_t* a, uint32_t 
   return lo;
 }
 
-__global__ __launch_bounds__(256) void k_tile_ranges(WsView w, int ntiles, int rank_bits) {
+__global__ __launch_bounds__(256) void k_tile_ranges(WsView w, int ntiles, int rank_bits,
+                                                     uint32_t max_pairs) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= ntiles) return;
-  const uint32_t n = w.status[2];
+  const uint32_t n = min(w.status[2], max_pairs);
   const uint32_t a = lower_bound_u64(w.pkeys_a, n, (uint64_t)t << rank_bits);
   const uint32_t b = lower_bound_u64(w.pkeys_a, n, (uint64_t)(t + 1) << rank_bits);
   w.tile_ranges[t] = make_uint2(a, b);
@@ -329,7 +346,7 @@ __global__ __launch_bounds__(256) void k_tile_ranges(WsView w, int ntiles, int r
 
 hipError_t launch_tile_ranges(const Layout& L, const WsView& w, hipStream_t s) {
   hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)((L.ntiles + 255) / 256)), dim3(256), 0, s, w,
-                     L.ntiles, L.rank_bits);
+                     L.ntiles, L.rank_bits, (uint32_t)L.max_pairs);
   return hipGetLastError();
 }
 

@@ -1,0 +1,131 @@
+"""C ABI contract checks that need no GPU: the HIP library loads, exports every
+entry point include/gsff.h declares, and its host-only calls (sizes, layout,
+defaults, argument validation) behave as documented.  Argument validation runs
+before any device work, so invalid calls return without touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def capi():
+    from paper_2504_19409_amd import _capi
+    if not os.path.exists(_capi.LIB_PATH):
+        from paper_2504_19409_amd import build
+        build.build()
+    _capi.load()
+    return _capi
+
+
+def _declared(header):
+    text = open(os.path.join(ROOT, "include", header)).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gsff_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(capi):
+    lib = capi.load()
+    names = _declared("gsff.h")
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    # and the binding declares a signature for each
+    assert not [n for n in names if n not in capi.SIGNATURES]
+
+
+def test_version_and_defaults(capi):
+    lib = capi.load()
+    a, b = ctypes.c_int32(-1), ctypes.c_int32(-1)
+    assert lib.gsff_version(ctypes.byref(a), ctypes.byref(b)) == 0
+    assert (a.value, b.value) >= (0, 1)
+    s = capi.default_settings()
+    assert s.alpha_min == pytest.approx(1 / 255)
+    assert s.alpha_max == pytest.approx(0.99)
+    assert s.t_min == pytest.approx(1e-4)
+    assert s.dilation == pytest.approx(0.3)
+    assert s.near_plane == pytest.approx(0.2)
+    assert s.render_features == 1
+
+
+def test_workspace_layout_consistent(capi):
+    for P, M, W, H in [(1, 16, 1, 1), (2000, 24000, 64, 48), (200_000, 5_000_000, 640, 480),
+                       (1_000_000, 40_000_000, 1200, 680)]:
+        n = capi.workspace_size(P, M, W, H)
+        lay = capi.workspace_layout(P, M, W, H)
+        assert lay.total_bytes == n
+        offs = [lay.status, lay.records, lay.rects, lay.depth_keys, lay.depth_ids,
+                lay.pair_keys, lay.tile_ranges, lay.pix_T, lay.pix_end, lay.grad2d]
+        assert lay.status == 0
+        assert all(o % 256 == 0 for o in offs)
+        assert offs == sorted(offs) and len(set(offs)) == len(offs)
+        assert lay.tiles_x == (W + 15) // 16 and lay.tiles_y == (H + 15) // 16
+        assert lay.rank_bits >= max(1, (P - 1).bit_length())
+        # monotone in every size
+        assert capi.workspace_size(P + 1, M, W, H) >= n
+        assert capi.workspace_size(P, M + 1000, W, H) >= n
+
+
+def test_unrepresentable_sizes_rejected(capi):
+    lib = capi.load()
+    n = ctypes.c_size_t(0)
+    # rank bits + tile bits > 32
+    assert lib.gsff_workspace_size(1 << 24, 100, 1 << 13, 1 << 13, ctypes.byref(n)) == \
+        capi.ERR_INVALID_ARGUMENT
+    assert lib.gsff_workspace_size(-1, 100, 64, 64, ctypes.byref(n)) == capi.ERR_INVALID_ARGUMENT
+    assert lib.gsff_workspace_size(10, 100, 0, 64, ctypes.byref(n)) == capi.ERR_INVALID_ARGUMENT
+    assert lib.gsff_workspace_size(10, 1 << 33, 64, 64, ctypes.byref(n)) == \
+        capi.ERR_INVALID_ARGUMENT
+    assert b"representable" in lib.gsff_last_error()
+
+
+def _args(capi, P=10, C=0, ws=0x100000, ws_bytes=1 << 30, max_pairs=1000, W=32, H=32):
+    fake = 0x7F0000000000  # never dereferenced: every call below fails validation first
+    g = capi.Gaussians(P, C, capi.DTYPE_F32, fake, fake, fake, fake, fake, fake if C else None)
+    c = capi.Camera(W, H, 30.0, 30.0, W / 2, H / 2, fake)
+    s = capi.default_settings()
+    return g, c, s, ws, ws_bytes, max_pairs
+
+
+def test_argument_validation(capi):
+    lib = capi.load()
+    E = capi.ERR_INVALID_ARGUMENT
+    g, c, s, ws, nb, mp = _args(capi)
+    b = ctypes.byref
+    # NULL structs / workspace / outputs
+    assert lib.gsff_forward(None, b(c), b(s), ws, nb, mp, 1, 1, 1, None, 0, None) == E
+    assert lib.gsff_forward(b(g), b(c), b(s), None, nb, mp, 1, 1, 1, None, 0, None) == E
+    assert lib.gsff_forward(b(g), b(c), b(s), ws, nb, mp, None, 1, 1, None, 0, None) == E
+    # misaligned and too-small workspace
+    assert lib.gsff_forward(b(g), b(c), b(s), ws + 4, nb, mp, 1, 1, 1, None, 0, None) == E
+    assert lib.gsff_forward(b(g), b(c), b(s), ws, 64, mp, 1, 1, 1, None, 0, None) == E
+    assert b"too small" in lib.gsff_last_error()
+    # bad settings
+    s2 = capi.default_settings(alpha_min=0.0)
+    assert lib.gsff_forward(b(g), b(c), b(s2), ws, nb, mp, 1, 1, 1, None, 0, None) == E
+    # features on, C > 0, but no feature output
+    g2, *_ = _args(capi, C=4)
+    assert lib.gsff_forward(b(g2), b(c), b(s), ws, nb, mp, 1, 1, 1, None, 0, None) == E
+    # unsupported dtypes
+    g3, *_ = _args(capi, C=4)
+    g3.feat_dtype = 7
+    assert lib.gsff_forward(b(g3), b(c), b(s), ws, nb, mp, 1, 1, 1, 1, 0, None) == \
+        capi.ERR_UNSUPPORTED
+    assert lib.gsff_forward(b(g2), b(c), b(s), ws, nb, mp, 1, 1, 1, 1, 9, None) == \
+        capi.ERR_UNSUPPORTED
+    # bad intrinsics / image
+    c2 = capi.Camera(0, 32, 30.0, 30.0, 16, 16, 1)
+    assert lib.gsff_forward(b(g), b(c2), b(s), ws, nb, mp, 1, 1, 1, None, 0, None) == E
+    c3 = capi.Camera(32, 32, -1.0, 30.0, 16, 16, 1)
+    assert lib.gsff_forward(b(g), b(c3), b(s), ws, nb, mp, 1, 1, 1, None, 0, None) == E
+    # backward: missing upstream for geometry gradients
+    gr = capi.Grads(1, None, None, None, None, None, None)
+    assert lib.gsff_backward(b(g), b(c), b(s), ws, nb, mp, None, 1, 1, None, b(gr), 0,
+                             None) == E
+    assert lib.gsff_backward(b(g), b(c), b(s), ws, nb, mp, 1, 1, 1, None, None, 0, None) == E
+    # l1 and status
+    assert lib.gsff_l1_grad(None, None, 10, 1.0, None, None, None) == E
+    assert lib.gsff_read_status(None, None, None, None) == E
