@@ -6,9 +6,10 @@ the camera frustum at 1-5 m, 640x480 pinhole camera (fx = fy = 525), RGB +
 depth + accumulated opacity + 16-channel FP32 features, camera pose perturbed
 by 1 cm / 1 degree from the pose the target images were rendered at.
 
-One step = preprocess -> depth sort -> tile binning -> tile sort -> tile
-ranges -> compositing -> L1 loss gradients of the four output groups ->
-compositing adjoint -> preprocess adjoint + pose reduction, all in libgsff
+One step = preprocess -> depth sort -> tile binning -> (tile sort -> tile
+ranges, no-ops on this tile grid) -> compositing -> adjoint of the L1 loss
+mean|rgb - t| + mean|depth - t| + mean|feat - t| (upstream formed inside the
+compositing adjoint) -> preprocess adjoint + pose reduction, all in libgsff
 kernels on one stream, inputs resident in HBM.
 
 Prints one JSON line (see the keys below); ``--gpus`` above 1 is refused: this
@@ -32,7 +33,8 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP32_VALU_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, TFLOP/s (packed FMA)
 
 STAGES = ["preprocess", "sort_depth", "bin", "sort_tiles", "tile_ranges", "composite_fwd",
-          "l1", "composite_bwd", "preprocess_bwd"]
+          "composite_bwd_l1", "preprocess_bwd"]
+L1_WEIGHTS = (1.0, 1.0, 0.0, 1.0)  # rgb, depth, alpha, feature
 
 
 def log(*a):
@@ -48,6 +50,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="wall-clock budget of the CPU oracle sample")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches only")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="for counter collection: eager steps only, no oracle work counts or "
+                         "CPU baseline, plus one plain 256 MiB device copy whose counters "
+                         "calibrate FETCH_SIZE / WRITE_SIZE")
     return ap.parse_args()
 
 
@@ -81,10 +87,9 @@ class Step:
     """One forward+backward iteration issued stage by stage."""
 
     def __init__(self, torch, fr, targets):
-        from paper_2504_19409_amd.rasterizer import l1_grad
-        self.torch, self.fr, self.targets, self.l1 = torch, fr, targets, l1_grad
+        self.torch, self.fr = torch, fr
+        self.targets = [targets[0], targets[1], None, targets[3]]  # alpha not in the loss
         self.outs = fr.alloc_outputs()
-        self.ups = [torch.empty_like(o) for o in self.outs]
         self.loss = torch.zeros(1, device="cuda")
         self.grads = fr.make_grads()
 
@@ -105,13 +110,10 @@ class Step:
         fr.composite_fwd(self.outs)
         rec(6)
         self.loss.zero_()
-        for o, tg, u in zip(self.outs, self.targets, self.ups):
-            self.l1(o, tg, 1.0 / o.numel(), u, self.loss)
+        fr.composite_bwd_l1(self.outs, self.targets, L1_WEIGHTS, self.grads, self.loss)
         rec(7)
-        fr.composite_bwd(*self.ups, self.grads)
-        rec(8)
         fr.preprocess_bwd(self.grads)
-        rec(9)
+        rec(8)
 
 
 def algorithmic_work(scene, n_pairs, torch):
@@ -166,13 +168,23 @@ def main():
     scene, fr, targets, n_pairs = build_problem(torch)
     step = Step(torch, fr, targets)
     log(f"pairs {n_pairs}, workspace {fr.ws_bytes / 1e6:.1f} MB")
+    if args.profile_run:
+        src = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)  # calibration: 256 MiB read + 256 MiB written
+        for _ in range(args.steps):
+            step.run()
+        torch.cuda.synchronize()
+        log("profile run done")
+        return
     for _ in range(args.warmup):
         step.run()
     torch.cuda.synchronize()
 
     # eager, with per-stage events
     K = args.steps
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(10)] for _ in range(K)]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(STAGES) + 1)]
+          for _ in range(K)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(K):
@@ -246,7 +258,7 @@ def roofline_for(stage, ms, wc, sz):
     measured average launch time.  Work per unit is stated in the design notes."""
     P, C, HW, M = sz["P"], sz["C"], sz["HW"], sz["n_pairs"]
     sec = ms * 1e-3
-    if stage in ("composite_fwd", "composite_bwd"):
+    if stage in ("composite_fwd", "composite_bwd_l1"):
         # FP32 VALU work: flops per alpha evaluation (evaluations up to each
         # pixel's stop) plus per contributing pair
         if stage == "composite_fwd":
@@ -263,7 +275,6 @@ def roofline_for(stage, ms, wc, sz):
         "bin": P * 8 * 2 + M * 4,
         "sort_tiles": 2 * M * 4 * 3,
         "tile_ranges": 8 * 1200,
-        "l1": HW * (5 + C) * 4 * 3,
         "preprocess_bwd": P * (44 + 40) + P * 56,
     }[stage]
     achieved = bytes_ / sec / 1e9

@@ -126,7 +126,8 @@ typedef struct gsff_ws_layout {
   uint64_t rects;       /* uint16[4][P]: tile rect x0,y0,x1,y1 (inclusive); empty => x0>x1 */
   uint64_t depth_keys;  /* uint32[P]: sorted depth keys (float bits)           */
   uint64_t depth_ids;   /* uint32[P]: Gaussian index in depth order            */
-  uint64_t pair_keys;   /* uint32[max_pairs]: (tile << rank_bits) | depth rank */
+  uint64_t pair_keys;   /* uint32[max_pairs]: Gaussian ids grouped by tile, in
+                           depth order inside every tile                        */
   uint64_t tile_ranges; /* uint32[2][ntiles]: [start, end) into pair_keys      */
   uint64_t pix_T;       /* float[H*W]: final transmittance                     */
   uint64_t pix_end;     /* uint32[H*W]: 1 + list position of last contributor  */
@@ -183,10 +184,34 @@ gsff_status gsff_backward(const gsff_gaussians* g, const gsff_camera* cam,
                           const float* g_alpha, const float* g_feat,
                           const gsff_grads* out, int32_t accumulate, void* stream);
 
+/* Backward of the L1 losses the method optimises (the tracking, mapping and
+ * feature losses, Eqs. 5, 8 and 11, are weighted sums of L1 terms):
+ *   L = w[0] mean|rgb - t_rgb| + w[1] mean|depth - t_depth|
+ *     + w[2] mean|alpha - t_alpha| + w[3] mean|feat - t_feat|
+ * with each mean over its group's elements (3HW, HW, HW, C*HW).  The adjoint
+ * forms the upstream gradient (w_k / numel_k) sign(out - target) per pixel
+ * itself, so no upstream images are materialised.  out_* are the outputs of
+ * the forward that last used `ws` (f32, same layouts); t_* the targets, where
+ * a NULL target leaves that group out of the loss.  weights: HOST pointer to
+ * 4 floats.  loss (device, may be NULL) receives += the loss terms whose
+ * gradients are computed (rgb / depth / alpha only when a geometry gradient is
+ * requested, feature only when out->feat is set and features are on).
+ * Otherwise as gsff_backward. */
+gsff_status gsff_backward_l1(const gsff_gaussians* g, const gsff_camera* cam,
+                             const gsff_settings* st, void* ws, size_t ws_bytes,
+                             int64_t max_pairs, const float* out_rgb, const float* out_depth,
+                             const float* out_alpha, const float* out_feat, const float* t_rgb,
+                             const float* t_depth, const float* t_alpha, const float* t_feat,
+                             const float* weights, float* loss, const gsff_grads* out,
+                             int32_t accumulate, void* stream);
+
 /* Stage entry points: the forward is exactly preprocess, sort_depth, bin,
  * sort_tiles, tile_ranges, composite_fwd in this order; the backward is
  * composite_bwd then preprocess_bwd.  Same arguments and conventions as the
- * two calls above; exposed for stage-by-stage testing and timing. */
+ * two calls above; exposed for stage-by-stage testing and timing.  For tile
+ * grids up to 4096 tiles `bin` writes every tile's list directly in depth
+ * order and `sort_tiles` / `tile_ranges` have nothing left to do; larger grids
+ * sort (tile, rank) keys instead. */
 gsff_status gsff_preprocess(const gsff_gaussians* g, const gsff_camera* cam,
                             const gsff_settings* st, void* ws, size_t ws_bytes,
                             int64_t max_pairs, void* stream);
@@ -213,6 +238,15 @@ gsff_status gsff_composite_bwd(const gsff_gaussians* g, const gsff_camera* cam,
                                const float* g_depth, const float* g_alpha,
                                const float* g_feat, const gsff_grads* out,
                                int32_t accumulate, void* stream);
+/* The compositing part of gsff_backward_l1 alone (its stage split: follow it
+ * with gsff_preprocess_bwd). */
+gsff_status gsff_composite_bwd_l1(const gsff_gaussians* g, const gsff_camera* cam,
+                                  const gsff_settings* st, void* ws, size_t ws_bytes,
+                                  int64_t max_pairs, const float* out_rgb, const float* out_depth,
+                                  const float* out_alpha, const float* out_feat,
+                                  const float* t_rgb, const float* t_depth, const float* t_alpha,
+                                  const float* t_feat, const float* weights, float* loss,
+                                  const gsff_grads* out, int32_t accumulate, void* stream);
 gsff_status gsff_preprocess_bwd(const gsff_gaussians* g, const gsff_camera* cam,
                                 const gsff_settings* st, void* ws, size_t ws_bytes,
                                 int64_t max_pairs, const gsff_grads* out,

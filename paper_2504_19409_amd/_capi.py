@@ -68,6 +68,10 @@ SIGNATURES = {
     "gsff_workspace_layout": (_i32, [_i64, _i64, _i32, _i32, ctypes.POINTER(WsLayout)]),
     "gsff_forward": (_i32, [_G, _C, _S, _vp, _sz, _i64, _vp, _vp, _vp, _vp, _i32, _vp]),
     "gsff_backward": (_i32, [_G, _C, _S, _vp, _sz, _i64, _vp, _vp, _vp, _vp, _R, _i32, _vp]),
+    "gsff_backward_l1": (_i32, [_G, _C, _S, _vp, _sz, _i64] + [_vp] * 8
+                         + [ctypes.POINTER(_f32), _vp, _R, _i32, _vp]),
+    "gsff_composite_bwd_l1": (_i32, [_G, _C, _S, _vp, _sz, _i64] + [_vp] * 8
+                              + [ctypes.POINTER(_f32), _vp, _R, _i32, _vp]),
     "gsff_preprocess": (_i32, [_G, _C, _S, _vp, _sz, _i64, _vp]),
     "gsff_sort_depth": (_i32, [_G, _C, _S, _vp, _sz, _i64, _vp]),
     "gsff_bin": (_i32, [_G, _C, _S, _vp, _sz, _i64, _vp]),

@@ -38,11 +38,14 @@ bool compute_layout(int64_t P, int64_t max_pairs, int32_t W, int32_t H, Layout* 
   l.ntiles = l.tiles_x * l.tiles_y;
   l.rank_bits = ceil_log2((uint64_t)(P < 2 ? 2 : P));
   l.tile_bits = ceil_log2((uint64_t)l.ntiles);
-  if (l.rank_bits + l.tile_bits > 32) return false;
+  l.direct_bin = l.ntiles <= kMaxDirectTiles;
+  // the fallback path packs (tile, rank) into 32-bit keys
+  if (!l.direct_bin && l.rank_bits + l.tile_bits > 32) return false;
   l.depth_chunks = (P + kRadixChunk - 1) / kRadixChunk;
   l.pair_chunks = (max_pairs + kRadixChunk - 1) / kRadixChunk;
   l.scan_blocks = (P + kScanBlock - 1) / kScanBlock;
   l.pose_blocks = (P + kPoseBlock - 1) / kPoseBlock;
+  l.bin_blocks = (P + kBinBlock - 1) / kBinBlock;
   const uint64_t HW = (uint64_t)W * H;
   const uint64_t A = 256;
   uint64_t o = 0;
@@ -60,16 +63,19 @@ bool compute_layout(int64_t P, int64_t max_pairs, int32_t W, int32_t H, Layout* 
   l.dids_b = take(4ull * P);
   l.offsets = take(4ull * (P + 1));
   l.pkeys_a = take(4ull * max_pairs);
-  l.pkeys_b = take(4ull * max_pairs);
+  l.pkeys_b = take(l.direct_bin ? 0ull : 4ull * max_pairs);
   l.tile_ranges = take(8ull * l.ntiles);
   l.pix_T = take(4ull * HW);
   l.pix_end = take(4ull * HW);
   l.grad2d = take(40ull * P);
-  const int64_t chunks = l.depth_chunks > l.pair_chunks ? l.depth_chunks : l.pair_chunks;
+  const int64_t chunks = (l.direct_bin || l.depth_chunks > l.pair_chunks) ? l.depth_chunks
+                                                                          : l.pair_chunks;
   l.hist = take(4ull * 256 * (uint64_t)(chunks > 0 ? chunks : 1));
   l.hist_tot = take(4ull * 256);
   l.scan_part = take(4ull * (uint64_t)(l.scan_blocks + 1));
   l.pose_part = take(8ull * 6 * (uint64_t)(l.pose_blocks + 1));
+  l.binhist = take(l.direct_bin ? 4ull * l.ntiles * (uint64_t)l.bin_blocks : 0ull);
+  l.tile_tot = take(l.direct_bin ? 4ull * l.ntiles : 0ull);
   l.total = o;
   *L = l;
   return true;
@@ -96,6 +102,8 @@ WsView make_view(void* ws, const Layout& L) {
   w.hist_tot = (uint32_t*)(b + L.hist_tot);
   w.scan_part = (uint32_t*)(b + L.scan_part);
   w.pose_part = (double*)(b + L.pose_part);
+  w.binhist = (uint32_t*)(b + L.binhist);
+  w.tile_tot = (uint32_t*)(b + L.tile_tot);
   return w;
 }
 
@@ -339,6 +347,59 @@ gsff_status gsff_backward(const gsff_gaussians* g, const gsff_camera* cam,
   if (rc != GSFF_OK || !geo) return rc;
   return hip_check(launch_preprocess_bwd(c.g, c.cam, c.st, c.L, c.w, *out, accumulate, c.s),
                    "preprocess_bwd");
+}
+
+static gsff_status backward_l1_impl(const gsff_gaussians* g, const gsff_camera* cam,
+                                    const gsff_settings* st, void* ws, size_t ws_bytes,
+                                    int64_t max_pairs, const float* out_rgb,
+                                    const float* out_depth, const float* out_alpha,
+                                    const float* out_feat, const float* t_rgb,
+                                    const float* t_depth, const float* t_alpha,
+                                    const float* t_feat, const float* weights, float* loss,
+                                    const gsff_grads* out, int32_t accumulate, void* stream,
+                                    bool with_preprocess) {
+  GSFF_PRELUDE
+  if (!out) return fail(GSFF_ERR_INVALID_ARGUMENT, "NULL grads");
+  if (!weights) return fail(GSFF_ERR_INVALID_ARGUMENT, "NULL weights");
+  for (int k = 0; k < 4; ++k)
+    if (!std::isfinite(weights[k])) return fail(GSFF_ERR_INVALID_ARGUMENT, "weights not finite");
+  if ((t_rgb && !out_rgb) || (t_depth && !out_depth) || (t_alpha && !out_alpha) ||
+      (t_feat && !out_feat))
+    return fail(GSFF_ERR_INVALID_ARGUMENT, "target given without the forward output");
+  if (out->feat && g->C == 0) return fail(GSFF_ERR_INVALID_ARGUMENT, "feat grad with C == 0");
+  const bool geo = any_geometry(out);
+  L1Args a{out_rgb, out_depth, out_alpha, out_feat, t_rgb, t_depth, t_alpha, t_feat,
+           (double)weights[0], (double)weights[1], (double)weights[2], (double)weights[3], loss};
+  gsff_status rc = hip_check(launch_composite_bwd_l1(c.g, c.st, c.L, c.w, a, geo, out->feat,
+                                                     accumulate, c.s),
+                             "composite_bwd_l1");
+  if (rc != GSFF_OK || !geo || !with_preprocess) return rc;
+  return hip_check(launch_preprocess_bwd(c.g, c.cam, c.st, c.L, c.w, *out, accumulate, c.s),
+                   "preprocess_bwd");
+}
+
+gsff_status gsff_backward_l1(const gsff_gaussians* g, const gsff_camera* cam,
+                             const gsff_settings* st, void* ws, size_t ws_bytes,
+                             int64_t max_pairs, const float* out_rgb, const float* out_depth,
+                             const float* out_alpha, const float* out_feat, const float* t_rgb,
+                             const float* t_depth, const float* t_alpha, const float* t_feat,
+                             const float* weights, float* loss, const gsff_grads* out,
+                             int32_t accumulate, void* stream) {
+  return backward_l1_impl(g, cam, st, ws, ws_bytes, max_pairs, out_rgb, out_depth, out_alpha,
+                          out_feat, t_rgb, t_depth, t_alpha, t_feat, weights, loss, out,
+                          accumulate, stream, true);
+}
+
+gsff_status gsff_composite_bwd_l1(const gsff_gaussians* g, const gsff_camera* cam,
+                                  const gsff_settings* st, void* ws, size_t ws_bytes,
+                                  int64_t max_pairs, const float* out_rgb, const float* out_depth,
+                                  const float* out_alpha, const float* out_feat,
+                                  const float* t_rgb, const float* t_depth, const float* t_alpha,
+                                  const float* t_feat, const float* weights, float* loss,
+                                  const gsff_grads* out, int32_t accumulate, void* stream) {
+  return backward_l1_impl(g, cam, st, ws, ws_bytes, max_pairs, out_rgb, out_depth, out_alpha,
+                          out_feat, t_rgb, t_depth, t_alpha, t_feat, weights, loss, out,
+                          accumulate, stream, false);
 }
 
 gsff_status gsff_l1_grad(const float* x, const float* y, int64_t n, float scale, float* grad,

@@ -59,14 +59,12 @@ __device__ __forceinline__ uint2 clamp_range(uint2 r, uint32_t max_pairs) {
   return make_uint2(min(r.x, e), e);
 }
 
-// Gaussian id of sorted pair `idx`; returns P (an out-of-range marker) if
-// the stored rank or id is not a valid index, so no gather can leave the
-// record arrays.
-__device__ __forceinline__ uint32_t pair_gid(const WsView& w, uint32_t idx, uint32_t rmask,
+// Gaussian id of pair `idx` (the pair buffer holds ids grouped by tile);
+// returns P (an out-of-range marker) for an id that is not a valid index, so
+// no gather can leave the record arrays.
+__device__ __forceinline__ uint32_t pair_gid(const WsView& w, uint32_t idx, uint32_t,
                                              int64_t P) {
-  const uint32_t rank = w.pkeys_a[idx] & rmask;
-  if (rank >= (uint32_t)P) return (uint32_t)P;
-  const uint32_t gid = w.dids_a[rank];
+  const uint32_t gid = w.pkeys_a[idx];
   return gid < (uint32_t)P ? gid : (uint32_t)P;
 }
 
@@ -320,12 +318,36 @@ constexpr int kBwdStride = 272;     // LDS row stride of the per-pixel products 
 // so each column accumulates its 16 pixels and one DPP row reduction
 // completes the sum.  Geometry terms come only from the colour, depth and
 // opacity upstream; the feature upstream only enters the feature sums.
-template <int CP, bool GEO>
+// Upstream gradient formed inside the adjoint for the L1 losses of the
+// method (Eqs. 5, 8, 11 are weighted sums of L1 terms):
+//   L = sum_k w_k * mean|out_k - target_k|  over the groups rgb, depth, alpha,
+// feature; the per-element gradient is (w_k / numel_k) sign(out - target).
+// A group with a NULL target does not enter the loss.
+struct L1Upstream {
+  const float* out_rgb;
+  const float* out_depth;
+  const float* out_alpha;
+  const float* out_feat;
+  const float* t_rgb;
+  const float* t_depth;
+  const float* t_alpha;
+  const float* t_feat;
+  float s_rgb, s_depth, s_alpha, s_feat;  // w_k / numel_k
+  float* loss;                            // += the loss (may be NULL)
+};
+
+__device__ __forceinline__ float l1_sign(float o, float t, float scale, float& l) {
+  const float d = o - t;
+  l += fabsf(d) * scale;
+  return d > 0.f ? scale : (d < 0.f ? -scale : 0.f);
+}
+
+template <int CP, bool GEO, bool L1>
 __global__ __launch_bounds__(kBlock) void k_composite_bwd(
     DevSettings st, int64_t P, int C, int c0, int W, int H, int tiles_x, int ntiles,
     int rank_bits, uint32_t max_pairs, WsView w, const float* __restrict__ g_rgb,
     const float* __restrict__ g_depth, const float* __restrict__ g_alpha,
-    const float* __restrict__ g_feat, float* __restrict__ d_feat) {
+    const float* __restrict__ g_feat, float* __restrict__ d_feat, L1Upstream l1) {
   constexpr int NL = (GEO ? 4 : 0) + CP;   // linear channels: r, g, b, depth, features
   constexpr int NLs = NL > 0 ? NL : 1;
   constexpr int NM = GEO ? 6 : 0;          // moments of dL/dpower
@@ -339,6 +361,7 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd(
   __shared__ float s_dp[GEO ? kBwdNB : 1][kBwdStride];
   __shared__ float s_gl[NLs][kBlock];
   __shared__ uint32_t s_end;
+  __shared__ float s_loss[kBlock / 64];
   const int tile = xcd_tile(blockIdx.x, ntiles);
   if (tile >= ntiles) return;
   const int tx = tile % tiles_x, ty = tile / tiles_x;
@@ -357,16 +380,27 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd(
   float T = 1.f, Tfin = 1.f;
   uint32_t pend = range.x;
   float gr = 0.f, gg = 0.f, gb = 0.f, gd = 0.f, ga = 0.f;
+  float loss = 0.f;
   if (inside) {
     Tfin = w.pix_T[p];
     T = Tfin;
     pend = w.pix_end[p];
     if (GEO) {
-      gr = g_rgb[p];
-      gg = g_rgb[HW + p];
-      gb = g_rgb[2 * HW + p];
-      gd = g_depth[p];
-      ga = g_alpha[p];
+      if (L1) {
+        if (l1.t_rgb) {
+          gr = l1_sign(l1.out_rgb[p], l1.t_rgb[p], l1.s_rgb, loss);
+          gg = l1_sign(l1.out_rgb[HW + p], l1.t_rgb[HW + p], l1.s_rgb, loss);
+          gb = l1_sign(l1.out_rgb[2 * HW + p], l1.t_rgb[2 * HW + p], l1.s_rgb, loss);
+        }
+        if (l1.t_depth) gd = l1_sign(l1.out_depth[p], l1.t_depth[p], l1.s_depth, loss);
+        if (l1.t_alpha) ga = l1_sign(l1.out_alpha[p], l1.t_alpha[p], l1.s_alpha, loss);
+      } else {
+        gr = g_rgb[p];
+        gg = g_rgb[HW + p];
+        gb = g_rgb[2 * HW + p];
+        gd = g_depth[p];
+        ga = g_alpha[p];
+      }
     }
   }
   if (GEO) {
@@ -376,11 +410,24 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd(
     s_gl[3][tid] = gd;
   }
 #pragma unroll
-  for (int c = 0; c < CP; ++c)
-    s_gl[(GEO ? 4 : 0) + c][tid] =
-        (inside && c < cn) ? g_feat[(int64_t)(c0 + c) * HW + p] : 0.f;
+  for (int c = 0; c < CP; ++c) {
+    float v = 0.f;
+    if (inside && c < cn) {
+      const int64_t q = (int64_t)(c0 + c) * HW + p;
+      v = L1 ? l1_sign(l1.out_feat[q], l1.t_feat[q], l1.s_feat, loss) : g_feat[q];
+    }
+    s_gl[(GEO ? 4 : 0) + c][tid] = v;
+  }
+  if (L1 && l1.loss) {  // uniform: one atomic per workgroup
+    const float v = wave_sum(loss);
+    if ((tid & 63) == 0) s_loss[tid >> 6] = v;
+  }
   if (tid == 0) s_end = range.x;
   __syncthreads();
+  if (L1 && l1.loss && tid == 0) {
+    const float v = (s_loss[0] + s_loss[1]) + (s_loss[2] + s_loss[3]);
+    if (v != 0.f) unsafeAtomicAdd(l1.loss, v);
+  }
   if (inside && pend > range.x) atomicMax(&s_end, pend);
   __syncthreads();
   const uint32_t blk_end = min(s_end, range.y);
@@ -411,7 +458,7 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd(
       if (inside && j < pend) {
         const AlphaEval e = eval_alpha(r0, r1, pxc, pyc, st.alpha_max);
         if (e.alpha >= st.alpha_min) {
-          const float inv = 1.f / (1.f - e.alpha);
+          const float inv = __builtin_amdgcn_rcpf(1.f - e.alpha);  // v_rcp_f32, 1 ulp
           const float Tb = T * inv;  // transmittance in front of this Gaussian
           wv = e.alpha * Tb;
           if constexpr (GEO) {
@@ -513,40 +560,43 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd(
   }
 }
 
-template <int CP, bool GEO>
+template <int CP, bool GEO, bool L1>
 static void launch_bwd_t(const DevSettings& st, const DevGaussians& g, const Layout& L,
                          const WsView& w, int c0, const float* g_rgb, const float* g_depth,
                          const float* g_alpha, const float* g_feat, float* d_feat,
-                         hipStream_t s) {
+                         const L1Upstream& l1, hipStream_t s) {
   const int grid = ((L.ntiles + kNumXcd - 1) / kNumXcd) * kNumXcd;
-  hipLaunchKernelGGL((k_composite_bwd<CP, GEO>), dim3(grid), dim3(kBlock), 0, s, st, g.P, g.C, c0,
-                     L.W, L.H, L.tiles_x, L.ntiles, L.rank_bits, (uint32_t)L.max_pairs, w, g_rgb,
-                     g_depth, g_alpha,
-                     g_feat, d_feat);
+  hipLaunchKernelGGL((k_composite_bwd<CP, GEO, L1>), dim3(grid), dim3(kBlock), 0, s, st, g.P,
+                     g.C, c0, L.W, L.H, L.tiles_x, L.ntiles, L.rank_bits, (uint32_t)L.max_pairs,
+                     w, g_rgb, g_depth, g_alpha, g_feat, d_feat, l1);
 }
 
-template <bool GEO>
+template <bool GEO, bool L1>
 static void launch_bwd_dispatch(int cn, const DevSettings& st, const DevGaussians& g,
                                 const Layout& L, const WsView& w, int c0, const float* g_rgb,
                                 const float* g_depth, const float* g_alpha, const float* g_feat,
-                                float* d_feat, hipStream_t s) {
+                                float* d_feat, const L1Upstream& l1, hipStream_t s) {
   if (cn <= 0)
-    launch_bwd_t<0, GEO>(st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat, d_feat, s);
+    launch_bwd_t<0, GEO, L1>(st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat, d_feat, l1, s);
   else if (cn <= 8)
-    launch_bwd_t<8, GEO>(st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat, d_feat, s);
+    launch_bwd_t<8, GEO, L1>(st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat, d_feat, l1, s);
   else if (cn <= 16)
-    launch_bwd_t<16, GEO>(st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat, d_feat, s);
+    launch_bwd_t<16, GEO, L1>(st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat, d_feat, l1, s);
   else if (cn <= 32)
-    launch_bwd_t<32, GEO>(st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat, d_feat, s);
+    launch_bwd_t<32, GEO, L1>(st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat, d_feat, l1, s);
   else
-    launch_bwd_t<64, GEO>(st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat, d_feat, s);
+    launch_bwd_t<64, GEO, L1>(st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat, d_feat, l1, s);
 }
 
-hipError_t launch_composite_bwd(const DevGaussians& g, const DevSettings& st, const Layout& L,
-                                const WsView& w, const float* g_rgb, const float* g_depth,
-                                const float* g_alpha, const float* g_feat, bool geometry,
-                                float* d_feat, int32_t accumulate, hipStream_t s) {
-  const bool feat_on = st.render_features && g.C > 0 && g_feat != nullptr && d_feat != nullptr;
+// l1 == nullptr: explicit upstream gradients; otherwise the L1 upstream is
+// formed inside the kernel (feature group on iff l1->t_feat is set).
+hipError_t launch_composite_bwd_impl(const DevGaussians& g, const DevSettings& st,
+                                     const Layout& L, const WsView& w, const float* g_rgb,
+                                     const float* g_depth, const float* g_alpha,
+                                     const float* g_feat, bool geometry, float* d_feat,
+                                     int32_t accumulate, const L1Upstream* l1, hipStream_t s) {
+  const bool has_gf = l1 ? (l1->t_feat != nullptr && l1->out_feat != nullptr) : g_feat != nullptr;
+  const bool feat_on = st.render_features && g.C > 0 && has_gf && d_feat != nullptr;
   if (geometry && L.P > 0) {
     const int64_t n = L.P * 10;
     hipLaunchKernelGGL(k_fill_zero<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
@@ -557,36 +607,104 @@ hipError_t launch_composite_bwd(const DevGaussians& g, const DevSettings& st, co
     hipLaunchKernelGGL(k_fill_zero<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                        d_feat, n);
   }
-  if (L.P == 0) return hipGetLastError();
+  L1Upstream none{};
+  const L1Upstream& u = l1 ? *l1 : none;
   const int nchunks = feat_on ? (g.C + GSFF_MAX_CHANNELS_PER_PASS - 1) / GSFF_MAX_CHANNELS_PER_PASS
                               : 1;
   for (int k = 0; k < nchunks; ++k) {
     const int c0 = k * GSFF_MAX_CHANNELS_PER_PASS;
     const int cn = feat_on ? min(GSFF_MAX_CHANNELS_PER_PASS, g.C - c0) : 0;
+    // the geometry chunk also carries the rgb / depth / alpha loss terms
     const bool geo = geometry && k == 0;
     if (!geo && cn == 0) continue;
-    if (geo)
-      launch_bwd_dispatch<true>(cn, st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat, d_feat, s);
-    else
-      launch_bwd_dispatch<false>(cn, st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat, d_feat, s);
+    if (L.P == 0 && !l1) continue;
+    if (l1) {
+      if (geo)
+        launch_bwd_dispatch<true, true>(cn, st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat,
+                                        d_feat, u, s);
+      else
+        launch_bwd_dispatch<false, true>(cn, st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat,
+                                         d_feat, u, s);
+    } else {
+      if (geo)
+        launch_bwd_dispatch<true, false>(cn, st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat,
+                                         d_feat, u, s);
+      else
+        launch_bwd_dispatch<false, false>(cn, st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat,
+                                          d_feat, u, s);
+    }
   }
   return hipGetLastError();
 }
 
+hipError_t launch_composite_bwd(const DevGaussians& g, const DevSettings& st, const Layout& L,
+                                const WsView& w, const float* g_rgb, const float* g_depth,
+                                const float* g_alpha, const float* g_feat, bool geometry,
+                                float* d_feat, int32_t accumulate, hipStream_t s) {
+  return launch_composite_bwd_impl(g, st, L, w, g_rgb, g_depth, g_alpha, g_feat, geometry, d_feat,
+                                   accumulate, nullptr, s);
+}
+
+hipError_t launch_composite_bwd_l1(const DevGaussians& g, const DevSettings& st, const Layout& L,
+                                   const WsView& w, const L1Args& a, bool geometry, float* d_feat,
+                                   int32_t accumulate, hipStream_t s) {
+  const double HW = (double)L.W * L.H;
+  L1Upstream u;
+  u.out_rgb = a.out_rgb;
+  u.out_depth = a.out_depth;
+  u.out_alpha = a.out_alpha;
+  u.out_feat = a.out_feat;
+  u.t_rgb = a.t_rgb;
+  u.t_depth = a.t_depth;
+  u.t_alpha = a.t_alpha;
+  u.t_feat = a.t_feat;
+  u.s_rgb = (float)(a.w_rgb / (3.0 * HW));
+  u.s_depth = (float)(a.w_depth / HW);
+  u.s_alpha = (float)(a.w_alpha / HW);
+  u.s_feat = (float)(g.C > 0 ? a.w_feat / ((double)g.C * HW) : 0.0);
+  u.loss = a.loss;
+  return launch_composite_bwd_impl(g, st, L, w, nullptr, nullptr, nullptr, nullptr, geometry,
+                                   d_feat, accumulate, &u, s);
+}
+
 // ---------------------------------------------------------------- L1 ------
 
+__device__ __forceinline__ float l1_elem(float x, float y, float scale, float& l) {
+  const float d = x - y;
+  l += fabsf(d);
+  return d > 0.f ? scale : (d < 0.f ? -scale : 0.f);
+}
+
+// grad = scale * sign(x - y), loss += scale * sum |x - y|.  VEC: four
+// elements per thread per step (16-byte loads and stores) plus a scalar tail;
+// grid-stride, one loss atomic per workgroup.
+template <bool VEC>
 __global__ __launch_bounds__(256) void k_l1_grad(const float* __restrict__ x,
                                                  const float* __restrict__ y, int64_t n,
                                                  float scale, float* __restrict__ grad,
                                                  float* __restrict__ loss) {
   __shared__ float s_part[4];
   float l = 0.f;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const float d = x[i] - y[i];
-    grad[i] = d > 0.f ? scale : (d < 0.f ? -scale : 0.f);
-    l += fabsf(d);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t done = 0;
+  if (VEC) {
+    const int64_t n4 = n / 4;
+    const float4* x4 = reinterpret_cast<const float4*>(x);
+    const float4* y4 = reinterpret_cast<const float4*>(y);
+    float4* g4 = reinterpret_cast<float4*>(grad);
+    for (int64_t i = t0; i < n4; i += stride) {
+      const float4 a = x4[i], b = y4[i];
+      float4 g;
+      g.x = l1_elem(a.x, b.x, scale, l);
+      g.y = l1_elem(a.y, b.y, scale, l);
+      g.z = l1_elem(a.z, b.z, scale, l);
+      g.w = l1_elem(a.w, b.w, scale, l);
+      g4[i] = g;
+    }
+    done = 4 * n4;
   }
+  for (int64_t i = done + t0; i < n; i += stride) grad[i] = l1_elem(x[i], y[i], scale, l);
   if (!loss) return;  // uniform
   l = wave_sum(l);
   if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = l;
@@ -600,10 +718,15 @@ __global__ __launch_bounds__(256) void k_l1_grad(const float* __restrict__ x,
 hipError_t launch_l1_grad(const float* x, const float* y, int64_t n, float scale, float* grad,
                           float* loss, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  int64_t blocks = (n + 255) / 256;
-  if (blocks > 512) blocks = 512;  // grid-stride: few atomics on the loss scalar
-  hipLaunchKernelGGL(k_l1_grad, dim3((unsigned)blocks), dim3(256), 0, s, x, y, n, scale, grad,
-                     loss);
+  const bool aligned = (((uintptr_t)x | (uintptr_t)y | (uintptr_t)grad) & 15u) == 0;
+  int64_t blocks = (n + 1023) / 1024;
+  if (blocks > 2048) blocks = 2048;  // grid-stride; bounds the loss atomics
+  if (aligned)
+    hipLaunchKernelGGL(k_l1_grad<true>, dim3((unsigned)blocks), dim3(256), 0, s, x, y, n, scale,
+                       grad, loss);
+  else
+    hipLaunchKernelGGL(k_l1_grad<false>, dim3((unsigned)blocks), dim3(256), 0, s, x, y, n, scale,
+                       grad, loss);
   return hipGetLastError();
 }
 

@@ -16,6 +16,8 @@ constexpr int kRadixIpt = 16;              // keys per lane in a radix chunk
 constexpr int kRadixChunk = 64 * kRadixIpt;  // keys per wave chunk
 constexpr int kScanBlock = 1024;           // elements per block in the count scan
 constexpr int kPoseBlock = 256;            // Gaussians per preprocess-adjoint block
+constexpr int kMaxDirectTiles = 4096;      // tile grids binned without a pair sort
+constexpr int kBinBlock = 256;             // depth ranks per direct-binning block
 
 inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
@@ -31,11 +33,12 @@ struct Layout {
   int64_t P = 0, max_pairs = 0;
   int32_t W = 0, H = 0, tiles_x = 0, tiles_y = 0, ntiles = 0;
   int32_t rank_bits = 0, tile_bits = 0;
-  int64_t depth_chunks = 0, pair_chunks = 0, scan_blocks = 0, pose_blocks = 0;
+  bool direct_bin = false;
+  int64_t depth_chunks = 0, pair_chunks = 0, scan_blocks = 0, pose_blocks = 0, bin_blocks = 0;
   uint64_t status = 0, records = 0, rects = 0, dkeys_a = 0, dkeys_b = 0, dids_a = 0,
            dids_b = 0, offsets = 0, pkeys_a = 0, pkeys_b = 0, tile_ranges = 0, pix_T = 0,
            pix_end = 0, grad2d = 0, hist = 0, hist_tot = 0, scan_part = 0, pose_part = 0,
-           total = 0;
+           binhist = 0, tile_tot = 0, total = 0;
 };
 
 // Returns false if the sizes are not representable (key bits, negative sizes).
@@ -61,6 +64,8 @@ struct WsView {
   uint32_t* hist_tot;    // radix digit totals [256]
   uint32_t* scan_part;   // count-scan block partials
   double* pose_part;     // [pose_blocks][6]
+  uint32_t* binhist;     // direct binning: per-tile counts per rank block [ntiles][blocks]
+  uint32_t* tile_tot;    // direct binning: pairs per tile [ntiles]
 };
 
 WsView make_view(void* ws, const Layout& L);
@@ -106,6 +111,18 @@ hipError_t launch_composite_bwd(const DevGaussians& g, const DevSettings& st,
                                 const float* g_depth, const float* g_alpha,
                                 const float* g_feat, bool geometry, float* d_feat,
                                 int32_t accumulate, hipStream_t s);
+// L1-loss upstream (see gsff_backward_l1): forward outputs, targets (NULL =
+// group not in the loss), group weights, and an optional loss accumulator.
+struct L1Args {
+  const float *out_rgb, *out_depth, *out_alpha, *out_feat;
+  const float *t_rgb, *t_depth, *t_alpha, *t_feat;
+  double w_rgb, w_depth, w_alpha, w_feat;
+  float* loss;
+};
+hipError_t launch_composite_bwd_l1(const DevGaussians& g, const DevSettings& st,
+                                   const Layout& L, const WsView& w, const L1Args& a,
+                                   bool geometry, float* d_feat, int32_t accumulate,
+                                   hipStream_t s);
 hipError_t launch_preprocess_bwd(const DevGaussians& g, const DevCamera& cam,
                                  const DevSettings& st, const Layout& L, const WsView& w,
                                  const gsff_grads& out, int32_t accumulate, hipStream_t s);

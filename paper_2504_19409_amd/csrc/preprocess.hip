@@ -205,15 +205,27 @@ __global__ __launch_bounds__(kPoseBlock) void k_preprocess_bwd(DevGaussians g, D
   }
 }
 
-// Sum the per-block pose partials in block order (deterministic).
-__global__ __launch_bounds__(64) void k_pose_final(const double* part, int nblocks, float* pose,
-                                                   int accumulate) {
-  const int lane = threadIdx.x;
+// Sum the per-block pose partials (a separate launch: a last-workgroup
+// reduction would need a device-scope fence in every workgroup, which writes
+// back the L2 of each XCD).  Each thread accumulates whole 6-double records;
+// the block reduction runs in a fixed order, so the result is deterministic.
+__global__ __launch_bounds__(256) void k_pose_final(const double* __restrict__ part, int nblocks,
+                                                    float* pose, int accumulate) {
+  __shared__ double s_red[4][6];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nblocks; b += 256)
+    for (int k = 0; k < 6; ++k) acc[k] += part[b * 6 + k];
   for (int k = 0; k < 6; ++k) {
-    double acc = 0.0;
-    for (int b = lane; b < nblocks; b += 64) acc += part[b * 6 + k];
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    if (lane == 0) pose[k] = accumulate ? pose[k] + (float)acc : (float)acc;
+    double v = acc[k];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) s_red[wv][k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const double v = (s_red[0][threadIdx.x] + s_red[1][threadIdx.x]) +
+                     (s_red[2][threadIdx.x] + s_red[3][threadIdx.x]);
+    pose[threadIdx.x] = accumulate ? pose[threadIdx.x] + (float)v : (float)v;
   }
 }
 
@@ -227,16 +239,12 @@ hipError_t launch_preprocess(const DevGaussians& g, const DevCamera& cam, const 
 hipError_t launch_preprocess_bwd(const DevGaussians& g, const DevCamera& cam,
                                  const DevSettings& st, const Layout& L, const WsView& w,
                                  const gsff_grads& out, int32_t accumulate, hipStream_t s) {
-  if (g.P > 0) {
+  if (g.P > 0)
     hipLaunchKernelGGL(k_preprocess_bwd, dim3((unsigned)L.pose_blocks), dim3(kPoseBlock), 0, s,
                        g, cam, st, w, out, (int)accumulate);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  if (out.pose) {
-    hipLaunchKernelGGL(k_pose_final, dim3(1), dim3(64), 0, s, w.pose_part,
+  if (out.pose)
+    hipLaunchKernelGGL(k_pose_final, dim3(1), dim3(256), 0, s, w.pose_part,
                        (int)(g.P > 0 ? L.pose_blocks : 0), out.pose, (int)accumulate);
-  }
   return hipGetLastError();
 }
 

@@ -1,16 +1,22 @@
-// Depth sort, tile binning and tile sort (Sec. 3.1: the projected Gaussians
-// are sorted by depth and blended front to back, per screen tile).
+// Depth sort, tile binning and per-tile lists (Sec. 3.1: the projected
+// Gaussians are sorted by depth and blended front to back, per screen tile).
 //
 // Order of work:
 //   1. LSD radix sort of the P depth keys (float32 bits of camera z, culled
 //      Gaussians keyed 0xFFFFFFFF), values = Gaussian ids.  Stable, so equal
 //      keys keep index order.
-//   2. Tile counts in depth-rank order, exclusive scan, and emission of one
-//      32-bit pair key (tile << rank_bits | rank) per (Gaussian, tile): the
-//      pair array comes out in global depth order.
-//   3. Stable LSD radix sort of the pair keys on the tile bits only; within a
-//      tile the depth order of step 2 survives.
-//   4. Per-tile [start, end) by binary search in the sorted pair keys.
+//   2. Binning in depth-rank order.  Ranks are cut into blocks of kScanBlock;
+//      every block counts its (Gaussian, tile) pairs per tile in LDS, the
+//      counts are scanned along the blocks for every tile and then across
+//      tiles, which gives every tile its [start, end) and every block its
+//      write cursor inside each tile.  A second pass over the block writes the
+//      Gaussian ids straight into their tiles' segments, wave by wave in rank
+//      order, so every tile's list comes out in depth order without sorting
+//      the pairs.  Needs 16 bytes of LDS per tile (kMaxDirectTiles).
+//   3. Larger tile grids fall back to emitting (tile << rank_bits | rank) keys
+//      in rank order, a stable LSD radix sort on the tile bits, a binary search
+//      for the tile ranges and a final rank -> id conversion.
+// Either way the pair buffer ends up holding Gaussian ids grouped by tile.
 //
 // Radix passes: every wave owns a chunk of kRadixChunk consecutive keys.
 //   hist    : per-chunk digit histogram (LDS atomics) -> hist[digit][chunk]
@@ -199,7 +205,7 @@ hipError_t launch_sort_depth(const Layout& L, const WsView& w, hipStream_t s) {
 }
 
 hipError_t launch_sort_tiles(const Layout& L, const WsView& w, hipStream_t s) {
-  if (L.P == 0 || L.tile_bits == 0 || L.max_pairs == 0) return hipSuccess;
+  if (L.direct_bin || L.P == 0 || L.tile_bits == 0 || L.max_pairs == 0) return hipSuccess;
   const int n1 = (L.tile_bits + 1) / 2, n2 = L.tile_bits - n1;
   hipError_t e = radix_pass(w.pkeys_a, nullptr, w.pkeys_b, nullptr, w.status + 2, 0u,
                             L.rank_bits, n1, (int)L.pair_chunks, (uint32_t)L.max_pairs, w, s);
@@ -308,9 +314,173 @@ __global__ __launch_bounds__(256) void k_emit(WsView w, int64_t P, int tiles_x, 
   }
 }
 
+// ------------------------------------------------------ direct binning ----
+
+// q = j / d for j < 2^16 and 1 <= d < 2^16, from a float reciprocal with
+// an exact one-step correction (d is wave-uniform).
+__device__ __forceinline__ uint32_t udiv_small(uint32_t j, uint32_t d, float rd) {
+  uint32_t q = (uint32_t)((float)j * rd);
+  const uint32_t r = j - q * d;
+  if ((int32_t)r < 0) --q;
+  else if (r >= d) ++q;
+  return q;
+}
+
+// Visit every (rank, tile) pair of the 64 ranks held by this wave's lanes, in
+// rank order; lanes split each rank's tiles.  fn(tile, gid) per pair.
+template <class Fn>
+__device__ __forceinline__ void wave_walk_pairs(const WsView& w, int64_t r, int64_t P,
+                                                int tiles_x, Fn&& fn) {
+  const int lane = threadIdx.x & 63;
+  ushort4 rc = make_ushort4(1, 1, 0, 0);
+  uint32_t gid = 0;
+  if (r < P) {
+    gid = w.dids_a[r];
+    if (gid < (uint32_t)P) rc = w.rects[gid];
+  }
+  const uint32_t cnt = rect_count(rc);
+  const uint32_t x0 = rc.x, y0 = rc.y, wd = (uint32_t)(rc.z - rc.x) + 1u;
+  for (int src = 0; src < 64; ++src) {
+    const uint32_t n = __builtin_amdgcn_readlane(cnt, src);
+    if (n == 0u) continue;  // uniform
+    const uint32_t bx = __builtin_amdgcn_readlane(x0, src);
+    const uint32_t by = __builtin_amdgcn_readlane(y0, src);
+    const uint32_t bw = __builtin_amdgcn_readlane(wd, src);
+    const uint32_t g = __builtin_amdgcn_readlane(gid, src);
+    const float rbw = __builtin_amdgcn_rcpf((float)bw);
+    for (uint32_t j = lane; j < n; j += 64) {
+      const uint32_t q = udiv_small(j, bw, rbw);
+      fn((by + q) * (uint32_t)tiles_x + bx + (j - q * bw), g);
+    }
+  }
+}
+
+// per-block, per-tile pair counts -> binhist[tile][block]
+__global__ __launch_bounds__(256) void k_bin_hist(WsView w, int64_t P, int ntiles, int tiles_x,
+                                                  int nblk) {
+  extern __shared__ uint32_t s_h[];
+  for (int t = threadIdx.x; t < ntiles; t += 256) s_h[t] = 0u;
+  __syncthreads();
+  wave_walk_pairs(w, (int64_t)blockIdx.x * kBinBlock + threadIdx.x, P, tiles_x,
+                  [&](uint32_t t, uint32_t) { atomicAdd(&s_h[t], 1u); });
+  __syncthreads();
+  for (int t = threadIdx.x; t < ntiles; t += 256)
+    w.binhist[(int64_t)t * nblk + blockIdx.x] = s_h[t];
+}
+
+// one wave per tile: exclusive scan of its counts along the blocks
+__global__ __launch_bounds__(256) void k_bin_colscan(WsView w, int ntiles, int nblk) {
+  const int lane = threadIdx.x & 63;
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t >= ntiles) return;  // whole wave
+  uint32_t* col = w.binhist + (int64_t)t * nblk;
+  uint32_t carry = 0;
+  for (int b0 = 0; b0 < nblk; b0 += 64) {
+    const int b = b0 + lane;
+    const uint32_t v = b < nblk ? col[b] : 0u;
+    const uint32_t inc = wave_incl_scan(v, lane);
+    if (b < nblk) col[b] = carry + inc - v;
+    carry += __shfl(inc, 63, 64);
+  }
+  if (lane == 0) w.tile_tot[t] = carry;
+}
+
+// one block: tile ranges from the tile totals, pair count and overflow flag
+__global__ __launch_bounds__(1024) void k_bin_tilescan(WsView w, int ntiles, uint64_t max_pairs) {
+  __shared__ uint64_t s_w[16];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint64_t carry = 0;
+  for (int b = 0; b < ntiles; b += 1024) {
+    const int i = b + threadIdx.x;
+    const uint64_t v = (i < ntiles) ? (uint64_t)w.tile_tot[i] : 0ull;
+    uint64_t inc = v;
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint64_t t = __shfl_up(inc, off, 64);
+      if (lane >= off) inc += t;
+    }
+    if (lane == 63) s_w[wv] = inc;
+    __syncthreads();
+    uint64_t pre = 0, tot = 0;
+    for (int k = 0; k < 16; ++k) {
+      if (k < wv) pre += s_w[k];
+      tot += s_w[k];
+    }
+    __syncthreads();
+    if (i < ntiles) {
+      const uint64_t st = carry + pre + inc - v;
+      const uint64_t en = st + v;
+      const bool fits = en <= max_pairs;
+      w.tile_ranges[i] = fits ? make_uint2((uint32_t)st, (uint32_t)en) : make_uint2(0u, 0u);
+    }
+    carry += tot;
+  }
+  const bool over = carry > max_pairs;
+  if (over)  // the frame renders empty: every range collapses
+    for (int i = threadIdx.x; i < ntiles; i += 1024) w.tile_ranges[i] = make_uint2(0u, 0u);
+  if (threadIdx.x == 0) {
+    if (over) w.status[0] |= GSFF_FLAG_PAIR_OVERFLOW;
+    w.status[1] = (uint32_t)(carry > 0xFFFFFFFFull ? 0xFFFFFFFFull : carry);
+    w.status[2] = over ? 0u : (uint32_t)carry;
+  }
+}
+
+// Stable scatter of Gaussian ids into their tiles' segments.  Wave wv owns
+// the block's ranks [64 wv, 64 wv + 64) and walks them in order; its cursors
+// start after the pairs of lower waves.  LDS atomics of one wave execute in
+// issue order, so the cursor bumps keep rank order without a dependency
+// chain, and the lanes of one rank always touch distinct tiles.
+__global__ __launch_bounds__(256) void k_bin_scatter(WsView w, int64_t P, int ntiles,
+                                                     int tiles_x, int nblk,
+                                                     uint32_t max_pairs) {
+  extern __shared__ uint32_t s_c[];  // [4][ntiles]: per-wave counts, then write cursors
+  if (w.status[2] == 0u) return;     // nothing to write, or overflow (uniform)
+  const int wv = threadIdx.x >> 6;
+  for (int t = threadIdx.x; t < 4 * ntiles; t += 256) s_c[t] = 0u;
+  __syncthreads();
+  const int64_t r = (int64_t)blockIdx.x * kBinBlock + threadIdx.x;
+  uint32_t* cw = s_c + wv * ntiles;
+  wave_walk_pairs(w, r, P, tiles_x, [&](uint32_t t, uint32_t) { atomicAdd(&cw[t], 1u); });
+  __syncthreads();
+  for (int t = threadIdx.x; t < ntiles; t += 256) {
+    uint32_t cur = w.tile_ranges[t].x + w.binhist[(int64_t)t * nblk + blockIdx.x];
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t c = s_c[k * ntiles + t];
+      s_c[k * ntiles + t] = cur;
+      cur += c;
+    }
+  }
+  __syncthreads();
+  wave_walk_pairs(w, r, P, tiles_x, [&](uint32_t t, uint32_t gid) {
+    const uint32_t pos = atomicAdd(&cw[t], 1u);
+    if (pos < max_pairs) w.pkeys_a[pos] = gid;
+  });
+}
+
+// fallback path: sorted (tile | rank) keys -> Gaussian ids, after the ranges
+__global__ __launch_bounds__(256) void k_keys_to_ids(WsView w, uint32_t rmask, int64_t P,
+                                                     uint32_t max_pairs) {
+  const uint32_t n = min(w.status[2], max_pairs);
+  for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const uint32_t r = w.pkeys_a[i] & rmask;
+    w.pkeys_a[i] = (r < (uint32_t)P) ? w.dids_a[r] : (uint32_t)P;
+  }
+}
+
 hipError_t launch_bin(const Layout& L, const WsView& w, hipStream_t s) {
   if (L.P == 0) {
     return hipSuccess;  // status was zeroed by the preprocess kernel
+  }
+  if (L.direct_bin) {
+    const size_t lds_h = 4ull * L.ntiles, lds_c = 16ull * L.ntiles;
+    hipLaunchKernelGGL(k_bin_hist, dim3((unsigned)L.bin_blocks), dim3(256), lds_h, s, w, L.P,
+                       L.ntiles, L.tiles_x, (int)L.bin_blocks);
+    hipLaunchKernelGGL(k_bin_colscan, dim3((unsigned)((L.ntiles + 3) / 4)), dim3(256), 0, s, w,
+                       L.ntiles, (int)L.bin_blocks);
+    hipLaunchKernelGGL(k_bin_tilescan, dim3(1), dim3(1024), 0, s, w, L.ntiles,
+                       (uint64_t)L.max_pairs);
+    hipLaunchKernelGGL(k_bin_scatter, dim3((unsigned)L.bin_blocks), dim3(256), lds_c, s, w, L.P,
+                       L.ntiles, L.tiles_x, (int)L.bin_blocks, (uint32_t)L.max_pairs);
+    return hipGetLastError();
   }
   hipLaunchKernelGGL(k_count_reduce, dim3((unsigned)L.scan_blocks), dim3(256), 0, s, w, L.P);
   hipLaunchKernelGGL(k_count_top, dim3(1), dim3(1024), 0, s, w, (int)L.scan_blocks,
@@ -345,8 +515,16 @@ __global__ __launch_bounds__(256) void k_tile_ranges(WsView w, int ntiles, int r
 }
 
 hipError_t launch_tile_ranges(const Layout& L, const WsView& w, hipStream_t s) {
+  if (L.direct_bin && L.P > 0) return hipSuccess;  // ranges came with the binning
   hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)((L.ntiles + 255) / 256)), dim3(256), 0, s, w,
                      L.ntiles, L.rank_bits, (uint32_t)L.max_pairs);
+  if (L.P > 0 && L.max_pairs > 0) {
+    const uint32_t rmask = (L.rank_bits >= 32) ? 0xFFFFFFFFu : ((1u << L.rank_bits) - 1u);
+    int64_t blocks = (L.max_pairs + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_keys_to_ids, dim3((unsigned)blocks), dim3(256), 0, s, w, rmask, L.P,
+                       (uint32_t)L.max_pairs);
+  }
   return hipGetLastError();
 }
 

@@ -165,6 +165,32 @@ class Frame:
                     "gsff_backward")
         return grads
 
+    def backward_l1(self, outs, targets, weights, grads, loss=None, accumulate=False):
+        """Backward of sum_k w_k mean|out_k - target_k| over (rgb, depth, alpha,
+        feat); a None target leaves its group out.  ``outs`` are this frame's
+        forward outputs (float32)."""
+        gs = self._grads_struct(grads)
+        w = (ctypes.c_float * 4)(*[float(x) for x in weights])
+        o = [(None if t is None else x) for x, t in zip(outs, targets)]
+        L = _capi.load()
+        _capi.check(L.gsff_backward_l1(*self._head(), *[_ptr(x) for x in o],
+                                       *[_ptr(t) for t in targets], w, _ptr(loss),
+                                       ctypes.byref(gs), int(accumulate), _stream()),
+                    "gsff_backward_l1")
+        return grads
+
+    def composite_bwd_l1(self, outs, targets, weights, grads, loss=None, accumulate=False):
+        """Only the compositing adjoint of backward_l1 (the preprocess adjoint
+        follows with preprocess_bwd); used to time the stages separately."""
+        gs = self._grads_struct(grads)
+        w = (ctypes.c_float * 4)(*[float(x) for x in weights])
+        o = [(None if t is None else x) for x, t in zip(outs, targets)]
+        L = _capi.load()
+        _capi.check(L.gsff_composite_bwd_l1(*self._head(), *[_ptr(x) for x in o],
+                                            *[_ptr(t) for t in targets], w, _ptr(loss),
+                                            ctypes.byref(gs), int(accumulate), _stream()),
+                    "gsff_composite_bwd_l1")
+
     def composite_bwd(self, g_rgb, g_depth, g_alpha, g_feat, grads, accumulate=False):
         gs = self._grads_struct(grads)
         L = _capi.load()

@@ -57,6 +57,12 @@ def _run(sc, orc, settings=None, feat_dtype=None, max_pairs=None, bwd=True, out_
     fr, d = H.make_frame(sc, torch, settings=settings, max_pairs=max_pairs, feat_dtype=feat_dtype)
     odt = out_feat_dtype or torch.float32
     outs = fr.forward(out_feat_dtype=odt)
+    flags, npairs = fr.read_status()
+    if flags:  # pair capacity too small for this scene: size it from the reported count
+        fr, d = H.make_frame(sc, torch, settings=settings, max_pairs=npairs + 1024,
+                             feat_dtype=feat_dtype)
+        outs = fr.forward(out_feat_dtype=odt)
+        assert fr.read_status()[0] == 0
     res = dict(zip(["rgb", "depth", "alpha", "feat"], [o.float().cpu().numpy() for o in outs]))
     res["frame"] = fr
     if bwd:
@@ -171,14 +177,14 @@ def test_stage_depth_sort_and_tile_lists(orc, kind):
     pk = fr.ws_view("pair_keys", torch.int32, npairs).cpu().numpy().view(np.uint32)
     rng_ = fr.ws_view("tile_ranges", torch.int32, 2 * lay.tiles_x * lay.tiles_y)
     rng_ = rng_.cpu().numpy().view(np.uint32).reshape(-1, 2)
-    rmask = (1 << lay.rank_bits) - 1
     counts, oids = orc.tile_lists(p, c, 16)
     starts = np.concatenate([[0], np.cumsum(counts)])
     extra = 0
+    # tiles partition the pair buffer in tile order
+    assert rng_[0, 0] == 0 and np.all(rng_[1:, 0] == rng_[:-1, 1])
     for t in range(len(counts)):
         a, b = rng_[t]
-        gl = ids[(pk[a:b] & rmask)].astype(np.int64)
-        assert np.all((pk[a:b] >> lay.rank_bits) == t)
+        gl = pk[a:b].astype(np.int64)  # Gaussian ids, depth order
         ol = oids[starts[t]:starts[t + 1]].astype(np.int64)
         inset = np.isin(gl, ol)
         assert np.array_equal(gl[inset], ol), t
@@ -195,6 +201,19 @@ def test_stage_depth_sort_and_tile_lists(orc, kind):
                                     ("dense", 8), ("tiny", 80)])
 def test_forward_backward_parity(orc, kind, C):
     sc = _scene(kind, C=C)
+    res = _run(sc, orc)
+    o = _oracle(sc, orc, ups=res["ups"])
+    _check_forward(res, o)
+    _check_backward(res, o)
+
+
+def test_fallback_binning_large_tile_grid(orc):
+    """More than 4096 tiles: (tile, rank) keys are radix-sorted instead of the
+    direct per-tile scatter; results must not change."""
+    sc = sg.make_scene(3000, 1040, 1040, 800.0, 800.0, 520.0, 520.0, 8, seed=21)
+    sc.log_scales += 0.5
+    fr, _ = H.make_frame(sc, torch)
+    assert fr.layout.tiles_x * fr.layout.tiles_y > 4096
     res = _run(sc, orc)
     o = _oracle(sc, orc, ups=res["ups"])
     _check_forward(res, o)
@@ -403,3 +422,63 @@ def test_autograd_function(orc):
     for k, t in leaves.items():
         assert H.rel_l2(t.grad.cpu().numpy(), ob[k]) <= H.TOL_GRAD, k
     assert H.rel_l2(tangent.grad.cpu().numpy(), ob["pose"]) <= H.TOL_GRAD
+
+
+# ------------------------------------------------------- fused L1 adjoint ----
+
+@pytest.mark.parametrize("kind,C,weights", [("tiny", 16, (1.0, 1.0, 0.0, 1.0)),
+                                            ("ragged", 5, (0.7, 0.3, 0.2, 2.0)),
+                                            ("tiny", 80, (1.0, 0.5, 0.0, 1.0))])
+def test_backward_l1_fused_upstream(orc, kind, C, weights):
+    """gsff_backward_l1 forms (w_k / numel_k) sign(out - target) inside the
+    adjoint; the oracle gets that same upstream explicitly."""
+    sc = _scene(kind, C=C)
+    fr, _ = H.make_frame(sc, torch)
+    outs = fr.forward()
+    W, Hh = sc.camera.width, sc.camera.height
+    rng = np.random.default_rng(17)
+    t_rgb, t_depth, t_feat = sg.make_targets(rng, W, Hh, C)
+    t_alpha = rng.random((Hh, W)).astype(np.float32)
+    targets_np = [t_rgb, t_depth, t_alpha, t_feat]
+    targets = [torch.from_numpy(t).cuda() for t in targets_np]
+    if weights[2] == 0.0:
+        targets[2] = None
+    loss = torch.zeros(1, device="cuda")
+    grads = fr.make_grads()
+    fr.backward_l1(outs, targets, weights, grads, loss)
+    torch.cuda.synchronize()
+    o = [x.cpu().numpy().astype(np.float64) for x in outs]
+    ups, ref_loss = [], 0.0
+    for k, (x, t) in enumerate(zip(o, targets_np)):
+        if targets[k] is None or weights[k] == 0.0:
+            ups.append(np.zeros_like(x))
+            continue
+        scale = weights[k] / x.size
+        ups.append(scale * np.sign(x - t))
+        ref_loss += scale * np.abs(x - t).sum()
+    assert loss.item() == pytest.approx(ref_loss, rel=2e-5)
+    p, c = orc.scene_dicts(sc)
+    ob = orc.backward(p, c, dict(g_rgb=ups[0], g_depth=ups[1], g_alpha=ups[2], g_feat=ups[3]))
+    for k in GRAD_KEYS:
+        assert H.rel_l2(grads[k].cpu().numpy(), ob[k]) <= H.TOL_GRAD, k
+
+
+def test_backward_l1_feature_only(orc):
+    sc = _scene("tiny", C=16)
+    fr, _ = H.make_frame(sc, torch)
+    outs = fr.forward()
+    rng = np.random.default_rng(19)
+    _, _, t_feat = sg.make_targets(rng, sc.camera.width, sc.camera.height, 16)
+    tf = torch.from_numpy(t_feat).cuda()
+    grads = {"feat": torch.empty((sc.P, 16), device="cuda")}
+    loss = torch.zeros(1, device="cuda")
+    fr.backward_l1(outs, [None, None, None, tf], (0.0, 0.0, 0.0, 1.0), grads, loss)
+    torch.cuda.synchronize()
+    of = outs[3].cpu().numpy().astype(np.float64)
+    up = np.sign(of - t_feat) / of.size
+    p, c = orc.scene_dicts(sc)
+    z = np.zeros((sc.camera.height, sc.camera.width))
+    ob = orc.backward(p, c, dict(g_rgb=np.zeros((3,) + z.shape), g_depth=z, g_alpha=z,
+                                 g_feat=up))
+    assert H.rel_l2(grads["feat"].cpu().numpy(), ob["feat"]) <= H.TOL_GRAD
+    assert loss.item() == pytest.approx(np.abs(of - t_feat).mean(), rel=2e-5)
