@@ -30,7 +30,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
-FP32_VALU_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, TFLOP/s (packed FMA)
+# VALU issue peak from the unit counts: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# lane-instructions ("slots") per second = 78.6 TFLOP/s of non-packed FP32 FMA
+# (packed FP32 is disabled on these machines).
+VALU_PEAK_TSLOTS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 STAGES = ["preprocess", "sort_depth", "bin", "sort_tiles", "tile_ranges", "composite_fwd",
           "composite_bwd_l1", "preprocess_bwd"]
@@ -259,16 +262,17 @@ def roofline_for(stage, ms, wc, sz):
     P, C, HW, M = sz["P"], sz["C"], sz["HW"], sz["n_pairs"]
     sec = ms * 1e-3
     if stage in ("composite_fwd", "composite_bwd_l1"):
-        # FP32 VALU work: flops per alpha evaluation (evaluations up to each
-        # pixel's stop) plus per contributing pair
+        # VALU slots the method needs (exp / rcp count 4): 15 per alpha
+        # evaluation; per contributing pair 9 + C in the forward, 22 adjoint +
+        # (10 + C) reduction in the backward
         if stage == "composite_fwd":
-            flops = wc["evals"] * 15 + wc["contribs"] * (2 * (4 + C) + 4)
+            slots = wc["evals"] * 15 + wc["contribs"] * (9 + C)
         else:
-            flops = wc["evals"] * 15 + wc["contribs"] * (60 + 2 * C)
-        achieved = flops / sec / 1e12
-        return {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VALU_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / FP32_VALU_PEAK_TFLOPS, 4),
-                "traffic": None, "stage": stage, "work_flops": flops}
+            slots = wc["evals"] * 15 + wc["contribs"] * (22 + 10 + C)
+        achieved = slots / sec / 1e12
+        return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TSLOTS, 2),
+                "unit": "Tslot/s", "frac": round(achieved / VALU_PEAK_TSLOTS, 4),
+                "traffic": None, "stage": stage, "work_slots": int(slots)}
     bytes_ = {
         "preprocess": P * (44 + 12) + P * (48 + 8 + 8),
         "sort_depth": 4 * P * 8 * 3,

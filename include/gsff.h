@@ -252,6 +252,36 @@ gsff_status gsff_preprocess_bwd(const gsff_gaussians* g, const gsff_camera* cam,
                                 int64_t max_pairs, const gsff_grads* out,
                                 int32_t accumulate, void* stream);
 
+/* ---- learned 1x1 feature decoder (the lift o(.) of Eq. 11) ------------------
+ * Y = GELU(X W1 + b1) W2 + b2 per pixel, GELU in its tanh form
+ * 0.5 z (1 + tanh(sqrt(2/pi) (z + 0.044715 z^3))), both products on BF16
+ * matrix cores with FP32 accumulation; X, W1, W2 and the hidden activations
+ * are rounded to BF16 (round to nearest even), everything else is FP32.
+ * Maps are planar: X bf16 [16, n_px] (the rasterizer's 16-channel latent
+ * output), Y / targets [512, n_px].  Weights are FP32 masters, row-major
+ * W1 [16, 128], b1 [128], W2 [128, 512], b2 [512]; the library makes the BF16
+ * copies in the decoder workspace.  Device pointers; ws 256-byte aligned. */
+
+/* Decoder workspace bytes for n_px pixels (host only). */
+gsff_status gsff_decoder_workspace_size(int64_t n_px, size_t* bytes);
+
+/* Inference: Y [512, n_px] in y_dtype (F32 or BF16). */
+gsff_status gsff_decoder_forward(const void* X, const float* W1, const float* b1,
+                                 const float* W2, const float* b2, void* Y, int32_t y_dtype,
+                                 int64_t n_px, void* ws, size_t ws_bytes, void* stream);
+
+/* One fused training step of L = scale * sum |Y - T| (T bf16 [512, n_px]):
+ * forward, L1, and the backward to the latent map and the weights.
+ * loss (device, may be NULL) += L; dX f32 [16, n_px] (feed it to the
+ * rasterizer's feature-only backward as the feature upstream); dW1 [16,128],
+ * db1 [128], dW2 [128,512], db2 [512] f32 are overwritten.  Gradients with
+ * respect to the FP32 master weights pass straight through the BF16 rounding. */
+gsff_status gsff_decoder_train_step(const void* X, const float* W1, const float* b1,
+                                    const float* W2, const float* b2, const void* T,
+                                    int64_t n_px, float scale, float* loss, float* dX,
+                                    float* dW1, float* db1, float* dW2, float* db2, void* ws,
+                                    size_t ws_bytes, void* stream);
+
 /* L1 loss of one output group (the tracking / mapping / semantic losses,
  * Eqs. 5, 8 and 11, are weighted L1 terms): grad[i] = scale * sign(x[i] - y[i])
  * (0 where equal) and, if loss != NULL, *loss += scale * sum |x - y| (FP32

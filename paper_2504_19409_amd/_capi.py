@@ -84,10 +84,9 @@ SIGNATURES = {
     "gsff_l1_grad": (_i32, [_vp, _vp, _i64, _f32, _vp, _vp, _vp]),
     "gsff_read_status": (_i32, [_vp, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(_i64),
                                 _vp]),
-    "gsff_decoder_forward": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _i32, _i64, _vp]),
-    "gsff_decoder_train_step": (_i32, [_vp] * 6 + [_i64, _f32, _vp, _vp, _vp, _vp, _vp, _vp,
-                                                   _vp, _sz, _vp]),
     "gsff_decoder_workspace_size": (_i32, [_i64, ctypes.POINTER(_sz)]),
+    "gsff_decoder_forward": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _i32, _i64, _vp, _sz, _vp]),
+    "gsff_decoder_train_step": (_i32, [_vp] * 6 + [_i64, _f32] + [_vp] * 7 + [_sz, _vp]),
 }
 
 _lib = None

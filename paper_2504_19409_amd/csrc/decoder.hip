@@ -1,0 +1,471 @@
+// Learned 1x1 feature decoder on BF16 matrix cores (gfx950 MFMA).
+//
+// The paper supervises the rendered N-channel feature map against 512-channel
+// foundation-model features through a lift o(.) with an L1 loss (Eq. 11).
+// Here o(.) is a per-pixel MLP  Y = GELU(X W1 + b1) W2 + b2  with
+// X: 16 latent channels, 128 hidden units, 512 outputs, GELU in its tanh form.
+// All maps are planar [channels, pixels], the layout of the rasterizer's
+// feature output, so the decoder reads the rendered latent map as is.
+//
+// MFMA v_mfma_f32_32x32x16_bf16 (lane l, g = l / 32, i = l % 32):
+//   A[i][8g + t], B[8g + t][i] for t = 0..7 (eight bf16 per lane),
+//   D: acc[r] = D[8 (r/4) + 4g + r%4][i].
+// Every product is computed transposed -- pixels along N -- so a lane always
+// holds one pixel.  The D registers of one product then serve directly as
+// the B operand of the next one if the reduction index is visited in the
+// order the registers hold it: K-step s of a dimension split in 32-blocks
+// covers, for k-slot (g, t), index
+//   pi(s, g, t) = 32 (s/2) + 16 (s%2) + 8 (t/4) + 4g + t%4.
+// The matching A operands are bf16 weight copies stored in that permuted
+// order (k_dec_prepare), one 16-byte load per lane and step.
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include "gsff_internal.h"
+
+namespace gsff {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kLat = 16, kHid = 128, kOut = 512;
+constexpr int kWgradGroups = 128;     // split-K workgroups of the weight-gradient GEMMs
+constexpr int kWgradWaves = 8;
+
+__host__ __device__ inline int dec_pi(int s, int g, int t) {
+  return 32 * (s / 2) + 16 * (s % 2) + 8 * (t / 4) + 4 * g + (t % 4);
+}
+
+// ---- decoder workspace layout (bytes, 256-aligned) ----
+struct DecLayout {
+  int64_t npx = 0, npad = 0, nblk = 0;
+  uint64_t w1t = 0, w1p = 0, w2tp = 0, w2p = 0, xbuf = 0, hbuf = 0, dzbuf = 0, dys = 0,
+           part2 = 0, part1 = 0, total = 0;
+};
+
+static DecLayout dec_layout(int64_t npx) {
+  DecLayout L;
+  L.npx = npx;
+  L.nblk = (npx + 31) / 32;
+  L.npad = L.nblk * 32;
+  uint64_t o = 0;
+  auto take = [&](uint64_t b) {
+    const uint64_t at = o;
+    o = align_up(o + b, 256);
+    return at;
+  };
+  L.w1t = take(2ull * kHid * kLat);
+  L.w1p = take(2ull * 32 * 8 * 16);
+  L.w2tp = take(2ull * kOut * 8 * 16);
+  L.w2p = take(2ull * kHid * 32 * 16);
+  L.xbuf = take(2ull * kLat * L.npad);
+  L.hbuf = take(2ull * kHid * L.npad);
+  L.dzbuf = take(2ull * kHid * L.npad);
+  L.dys = take(1ull * kOut * L.npad);
+  L.part2 = take(4ull * kWgradGroups * (kHid * kOut + kOut));
+  L.part1 = take(4ull * kWgradGroups * (32 * kHid + kHid));
+  L.total = o;
+  return L;
+}
+
+__device__ __forceinline__ float gelu_f(float z) {
+  const float u = 0.7978845608028654f * (z + 0.044715f * z * z * z);
+  const float t = 1.f - 2.f / (__expf(2.f * u) + 1.f);  // tanh(u)
+  return 0.5f * z * (1.f + t);
+}
+
+__device__ __forceinline__ float gelu_grad_f(float z) {
+  const float u = 0.7978845608028654f * (z + 0.044715f * z * z * z);
+  const float t = 1.f - 2.f / (__expf(2.f * u) + 1.f);
+  const float du = 0.7978845608028654f * (1.f + 3.f * 0.044715f * z * z);
+  return 0.5f * (1.f + t) + 0.5f * z * (1.f - t * t) * du;
+}
+
+__device__ __forceinline__ bf16x8 load8(const __bf16* p) {
+  return *reinterpret_cast<const bf16x8*>(p);
+}
+
+// --------------------------------------------------------- weight copies ----
+
+// bf16 copies of the FP32 master weights in the operand orders above:
+//   w1t [128 hid][16 k]           A of layer 1 (natural k order)
+//   w1p [32 rows][8 s][2 g][8 t]  A of dX^T = W1 dZ^T (rows >= 16 zero)
+//   w2tp[512 ch][8 s][2 g][8 t]   A of Y^T = W2^T H^T
+//   w2p [128 hid][32 s][2 g][8 t] A of dH^T = W2 dY^T
+__global__ __launch_bounds__(256) void k_dec_prepare(const float* __restrict__ W1,
+                                                     const float* __restrict__ W2,
+                                                     __bf16* w1t, __bf16* w1p, __bf16* w2tp,
+                                                     __bf16* w2p) {
+  const int n1 = kHid * kLat, n2 = 32 * 8 * 16, n3 = kOut * 8 * 16, n4 = kHid * 32 * 16;
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < n1 + n2 + n3 + n4; e += gridDim.x * 256) {
+    if (e < n1) {
+      const int h = e / kLat, k = e % kLat;
+      w1t[e] = (__bf16)W1[k * kHid + h];
+    } else if (e < n1 + n2) {
+      const int q = e - n1;
+      const int row = q / 128, s = (q / 16) % 8, g = (q / 8) % 2, t = q % 8;
+      w1p[q] = row < kLat ? (__bf16)W1[row * kHid + dec_pi(s, g, t)] : (__bf16)0.f;
+    } else if (e < n1 + n2 + n3) {
+      const int q = e - n1 - n2;
+      const int ch = q / 128, s = (q / 16) % 8, g = (q / 8) % 2, t = q % 8;
+      w2tp[q] = (__bf16)W2[dec_pi(s, g, t) * kOut + ch];
+    } else {
+      const int q = e - n1 - n2 - n3;
+      const int h = q / 512, s = (q / 16) % 32, g = (q / 8) % 2, t = q % 8;
+      w2p[q] = (__bf16)W2[h * kOut + dec_pi(s, g, t)];
+    }
+  }
+}
+
+// The eight bf16 of K-step s (within a 32-block) from a D register block.
+__device__ __forceinline__ bf16x8 regs_to_b(const f32x16& d, int half) {
+  bf16x8 b;
+#pragma unroll
+  for (int t = 0; t < 8; ++t) b[t] = (__bf16)d[8 * half + t];
+  return b;
+}
+
+// ------------------------------------------------------------- forward -----
+
+// One wave decodes NPB blocks of 32 pixels; the weight fragments of each
+// K-step are loaded once per wave and used for all NPB blocks.
+template <int NPB, typename OT>
+__global__ __launch_bounds__(256) void k_dec_forward(const __bf16* __restrict__ X,
+                                                     const float* __restrict__ b1,
+                                                     const float* __restrict__ b2,
+                                                     const __bf16* __restrict__ w1t,
+                                                     const __bf16* __restrict__ w2tp,
+                                                     OT* __restrict__ Y, int64_t npx) {
+  const int lane = threadIdx.x & 63, g = lane >> 5, i = lane & 31;
+  const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  bf16x8 hf[NPB][8];
+  int64_t px[NPB];
+  bool ok[NPB];
+#pragma unroll
+  for (int q = 0; q < NPB; ++q) {
+    px[q] = (wave * NPB + q) * 32 + i;
+    ok[q] = px[q] < npx;
+    bf16x8 xb;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) xb[t] = ok[q] ? X[(int64_t)(8 * g + t) * npx + px[q]] : (__bf16)0.f;
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      f32x16 z = {};
+      z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load8(w1t + (32 * h + i) * kLat + 8 * g), xb, z,
+                                                  0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) z[r] = gelu_f(z[r] + b1[32 * h + 8 * (r / 4) + 4 * g + r % 4]);
+      hf[q][2 * h] = regs_to_b(z, 0);
+      hf[q][2 * h + 1] = regs_to_b(z, 1);
+    }
+  }
+  for (int c = 0; c < kOut / 32; ++c) {
+    f32x16 acc[NPB];
+#pragma unroll
+    for (int q = 0; q < NPB; ++q) acc[q] = f32x16{};
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const bf16x8 a = load8(w2tp + ((32 * c + i) * 8 + s) * 16 + 8 * g);
+#pragma unroll
+      for (int q = 0; q < NPB; ++q)
+        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, hf[q][s], acc[q], 0, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < NPB; ++q) {
+      if (!ok[q]) continue;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int ch = 32 * c + 8 * (r / 4) + 4 * g + r % 4;
+        Y[(int64_t)ch * npx + px[q]] = (OT)(acc[q][r] + b2[ch]);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------- train step -----
+
+// Fused forward, L1 against the target and the backward to the latent:
+// per 32-pixel wave, Z, H and Y by MFMA; dY = sign(Y - T) (its sign is kept
+// in int8 for the weight gradients, the scale applied to FP32 results);
+// dH^T = W2 dY^T accumulated over the 16 output blocks as they are produced;
+// dZ = scale dH GELU'(Z); dX^T = W1 dZ^T.  H and dZ are stored in bf16 for
+// the weight-gradient GEMMs.  Pixels beyond npx contribute zeros.
+__global__ __launch_bounds__(256) void k_dec_train(
+    const __bf16* __restrict__ X, const float* __restrict__ b1, const float* __restrict__ b2,
+    const __bf16* __restrict__ T, const __bf16* __restrict__ w1t, const __bf16* __restrict__ w1p,
+    const __bf16* __restrict__ w2tp, const __bf16* __restrict__ w2p, __bf16* __restrict__ xbuf,
+    __bf16* __restrict__ hbuf, __bf16* __restrict__ dzbuf, int8_t* __restrict__ dys,
+    float* __restrict__ dX, float* loss, float scale, int64_t npx, int64_t npad) {
+  __shared__ float s_loss[4];
+  const int lane = threadIdx.x & 63, g = lane >> 5, i = lane & 31;
+  const int64_t px = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 32 + i;
+  const bool ok = px < npx;
+  const bool in_pad = px < npad;
+  bf16x8 xb;
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    xb[t] = ok ? X[(int64_t)(8 * g + t) * npx + px] : (__bf16)0.f;
+    if (in_pad) xbuf[(int64_t)(8 * g + t) * npad + px] = xb[t];  // zero-padded copy for dW1
+  }
+  f32x16 z[4];
+  bf16x8 hf[8];
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    z[h] = f32x16{};
+    z[h] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load8(w1t + (32 * h + i) * kLat + 8 * g), xb,
+                                                   z[h], 0, 0, 0);
+    f32x16 hv;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int hid = 32 * h + 8 * (r / 4) + 4 * g + r % 4;
+      z[h][r] += b1[hid];
+      hv[r] = ok ? gelu_f(z[h][r]) : 0.f;
+      if (in_pad) hbuf[(int64_t)hid * npad + px] = (__bf16)hv[r];
+    }
+    hf[2 * h] = regs_to_b(hv, 0);
+    hf[2 * h + 1] = regs_to_b(hv, 1);
+  }
+  f32x16 dh[4];
+#pragma unroll
+  for (int h = 0; h < 4; ++h) dh[h] = f32x16{};
+  float lsum = 0.f;
+  for (int c = 0; c < kOut / 32; ++c) {
+    f32x16 acc = {};
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load8(w2tp + ((32 * c + i) * 8 + s) * 16 + 8 * g),
+                                                    hf[s], acc, 0, 0, 0);
+    f32x16 sg;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int ch = 32 * c + 8 * (r / 4) + 4 * g + r % 4;
+      float sv = 0.f;
+      if (ok) {
+        const float d = acc[r] + b2[ch] - (float)T[(int64_t)ch * npx + px];
+        lsum += fabsf(d);
+        sv = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
+      }
+      sg[r] = sv;
+      if (in_pad) dys[(int64_t)ch * npad + px] = (int8_t)sv;
+    }
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const bf16x8 b = regs_to_b(sg, e);
+#pragma unroll
+      for (int h = 0; h < 4; ++h)
+        dh[h] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+            load8(w2p + ((32 * h + i) * 32 + 2 * c + e) * 16 + 8 * g), b, dh[h], 0, 0, 0);
+    }
+  }
+  bf16x8 dzf[8];
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    f32x16 dz;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int hid = 32 * h + 8 * (r / 4) + 4 * g + r % 4;
+      dz[r] = ok ? scale * dh[h][r] * gelu_grad_f(z[h][r]) : 0.f;
+      if (in_pad) dzbuf[(int64_t)hid * npad + px] = (__bf16)dz[r];
+    }
+    dzf[2 * h] = regs_to_b(dz, 0);
+    dzf[2 * h + 1] = regs_to_b(dz, 1);
+  }
+  f32x16 dx = {};
+#pragma unroll
+  for (int s = 0; s < 8; ++s)
+    dx = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load8(w1p + (i * 8 + s) * 16 + 8 * g), dzf[s], dx,
+                                                 0, 0, 0);
+  if (ok) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {  // rows 8(r/4) + 4g + r%4 < 16
+      const int k = 8 * (r / 4) + 4 * g + r % 4;
+      dX[(int64_t)k * npx + px] = dx[r];
+    }
+  }
+  if (loss) {
+    float v = lsum;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) s_loss[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const float t = (s_loss[0] + s_loss[1]) + (s_loss[2] + s_loss[3]);
+      if (t != 0.f) unsafeAtomicAdd(loss, t * scale);
+    }
+  }
+}
+
+// -------------------------------------------------- weight-gradient GEMM ----
+
+// part[wg][m][n] = sum over this workgroup's pixel range of A[m][k] B[n][k]
+// and part[wg][M*N + n] = sum_k B[n][k].  A: bf16 [rows >= 32 MB][ld], rows
+// >= m_valid read as zero; B: bf16 or int8 [N][ld].  Output blocks (mb, nb)
+// are dealt round-robin to the 8 waves.
+__device__ __forceinline__ bf16x8 load_b8(const __bf16* p) { return load8(p); }
+__device__ __forceinline__ bf16x8 load_b8(const int8_t* p) {
+  const int2 v = *reinterpret_cast<const int2*>(p);
+  bf16x8 b;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    b[t] = (__bf16)(float)(int8_t)((v.x >> (8 * t)) & 0xFF);
+    b[4 + t] = (__bf16)(float)(int8_t)((v.y >> (8 * t)) & 0xFF);
+  }
+  return b;
+}
+
+template <typename BT, int MAXB>
+__global__ __launch_bounds__(64 * kWgradWaves) void k_dec_wgrad(
+    const __bf16* __restrict__ A, int m_valid, int MB, const BT* __restrict__ B, int NB,
+    int64_t ld, int64_t kchunk, float* __restrict__ part) {
+  const int lane = threadIdx.x & 63, g = lane >> 5, i = lane & 31;
+  const int wv = threadIdx.x >> 6;
+  const int nblocks = MB * NB;
+  const int M = 32 * MB, N = 32 * NB;
+  const int64_t k0 = (int64_t)blockIdx.x * kchunk;
+  const int64_t k1 = min(k0 + kchunk, ld);
+  f32x16 acc[MAXB];
+  float bsum[MAXB];
+#pragma unroll
+  for (int j = 0; j < MAXB; ++j) {
+    acc[j] = f32x16{};
+    bsum[j] = 0.f;
+  }
+  for (int64_t k = k0; k < k1; k += 16) {
+#pragma unroll
+    for (int j = 0; j < MAXB; ++j) {
+      const int b = wv + kWgradWaves * j;
+      if (b >= nblocks) break;
+      const int mb = b / NB, nb = b % NB;
+      const int row = 32 * mb + i;
+      const bf16x8 a = row < m_valid ? load8(A + (int64_t)row * ld + k + 8 * g) : bf16x8{};
+      const bf16x8 bb = load_b8(B + (int64_t)(32 * nb + i) * ld + k + 8 * g);
+      acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb, acc[j], 0, 0, 0);
+      if (mb == 0) {
+        float sacc = 0.f;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) sacc += (float)bb[t];
+        bsum[j] += sacc;
+      }
+    }
+  }
+  float* out = part + (int64_t)blockIdx.x * (M * N + N);
+#pragma unroll
+  for (int j = 0; j < MAXB; ++j) {
+    const int b = wv + kWgradWaves * j;
+    if (b >= nblocks) break;
+    const int mb = b / NB, nb = b % NB;
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+      out[(32 * mb + 8 * (r / 4) + 4 * g + r % 4) * N + 32 * nb + i] = acc[j][r];
+    if (mb == 0) {
+      const float v = bsum[j] + __shfl_xor(bsum[j], 32, 64);
+      if (g == 0) out[M * N + 32 * nb + i] = v;
+    }
+  }
+}
+
+// out[e] = scale * sum_wg part[wg][src(e)]; rows >= m_valid of the M x N
+// block are dropped, the N bias sums follow the m_valid x N gradient.
+__global__ __launch_bounds__(256) void k_dec_reduce(const float* __restrict__ part, int groups,
+                                                    int M, int N, int m_valid, float scale_w,
+                                                    float scale_b, float* __restrict__ dW,
+                                                    float* __restrict__ db) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  const int nw = m_valid * N;
+  if (e >= nw + N) return;
+  const int src = e < nw ? e : M * N + (e - nw);
+  const int64_t stride = (int64_t)M * N + N;
+  float acc = 0.f;
+  for (int w = 0; w < groups; ++w) acc += part[w * stride + src];
+  if (e < nw)
+    dW[e] = scale_w * acc;
+  else
+    db[e - nw] = scale_b * acc;
+}
+
+}  // namespace gsff
+
+using namespace gsff;
+
+extern "C" {
+
+gsff_status gsff_decoder_workspace_size(int64_t n_px, size_t* bytes) {
+  if (!bytes || n_px < 0) return GSFF_ERR_INVALID_ARGUMENT;
+  *bytes = (size_t)dec_layout(n_px).total;
+  return GSFF_OK;
+}
+
+static hipError_t dec_prepare(const float* W1, const float* W2, char* ws, const DecLayout& L,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_dec_prepare, dim3(256), dim3(256), 0, s, W1, W2, (__bf16*)(ws + L.w1t),
+                     (__bf16*)(ws + L.w1p), (__bf16*)(ws + L.w2tp), (__bf16*)(ws + L.w2p));
+  return hipGetLastError();
+}
+
+gsff_status gsff_decoder_forward(const void* X, const float* W1, const float* b1,
+                                 const float* W2, const float* b2, void* Y, int32_t y_dtype,
+                                 int64_t n_px, void* ws, size_t ws_bytes, void* stream) {
+  if (n_px < 0 || !ws || (n_px > 0 && (!X || !W1 || !b1 || !W2 || !b2 || !Y)))
+    return GSFF_ERR_INVALID_ARGUMENT;
+  if (y_dtype != GSFF_DTYPE_F32 && y_dtype != GSFF_DTYPE_BF16) return GSFF_ERR_UNSUPPORTED;
+  if (((uintptr_t)ws & 255u) != 0) return GSFF_ERR_INVALID_ARGUMENT;
+  const DecLayout L = dec_layout(n_px);
+  if (ws_bytes < L.total) return GSFF_ERR_INVALID_ARGUMENT;
+  if (n_px == 0) return GSFF_OK;
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  if (dec_prepare(W1, W2, w, L, s) != hipSuccess) return GSFF_ERR_HIP;
+  constexpr int NPB = 4;
+  const int64_t waves = (L.nblk + NPB - 1) / NPB;
+  const unsigned grid = (unsigned)((waves + 3) / 4);
+  if (y_dtype == GSFF_DTYPE_BF16)
+    hipLaunchKernelGGL((k_dec_forward<NPB, __bf16>), dim3(grid), dim3(256), 0, s,
+                       (const __bf16*)X, b1, b2, (const __bf16*)(w + L.w1t),
+                       (const __bf16*)(w + L.w2tp), (__bf16*)Y, n_px);
+  else
+    hipLaunchKernelGGL((k_dec_forward<NPB, float>), dim3(grid), dim3(256), 0, s,
+                       (const __bf16*)X, b1, b2, (const __bf16*)(w + L.w1t),
+                       (const __bf16*)(w + L.w2tp), (float*)Y, n_px);
+  return hipGetLastError() == hipSuccess ? GSFF_OK : GSFF_ERR_HIP;
+}
+
+gsff_status gsff_decoder_train_step(const void* X, const float* W1, const float* b1,
+                                    const float* W2, const float* b2, const void* T,
+                                    int64_t n_px, float scale, float* loss, float* dX,
+                                    float* dW1, float* db1, float* dW2, float* db2, void* ws,
+                                    size_t ws_bytes, void* stream) {
+  if (n_px <= 0 || !ws || !X || !W1 || !b1 || !W2 || !b2 || !T || !dX || !dW1 || !db1 || !dW2 ||
+      !db2)
+    return GSFF_ERR_INVALID_ARGUMENT;
+  if (((uintptr_t)ws & 255u) != 0) return GSFF_ERR_INVALID_ARGUMENT;
+  const DecLayout L = dec_layout(n_px);
+  if (ws_bytes < L.total) return GSFF_ERR_INVALID_ARGUMENT;
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  if (dec_prepare(W1, W2, w, L, s) != hipSuccess) return GSFF_ERR_HIP;
+  const unsigned grid = (unsigned)((L.nblk + 3) / 4);
+  hipLaunchKernelGGL(k_dec_train, dim3(grid), dim3(256), 0, s, (const __bf16*)X, b1, b2,
+                     (const __bf16*)T, (const __bf16*)(w + L.w1t), (const __bf16*)(w + L.w1p),
+                     (const __bf16*)(w + L.w2tp), (const __bf16*)(w + L.w2p),
+                     (__bf16*)(w + L.xbuf), (__bf16*)(w + L.hbuf), (__bf16*)(w + L.dzbuf),
+                     (int8_t*)(w + L.dys), dX, loss, scale, n_px, L.npad);
+  // split-K over the padded pixel range, in steps of 16
+  int64_t kchunk = (L.npad + kWgradGroups - 1) / kWgradGroups;
+  kchunk = (kchunk + 15) / 16 * 16;
+  const int64_t groups = (L.npad + kchunk - 1) / kchunk;
+  // dW2[h][c] = scale sum_p H[h][p] sign[c][p];  db2[c] = scale sum_p sign[c][p]
+  hipLaunchKernelGGL((k_dec_wgrad<int8_t, 8>), dim3((unsigned)groups), dim3(64 * kWgradWaves), 0,
+                     s, (const __bf16*)(w + L.hbuf), kHid, kHid / 32, (const int8_t*)(w + L.dys),
+                     kOut / 32, L.npad, kchunk, (float*)(w + L.part2));
+  // dW1[k][h] = sum_p X[k][p] dZ[h][p];  db1[h] = sum_p dZ[h][p]  (dZ carries the scale)
+  hipLaunchKernelGGL((k_dec_wgrad<__bf16, 1>), dim3((unsigned)groups), dim3(64 * kWgradWaves), 0,
+                     s, (const __bf16*)(w + L.xbuf), kLat, 1, (const __bf16*)(w + L.dzbuf),
+                     kHid / 32, L.npad, kchunk, (float*)(w + L.part1));
+  hipLaunchKernelGGL(k_dec_reduce, dim3((kHid * kOut + kOut + 255) / 256), dim3(256), 0, s,
+                     (const float*)(w + L.part2), (int)groups, kHid, kOut, kHid, scale, scale,
+                     dW2, db2);
+  hipLaunchKernelGGL(k_dec_reduce, dim3((kLat * kHid + kHid + 255) / 256), dim3(256), 0, s,
+                     (const float*)(w + L.part1), (int)groups, 32, kHid, kLat, 1.f, 1.f, dW1, db1);
+  return hipGetLastError() == hipSuccess ? GSFF_OK : GSFF_ERR_HIP;
+}
+
+}  // extern "C"

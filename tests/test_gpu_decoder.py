@@ -1,0 +1,97 @@
+"""GPU parity of the BF16-MFMA decoder kernels against the FP64 decoder
+reference (same BF16 rounding points), through the C ABI.
+
+Tolerances (relative L2): 1e-3 for FP32 outputs and every gradient group
+(FP32 accumulation vs FP64; a hidden activation can round to the other BF16
+neighbour when FP32 and FP64 pre-activations straddle a rounding boundary),
+5e-3 with a BF16 output map (one more rounding).
+"""
+import numpy as np
+import pytest
+
+import helpers as H
+from oracle import decoder as ref
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2504_19409_amd import _capi
+    _capi.load()
+
+
+def _problem(n, seed):
+    from paper_2504_19409_amd import decoder as dec
+    rng = np.random.default_rng(seed)
+    X = rng.normal(size=(16, n)).astype(np.float32)
+    p = dec.init_params(seed)
+    p["b1"] = torch.from_numpy(rng.normal(0, 0.1, 128).astype(np.float32)).cuda()
+    p["b2"] = torch.from_numpy(rng.normal(0, 0.1, 512).astype(np.float32)).cuda()
+    Xb = torch.from_numpy(X).cuda().to(torch.bfloat16)
+    npp = {k: v.cpu().numpy().astype(np.float64) for k, v in p.items()}
+    return Xb, p, npp, rng
+
+
+@pytest.mark.parametrize("n", [1000, 4096])
+def test_decoder_forward_parity(n):
+    from paper_2504_19409_amd import decoder as dec
+    Xb, p, npp, _ = _problem(n, 1)
+    ws = dec.workspace(n)
+    Y = dec.forward(Xb, p, ws, out_dtype=torch.float32)
+    Yb = dec.forward(Xb, p, ws, out_dtype=torch.bfloat16)
+    torch.cuda.synchronize()
+    Xn = Xb.float().cpu().numpy().astype(np.float64)
+    r = ref.forward(Xn.T, npp["W1"], npp["b1"], npp["W2"], npp["b2"])["Y"].T
+    assert H.rel_l2(Y.cpu().numpy(), r) <= 1e-3
+    assert H.rel_l2(Yb.float().cpu().numpy(), r) <= 5e-3
+
+
+@pytest.mark.parametrize("n", [1000, 4096])
+def test_decoder_train_step_parity(n):
+    from paper_2504_19409_amd import decoder as dec
+    Xb, p, npp, rng = _problem(n, 2)
+    T = rng.normal(size=(512, n)).astype(np.float32)
+    Tb = torch.from_numpy(T).cuda().to(torch.bfloat16)
+    ws = dec.workspace(n)
+    loss = torch.zeros(1, device="cuda")
+    scale = 1.0 / (512 * n)
+    g = dec.train_step(Xb, p, Tb, ws, scale, loss)
+    torch.cuda.synchronize()
+    Xn = Xb.float().cpu().numpy().astype(np.float64)
+    Tn = Tb.float().cpu().numpy().astype(np.float64)
+    r = ref.l1_backward(Xn.T, npp["W1"], npp["b1"], npp["W2"], npp["b2"], Tn.T, scale)
+    assert loss.item() == pytest.approx(r["loss"], rel=1e-4)
+    pairs = [("dX", g["dX"], r["dX"].T), ("dW1", g["dW1"], r["dW1"]), ("db1", g["db1"], r["db1"]),
+             ("dW2", g["dW2"], r["dW2"]), ("db2", g["db2"], r["db2"])]
+    for name, a, b in pairs:
+        assert H.rel_l2(a.cpu().numpy(), b) <= 1e-3, (name, H.rel_l2(a.cpu().numpy(), b))
+
+
+def test_decoder_full_frame_sampled():
+    """640x480 = 307,200 pixels, the decoder workload's frame size: forward and
+    the latent gradient on sampled pixels (both are per-pixel), weight
+    gradients against the full FP64 reference."""
+    from paper_2504_19409_amd import decoder as dec
+    n = 640 * 480
+    Xb, p, npp, rng = _problem(n, 3)
+    T = rng.normal(size=(512, n)).astype(np.float32)
+    Tb = torch.from_numpy(T).cuda().to(torch.bfloat16)
+    ws = dec.workspace(n)
+    Y = dec.forward(Xb, p, ws, out_dtype=torch.float32)
+    g = dec.train_step(Xb, p, Tb, ws)
+    torch.cuda.synchronize()
+    Xn = Xb.float().cpu().numpy().astype(np.float64)
+    Tn = Tb.float().cpu().numpy().astype(np.float64)
+    pick = np.sort(rng.choice(n, 2000, replace=False))
+    fr = ref.forward(Xn[:, pick].T, npp["W1"], npp["b1"], npp["W2"], npp["b2"])
+    assert H.rel_l2(Y.cpu().numpy()[:, pick], fr["Y"].T) <= 1e-3
+    scale = 1.0 / (512 * n)
+    r = ref.l1_backward(Xn.T, npp["W1"], npp["b1"], npp["W2"], npp["b2"], Tn.T, scale)
+    assert H.rel_l2(g["dX"].cpu().numpy()[:, pick], r["dX"].T[:, pick]) <= 1e-3
+    for name in ["dW1", "db1", "dW2", "db2"]:
+        assert H.rel_l2(g[name].cpu().numpy(), r[name]) <= 1e-3, name
