@@ -224,3 +224,63 @@ def workload_scene(name: str, perturb_pose: bool | None = None,
         vm, _ = perturbed_viewmat(prng, identity_viewmat(), 0.01, 1.0)
         scene.camera.viewmat = vm
     return scene, rng
+
+
+# --------------------------------------------------------------------------
+# multi-view and semantic inputs
+# --------------------------------------------------------------------------
+
+def look_at_viewmat(cam_pos, target) -> np.ndarray:
+    """3x4 world->camera matrix of a camera at cam_pos looking at target, with
+    camera y pointing down along world +y (OpenCV axes)."""
+    c = np.asarray(cam_pos, np.float64)
+    z = np.asarray(target, np.float64) - c
+    z /= np.linalg.norm(z)
+    y0 = np.array([0.0, 1.0, 0.0])
+    x = np.cross(y0, z)
+    x /= np.linalg.norm(x)
+    y = np.cross(z, x)
+    R = np.stack([x, y, z])
+    V = np.zeros((3, 4))
+    V[:, :3] = R
+    V[:, 3] = -R @ c
+    return V
+
+
+def arc_viewmats(rng, n_views: int, radius: float = 3.0, arc: float = 2.0,
+                 center=(0.0, 0.0, 3.0), jitter_deg: float = 2.0):
+    """Cameras on a horizontal circular arc of the given length around
+    `center`, centred on the reference camera at the origin, each looking at
+    the centre, then left-perturbed by a seeded rotation of up to jitter_deg."""
+    half = 0.5 * arc / radius
+    angles = np.linspace(-half, half, n_views) if n_views > 1 else np.zeros(1)
+    c = np.asarray(center, np.float64)
+    out = []
+    for phi in angles:
+        pos = c + radius * np.array([np.sin(phi), 0.0, -np.cos(phi)])
+        V = look_at_viewmat(pos, c)
+        if jitter_deg > 0:
+            V, _ = perturbed_viewmat(rng, V.astype(np.float32), 0.0, jitter_deg)
+        out.append(np.asarray(V, np.float32))
+    return out
+
+
+def semantic_features(rng, means: np.ndarray, n_classes: int = 32, dim: int = 512,
+                      noise: float = 0.05):
+    """Class-structured high-dimensional features standing in for text
+    embeddings of labelled regions: n_classes seeded unit query vectors q_k,
+    class centres at n_classes seeded Gaussian means, every Gaussian takes the
+    class of its nearest centre and the feature normalize(q_k + noise xi).
+    Returns (feat [P, dim] float32, labels [P] int32, queries [n_classes, dim])."""
+    P = means.shape[1]
+    q = rng.normal(size=(n_classes, dim))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    centers = means[:, rng.choice(P, n_classes, replace=False)].T.astype(np.float64)
+    labels = np.empty(P, dtype=np.int32)
+    pts = means.T.astype(np.float64)
+    for a in range(0, P, 65536):
+        d = ((pts[a:a + 65536, None, :] - centers[None]) ** 2).sum(-1)
+        labels[a:a + 65536] = d.argmin(1)
+    f = q[labels] + noise * rng.normal(size=(P, dim))
+    f /= np.linalg.norm(f, axis=1, keepdims=True)
+    return f.astype(np.float32), labels, q.astype(np.float32)
