@@ -87,6 +87,8 @@ def lib():
         L.orc_project.restype = ctypes.c_int
         L.orc_render.argtypes = [sp, cp, stp] + [vp] * 8
         L.orc_render.restype = ctypes.c_int
+        L.orc_render_pixels.argtypes = [sp, cp, stp, ctypes.c_int64, vp, vp, vp]
+        L.orc_render_pixels.restype = ctypes.c_int
         L.orc_backward.argtypes = [sp, cp, stp] + [vp] * 12
         L.orc_backward.restype = ctypes.c_int
         L.orc_tile_lists.argtypes = [sp, cp, stp, ctypes.c_int32, vp, vp]
@@ -167,6 +169,21 @@ def render(params, camera, settings=None, with_hash=False):
     if with_hash:
         out["hash"] = int(h.value)
     return out
+
+
+def render_pixels(params, camera, px, py, settings=None):
+    """Forward at listed pixels: dict rgb [n,3], depth [n], alpha [n], feat [n,C]."""
+    m = _Marshal(params, camera)
+    st = settings or default_settings()
+    px = np.ascontiguousarray(px, dtype=np.int32)
+    py = np.ascontiguousarray(py, dtype=np.int32)
+    n = px.size
+    out = np.zeros((n, 5 + m.C))
+    rc = lib().orc_render_pixels(ctypes.byref(m.scene), ctypes.byref(m.camera), ctypes.byref(st),
+                                 n, _ptr(px), _ptr(py), _ptr(out))
+    if rc != 0:
+        raise ValueError("orc_render_pixels failed")
+    return dict(rgb=out[:, :3], depth=out[:, 3], alpha=out[:, 4], feat=out[:, 5:])
 
 
 def backward(params, camera, grads, settings=None):

@@ -350,6 +350,40 @@ extern "C" int orc_render(const orc_scene* s, const orc_camera* cam,
   return 0;
 }
 
+extern "C" int orc_render_pixels(const orc_scene* s, const orc_camera* cam,
+                                 const orc_settings* st, int64_t n, const int32_t* px,
+                                 const int32_t* py, double* out) {
+  if (!check_args(s, cam, st) || n < 0 || (n > 0 && (!px || !py || !out))) return -1;
+  Prepared pr;
+  prepare(s, cam, st, pr);
+  const int C = s->C;
+  const int64_t P = s->P;
+  std::vector<double> F(C);
+  for (int64_t k = 0; k < n; ++k) {
+    if (px[k] < 0 || px[k] >= cam->width || py[k] < 0 || py[k] >= cam->height) return -1;
+    double col[3] = {0, 0, 0}, dep = 0;
+    std::fill(F.begin(), F.end(), 0.0);
+    const double T = composite_pixel(
+        pr, st, px[k], py[k],
+        [&](const Eval& e, double Tin) {
+          const double w = e.alpha * Tin;
+          for (int q = 0; q < 3; ++q) col[q] += w * s->rgb[q * P + e.i];
+          dep += w * pr.proj[e.i].mc[2];
+          if (st->render_features)
+            for (int c = 0; c < C; ++c) F[c] += w * s->feat[e.i * C + c];
+        },
+        nullptr, nullptr, nullptr);
+    double* o = out + k * (5 + C);
+    o[0] = col[0];
+    o[1] = col[1];
+    o[2] = col[2];
+    o[3] = dep;
+    o[4] = 1.0 - T;
+    for (int c = 0; c < C; ++c) o[5 + c] = st->render_features ? F[c] : 0.0;
+  }
+  return 0;
+}
+
 extern "C" int orc_backward(const orc_scene* s, const orc_camera* cam,
                             const orc_settings* st, const double* g_rgb,
                             const double* g_depth, const double* g_alpha,
@@ -379,6 +413,12 @@ extern "C" int orc_backward(const orc_scene* s, const orc_camera* cam,
   for (long py = 0; py < H; ++py)
     for (long px = 0; px < W; ++px) {
       const int64_t p = py * W + px;
+      // a pixel whose upstream is exactly zero contributes exactly zero
+      bool any = g_rgb[p] != 0.0 || g_rgb[HW + p] != 0.0 || g_rgb[2 * HW + p] != 0.0 ||
+                 g_depth[p] != 0.0 || g_alpha[p] != 0.0;
+      if (feat_on)
+        for (int c = 0; c < C && !any; ++c) any = g_feat[c * HW + p] != 0.0;
+      if (!any) continue;
       // pass 1: contributors and the final outputs O_k (k = r, g, b, depth)
       list.clear();
       double O[4] = {0, 0, 0, 0};

@@ -83,6 +83,11 @@ int orc_render(const orc_scene* s, const orc_camera* cam, const orc_settings* st
                double* out_feat, double* out_T, int32_t* out_n,
                double* out_margin, uint64_t* hash);
 
+/* Forward at n listed pixels only: out[k] = (r, g, b, depth, alpha,
+ * feat[0..C)) of pixel (px[k], py[k]), (5 + C) doubles per pixel. */
+int orc_render_pixels(const orc_scene* s, const orc_camera* cam, const orc_settings* st,
+                      int64_t n, const int32_t* px, const int32_t* py, double* out);
+
 /* Gradient of  sum(g_rgb*rgb) + sum(g_depth*depth) + sum(g_alpha*alpha)
  *            + sum(g_feat*feat)  with respect to every input.
  * Outputs are overwritten.  g_feat may be NULL (treated as zero).  d2d, if not

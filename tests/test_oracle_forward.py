@@ -286,3 +286,17 @@ def test_culling_rules(oracle_lib):
                viewmat=sg.identity_viewmat())
     pr = oracle_lib.project(params, cam)
     assert list(pr["valid"]) == [0, 0, 0, 0, 1]
+
+
+def test_render_pixels_matches_full_render(oracle_lib):
+    sc = _tiny_scene(8)
+    p, c = oracle_lib.scene_dicts(sc)
+    full = oracle_lib.render(p, c)
+    rng = np.random.default_rng(0)
+    px = rng.integers(0, c["width"], 50)
+    py = rng.integers(0, c["height"], 50)
+    s = oracle_lib.render_pixels(p, c, px, py)
+    np.testing.assert_array_equal(s["rgb"], full["rgb"][:, py, px].T)
+    np.testing.assert_array_equal(s["depth"], full["depth"][py, px])
+    np.testing.assert_array_equal(s["alpha"], full["alpha"][py, px])
+    np.testing.assert_array_equal(s["feat"], full["feat"][:, py, px].T)
