@@ -57,7 +57,8 @@ typedef int32_t gsff_status;
 #define GSFF_DTYPE_F16 2
 
 /* largest channel count composited in one pass; wider payloads are rendered in
- * channel chunks of this size that recompute the blending weights */
+ * channel chunks of this size that recompute the blending weights (the
+ * adjoint's first pass, which also carries the geometry, takes at most 32) */
 #define GSFF_MAX_CHANNELS_PER_PASS 64
 
 /* Screen tiles are GSFF_TILE x GSFF_TILE pixels. */

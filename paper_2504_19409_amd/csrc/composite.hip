@@ -279,45 +279,35 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
-// v + (v from the lane given by a DPP permutation inside each row of 16)
-template <int CTRL>
-__device__ __forceinline__ float dpp_add(float v) {
-  return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kBwdNB = 16;              // Gaussians per batch = rows of the contraction
+constexpr int kBwdStride = kBlock + 4;  // LDS row stride (floats) of the per-pair products
+constexpr int kBwdGeoChannels = 32;     // feature channels carried by the geometry pass
+constexpr int kBwdMaxChannels = 64;     // feature channels of a feature-only pass
+
+// x = hi + lo + r with hi = bf16(x), lo = bf16(x - hi), |r| <= 2^-16 |x|.
+__device__ __forceinline__ void split8(const float4 a, const float4 b, bf16x8& hi, bf16x8& lo) {
+  const float v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    hi[t] = (__bf16)v[t];
+    lo[t] = (__bf16)(v[t] - (float)hi[t]);
+  }
 }
 
-// Sum over the 16 lanes of a DPP row, result in every lane of the row:
-// butterflies over lane^1, lane^2 (quad permutes), then the half-row and
-// row mirrors, each pairing a lane with one in the other half it has not
-// combined with yet.
-__device__ __forceinline__ float row16_allreduce(float v) {
-  v = dpp_add<0xB1>(v);   // quad_perm [1,0,3,2]
-  v = dpp_add<0x4E>(v);   // quad_perm [2,3,0,1]
-  v = dpp_add<0x141>(v);  // row_half_mirror
-  v = dpp_add<0x140>(v);  // row_mirror
-  return v;
+__device__ __forceinline__ bf16x8 to_bf16x8(const float4 a, const float4 b) {
+  bf16x8 h;
+  h[0] = (__bf16)a.x; h[1] = (__bf16)a.y; h[2] = (__bf16)a.z; h[3] = (__bf16)a.w;
+  h[4] = (__bf16)b.x; h[5] = (__bf16)b.y; h[6] = (__bf16)b.z; h[7] = (__bf16)b.w;
+  return h;
 }
 
-constexpr int kBwdNB = 16;          // Gaussians per batch (one per DPP row in the contraction)
-constexpr int kBwdStride = 272;     // LDS row stride of the per-pixel products (bank spread)
+__device__ __forceinline__ f32x4 mfma16(const bf16x8 a, const bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
 
-// The per-pixel adjoint of a tile, as a contraction.
-//
-// Phase A (one thread per pixel, back to front over a batch of kBwdNB
-// Gaussians): recover T, and store the blending weight w_ip and
-// dL/dpower_ip (zero where the pixel does not use Gaussian i or alpha is
-// clamped) in LDS.
-// Phase B (thread = (Gaussian i, pixel column)): every per-Gaussian gradient is
-// a sum over the tile's pixels of one of these two values times a per-pixel
-// constant:
-//   colour / depth / feature : sum_p w_ip g_k(p)
-//   image-space mean, conic  : sums of dL/dpower_ip times 1, x, y, x^2, xy, y^2
-//                              (tile-local pixel coordinates), from which
-//                              du, dv, dA, dB, dC follow in closed form
-//   opacity                  : sum_p dL/dpower_ip / o_i  (d alpha/d o = G,
-//                              d alpha/d power = o G)
-// so each column accumulates its 16 pixels and one DPP row reduction
-// completes the sum.  Geometry terms come only from the colour, depth and
-// opacity upstream; the feature upstream only enters the feature sums.
 // Upstream gradient formed inside the adjoint for the L1 losses of the
 // method (Eqs. 5, 8, 11 are weighted sums of L1 terms):
 //   L = sum_k w_k * mean|out_k - target_k|  over the groups rgb, depth, alpha,
@@ -336,36 +326,79 @@ struct L1Upstream {
   float* loss;                            // += the loss (may be NULL)
 };
 
-__device__ __forceinline__ float l1_sign(float o, float t, float scale, float& l) {
+// sign(o - t) in {-1, 0, 1}; l += |o - t| * scale
+__device__ __forceinline__ float l1_unit_sign(float o, float t, float scale, float& l) {
   const float d = o - t;
   l += fabsf(d) * scale;
-  return d > 0.f ? scale : (d < 0.f ? -scale : 0.f);
+  return d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
+}
+
+// The per-pixel adjoint of a tile, with the per-Gaussian sums as matrix
+// products on the matrix cores.
+//
+// Every gradient a Gaussian i receives from a tile is a sum over the tile's
+// pixels p of one of two per-pair values times a per-pixel quantity:
+//   colour, depth, feature k : sum_p w_ip g_k(p)           (w = blending weight)
+//   image-space mean, conic  : sums of dL/dpower_ip times 1, x, y, x^2, xy, y^2
+//                              (pixel centre relative to the tile centre),
+//                              from which du, dv, dA, dB, dC follow in closed form
+//   opacity                  : sum_p dL/dpower_ip / o_i
+// For a batch of 16 Gaussians these are the products W (16 x 256) * G
+// (256 x channels) and DP (16 x 256) * M (256 x 6).
+//
+// Per batch (back to front over the tile's list):
+//  phase A  one thread per pixel walks the 16 Gaussians back to front,
+//           recovering T_i = T_{i+1} / (1 - alpha_i) from the final
+//           transmittance, and writes w_ip and dL/dpower_ip (zero where the
+//           pixel does not use Gaussian i, or alpha is clamped) to LDS.  With
+//           D = sum over the contributors behind i of w_m (g . c_m),
+//             dL/dalpha_i = T_i (g . c_i) + (g_alpha T_final - D) / (1 - alpha_i).
+//  phase B  one wave per 16-column output block runs the K = 256 contraction
+//           with 16x16x32 BF16 MFMA: the FP32 left operand is split as hi + lo
+//           (both BF16), the right operand is either exact in BF16 (L1 signs,
+//           moments of half-integer coordinates) or split the same way, so
+//           every product is kept to about 2^-16 relative; accumulation is FP32.
+//           The accumulator lanes then add their (Gaussian, channel) results
+//           to the global gradients.
+// Geometry terms come only from the colour, depth and opacity upstream; the
+// feature upstream only enters the feature sums (Sec. 3.1, last paragraph).
+// Register budget: four waves per SIMD (four workgroups per CU, which the
+// LDS use also allows); the explicit-upstream variant keeps twice the right
+// operands in registers and runs three.
+// Workgroup barrier that orders LDS only: global loads and atomics issued
+// before it stay in flight (a full __syncthreads() would wait for every
+// outstanding global atomic of the wave).  All communication between the
+// waves of the adjoint goes through LDS.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 template <int CP, bool GEO, bool L1>
-__global__ __launch_bounds__(kBlock) void k_composite_bwd(
+__global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
+                          amdgpu_waves_per_eu(L1 ? 4 : 3))) void k_composite_bwd(
     DevSettings st, int64_t P, int C, int c0, int W, int H, int tiles_x, int ntiles,
     int rank_bits, uint32_t max_pairs, WsView w, const float* __restrict__ g_rgb,
     const float* __restrict__ g_depth, const float* __restrict__ g_alpha,
     const float* __restrict__ g_feat, float* __restrict__ d_feat, L1Upstream l1) {
-  constexpr int NL = (GEO ? 4 : 0) + CP;   // linear channels: r, g, b, depth, features
-  constexpr int NLs = NL > 0 ? NL : 1;
-  constexpr int NM = GEO ? 6 : 0;          // moments of dL/dpower
-  constexpr int NO = NL + NM;
-  constexpr int NF = (GEO ? 10 : 0) + CP;  // outputs per Gaussian
-  constexpr int NOs = NO > 0 ? NO : 1;
-  __shared__ float4 s_r0[kBwdNB], s_r1[kBwdNB], s_r2[kBwdNB];
-  __shared__ uint32_t s_gid[kBwdNB];
-  __shared__ int s_any[kBwdNB];
-  __shared__ float s_w[kBwdNB][kBwdStride];
-  __shared__ float s_dp[GEO ? kBwdNB : 1][kBwdStride];
-  __shared__ float s_gl[NLs][kBlock];
+  constexpr int NL = (GEO ? 4 : 0) + CP;      // linear channels: r, g, b, depth, features
+  constexpr int NCB = (NL + 15) / 16;         // 16-column blocks of W * G
+  constexpr int NT = NCB + (GEO ? 1 : 0);     // output blocks (+ the moments block)
+  static_assert(NT <= kBlock / 64, "one wave per output block");
+  static_assert(NL > 0, "nothing to differentiate");
+  __shared__ __attribute__((aligned(16))) float s_W[kBwdNB][kBwdStride];
+  __shared__ __attribute__((aligned(16))) float s_DP[GEO ? kBwdNB : 1][GEO ? kBwdStride : 4];
+  __shared__ float4 s_r0[2][kBwdNB], s_r1[2][kBwdNB], s_r2[2][kBwdNB];
+  __shared__ uint32_t s_gid[2][kBwdNB];
+  __shared__ float s_mom[kBwdNB][8];
   __shared__ uint32_t s_end;
   __shared__ float s_loss[kBlock / 64];
   const int tile = xcd_tile(blockIdx.x, ntiles);
   if (tile >= ntiles) return;
   const int tx = tile % tiles_x, ty = tile / tiles_x;
   const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63, lq = lane >> 4, lj = lane & 15;
   const int px = tx * kTile + (tid & (kTile - 1));
   const int py = ty * kTile + (tid / kTile);
   const bool inside = px < W && py < H;
@@ -376,187 +409,290 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd(
   const int64_t HW = (int64_t)W * H;
   const int64_t p = (int64_t)py * W + px;
 
-  // per-pixel state and upstream gradients
-  float T = 1.f, Tfin = 1.f;
+  // ---- per-pixel state and upstream gradients
+  float Tfin = 1.f;
   uint32_t pend = range.x;
-  float gr = 0.f, gg = 0.f, gb = 0.f, gd = 0.f, ga = 0.f;
+  float gr = 0.f, gg = 0.f, gb = 0.f, gd = 0.f, ga = 0.f;  // geometry upstream (scaled)
+  float ur = 0.f, ug = 0.f, ub = 0.f, ud = 0.f;           // same, as contraction operands
   float loss = 0.f;
   if (inside) {
     Tfin = w.pix_T[p];
-    T = Tfin;
     pend = w.pix_end[p];
     if (GEO) {
       if (L1) {
         if (l1.t_rgb) {
-          gr = l1_sign(l1.out_rgb[p], l1.t_rgb[p], l1.s_rgb, loss);
-          gg = l1_sign(l1.out_rgb[HW + p], l1.t_rgb[HW + p], l1.s_rgb, loss);
-          gb = l1_sign(l1.out_rgb[2 * HW + p], l1.t_rgb[2 * HW + p], l1.s_rgb, loss);
+          ur = l1_unit_sign(l1.out_rgb[p], l1.t_rgb[p], l1.s_rgb, loss);
+          ug = l1_unit_sign(l1.out_rgb[HW + p], l1.t_rgb[HW + p], l1.s_rgb, loss);
+          ub = l1_unit_sign(l1.out_rgb[2 * HW + p], l1.t_rgb[2 * HW + p], l1.s_rgb, loss);
         }
-        if (l1.t_depth) gd = l1_sign(l1.out_depth[p], l1.t_depth[p], l1.s_depth, loss);
-        if (l1.t_alpha) ga = l1_sign(l1.out_alpha[p], l1.t_alpha[p], l1.s_alpha, loss);
+        if (l1.t_depth) ud = l1_unit_sign(l1.out_depth[p], l1.t_depth[p], l1.s_depth, loss);
+        if (l1.t_alpha) ga = l1_unit_sign(l1.out_alpha[p], l1.t_alpha[p], l1.s_alpha, loss) *
+                             l1.s_alpha;
+        gr = ur * l1.s_rgb;
+        gg = ug * l1.s_rgb;
+        gb = ub * l1.s_rgb;
+        gd = ud * l1.s_depth;
       } else {
-        gr = g_rgb[p];
-        gg = g_rgb[HW + p];
-        gb = g_rgb[2 * HW + p];
-        gd = g_depth[p];
+        gr = ur = g_rgb[p];
+        gg = ug = g_rgb[HW + p];
+        gb = ub = g_rgb[2 * HW + p];
+        gd = ud = g_depth[p];
         ga = g_alpha[p];
       }
     }
   }
-  if (GEO) {
-    s_gl[0][tid] = gr;
-    s_gl[1][tid] = gg;
-    s_gl[2][tid] = gb;
-    s_gl[3][tid] = gd;
-  }
-#pragma unroll
-  for (int c = 0; c < CP; ++c) {
-    float v = 0.f;
-    if (inside && c < cn) {
-      const int64_t q = (int64_t)(c0 + c) * HW + p;
-      v = L1 ? l1_sign(l1.out_feat[q], l1.t_feat[q], l1.s_feat, loss) : g_feat[q];
-    }
-    s_gl[(GEO ? 4 : 0) + c][tid] = v;
-  }
-  if (L1 && l1.loss) {  // uniform: one atomic per workgroup
-    const float v = wave_sum(loss);
-    if ((tid & 63) == 0) s_loss[tid >> 6] = v;
-  }
   if (tid == 0) s_end = range.x;
-  __syncthreads();
+
+  // ---- right operands, kept in registers for the tile: wave b < NCB holds
+  // G[pixels 32s + 8 lq .. +7][channel 16 b + lj] for s = 0..7, the moments
+  // wave (b = NCB) the moment values of the same pixels.
+  // The per-pixel values are staged through s_W one 16-channel block at a time.
+  bf16x8 bh[8], bl[8];
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb) {
+    lds_barrier();  // s_W free
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int k = 16 * cb + j;
+      float v = 0.f;
+      if (k < NL && inside) {
+        if (GEO && k < 4) {
+          v = k == 0 ? ur : (k == 1 ? ug : (k == 2 ? ub : ud));
+        } else {
+          const int c = k - (GEO ? 4 : 0);
+          if (c < cn) {
+            const int64_t q = (int64_t)(c0 + c) * HW + p;
+            v = L1 ? l1_unit_sign(l1.out_feat[q], l1.t_feat[q], l1.s_feat, loss) : g_feat[q];
+          }
+        }
+      }
+      s_W[j][tid] = v;
+    }
+    lds_barrier();
+    if (wave == cb) {
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const float* src = &s_W[lj][32 * s + 8 * lq];
+        const float4 a = *reinterpret_cast<const float4*>(src);
+        const float4 b = *reinterpret_cast<const float4*>(src + 4);
+        if (L1) {
+          bh[s] = to_bf16x8(a, b);  // signs: exact
+        } else {
+          split8(a, b, bh[s], bl[s]);
+        }
+      }
+    }
+  }
+  if constexpr (GEO) {
+    // the moments wave: right operand M[pixel][j] = 1, x, y, x^2, xy, y^2 for
+    // j = lj (zero for lj >= 6), pixel 32 s + 8 lq + t at x = 8 (lq & 1) + t - 7.5,
+    // y = 2 s + lq / 2 - 7.5 relative to the tile centre; products of
+    // half-integers below 8 in magnitude, so exact in BF16
+    if (wave == NCB) {
+      const float c0 = lj == 0 ? 1.f : 0.f, c1 = lj == 1 ? 1.f : 0.f;
+      const float c2 = lj == 2 ? 1.f : 0.f, c3 = lj == 3 ? 1.f : 0.f;
+      const float c4 = lj == 4 ? 1.f : 0.f, c5 = lj == 5 ? 1.f : 0.f;
+      const float x0 = (float)(8 * (lq & 1)) - 7.5f;
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const float y = (float)(2 * s + (lq >> 1)) - 7.5f;
+        const float base = __builtin_fmaf(y, __builtin_fmaf(c5, y, c2), c0);
+        const float lin = __builtin_fmaf(c4, y, c1);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const float x = x0 + (float)t;
+          bh[s][t] = (__bf16)__builtin_fmaf(x, __builtin_fmaf(c3, x, lin), base);
+        }
+      }
+    }
+  }
+  if (L1 && l1.loss) {
+    const float v = wave_sum(loss);
+    if (lane == 0) s_loss[wave] = v;
+  }
+  if (inside && pend > range.x) atomicMax(&s_end, pend);
+  lds_barrier();
   if (L1 && l1.loss && tid == 0) {
     const float v = (s_loss[0] + s_loss[1]) + (s_loss[2] + s_loss[3]);
     if (v != 0.f) unsafeAtomicAdd(l1.loss, v);
   }
-  if (inside && pend > range.x) atomicMax(&s_end, pend);
-  __syncthreads();
   const uint32_t blk_end = min(s_end, range.y);
-  float S_r = 0.f, S_g = 0.f, S_b = 0.f, S_d = 0.f;  // sums over the contributors behind
+  if (blk_end <= range.x) return;  // uniform: no pixel of the tile uses any Gaussian
 
-  // phase-B role of this thread
-  const int bj = tid >> 4;          // Gaussian slot in the batch (one DPP row)
-  const int bq = tid & 15;          // pixel column of the tile
-  const float xl = (float)bq + 0.5f - 0.5f * kTile;  // tile-local x of the column
+  // Batches run back to front: [b0, b1), then [nb0, nb1 = b0), then
+  // [mb0, mb1 = nb0), ...; only the front-most one can be shorter than 16.
+  // Loads are pipelined: while batch b is processed, the records of b+1
+  // (whose ids arrived during b-1) and the ids of b+2 are in flight.
+  const uint32_t rx = range.x;
+  auto batch_start = [rx](uint32_t end) {
+    return end > rx ? end - min((uint32_t)kBwdNB, end - rx) : end;
+  };
+  // The loads are issued by the first 16 lanes of the last wave, which has no
+  // output block when NT < 4 (its memory queue then holds no gradient atomics).
+  // Ids stay unchecked until use: load_record and the atomics test id < P.
+  const int pf = tid - (kBlock - 64);
+  const bool pf_lane = pf >= 0 && pf < kBwdNB;
+  uint32_t b1 = blk_end, b0 = batch_start(b1);
+  uint32_t nb1 = b0, nb0 = batch_start(nb1);
+  if (pf_lane) {
+    const uint32_t idx = b0 + pf;
+    const uint32_t gid = idx < b1 ? pair_gid(w, idx, rmask, P) : (uint32_t)P;
+    s_gid[0][pf] = gid;
+    load_record(w, gid, P, s_r0[0][pf], s_r1[0][pf], s_r2[0][pf]);
+  }
+  uint32_t g_next = (uint32_t)P;  // ids of the next batch, per prefetch lane
+  if (pf_lane && nb0 + pf < nb1) g_next = w.pkeys_a[nb0 + pf];
+  lds_barrier();
+
+  float T = Tfin, D = 0.f;
+  const float gaT = ga * Tfin;
   const float tcx = (float)(tx * kTile) + 0.5f * kTile, tcy = (float)(ty * kTile) + 0.5f * kTile;
+  int buf = 0;
+  while (true) {
+    const bool more = nb1 > rx;  // another batch follows this one
+    // records of the next batch, ids of the one after
+    const uint32_t pgid = g_next;
+    float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f), p1 = p0, p2 = p0;
+    const uint32_t mb1 = nb0, mb0 = batch_start(mb1);
+    if (pf_lane) {
+      if (more) load_record(w, pgid, P, p0, p1, p2);
+      g_next = (more && mb0 + pf < mb1) ? w.pkeys_a[mb0 + pf] : (uint32_t)P;
+    }
 
-  for (uint32_t b1 = blk_end; b1 > range.x;) {
-    const uint32_t b0 = (b1 - range.x > (uint32_t)kBwdNB) ? b1 - kBwdNB : range.x;
-    const int n = (int)(b1 - b0);
-    __syncthreads();  // previous batch fully consumed
-    if (tid < n) {
-      const uint32_t gid = pair_gid(w, b0 + tid, rmask, P);
-      s_gid[tid] = gid;
-      load_record(w, gid, P, s_r0[tid], s_r1[tid], s_r2[tid]);
-    }
-    if (tid < kBwdNB) s_any[tid] = 0;
-    __syncthreads();
     // ---- phase A: per-pixel products, back to front
-    for (int jj = n - 1; jj >= 0; --jj) {
-      const uint32_t j = b0 + (uint32_t)jj;
-      const float4 r0 = s_r0[jj], r1 = s_r1[jj];
-      float wv = 0.f, dp = 0.f;
-      if (inside && j < pend) {
+    const bool wave_any = __ballot(inside && pend > b0) != 0ull;
+    if (wave_any) {
+      // Branch-free: every value is computed for every (pixel, Gaussian) and
+      // masked, so the record reads of later Gaussians can be issued early.
+#pragma unroll
+      for (int jj = kBwdNB - 1; jj >= 0; --jj) {
+        const float4 r0 = s_r0[buf][jj], r1 = s_r1[buf][jj];
         const AlphaEval e = eval_alpha(r0, r1, pxc, pyc, st.alpha_max);
-        if (e.alpha >= st.alpha_min) {
-          const float inv = __builtin_amdgcn_rcpf(1.f - e.alpha);  // v_rcp_f32, 1 ulp
-          const float Tb = T * inv;  // transmittance in front of this Gaussian
-          wv = e.alpha * Tb;
-          if constexpr (GEO) {
-            const float4 r2 = s_r2[jj];
-            const float dal = Tb * (gr * r2.x + gg * r2.y + gb * r2.z + gd * r1.z) -
-                              (gr * S_r + gg * S_g + gb * S_b + gd * S_d) * inv + ga * Tfin * inv;
-            S_r += wv * r2.x;
-            S_g += wv * r2.y;
-            S_b += wv * r2.z;
-            S_d += wv * r1.z;
-            dp = (e.oG < st.alpha_max) ? dal * e.oG : 0.f;
+        const bool act = (b0 + (uint32_t)jj < pend) && (e.alpha >= st.alpha_min);
+        const float am = act ? 1.f : 0.f;
+        const float inv = __builtin_amdgcn_rcpf(1.f - e.alpha);  // v_rcp_f32, 1 ulp
+        const float Tb = T * inv;  // transmittance in front of this Gaussian
+        const float wv = am * (e.alpha * Tb);
+        if constexpr (GEO) {
+          const float4 r2 = s_r2[buf][jj];
+          const float gc = gr * r2.x + gg * r2.y + gb * r2.z + gd * r1.z;
+          const float dal = Tb * gc + (gaT - D) * inv;
+          const float og = (e.oG < st.alpha_max) ? am * e.oG : 0.f;
+          D = fmaf(wv, gc, D);
+          s_DP[jj][tid] = dal * og;
+        }
+        T = act ? Tb : T;
+        s_W[jj][tid] = wv;
+      }
+    } else {
+#pragma unroll
+      for (int jj = 0; jj < kBwdNB; ++jj) {
+        s_W[jj][tid] = 0.f;
+        if constexpr (GEO) s_DP[jj][tid] = 0.f;
+      }
+    }
+    lds_barrier();
+
+    // ---- phase B: contraction over the tile's pixels on the matrix cores
+    if (wave < NCB) {
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const float* src = &s_W[lj][32 * s + 8 * lq];
+        bf16x8 ah, al;
+        split8(*reinterpret_cast<const float4*>(src), *reinterpret_cast<const float4*>(src + 4),
+               ah, al);
+        acc = mfma16(ah, bh[s], acc);
+        acc = mfma16(al, bh[s], acc);
+        if (!L1) acc = mfma16(ah, bl[s], acc);
+      }
+      // acc[r]: Gaussian 4 lq + r of the batch, channel 16 wave + lj
+      const int k = 16 * wave + lj;
+      if (k < NL) {
+        float scale = 1.f;
+        float* dst = nullptr;
+        int64_t stride = 0;
+        if (GEO && k < 4) {
+          if (L1) scale = k < 3 ? l1.s_rgb : l1.s_depth;
+          dst = w.grad2d + (k < 3 ? 6 + k : 9);
+          stride = 10;
+        } else {
+          const int c = k - (GEO ? 4 : 0);
+          if (c < cn) {
+            if (L1) scale = l1.s_feat;
+            dst = d_feat + c0 + c;
+            stride = C;
           }
-          T = Tb;
-          s_any[jj] = 1;
         }
-      }
-      s_w[jj][tid] = wv;
-      if (GEO) s_dp[jj][tid] = dp;
-    }
-    __syncthreads();
-    // ---- phase B: contraction over the tile's pixels, one column per lane
-    const bool wave_active =
-        __ballot(bj < n && s_any[bj] != 0) != 0ull;  // uniform per wave: skip idle waves
-    if (!wave_active) {
-      b1 = b0;
-      continue;
-    }
-    float acc[NOs];
+        if (dst) {
 #pragma unroll
-    for (int k = 0; k < NO; ++k) acc[k] = 0.f;
-    if (bj < n && s_any[bj]) {
-#pragma unroll 4
-      for (int i = 0; i < kTile; ++i) {
-        const int pp = i * kTile + bq;
-        const float wv = s_w[bj][pp];
-#pragma unroll
-        for (int k = 0; k < NL; ++k) acc[k] += wv * s_gl[k][pp];
-        if constexpr (GEO) {
-          const float dp = s_dp[bj][pp];
-          const float yl = (float)i + 0.5f - 0.5f * kTile;
-          const float dx = dp * xl, dy = dp * yl;
-          acc[NL + 0] += dp;
-          acc[NL + 1] += dx;
-          acc[NL + 2] += dy;
-          acc[NL + 3] += dx * xl;
-          acc[NL + 4] += dx * yl;
-          acc[NL + 5] += dy * yl;
-        }
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < NO; ++k) acc[k] = row16_allreduce(acc[k]);
-    // ---- phase C: per-Gaussian outputs, spread over the 16 lanes of the row
-    if (bj < n && s_any[bj]) {
-      const uint32_t gid = s_gid[bj];
-      if (gid < (uint32_t)P) {
-        float geo[10];
-        if constexpr (GEO) {
-          const float4 r0 = s_r0[bj], r1 = s_r1[bj];
-          const float ud = r0.x - tcx, vd = r0.y - tcy;  // mean relative to the tile centre
-          const float M0 = acc[NL], M1 = acc[NL + 1], M2 = acc[NL + 2];
-          const float M3 = acc[NL + 3], M4 = acc[NL + 4], M5 = acc[NL + 5];
-          // sums of dL/dpower times (u - x_p), (v - y_p) and their products
-          const float Sx = ud * M0 - M1, Sy = vd * M0 - M2;
-          const float Sxx = ud * ud * M0 - 2.f * ud * M1 + M3;
-          const float Sxy = ud * vd * M0 - ud * M2 - vd * M1 + M4;
-          const float Syy = vd * vd * M0 - 2.f * vd * M2 + M5;
-          geo[0] = -(r0.z * Sx + r0.w * Sy);
-          geo[1] = -(r0.w * Sx + r1.x * Sy);
-          geo[2] = -0.5f * Sxx;
-          geo[3] = -Sxy;
-          geo[4] = -0.5f * Syy;
-          geo[5] = r1.y > 0.f ? M0 / r1.y : 0.f;
-          geo[6] = acc[0];
-          geo[7] = acc[1];
-          geo[8] = acc[2];
-          geo[9] = acc[3];
-        }
-#pragma unroll
-        for (int f0 = 0; f0 < NF; f0 += 16) {
-          const int f = f0 + bq;
-          if (f >= NF) break;
-          if (GEO && f < 10) {  // geometry slots exist only when GEO
-            float v = 0.f;
-#pragma unroll
-            for (int k = 0; k < 10; ++k) v = (k == f) ? geo[k] : v;
-            if (v != 0.f) unsafeAtomicAdd(&w.grad2d[(int64_t)gid * 10 + f], v);
-          } else {
-            const int c = f - (GEO ? 10 : 0);
-            float v = 0.f;
-#pragma unroll
-            for (int k = 0; k < CP; ++k) v = (k == c) ? acc[(GEO ? 4 : 0) + k] : v;
-            if (c < cn && v != 0.f) unsafeAtomicAdd(&d_feat[(int64_t)gid * C + c0 + c], v);
+          for (int r = 0; r < 4; ++r) {
+            const uint32_t gid = s_gid[buf][4 * lq + r];
+            const float v = acc[r] * scale;
+            if (gid < (uint32_t)P && v != 0.f) unsafeAtomicAdd(dst + (int64_t)gid * stride, v);
           }
         }
       }
+    } else if constexpr (GEO) {
+      if (wave == NCB) {
+        // moments of dL/dpower (the right operand, in bh, holds the moments)
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          const float* src = &s_DP[lj][32 * s + 8 * lq];
+          bf16x8 ah, al;
+          split8(*reinterpret_cast<const float4*>(src), *reinterpret_cast<const float4*>(src + 4),
+                 ah, al);
+          acc = mfma16(ah, bh[s], acc);
+          acc = mfma16(al, bh[s], acc);
+        }
+        if (lj < 6) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) s_mom[4 * lq + r][lj] = acc[r];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (lane < kBwdNB) {
+          const uint32_t gid = s_gid[buf][lane];
+          if (gid < (uint32_t)P) {
+            const float4 r0 = s_r0[buf][lane], r1 = s_r1[buf][lane];
+            const float M0 = s_mom[lane][0], M1 = s_mom[lane][1], M2 = s_mom[lane][2];
+            const float M3 = s_mom[lane][3], M4 = s_mom[lane][4], M5 = s_mom[lane][5];
+            const float udx = r0.x - tcx, vdy = r0.y - tcy;  // mean relative to the tile centre
+            // sums of dL/dpower times (u - x_p), (v - y_p) and their products
+            const float Sx = udx * M0 - M1, Sy = vdy * M0 - M2;
+            const float Sxx = udx * udx * M0 - 2.f * udx * M1 + M3;
+            const float Sxy = udx * vdy * M0 - udx * M2 - vdy * M1 + M4;
+            const float Syy = vdy * vdy * M0 - 2.f * vdy * M2 + M5;
+            float geo[6];
+            geo[0] = -(r0.z * Sx + r0.w * Sy);
+            geo[1] = -(r0.w * Sx + r1.x * Sy);
+            geo[2] = -0.5f * Sxx;
+            geo[3] = -Sxy;
+            geo[4] = -0.5f * Syy;
+            geo[5] = r1.y > 0.f ? M0 * __builtin_amdgcn_rcpf(r1.y) : 0.f;
+            float* dst = w.grad2d + (int64_t)gid * 10;
+#pragma unroll
+            for (int f = 0; f < 6; ++f)
+              if (geo[f] != 0.f) unsafeAtomicAdd(dst + f, geo[f]);
+          }
+        }
+      }
     }
-    b1 = b0;
+    if (more && pf_lane) {
+      s_gid[buf ^ 1][pf] = pgid;
+      s_r0[buf ^ 1][pf] = p0;
+      s_r1[buf ^ 1][pf] = p1;
+      s_r2[buf ^ 1][pf] = p2;
+    }
+    lds_barrier();  // products consumed, next records visible
+    if (!more) break;
+    b1 = nb1;
+    b0 = nb0;
+    nb1 = mb1;
+    nb0 = mb0;
+    buf ^= 1;
   }
 }
 
@@ -576,20 +712,26 @@ static void launch_bwd_dispatch(int cn, const DevSettings& st, const DevGaussian
                                 const Layout& L, const WsView& w, int c0, const float* g_rgb,
                                 const float* g_depth, const float* g_alpha, const float* g_feat,
                                 float* d_feat, const L1Upstream& l1, hipStream_t s) {
-  if (cn <= 0)
-    launch_bwd_t<0, GEO, L1>(st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat, d_feat, l1, s);
-  else if (cn <= 8)
+  if (cn <= 0) {
+    if constexpr (GEO)
+      launch_bwd_t<0, GEO, L1>(st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat, d_feat, l1, s);
+  } else if (cn <= 8) {
     launch_bwd_t<8, GEO, L1>(st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat, d_feat, l1, s);
-  else if (cn <= 16)
+  } else if (cn <= 16) {
     launch_bwd_t<16, GEO, L1>(st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat, d_feat, l1, s);
-  else if (cn <= 32)
+  } else if (cn <= 32) {
     launch_bwd_t<32, GEO, L1>(st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat, d_feat, l1, s);
-  else
-    launch_bwd_t<64, GEO, L1>(st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat, d_feat, l1, s);
+  } else {
+    if constexpr (!GEO)
+      launch_bwd_t<64, GEO, L1>(st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat, d_feat, l1, s);
+  }
 }
 
 // l1 == nullptr: explicit upstream gradients; otherwise the L1 upstream is
 // formed inside the kernel (feature group on iff l1->t_feat is set).
+// Channel passes: the geometry pass carries up to kBwdGeoChannels feature
+// channels, every further pass up to kBwdMaxChannels; each pass recomputes
+// the blending weights.
 hipError_t launch_composite_bwd_impl(const DevGaussians& g, const DevSettings& st,
                                      const Layout& L, const WsView& w, const float* g_rgb,
                                      const float* g_depth, const float* g_alpha,
@@ -607,32 +749,31 @@ hipError_t launch_composite_bwd_impl(const DevGaussians& g, const DevSettings& s
     hipLaunchKernelGGL(k_fill_zero<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                        d_feat, n);
   }
+  if (L.P == 0 && !l1) return hipGetLastError();
   L1Upstream none{};
   const L1Upstream& u = l1 ? *l1 : none;
-  const int nchunks = feat_on ? (g.C + GSFF_MAX_CHANNELS_PER_PASS - 1) / GSFF_MAX_CHANNELS_PER_PASS
-                              : 1;
-  for (int k = 0; k < nchunks; ++k) {
-    const int c0 = k * GSFF_MAX_CHANNELS_PER_PASS;
-    const int cn = feat_on ? min(GSFF_MAX_CHANNELS_PER_PASS, g.C - c0) : 0;
-    // the geometry chunk also carries the rgb / depth / alpha loss terms
-    const bool geo = geometry && k == 0;
-    if (!geo && cn == 0) continue;
-    if (L.P == 0 && !l1) continue;
-    if (l1) {
-      if (geo)
+  const int C = feat_on ? g.C : 0;
+  int c0 = 0;
+  bool geo = geometry;
+  while (geo || c0 < C) {
+    const int cn = min(geo ? kBwdGeoChannels : kBwdMaxChannels, C - c0);
+    if (geo) {
+      if (l1)
         launch_bwd_dispatch<true, true>(cn, st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat,
                                         d_feat, u, s);
       else
-        launch_bwd_dispatch<false, true>(cn, st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat,
+        launch_bwd_dispatch<true, false>(cn, st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat,
                                          d_feat, u, s);
     } else {
-      if (geo)
-        launch_bwd_dispatch<true, false>(cn, st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat,
+      if (l1)
+        launch_bwd_dispatch<false, true>(cn, st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat,
                                          d_feat, u, s);
       else
         launch_bwd_dispatch<false, false>(cn, st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat,
                                           d_feat, u, s);
     }
+    c0 += cn;
+    geo = false;
   }
   return hipGetLastError();
 }
