@@ -26,8 +26,6 @@
 
 namespace gsff {
 
-constexpr int kFwdBatch = 64;
-constexpr int kBwdBatch = 64;
 constexpr int kNumXcd = 8;
 
 __device__ __forceinline__ int xcd_tile(int b, int ntiles) {
@@ -104,77 +102,263 @@ __device__ __forceinline__ AlphaEval eval_alpha(const float4 r0, const float4 r1
   return e;
 }
 
+// ------------------------------------------------------ matrix helpers -----
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// x = hi + lo + r with hi = bf16(x), lo = bf16(x - hi), |r| <= 2^-16 |x|.
+__device__ __forceinline__ void split8(const float4 a, const float4 b, bf16x8& hi, bf16x8& lo) {
+  const float v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    hi[t] = (__bf16)v[t];
+    lo[t] = (__bf16)(v[t] - (float)hi[t]);
+  }
+}
+
+__device__ __forceinline__ bf16x8 to_bf16x8(const float4 a, const float4 b) {
+  bf16x8 h;
+  h[0] = (__bf16)a.x; h[1] = (__bf16)a.y; h[2] = (__bf16)a.z; h[3] = (__bf16)a.w;
+  h[4] = (__bf16)b.x; h[5] = (__bf16)b.y; h[6] = (__bf16)b.z; h[7] = (__bf16)b.w;
+  return h;
+}
+
+// D += A B for one 16x16x32 BF16 tile (FP32 accumulate).  Lane l holds
+// A[l % 16][8 (l / 16) .. +7], B[8 (l / 16) .. +7][l % 16] and
+// D[4 (l / 16) + r][l % 16] in acc[r].
+__device__ __forceinline__ f32x4 mfma16(const bf16x8 a, const bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Workgroup barrier that orders LDS only: global loads and atomics issued
+// before it stay in flight (a full __syncthreads() would wait for every
+// outstanding global access of the wave).  All communication between the
+// waves of the compositing kernels goes through LDS.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ------------------------------------------------------------ forward -----
 
+constexpr int kFwdNB = 16;       // Gaussians per batch
+constexpr int kFwdWStride = 20;  // LDS row stride (floats) of a pixel's batch weights
+constexpr int kFwdFStride = 24;  // LDS row stride (bf16) of a channel's batch features
+
+template <typename FT>
+__device__ __forceinline__ void feat_split(const FT* p, int64_t i, __bf16& hi, __bf16& lo) {
+  const float v = load_feat(p, i);
+  hi = (__bf16)v;
+  lo = (__bf16)(v - (float)hi);
+}
+__device__ __forceinline__ void feat_split(const uint16_t* p, int64_t i, __bf16& hi, __bf16& lo) {
+  hi = __builtin_bit_cast(__bf16, p[i]);  // BF16 payload: exact
+  lo = (__bf16)0.f;
+}
+
+// Front-to-back compositing of one tile per workgroup, one thread per pixel.
+//
+// The tile's list is walked in batches of 16 Gaussians:
+//  phase A  each thread walks the batch front to front, branch-free: alpha,
+//           the skip / stop decisions, the blending weight w, transmittance
+//           and the colour and depth sums (FP32, in list order); the 16
+//           weights go to the wave's own LDS rows.
+//  phase B  the feature sums of the wave's 64 pixels for the batch are one
+//           16x16x32 BF16 matrix product per 16 pixels x 16 channels: K
+//           holds the 16 weights twice, as hi and as lo BF16 parts, against
+//           the BF16 features (exact for a BF16 payload; FP32 / FP16
+//           payloads add a second product with the features' lo parts), so
+//           every product keeps about 2^-16 relative accuracy and the
+//           accumulation is FP32.
+// Records, ids and features of the next batches are loaded while a batch is
+// processed (ids two batches ahead); one LDS-only barrier per batch.  The
+// workgroup stops after the batch in which its last pixel saturated.
+// Register budget: every tile of a 640x480 frame resident at once needs five
+// workgroups (waves) per CU (SIMD); wider channel blocks hold more accumulators.
 template <int CP, typename FT, typename OT>
-__global__ __launch_bounds__(kBlock) void k_composite_fwd(
+__global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
+                          amdgpu_waves_per_eu(CP <= 16 ? 5 : (CP <= 32 ? 4 : 3))))
+void k_composite_fwd(
     DevSettings st, int64_t P, int C, int c0, int W, int H, int tiles_x, int ntiles,
     int rank_bits, uint32_t max_pairs, WsView w, const FT* __restrict__ feat,
-    float* __restrict__ out_rgb,
-    float* __restrict__ out_depth, float* __restrict__ out_alpha, OT* __restrict__ out_feat,
-    int write_geo) {
+    float* __restrict__ out_rgb, float* __restrict__ out_depth, float* __restrict__ out_alpha,
+    OT* __restrict__ out_feat, int write_geo) {
+  constexpr int NB = kFwdNB;
+  constexpr int NCB = (CP + 15) / 16;                   // 16-channel output blocks
+  constexpr bool EXACT = sizeof(FT) == 2 && !__is_same(FT, _Float16);  // BF16 payload
   constexpr int CPs = CP > 0 ? CP : 1;
-  __shared__ float4 s_r0[kFwdBatch], s_r1[kFwdBatch], s_r2[kFwdBatch];
-  __shared__ float s_f[kFwdBatch][CPs];
+  constexpr int FPT = CP > 0 ? (NB * CP + kBlock - 1) / kBlock : 0;  // features per thread
+  __shared__ __attribute__((aligned(16))) float s_w[kBlock][kFwdWStride];
+  __shared__ __attribute__((aligned(16))) __bf16 s_fh[2][CPs][kFwdFStride];
+  __shared__ __attribute__((aligned(16))) __bf16 s_fl[EXACT ? 1 : 2][EXACT ? 1 : CPs][kFwdFStride];
+  __shared__ float4 s_r0[2][NB], s_r1[2][NB], s_r2[2][NB];
+  __shared__ uint32_t s_ids[2][NB];
+  __shared__ int s_act[2][kBlock / 64];
   const int tile = xcd_tile(blockIdx.x, ntiles);
   if (tile >= ntiles) return;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63, lq = lane >> 4, lj = lane & 15;
   const int tx = tile % tiles_x, ty = tile / tiles_x;
-  const int px = tx * kTile + (threadIdx.x & (kTile - 1));
-  const int py = ty * kTile + (threadIdx.x / kTile);
+  const int px = tx * kTile + (tid & (kTile - 1));
+  const int py = ty * kTile + (tid / kTile);
   const bool inside = px < W && py < H;
   const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
   const uint2 range = clamp_range(w.tile_ranges[tile], max_pairs);
   const uint32_t rmask = (rank_bits >= 32) ? 0xFFFFFFFFu : ((1u << rank_bits) - 1u);
   const int cn = CP > 0 ? min(CP, C - c0) : 0;
+  // loads are issued by the first 16 lanes of the last wave
+  const int pf = tid - (kBlock - 64);
+  const bool pf_lane = pf >= 0 && pf < NB;
 
   float T = 1.f, cr = 0.f, cg = 0.f, cb = 0.f, dep = 0.f;
-  float acc[CPs];
-#pragma unroll
-  for (int c = 0; c < CPs; ++c) acc[c] = 0.f;
   bool done = !inside;
   uint32_t end = range.x;
-
-  for (uint32_t b0 = range.x; b0 < range.y; b0 += kFwdBatch) {
-    if (__syncthreads_count(!done) == 0) break;
-    const uint32_t n = min((uint32_t)kFwdBatch, range.y - b0);
-    if (threadIdx.x < n) {
-      const uint32_t gid = pair_gid(w, b0 + threadIdx.x, rmask, P);
-      load_record(w, gid, P, s_r0[threadIdx.x], s_r1[threadIdx.x], s_r2[threadIdx.x]);
-      if (CP > 0) {
+  f32x4 acc[4][NCB > 0 ? NCB : 1];
 #pragma unroll
-        for (int c = 0; c < CP; ++c)
-          s_f[threadIdx.x][c] =
-              (c < cn && gid < (uint32_t)P) ? load_feat(feat, (int64_t)gid * C + c0 + c) : 0.f;
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int k = 0; k < (NCB > 0 ? NCB : 1); ++k) acc[rb][k] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  // ---- prologue: ids, records and features of batch 0, ids of batch 1
+  uint32_t g_next = (uint32_t)P;
+  if (range.x < range.y) {
+    if (pf_lane) {
+      const uint32_t idx = range.x + pf;
+      const uint32_t gid = idx < range.y ? pair_gid(w, idx, rmask, P) : (uint32_t)P;
+      s_ids[0][pf] = gid;
+      load_record(w, gid, P, s_r0[0][pf], s_r1[0][pf], s_r2[0][pf]);
+      const uint32_t nidx = range.x + NB + pf;
+      if (nidx < range.y) g_next = w.pkeys_a[nidx];
+    }
+    lds_barrier();
+    if constexpr (CP > 0) {
+#pragma unroll
+      for (int k = 0; k < FPT; ++k) {
+        const int e = tid + kBlock * k;
+        const int g = e / CP, c = e % CP;
+        if (g < NB) {
+          const uint32_t gid = s_ids[0][g];
+          __bf16 h = (__bf16)0.f, l = (__bf16)0.f;
+          if (c < cn && gid < (uint32_t)P) feat_split(feat, (int64_t)gid * C + c0 + c, h, l);
+          s_fh[0][c][g] = h;
+          if constexpr (!EXACT) s_fl[0][c][g] = l;
+        }
       }
     }
-    __syncthreads();
-    if (!done) {
-      for (uint32_t j = 0; j < n; ++j) {
-        const float4 r0 = s_r0[j], r1 = s_r1[j];
-        const AlphaEval e = eval_alpha(r0, r1, pxc, pyc, st.alpha_max);
-        if (e.alpha < st.alpha_min) continue;
-        const float Tn = T * (1.f - e.alpha);
-        if (Tn < st.t_min) {
-          done = true;
-          break;
+    if (pf_lane) s_ids[1][pf] = g_next;
+    lds_barrier();
+  }
+
+  int buf = 0;
+  for (uint32_t b0 = range.x; b0 < range.y; b0 += NB) {
+    const bool more = b0 + NB < range.y;
+    // ---- loads for the next batch (ids already in LDS) and ids two ahead
+    float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f), p1 = p0, p2 = p0;
+    uint32_t g_after = (uint32_t)P;
+    if (more && pf_lane) {
+      load_record(w, s_ids[buf ^ 1][pf], P, p0, p1, p2);
+      const uint32_t idx = b0 + 2 * NB + pf;
+      if (idx < range.y) g_after = w.pkeys_a[idx];
+    }
+    __bf16 fh[FPT > 0 ? FPT : 1], fl[FPT > 0 ? FPT : 1];
+    if constexpr (CP > 0) {
+#pragma unroll
+      for (int k = 0; k < FPT; ++k) {
+        fh[k] = (__bf16)0.f;
+        fl[k] = (__bf16)0.f;
+        const int e = tid + kBlock * k;
+        const int g = e / CP, c = e % CP;
+        if (more && g < NB) {
+          const uint32_t gid = s_ids[buf ^ 1][g];
+          if (c < cn && gid < (uint32_t)P) feat_split(feat, (int64_t)gid * C + c0 + c, fh[k], fl[k]);
         }
-        const float wgt = e.alpha * T;
-        const float4 r2 = s_r2[j];
+      }
+    }
+
+    const bool wave_active = __ballot(!done) != 0ull;
+    if (wave_active) {
+      // ---- phase A: weights, transmittance, colour and depth, front to back
+      float wv[4];
+#pragma unroll
+      for (int jj = 0; jj < NB; ++jj) {
+        const float4 r0 = s_r0[buf][jj], r1 = s_r1[buf][jj], r2 = s_r2[buf][jj];
+        const AlphaEval e = eval_alpha(r0, r1, pxc, pyc, st.alpha_max);
+        const bool valid = !done && e.alpha >= st.alpha_min;
+        const float Tn = T * (1.f - e.alpha);
+        const bool stop = valid && Tn < st.t_min;
+        const bool use = valid && !stop;
+        done = done || stop;
+        const float wgt = use ? e.alpha * T : 0.f;
         cr += wgt * r2.x;
         cg += wgt * r2.y;
         cb += wgt * r2.z;
         dep += wgt * r1.z;
+        T = use ? Tn : T;
+        end = use ? b0 + (uint32_t)jj + 1u : end;
+        wv[jj & 3] = wgt;
+        if (CP > 0 && (jj & 3) == 3)
+          reinterpret_cast<float4*>(&s_w[tid][0])[jj >> 2] = make_float4(wv[0], wv[1], wv[2], wv[3]);
+      }
+      if constexpr (CP > 0) {
+        // the wave reads back only its own rows
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+        // ---- phase B: feature sums on the matrix cores
+        const int gk = 8 * (lq & 1);  // Gaussians gk .. gk+7 of the batch
 #pragma unroll
-        for (int c = 0; c < CP; ++c) acc[c] += wgt * s_f[j][c];
-        T = Tn;
-        end = b0 + j + 1;
+        for (int rb = 0; rb < 4; ++rb) {
+          const float* src = &s_w[64 * wave + 16 * rb + lj][gk];
+          bf16x8 hi, lo;
+          split8(*reinterpret_cast<const float4*>(src), *reinterpret_cast<const float4*>(src + 4),
+                 hi, lo);
+          const bf16x8 a = lq < 2 ? hi : lo;
+#pragma unroll
+          for (int k = 0; k < NCB; ++k) {
+            const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&s_fh[buf][16 * k + lj][gk]);
+            acc[rb][k] = mfma16(a, bh, acc[rb][k]);
+            if constexpr (!EXACT) {
+              bf16x8 bl = *reinterpret_cast<const bf16x8*>(&s_fl[buf][16 * k + lj][gk]);
+              if (lq >= 2) bl = bf16x8{};
+              acc[rb][k] = mfma16(a, bl, acc[rb][k]);
+            }
+          }
+        }
       }
     }
+    // ---- stage the next batch, report activity
+    if (more) {
+      if (pf_lane) {
+        s_r0[buf ^ 1][pf] = p0;
+        s_r1[buf ^ 1][pf] = p1;
+        s_r2[buf ^ 1][pf] = p2;
+        s_ids[buf][pf] = g_after;  // the slot of batch b + 2
+      }
+      if constexpr (CP > 0) {
+#pragma unroll
+        for (int k = 0; k < FPT; ++k) {
+          const int e = tid + kBlock * k;
+          const int g = e / CP, c = e % CP;
+          if (g < NB) {
+            s_fh[buf ^ 1][c][g] = fh[k];
+            if constexpr (!EXACT) s_fl[buf ^ 1][c][g] = fl[k];
+          }
+        }
+      }
+    }
+    const bool still = __ballot(!done) != 0ull;
+    if (lane == 0) s_act[buf][wave] = still ? 1 : 0;
+    lds_barrier();
+    if (!more) break;
+    if ((s_act[buf][0] | s_act[buf][1] | s_act[buf][2] | s_act[buf][3]) == 0) break;
+    buf ^= 1;
   }
-  if (!inside) return;
+
   const int64_t HW = (int64_t)W * H;
-  const int64_t p = (int64_t)py * W + px;
-  if (write_geo) {
+  if (inside && write_geo) {
+    const int64_t p = (int64_t)py * W + px;
     out_rgb[p] = cr;
     out_rgb[HW + p] = cg;
     out_rgb[2 * HW + p] = cb;
@@ -183,10 +367,24 @@ __global__ __launch_bounds__(kBlock) void k_composite_fwd(
     w.pix_T[p] = T;
     w.pix_end[p] = end;
   }
-  if (CP > 0 && out_feat) {
+  if constexpr (CP > 0) {
+    if (out_feat) {
+      // acc[rb][k][r]: pixel 64 wave + 16 rb + 4 lq + r of the tile, channel 16 k + lj
 #pragma unroll
-    for (int c = 0; c < CP; ++c)
-      if (c < cn) store_out(out_feat, (int64_t)(c0 + c) * HW + p, acc[c]);
+      for (int k = 0; k < NCB; ++k) {
+        const int c = 16 * k + lj;
+        if (c >= cn) continue;
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int tp = 64 * wave + 16 * rb + 4 * lq + r;
+            const int qx = tx * kTile + (tp & (kTile - 1)), qy = ty * kTile + tp / kTile;
+            if (qx < W && qy < H)
+              store_out(out_feat, (int64_t)(c0 + c) * HW + (int64_t)qy * W + qx, acc[rb][k][r]);
+          }
+      }
+    }
   }
 }
 
@@ -279,34 +477,12 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kBwdNB = 16;              // Gaussians per batch = rows of the contraction
 constexpr int kBwdStride = kBlock + 4;  // LDS row stride (floats) of the per-pair products
 constexpr int kBwdGeoChannels = 32;     // feature channels carried by the geometry pass
 constexpr int kBwdMaxChannels = 64;     // feature channels of a feature-only pass
 
-// x = hi + lo + r with hi = bf16(x), lo = bf16(x - hi), |r| <= 2^-16 |x|.
-__device__ __forceinline__ void split8(const float4 a, const float4 b, bf16x8& hi, bf16x8& lo) {
-  const float v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
-#pragma unroll
-  for (int t = 0; t < 8; ++t) {
-    hi[t] = (__bf16)v[t];
-    lo[t] = (__bf16)(v[t] - (float)hi[t]);
-  }
-}
-
-__device__ __forceinline__ bf16x8 to_bf16x8(const float4 a, const float4 b) {
-  bf16x8 h;
-  h[0] = (__bf16)a.x; h[1] = (__bf16)a.y; h[2] = (__bf16)a.z; h[3] = (__bf16)a.w;
-  h[4] = (__bf16)b.x; h[5] = (__bf16)b.y; h[6] = (__bf16)b.z; h[7] = (__bf16)b.w;
-  return h;
-}
-
-__device__ __forceinline__ f32x4 mfma16(const bf16x8 a, const bf16x8 b, f32x4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
 
 // Upstream gradient formed inside the adjoint for the L1 losses of the
 // method (Eqs. 5, 8, 11 are weighted sums of L1 terms):
@@ -365,15 +541,6 @@ __device__ __forceinline__ float l1_unit_sign(float o, float t, float scale, flo
 // Register budget: four waves per SIMD (four workgroups per CU, which the
 // LDS use also allows); the explicit-upstream variant keeps twice the right
 // operands in registers and runs three.
-// Workgroup barrier that orders LDS only: global loads and atomics issued
-// before it stay in flight (a full __syncthreads() would wait for every
-// outstanding global atomic of the wave).  All communication between the
-// waves of the adjoint goes through LDS.
-__device__ __forceinline__ void lds_barrier() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
 
 template <int CP, bool GEO, bool L1>
 __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
