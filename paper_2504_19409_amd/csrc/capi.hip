@@ -41,7 +41,7 @@ bool compute_layout(int64_t P, int64_t max_pairs, int32_t W, int32_t H, Layout* 
   l.direct_bin = l.ntiles <= kMaxDirectTiles;
   // the fallback path packs (tile, rank) into 32-bit keys
   if (!l.direct_bin && l.rank_bits + l.tile_bits > 32) return false;
-  l.depth_chunks = (P + kRadixChunk - 1) / kRadixChunk;
+  l.depth_chunks = (P + kDepthChunk - 1) / kDepthChunk;
   l.pair_chunks = (max_pairs + kRadixChunk - 1) / kRadixChunk;
   l.scan_blocks = (P + kScanBlock - 1) / kScanBlock;
   l.pose_blocks = (P + kPoseBlock - 1) / kPoseBlock;
@@ -76,6 +76,8 @@ bool compute_layout(int64_t P, int64_t max_pairs, int32_t W, int32_t H, Layout* 
   l.pose_part = take(8ull * 6 * (uint64_t)(l.pose_blocks + 1));
   l.binhist = take(l.direct_bin ? 4ull * l.ntiles * (uint64_t)l.bin_blocks : 0ull);
   l.tile_tot = take(l.direct_bin ? 4ull * l.ntiles : 0ull);
+  l.curbase = take(l.direct_bin ? 4ull * l.ntiles * (uint64_t)l.bin_blocks : 0ull);
+
   l.total = o;
   *L = l;
   return true;
@@ -104,6 +106,7 @@ WsView make_view(void* ws, const Layout& L) {
   w.pose_part = (double*)(b + L.pose_part);
   w.binhist = (uint32_t*)(b + L.binhist);
   w.tile_tot = (uint32_t*)(b + L.tile_tot);
+  w.curbase = (uint32_t*)(b + L.curbase);
   return w;
 }
 

@@ -12,8 +12,10 @@ namespace gsff {
 
 constexpr int kTile = GSFF_TILE;           // 16x16 pixel screen tiles
 constexpr int kBlock = kTile * kTile;      // one thread per pixel of a tile
-constexpr int kRadixIpt = 16;              // keys per lane in a radix chunk
-constexpr int kRadixChunk = 64 * kRadixIpt;  // keys per wave chunk
+constexpr int kRadixIpt = 16;              // keys per lane in a pair-sort radix chunk
+constexpr int kRadixChunk = 64 * kRadixIpt;  // keys per wave chunk (pair sort)
+constexpr int kDepthIpt = 4;               // keys per lane in a depth-sort radix chunk
+constexpr int kDepthChunk = 64 * kDepthIpt;  // small chunks: a 200k-key sort fills the chip
 constexpr int kScanBlock = 1024;           // elements per block in the count scan
 constexpr int kPoseBlock = 256;            // Gaussians per preprocess-adjoint block
 constexpr int kMaxDirectTiles = 4096;      // tile grids binned without a pair sort
@@ -38,7 +40,7 @@ struct Layout {
   uint64_t status = 0, records = 0, rects = 0, dkeys_a = 0, dkeys_b = 0, dids_a = 0,
            dids_b = 0, offsets = 0, pkeys_a = 0, pkeys_b = 0, tile_ranges = 0, pix_T = 0,
            pix_end = 0, grad2d = 0, hist = 0, hist_tot = 0, scan_part = 0, pose_part = 0,
-           binhist = 0, tile_tot = 0, total = 0;
+           binhist = 0, tile_tot = 0, curbase = 0, total = 0;
 };
 
 // Returns false if the sizes are not representable (key bits, negative sizes).
@@ -66,6 +68,7 @@ struct WsView {
   double* pose_part;     // [pose_blocks][6]
   uint32_t* binhist;     // direct binning: per-tile counts per rank block [ntiles][blocks]
   uint32_t* tile_tot;    // direct binning: pairs per tile [ntiles]
+  uint32_t* curbase;     // direct binning: pairs of earlier blocks per tile [blocks][ntiles]
 };
 
 WsView make_view(void* ws, const Layout& L);

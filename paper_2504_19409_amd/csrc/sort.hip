@@ -18,7 +18,8 @@
 //      for the tile ranges and a final rank -> id conversion.
 // Either way the pair buffer ends up holding Gaussian ids grouped by tile.
 //
-// Radix passes: every wave owns a chunk of kRadixChunk consecutive keys.
+// Radix passes: every wave owns a chunk of 64 * IPT consecutive keys (256 for the
+// depth sort, 1024 for the pair sort).
 //   hist    : per-chunk digit histogram (LDS atomics) -> hist[digit][chunk]
 //   rowscan : one block per digit, exclusive scan along the chunk axis,
 //             digit totals -> hist_tot
@@ -67,6 +68,7 @@ __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t* s_t
 
 // ---------------------------------------------------------------- radix ----
 
+template <int IPT>
 __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__ keys,
                                                     const uint32_t* __restrict__ n_dev,
                                                     uint32_t n_static, int shift, int nbits,
@@ -80,9 +82,9 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__
   for (uint32_t d = lane; d < nbins; d += 64) s_hist[wv][d] = 0u;
   __syncthreads();
   if (chunk < nchunks) {
-    const uint64_t base = (uint64_t)chunk * kRadixChunk;
+    const uint64_t base = (uint64_t)chunk * (64 * IPT);
 #pragma unroll
-    for (int it = 0; it < kRadixIpt; ++it) {
+    for (int it = 0; it < IPT; ++it) {
       const uint64_t idx = base + (uint64_t)it * 64 + lane;
       if (idx < n) atomicAdd(&s_hist[wv][(keys[idx] >> shift) & mask], 1u);
     }
@@ -109,7 +111,7 @@ __global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t* __restrict__ hi
   if (threadIdx.x == 0) hist_tot[d] = carry;
 }
 
-template <bool HasVals>
+template <int IPT, bool HasVals>
 __global__ __launch_bounds__(256) void k_radix_scatter(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
@@ -134,18 +136,18 @@ __global__ __launch_bounds__(256) void k_radix_scatter(
   if (chunk >= nchunks) return;  // whole wave; no barrier follows
   for (uint32_t d = lane; d < nbins; d += 64)
     s_cnt[wv][d] = s_base[d] + hist[(uint64_t)d * nchunks + chunk];
-  const uint64_t base = (uint64_t)chunk * kRadixChunk;
-  uint32_t k[kRadixIpt];
-  uint32_t v[kRadixIpt];
+  const uint64_t base = (uint64_t)chunk * (64 * IPT);
+  uint32_t k[IPT];
+  uint32_t v[IPT];
 #pragma unroll
-  for (int it = 0; it < kRadixIpt; ++it) {
+  for (int it = 0; it < IPT; ++it) {
     const uint64_t idx = base + (uint64_t)it * 64 + lane;
     k[it] = (idx < n) ? keys_in[idx] : 0u;
     if (HasVals) v[it] = (idx < n) ? vals_in[idx] : 0u;
   }
   const uint64_t lt = lanemask_lt(lane);
 #pragma unroll
-  for (int it = 0; it < kRadixIpt; ++it) {
+  for (int it = 0; it < IPT; ++it) {
     const uint64_t idx = base + (uint64_t)it * 64 + lane;
     const bool valid = idx < n;
     const uint32_t d = (k[it] >> shift) & mask;
@@ -166,21 +168,25 @@ __global__ __launch_bounds__(256) void k_radix_scatter(
   }
 }
 
+// One stable LSD pass over nbits digits at `shift`; chunks of 64 * IPT keys.
+template <int IPT>
 static hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
                              uint32_t* vout, const uint32_t* n_dev, uint32_t n_static,
                              int shift, int nbits, int nchunks, uint32_t cap, const WsView& w,
                              hipStream_t s) {
   const unsigned blocks = (unsigned)((nchunks + 3) / 4);
-  hipLaunchKernelGGL(k_radix_hist, dim3(blocks), dim3(256), 0, s, kin, n_dev, n_static, shift,
-                     nbits, w.hist, nchunks, cap);
+  hipLaunchKernelGGL(k_radix_hist<IPT>, dim3(blocks), dim3(256), 0, s, kin, n_dev, n_static,
+                     shift, nbits, w.hist, nchunks, cap);
   hipLaunchKernelGGL(k_radix_rowscan, dim3(1u << nbits), dim3(256), 0, s, w.hist, nchunks,
                      w.hist_tot);
   if (vin)
-    hipLaunchKernelGGL(k_radix_scatter<true>, dim3(blocks), dim3(256), 0, s, kin, vin, kout, vout,
-                       n_dev, n_static, shift, nbits, w.hist, w.hist_tot, nchunks, cap);
+    hipLaunchKernelGGL((k_radix_scatter<IPT, true>), dim3(blocks), dim3(256), 0, s, kin, vin,
+                       kout, vout, n_dev, n_static, shift, nbits, w.hist, w.hist_tot, nchunks,
+                       cap);
   else
-    hipLaunchKernelGGL(k_radix_scatter<false>, dim3(blocks), dim3(256), 0, s, kin, nullptr, kout,
-                       nullptr, n_dev, n_static, shift, nbits, w.hist, w.hist_tot, nchunks, cap);
+    hipLaunchKernelGGL((k_radix_scatter<IPT, false>), dim3(blocks), dim3(256), 0, s, kin,
+                       nullptr, kout, nullptr, n_dev, n_static, shift, nbits, w.hist, w.hist_tot,
+                       nchunks, cap);
   return hipGetLastError();
 }
 
@@ -191,8 +197,8 @@ hipError_t launch_sort_depth(const Layout& L, const WsView& w, hipStream_t s) {
   uint32_t* va = w.dids_a;
   uint32_t* vb = w.dids_b;
   for (int pass = 0; pass < 4; ++pass) {
-    hipError_t e = radix_pass(ka, va, kb, vb, nullptr, (uint32_t)L.P, pass * 8, 8,
-                              (int)L.depth_chunks, (uint32_t)L.P, w, s);
+    hipError_t e = radix_pass<kDepthIpt>(ka, va, kb, vb, nullptr, (uint32_t)L.P, pass * 8, 8,
+                                         (int)L.depth_chunks, (uint32_t)L.P, w, s);
     if (e != hipSuccess) return e;
     uint32_t* t = ka;
     ka = kb;
@@ -207,11 +213,11 @@ hipError_t launch_sort_depth(const Layout& L, const WsView& w, hipStream_t s) {
 hipError_t launch_sort_tiles(const Layout& L, const WsView& w, hipStream_t s) {
   if (L.direct_bin || L.P == 0 || L.tile_bits == 0 || L.max_pairs == 0) return hipSuccess;
   const int n1 = (L.tile_bits + 1) / 2, n2 = L.tile_bits - n1;
-  hipError_t e = radix_pass(w.pkeys_a, nullptr, w.pkeys_b, nullptr, w.status + 2, 0u,
+  hipError_t e = radix_pass<kRadixIpt>(w.pkeys_a, nullptr, w.pkeys_b, nullptr, w.status + 2, 0u,
                             L.rank_bits, n1, (int)L.pair_chunks, (uint32_t)L.max_pairs, w, s);
   if (e != hipSuccess) return e;
   // second pass (possibly 0 bits: a stable copy) brings the keys back to pkeys_a
-  return radix_pass(w.pkeys_b, nullptr, w.pkeys_a, nullptr, w.status + 2, 0u,
+  return radix_pass<kRadixIpt>(w.pkeys_b, nullptr, w.pkeys_a, nullptr, w.status + 2, 0u,
                     L.rank_bits + n1, n2, (int)L.pair_chunks, (uint32_t)L.max_pairs, w, s);
 }
 
@@ -368,18 +374,20 @@ __global__ __launch_bounds__(256) void k_bin_hist(WsView w, int64_t P, int ntile
     w.binhist[(int64_t)t * nblk + blockIdx.x] = s_h[t];
 }
 
-// one wave per tile: exclusive scan of its counts along the blocks
+// One wave per tile: exclusive scan of its counts along the blocks, written
+// block-major to curbase[block][tile] so each scatter block reads its row
+// contiguously; tile totals.
 __global__ __launch_bounds__(256) void k_bin_colscan(WsView w, int ntiles, int nblk) {
   const int lane = threadIdx.x & 63;
   const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (t >= ntiles) return;  // whole wave
-  uint32_t* col = w.binhist + (int64_t)t * nblk;
+  const uint32_t* col = w.binhist + (int64_t)t * nblk;
   uint32_t carry = 0;
   for (int b0 = 0; b0 < nblk; b0 += 64) {
     const int b = b0 + lane;
     const uint32_t v = b < nblk ? col[b] : 0u;
     const uint32_t inc = wave_incl_scan(v, lane);
-    if (b < nblk) col[b] = carry + inc - v;
+    if (b < nblk) w.curbase[(int64_t)b * ntiles + t] = carry + inc - v;
     carry += __shfl(inc, 63, 64);
   }
   if (lane == 0) w.tile_tot[t] = carry;
@@ -442,7 +450,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter(WsView w, int64_t P, int nt
   wave_walk_pairs(w, r, P, tiles_x, [&](uint32_t t, uint32_t) { atomicAdd(&cw[t], 1u); });
   __syncthreads();
   for (int t = threadIdx.x; t < ntiles; t += 256) {
-    uint32_t cur = w.tile_ranges[t].x + w.binhist[(int64_t)t * nblk + blockIdx.x];
+    uint32_t cur = w.tile_ranges[t].x + w.curbase[(int64_t)blockIdx.x * ntiles + t];
     for (int k = 0; k < 4; ++k) {
       const uint32_t c = s_c[k * ntiles + t];
       s_c[k * ntiles + t] = cur;
