@@ -132,7 +132,9 @@ typedef struct gsff_ws_layout {
   uint64_t tile_ranges; /* uint32[2][ntiles]: [start, end) into pair_keys      */
   uint64_t pix_T;       /* float[H*W]: final transmittance                     */
   uint64_t pix_end;     /* uint32[H*W]: 1 + list position of last contributor  */
-  uint64_t grad2d;      /* float[P][10]: du dv dA dB dC do dr dg db dz         */
+  uint64_t grad2d;      /* float[P][10]: du dv dA dB dC do dr dg db dz; cleared by
+                           gsff_preprocess, accumulated by the compositing
+                           adjoint, consumed and cleared by gsff_preprocess_bwd */
   uint64_t total_bytes;
   int32_t rank_bits;    /* bits of the depth rank inside a pair key            */
   int32_t tiles_x, tiles_y;
@@ -212,7 +214,10 @@ gsff_status gsff_backward_l1(const gsff_gaussians* g, const gsff_camera* cam,
  * two calls above; exposed for stage-by-stage testing and timing.  For tile
  * grids up to 4096 tiles `bin` writes every tile's list directly in depth
  * order and `sort_tiles` / `tile_ranges` have nothing left to do; larger grids
- * sort (tile, rank) keys instead. */
+ * sort (tile, rank) keys instead.  The compositing adjoints accumulate
+ * per-Gaussian image-space gradients inside `ws`, which `preprocess` clears
+ * and `preprocess_bwd` consumes and clears: each composite_bwd (or
+ * composite_bwd_l1) is followed by one preprocess_bwd. */
 gsff_status gsff_preprocess(const gsff_gaussians* g, const gsff_camera* cam,
                             const gsff_settings* st, void* ws, size_t ws_bytes,
                             int64_t max_pairs, void* stream);

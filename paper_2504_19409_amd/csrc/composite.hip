@@ -906,11 +906,8 @@ hipError_t launch_composite_bwd_impl(const DevGaussians& g, const DevSettings& s
                                      int32_t accumulate, const L1Upstream* l1, hipStream_t s) {
   const bool has_gf = l1 ? (l1->t_feat != nullptr && l1->out_feat != nullptr) : g_feat != nullptr;
   const bool feat_on = st.render_features && g.C > 0 && has_gf && d_feat != nullptr;
-  if (geometry && L.P > 0) {
-    const int64_t n = L.P * 10;
-    hipLaunchKernelGGL(k_fill_zero<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                       w.grad2d, n);
-  }
+  // grad2d is zero here: the forward preprocess clears it and the preprocess
+  // adjoint clears it again after consuming it
   if (d_feat && !accumulate && L.P > 0 && g.C > 0) {
     const int64_t n = L.P * g.C;
     hipLaunchKernelGGL(k_fill_zero<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,

@@ -59,6 +59,10 @@ __global__ __launch_bounds__(256) void k_preprocess(DevGaussians g, DevCamera ca
   w.rec[P + i] = r1;
   w.rec[2 * P + i] = r2;
   w.rects[i] = rect;
+  // the image-space gradients the compositing adjoint accumulates start at zero
+  float* d2 = w.grad2d + i * 10;
+#pragma unroll
+  for (int k = 0; k < 10; ++k) d2[k] = 0.f;
   // culled Gaussians keep the largest key and an empty rectangle
   w.dkeys_a[i] = (p.valid && rect.x <= rect.z) ? p.key : 0xFFFFFFFFu;
   w.dids_a[i] = (uint32_t)i;
@@ -76,7 +80,14 @@ __global__ __launch_bounds__(kPoseBlock) void k_preprocess_bwd(DevGaussians g, D
   float pose[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   if (i < P) {
     const Proj p = project_gaussian(g, cam, st, V, i);
-    const float* d = w.grad2d + i * 10;
+    // consume the accumulated image-space gradients and re-arm them at zero,
+    // so another adjoint of the same forward starts from nothing
+    float* d2 = w.grad2d + i * 10;
+    float d[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) d[k] = d2[k];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) d2[k] = 0.f;
     float dmean[3] = {0.f, 0.f, 0.f}, dls[3] = {0.f, 0.f, 0.f}, dq[4] = {0.f, 0.f, 0.f, 0.f};
     float dlogit = 0.f;
     const float drgb[3] = {d[6], d[7], d[8]};
