@@ -150,14 +150,16 @@ const char* gsff_last_error(void);
 /* Fill *st with the defaults listed above (host only). */
 gsff_status gsff_default_settings(gsff_settings* st);
 
-/* Workspace bytes for P Gaussians, a pair capacity of max_pairs
- * (Gaussian-tile overlaps), and a width x height image (host only).
- * Requires ceil(log2(max(P,2))) + ceil(log2(tiles)) <= 32. */
-gsff_status gsff_workspace_size(int64_t P, int64_t max_pairs, int32_t width,
+/* Workspace bytes for P Gaussians with `channels` feature channels (the C of
+ * the gsff_gaussians the workspace will serve; 0..4096), a pair capacity of
+ * max_pairs (Gaussian-tile overlaps), and a width x height image (host only).
+ * Requires ceil(log2(max(P,2))) + ceil(log2(tiles)) <= 32.  The workspace
+ * needs no initialisation. */
+gsff_status gsff_workspace_size(int64_t P, int32_t channels, int64_t max_pairs, int32_t width,
                                 int32_t height, size_t* bytes);
 
 /* Region offsets of a workspace for these sizes (host only). */
-gsff_status gsff_workspace_layout(int64_t P, int64_t max_pairs, int32_t width,
+gsff_status gsff_workspace_layout(int64_t P, int32_t channels, int64_t max_pairs, int32_t width,
                                   int32_t height, gsff_ws_layout* out);
 
 /* Forward render (Sec. 3.1, Eqs. 1-3): preprocess, depth sort, tile binning,
@@ -214,10 +216,13 @@ gsff_status gsff_backward_l1(const gsff_gaussians* g, const gsff_camera* cam,
  * two calls above; exposed for stage-by-stage testing and timing.  For tile
  * grids up to 4096 tiles `bin` writes every tile's list directly in depth
  * order and `sort_tiles` / `tile_ranges` have nothing left to do; larger grids
- * sort (tile, rank) keys instead.  The compositing adjoints accumulate
- * per-Gaussian image-space gradients inside `ws`, which `preprocess` clears
- * and `preprocess_bwd` consumes and clears: each composite_bwd (or
- * composite_bwd_l1) is followed by one preprocess_bwd. */
+ * sort (tile, rank) keys instead.  The compositing adjoints leave their
+ * per-Gaussian sums (image-space terms and feature gradients) inside `ws` as
+ * one row per walked (tile, Gaussian) pair, filed per Gaussian, plus direct
+ * accumulation for tiles whose rows do not fit; `preprocess` resets them and
+ * `preprocess_bwd` adds them up, writes the feature gradient (out->feat, +=)
+ * and resets them again: each composite_bwd (or composite_bwd_l1) is followed
+ * by one preprocess_bwd with the same `out`. */
 gsff_status gsff_preprocess(const gsff_gaussians* g, const gsff_camera* cam,
                             const gsff_settings* st, void* ws, size_t ws_bytes,
                             int64_t max_pairs, void* stream);

@@ -64,8 +64,8 @@ SIGNATURES = {
     "gsff_version": (_i32, [ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "gsff_last_error": (ctypes.c_char_p, []),
     "gsff_default_settings": (_i32, [_S]),
-    "gsff_workspace_size": (_i32, [_i64, _i64, _i32, _i32, ctypes.POINTER(_sz)]),
-    "gsff_workspace_layout": (_i32, [_i64, _i64, _i32, _i32, ctypes.POINTER(WsLayout)]),
+    "gsff_workspace_size": (_i32, [_i64, _i32, _i64, _i32, _i32, ctypes.POINTER(_sz)]),
+    "gsff_workspace_layout": (_i32, [_i64, _i32, _i64, _i32, _i32, ctypes.POINTER(WsLayout)]),
     "gsff_forward": (_i32, [_G, _C, _S, _vp, _sz, _i64, _vp, _vp, _vp, _vp, _i32, _vp]),
     "gsff_backward": (_i32, [_G, _C, _S, _vp, _sz, _i64, _vp, _vp, _vp, _vp, _R, _i32, _vp]),
     "gsff_backward_l1": (_i32, [_G, _C, _S, _vp, _sz, _i64] + [_vp] * 8
@@ -128,15 +128,15 @@ def default_settings(**kw) -> Settings:
     return s
 
 
-def workspace_size(P, max_pairs, width, height) -> int:
+def workspace_size(P, C, max_pairs, width, height) -> int:
     n = _sz(0)
-    check(load().gsff_workspace_size(P, max_pairs, width, height, ctypes.byref(n)),
+    check(load().gsff_workspace_size(P, C, max_pairs, width, height, ctypes.byref(n)),
           "gsff_workspace_size")
     return int(n.value)
 
 
-def workspace_layout(P, max_pairs, width, height) -> WsLayout:
+def workspace_layout(P, C, max_pairs, width, height) -> WsLayout:
     lay = WsLayout()
-    check(load().gsff_workspace_layout(P, max_pairs, width, height, ctypes.byref(lay)),
+    check(load().gsff_workspace_layout(P, C, max_pairs, width, height, ctypes.byref(lay)),
           "gsff_workspace_layout")
     return lay

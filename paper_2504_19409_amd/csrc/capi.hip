@@ -24,10 +24,11 @@ static gsff_status hip_check(hipError_t e, const char* what) {
   return fail(GSFF_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-bool compute_layout(int64_t P, int64_t max_pairs, int32_t W, int32_t H, Layout* L) {
-  if (P < 0 || max_pairs < 0 || W <= 0 || H <= 0) return false;
+bool compute_layout(int64_t P, int32_t C, int64_t max_pairs, int32_t W, int32_t H, Layout* L) {
+  if (P < 0 || C < 0 || C > 4096 || max_pairs < 0 || W <= 0 || H <= 0) return false;
   if (P > (int64_t)0x7FFFFFFF || max_pairs > (int64_t)0xFFFFFFFEu) return false;
   Layout l;
+  l.C = C;
   l.P = P;
   l.max_pairs = max_pairs;
   l.W = W;
@@ -77,6 +78,24 @@ bool compute_layout(int64_t P, int64_t max_pairs, int32_t W, int32_t H, Layout* 
   l.binhist = take(l.direct_bin ? 4ull * l.ntiles * (uint64_t)l.bin_blocks : 0ull);
   l.tile_tot = take(l.direct_bin ? 4ull * l.ntiles : 0ull);
   l.curbase = take(l.direct_bin ? 4ull * l.ntiles * (uint64_t)l.bin_blocks : 0ull);
+  // adjoint partial rows: room for two walked pairs per Gaussian (a tile whose
+  // rows do not fit falls back to atomic accumulation)
+  l.row_width = 10 + C;
+  l.row_cap = 2 * P + 4096;
+  if (l.row_cap > max_pairs + 4096) l.row_cap = max_pairs + 4096;
+  if (l.row_cap > 0xFFFFFFFFll) l.row_cap = 0xFFFFFFFFll;  // 32-bit row indices
+  l.rows = take(4ull * (uint64_t)l.row_cap * (uint64_t)l.row_width);
+  l.tile_walk = take(4ull * l.ntiles);
+  l.walk_off = take(4ull * l.ntiles);
+  l.slot_local = take(4ull * P);
+  l.slot_blk = take(4ull * (uint64_t)(l.pose_blocks + 1));
+  l.nslot = take(4ull * P);
+  l.slots = take(4ull * max_pairs);
+  // a work item per Gaussian with rows, plus one per further full 64 rows
+  l.item_cap = P + l.row_cap / 64 + 1;
+  if (l.item_cap > 0xFFFFFFFFll) l.item_cap = 0xFFFFFFFFll;
+  l.item_n = take(4ull);
+  l.items = take(8ull * (uint64_t)l.item_cap);
 
   l.total = o;
   *L = l;
@@ -107,6 +126,18 @@ WsView make_view(void* ws, const Layout& L) {
   w.binhist = (uint32_t*)(b + L.binhist);
   w.tile_tot = (uint32_t*)(b + L.tile_tot);
   w.curbase = (uint32_t*)(b + L.curbase);
+  w.rows = (float*)(b + L.rows);
+  w.tile_walk = (uint32_t*)(b + L.tile_walk);
+  w.walk_off = (uint32_t*)(b + L.walk_off);
+  w.slot_local = (uint32_t*)(b + L.slot_local);
+  w.slot_blk = (uint32_t*)(b + L.slot_blk);
+  w.nslot = (uint32_t*)(b + L.nslot);
+  w.slots = (uint32_t*)(b + L.slots);
+  w.item_n = (uint32_t*)(b + L.item_n);
+  w.items = (uint2*)(b + L.items);
+  w.row_cap = (uint32_t)L.row_cap;
+  w.row_width = L.row_width;
+  w.item_cap = (uint32_t)L.item_cap;
   return w;
 }
 
@@ -143,7 +174,7 @@ gsff_status check_common(const gsff_gaussians* g, const gsff_camera* cam, const 
     return fail(GSFF_ERR_INVALID_ARGUMENT, "settings out of range");
   if (!ws) return fail(GSFF_ERR_INVALID_ARGUMENT, "NULL workspace");
   if (((uintptr_t)ws & 255u) != 0) return fail(GSFF_ERR_INVALID_ARGUMENT, "workspace not 256-byte aligned");
-  if (!compute_layout(g->P, max_pairs, cam->width, cam->height, &c->L))
+  if (!compute_layout(g->P, g->C, max_pairs, cam->width, cam->height, &c->L))
     return fail(GSFF_ERR_INVALID_ARGUMENT,
                 "sizes not representable (P, max_pairs, image, or rank+tile bits > 32)");
   if (ws_bytes < c->L.total) return fail(GSFF_ERR_INVALID_ARGUMENT, "workspace too small");
@@ -200,21 +231,21 @@ gsff_status gsff_default_settings(gsff_settings* st) {
   return GSFF_OK;
 }
 
-gsff_status gsff_workspace_size(int64_t P, int64_t max_pairs, int32_t width, int32_t height,
-                                size_t* bytes) {
+gsff_status gsff_workspace_size(int64_t P, int32_t channels, int64_t max_pairs, int32_t width,
+                                int32_t height, size_t* bytes) {
   if (!bytes) return fail(GSFF_ERR_INVALID_ARGUMENT, "NULL bytes");
   Layout L;
-  if (!compute_layout(P, max_pairs, width, height, &L))
+  if (!compute_layout(P, channels, max_pairs, width, height, &L))
     return fail(GSFF_ERR_INVALID_ARGUMENT, "sizes not representable");
   *bytes = (size_t)L.total;
   return GSFF_OK;
 }
 
-gsff_status gsff_workspace_layout(int64_t P, int64_t max_pairs, int32_t width, int32_t height,
-                                  gsff_ws_layout* out) {
+gsff_status gsff_workspace_layout(int64_t P, int32_t channels, int64_t max_pairs, int32_t width,
+                                  int32_t height, gsff_ws_layout* out) {
   if (!out) return fail(GSFF_ERR_INVALID_ARGUMENT, "NULL layout");
   Layout L;
-  if (!compute_layout(P, max_pairs, width, height, &L))
+  if (!compute_layout(P, channels, max_pairs, width, height, &L))
     return fail(GSFF_ERR_INVALID_ARGUMENT, "sizes not representable");
   out->status = L.status;
   out->records = L.records;
@@ -347,7 +378,9 @@ gsff_status gsff_backward(const gsff_gaussians* g, const gsff_camera* cam,
   gsff_status rc = hip_check(launch_composite_bwd(c.g, c.st, c.L, c.w, g_rgb, g_depth, g_alpha,
                                                   g_feat, geo, out->feat, accumulate, c.s),
                              "composite_bwd");
-  if (rc != GSFF_OK || !geo) return rc;
+  // the preprocess adjoint also turns the adjoint's rows into out->feat, so it
+  // runs for a feature-only gradient too
+  if (rc != GSFF_OK) return rc;
   return hip_check(launch_preprocess_bwd(c.g, c.cam, c.st, c.L, c.w, *out, accumulate, c.s),
                    "preprocess_bwd");
 }
@@ -376,7 +409,7 @@ static gsff_status backward_l1_impl(const gsff_gaussians* g, const gsff_camera* 
   gsff_status rc = hip_check(launch_composite_bwd_l1(c.g, c.st, c.L, c.w, a, geo, out->feat,
                                                      accumulate, c.s),
                              "composite_bwd_l1");
-  if (rc != GSFF_OK || !geo || !with_preprocess) return rc;
+  if (rc != GSFF_OK || !with_preprocess) return rc;
   return hip_check(launch_preprocess_bwd(c.g, c.cam, c.st, c.L, c.w, *out, accumulate, c.s),
                    "preprocess_bwd");
 }

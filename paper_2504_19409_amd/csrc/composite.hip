@@ -356,6 +356,15 @@ void k_composite_fwd(
     buf ^= 1;
   }
 
+  if (write_geo) {  // uniform: end of the walk of this tile's list, for the adjoint
+    __shared__ uint32_t s_wend;
+    if (tid == 0) s_wend = range.x;
+    lds_barrier();
+    if (inside) atomicMax(&s_wend, end);
+    lds_barrier();
+    if (tid == 0) w.tile_walk[tile] = s_wend;
+  }
+
   const int64_t HW = (int64_t)W * H;
   if (inside && write_geo) {
     const int64_t p = (int64_t)py * W + px;
@@ -392,6 +401,39 @@ template <typename OT>
 __global__ void k_fill_zero(OT* p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = OT(0);
+}
+
+// One block: the adjoint's first row of every tile, an exclusive scan of the
+// walk lengths (the list prefix the forward visited) over the tiles.
+__global__ __launch_bounds__(1024) void k_walk_scan(WsView w, int ntiles, uint32_t max_pairs) {
+  __shared__ uint32_t s_w[16];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t carry = 0;
+  for (int b = 0; b < ntiles; b += 1024) {
+    const int i = b + threadIdx.x;
+    uint32_t v = 0;
+    if (i < ntiles) {
+      const uint2 r = clamp_range(w.tile_ranges[i], max_pairs);
+      const uint32_t e = min(max(w.tile_walk[i], r.x), r.y);
+      v = e - r.x;
+    }
+    uint32_t inc = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t t = __shfl_up(inc, off, 64);
+      if (lane >= off) inc += t;
+    }
+    if (lane == 63) s_w[wv] = inc;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+    for (int k = 0; k < 16; ++k) {
+      if (k < wv) pre += s_w[k];
+      tot += s_w[k];
+    }
+    __syncthreads();
+    if (i < ntiles) w.walk_off[i] = carry + pre + inc - v;
+    carry += tot;
+  }
 }
 
 template <int CP, typename FT, typename OT>
@@ -466,6 +508,7 @@ hipError_t launch_composite_fwd(const DevGaussians& g, const DevSettings& st, co
                                           out_feat, wg, s);
     }
   }
+  hipLaunchKernelGGL(k_walk_scan, dim3(1), dim3(1024), 0, s, w, L.ntiles, (uint32_t)L.max_pairs);
   return hipGetLastError();
 }
 
@@ -548,7 +591,8 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
     DevSettings st, int64_t P, int C, int c0, int W, int H, int tiles_x, int ntiles,
     int rank_bits, uint32_t max_pairs, WsView w, const float* __restrict__ g_rgb,
     const float* __restrict__ g_depth, const float* __restrict__ g_alpha,
-    const float* __restrict__ g_feat, float* __restrict__ d_feat, L1Upstream l1) {
+    const float* __restrict__ g_feat, float* __restrict__ d_feat, L1Upstream l1, int first_pass,
+    int zero_geo, int zero_feat) {
   constexpr int NL = (GEO ? 4 : 0) + CP;      // linear channels: r, g, b, depth, features
   constexpr int NCB = (NL + 15) / 16;         // 16-column blocks of W * G
   constexpr int NT = NCB + (GEO ? 1 : 0);     // output blocks (+ the moments block)
@@ -685,6 +729,13 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
   }
   const uint32_t blk_end = min(s_end, range.y);
   if (blk_end <= range.x) return;  // uniform: no pixel of the tile uses any Gaussian
+  // The tile's results go to one row per walked list position (the rows of
+  // the tiles follow each other in tile order) when they fit; otherwise they
+  // are added to the per-Gaussian gradients with atomics.
+  const uint32_t wstart = w.walk_off[tile];
+  const bool rows_ok = w.tile_walk[tile] == blk_end &&
+                       (uint64_t)wstart + (blk_end - range.x) <= (uint64_t)w.row_cap;
+  const int RW = w.row_width;
 
   // Batches run back to front: [b0, b1), then [nb0, nb1 = b0), then
   // [mb0, mb1 = nb0), ...; only the front-most one can be shorter than 16.
@@ -775,29 +826,47 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
       }
       // acc[r]: Gaussian 4 lq + r of the batch, channel 16 wave + lj
       const int k = 16 * wave + lj;
+      float scale = 1.f;
+      int col = -1;  // column in a row: du dv dA dB dC do dr dg db dz, then features
+      float* dst = nullptr;
+      int64_t stride = 0;
       if (k < NL) {
-        float scale = 1.f;
-        float* dst = nullptr;
-        int64_t stride = 0;
         if (GEO && k < 4) {
           if (L1) scale = k < 3 ? l1.s_rgb : l1.s_depth;
-          dst = w.grad2d + (k < 3 ? 6 + k : 9);
+          col = k < 3 ? 6 + k : 9;
+          dst = w.grad2d + col;
           stride = 10;
         } else {
           const int c = k - (GEO ? 4 : 0);
           if (c < cn) {
             if (L1) scale = l1.s_feat;
+            col = 10 + c0 + c;
             dst = d_feat + c0 + c;
             stride = C;
           }
         }
-        if (dst) {
+      }
+      if (rows_ok) {
+        const uint32_t nb = b1 - b0;  // Gaussians in this batch
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const uint32_t gid = s_gid[buf][4 * lq + r];
-            const float v = acc[r] * scale;
-            if (gid < (uint32_t)P && v != 0.f) unsafeAtomicAdd(dst + (int64_t)gid * stride, v);
+        for (int r = 0; r < 4; ++r) {
+          const uint32_t g = 4 * lq + r;
+          if (g < nb) {
+            float* row = w.rows + (int64_t)(wstart + (b0 + g - range.x)) * RW;
+            if (col >= 0) row[col] = acc[r] * scale;
+            if (wave == 0 && first_pass) {  // columns no pass of this call writes
+              if (zero_geo && lj < 10) row[lj] = 0.f;
+              if (zero_feat)
+                for (int cc = lj; cc < C; cc += 16) row[10 + cc] = 0.f;
+            }
           }
+        }
+      } else if (dst) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const uint32_t gid = s_gid[buf][4 * lq + r];
+          const float v = acc[r] * scale;
+          if (gid < (uint32_t)P && v != 0.f) unsafeAtomicAdd(dst + (int64_t)gid * stride, v);
         }
       }
     } else if constexpr (GEO) {
@@ -822,7 +891,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         if (lane < kBwdNB) {
           const uint32_t gid = s_gid[buf][lane];
-          if (gid < (uint32_t)P) {
+          if (gid < (uint32_t)P && (rows_ok ? (uint32_t)lane < b1 - b0 : true)) {
             const float4 r0 = s_r0[buf][lane], r1 = s_r1[buf][lane];
             const float M0 = s_mom[lane][0], M1 = s_mom[lane][1], M2 = s_mom[lane][2];
             const float M3 = s_mom[lane][3], M4 = s_mom[lane][4], M5 = s_mom[lane][5];
@@ -839,11 +908,33 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
             geo[3] = -Sxy;
             geo[4] = -0.5f * Syy;
             geo[5] = r1.y > 0.f ? M0 * __builtin_amdgcn_rcpf(r1.y) : 0.f;
-            float* dst = w.grad2d + (int64_t)gid * 10;
+            if (rows_ok) {
+              float* row = w.rows + (int64_t)(wstart + (b0 + (uint32_t)lane - range.x)) * RW;
 #pragma unroll
-            for (int f = 0; f < 6; ++f)
-              if (geo[f] != 0.f) unsafeAtomicAdd(dst + f, geo[f]);
+              for (int f = 0; f < 6; ++f) row[f] = geo[f];
+            } else {
+              float* dst = w.grad2d + (int64_t)gid * 10;
+#pragma unroll
+              for (int f = 0; f < 6; ++f)
+                if (geo[f] != 0.f) unsafeAtomicAdd(dst + f, geo[f]);
+            }
           }
+        }
+      }
+    }
+    // the first pass files each valid Gaussian's row in the Gaussian's slots
+    // (a Gaussian has a slot per tile of its rectangle and meets each tile once)
+    // and opens a reduction work item at every 64th slot
+    if (first_pass && rows_ok && pf_lane) {
+      const uint32_t gid = s_gid[buf][pf];
+      if ((uint32_t)pf < b1 - b0 && gid < (uint32_t)P) {
+        const uint32_t row = wstart + (b0 + (uint32_t)pf - range.x);
+        const uint32_t k = atomicAdd(&w.nslot[gid], 1u);
+        const uint32_t sl = w.slot_blk[gid >> 8] + w.slot_local[gid] + k;
+        if (sl < max_pairs) w.slots[sl] = row;
+        if ((k & 63u) == 0u) {
+          const uint32_t t = atomicAdd(w.item_n, 1u);
+          if (t < w.item_cap) w.items[t] = make_uint2(gid, k);
         }
       }
     }
@@ -863,34 +954,46 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
   }
 }
 
+// Which columns of the adjoint rows a pass writes beyond its own: the first
+// pass of a call links the rows and writes zeros where no pass writes.
+struct PassFlags {
+  int first, zero_geo, zero_feat;
+};
+
 template <int CP, bool GEO, bool L1>
 static void launch_bwd_t(const DevSettings& st, const DevGaussians& g, const Layout& L,
                          const WsView& w, int c0, const float* g_rgb, const float* g_depth,
                          const float* g_alpha, const float* g_feat, float* d_feat,
-                         const L1Upstream& l1, hipStream_t s) {
+                         const L1Upstream& l1, const PassFlags& pf, hipStream_t s) {
   const int grid = ((L.ntiles + kNumXcd - 1) / kNumXcd) * kNumXcd;
   hipLaunchKernelGGL((k_composite_bwd<CP, GEO, L1>), dim3(grid), dim3(kBlock), 0, s, st, g.P,
                      g.C, c0, L.W, L.H, L.tiles_x, L.ntiles, L.rank_bits, (uint32_t)L.max_pairs,
-                     w, g_rgb, g_depth, g_alpha, g_feat, d_feat, l1);
+                     w, g_rgb, g_depth, g_alpha, g_feat, d_feat, l1, pf.first, pf.zero_geo,
+                     pf.zero_feat);
 }
 
 template <bool GEO, bool L1>
 static void launch_bwd_dispatch(int cn, const DevSettings& st, const DevGaussians& g,
                                 const Layout& L, const WsView& w, int c0, const float* g_rgb,
                                 const float* g_depth, const float* g_alpha, const float* g_feat,
-                                float* d_feat, const L1Upstream& l1, hipStream_t s) {
+                                float* d_feat, const L1Upstream& l1, const PassFlags& pf,
+                                hipStream_t s) {
   if (cn <= 0) {
     if constexpr (GEO)
-      launch_bwd_t<0, GEO, L1>(st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat, d_feat, l1, s);
+      launch_bwd_t<0, GEO, L1>(st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat, d_feat, l1, pf,
+                               s);
   } else if (cn <= 8) {
-    launch_bwd_t<8, GEO, L1>(st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat, d_feat, l1, s);
+    launch_bwd_t<8, GEO, L1>(st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat, d_feat, l1, pf, s);
   } else if (cn <= 16) {
-    launch_bwd_t<16, GEO, L1>(st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat, d_feat, l1, s);
+    launch_bwd_t<16, GEO, L1>(st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat, d_feat, l1, pf,
+                              s);
   } else if (cn <= 32) {
-    launch_bwd_t<32, GEO, L1>(st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat, d_feat, l1, s);
+    launch_bwd_t<32, GEO, L1>(st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat, d_feat, l1, pf,
+                              s);
   } else {
     if constexpr (!GEO)
-      launch_bwd_t<64, GEO, L1>(st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat, d_feat, l1, s);
+      launch_bwd_t<64, GEO, L1>(st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat, d_feat, l1, pf,
+                                s);
   }
 }
 
@@ -919,25 +1022,30 @@ hipError_t launch_composite_bwd_impl(const DevGaussians& g, const DevSettings& s
   const int C = feat_on ? g.C : 0;
   int c0 = 0;
   bool geo = geometry;
+  bool first = true;
   while (geo || c0 < C) {
     const int cn = min(geo ? kBwdGeoChannels : kBwdMaxChannels, C - c0);
+    // rows hold 10 + g.C columns; the first pass zeroes the ones no pass writes
+    const PassFlags pf{first ? 1 : 0, (first && !geometry) ? 1 : 0,
+                       (first && C == 0 && g.C > 0) ? 1 : 0};
     if (geo) {
       if (l1)
         launch_bwd_dispatch<true, true>(cn, st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat,
-                                        d_feat, u, s);
+                                        d_feat, u, pf, s);
       else
         launch_bwd_dispatch<true, false>(cn, st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat,
-                                         d_feat, u, s);
+                                         d_feat, u, pf, s);
     } else {
       if (l1)
         launch_bwd_dispatch<false, true>(cn, st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat,
-                                         d_feat, u, s);
+                                         d_feat, u, pf, s);
       else
         launch_bwd_dispatch<false, false>(cn, st, g, L, w, c0, g_rgb, g_depth, g_alpha, g_feat,
-                                          d_feat, u, s);
+                                          d_feat, u, pf, s);
     }
     c0 += cn;
     geo = false;
+    first = false;
   }
   return hipGetLastError();
 }

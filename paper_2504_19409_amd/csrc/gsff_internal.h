@@ -33,6 +33,10 @@ inline int ceil_log2(uint64_t v) {
 // for gsff_workspace_size / gsff_workspace_layout and for every launch.
 struct Layout {
   int64_t P = 0, max_pairs = 0;
+  int32_t C = 0;
+  int64_t row_cap = 0;      // adjoint partial rows (one per walked pair)
+  int32_t row_width = 0;    // floats per row: 10 image-space terms + C features
+  int64_t item_cap = 0;     // adjoint reduction work items (64-row chunks)
   int32_t W = 0, H = 0, tiles_x = 0, tiles_y = 0, ntiles = 0;
   int32_t rank_bits = 0, tile_bits = 0;
   bool direct_bin = false;
@@ -40,11 +44,13 @@ struct Layout {
   uint64_t status = 0, records = 0, rects = 0, dkeys_a = 0, dkeys_b = 0, dids_a = 0,
            dids_b = 0, offsets = 0, pkeys_a = 0, pkeys_b = 0, tile_ranges = 0, pix_T = 0,
            pix_end = 0, grad2d = 0, hist = 0, hist_tot = 0, scan_part = 0, pose_part = 0,
-           binhist = 0, tile_tot = 0, curbase = 0, total = 0;
+           binhist = 0, tile_tot = 0, curbase = 0, rows = 0, tile_walk = 0, walk_off = 0,
+           slot_local = 0, slot_blk = 0, nslot = 0, slots = 0, item_n = 0, items = 0,
+           total = 0;
 };
 
 // Returns false if the sizes are not representable (key bits, negative sizes).
-bool compute_layout(int64_t P, int64_t max_pairs, int32_t W, int32_t H, Layout* L);
+bool compute_layout(int64_t P, int32_t C, int64_t max_pairs, int32_t W, int32_t H, Layout* L);
 
 // Device-side view of a workspace.
 struct WsView {
@@ -69,6 +75,22 @@ struct WsView {
   uint32_t* binhist;     // direct binning: per-tile counts per rank block [ntiles][blocks]
   uint32_t* tile_tot;    // direct binning: pairs per tile [ntiles]
   uint32_t* curbase;     // direct binning: pairs of earlier blocks per tile [blocks][ntiles]
+  // Adjoint partial sums: the compositing adjoint writes one row per walked
+  // (tile, Gaussian) pair and files the row index in the Gaussian's slots
+  // (slot range = the Gaussian's rectangle tile count, counted by nslot); the
+  // adjoint reduction sums every Gaussian's rows, one work item per 64 slots.
+  float* rows;           // [row_cap][row_width]
+  uint32_t* tile_walk;   // [ntiles] end of the forward's walk of every tile list
+  uint32_t* walk_off;    // [ntiles] first row of every tile
+  uint32_t* slot_local;  // [P] first slot of each Gaussian inside its 256-Gaussian block
+  uint32_t* slot_blk;    // [P/256]: slot count of each block, then its first slot
+  uint32_t* nslot;       // [P] slots filled per Gaussian
+  uint32_t* slots;       // [max_pairs] row index per filed (tile, Gaussian) pair
+  uint32_t* item_n;      // [1] work items filed
+  uint2* items;          // [item_cap] (Gaussian, first slot) of every 64-slot chunk
+  uint32_t row_cap;
+  int32_t row_width;
+  uint32_t item_cap;
 };
 
 WsView make_view(void* ws, const Layout& L);

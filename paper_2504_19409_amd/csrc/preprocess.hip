@@ -26,7 +26,8 @@ __global__ __launch_bounds__(256) void k_preprocess(DevGaussians g, DevCamera ca
     w.status[3] = 0u;
   }
   const int64_t P = g.P;
-  if (i >= P) return;
+  uint32_t ntile = 0;  // tiles of the support rectangle
+  if (i < P) {
   float V[12];
 #pragma unroll
   for (int k = 0; k < 12; ++k) V[k] = cam.viewmat[k];
@@ -59,13 +60,117 @@ __global__ __launch_bounds__(256) void k_preprocess(DevGaussians g, DevCamera ca
   w.rec[P + i] = r1;
   w.rec[2 * P + i] = r2;
   w.rects[i] = rect;
-  // the image-space gradients the compositing adjoint accumulates start at zero
+  // the image-space gradients the compositing adjoint accumulates start at
+  // zero, and the Gaussian's list of adjoint rows empty
   float* d2 = w.grad2d + i * 10;
 #pragma unroll
   for (int k = 0; k < 10; ++k) d2[k] = 0.f;
+  w.nslot[i] = 0u;
+  if (i == 0) *w.item_n = 0u;
   // culled Gaussians keep the largest key and an empty rectangle
   w.dkeys_a[i] = (p.valid && rect.x <= rect.z) ? p.key : 0xFFFFFFFFu;
   w.dids_a[i] = (uint32_t)i;
+  if (rect.x <= rect.z && rect.y <= rect.w)
+    ntile = (uint32_t)(rect.z - rect.x + 1) * (uint32_t)(rect.w - rect.y + 1);
+  }
+  // slots for the adjoint: a Gaussian gets one per tile of its rectangle;
+  // block-local exclusive offsets here, the block bases in k_slot_scan
+  __shared__ uint32_t s_ws[4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t inc = ntile;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t t = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += t;
+  }
+  if (lane == 63) s_ws[wv] = inc;
+  __syncthreads();
+  uint32_t pre = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (k < wv) pre += s_ws[k];
+    tot += s_ws[k];
+  }
+  if (i < P) w.slot_local[i] = pre + inc - ntile;
+  if (threadIdx.x == 0) w.slot_blk[blockIdx.x] = tot;
+}
+
+// One block: exclusive scan of the per-block slot counts into block bases.
+__global__ __launch_bounds__(1024) void k_slot_scan(WsView w, int nblk) {
+  __shared__ uint32_t s_w[16];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t carry = 0;
+  for (int b = 0; b < nblk; b += 1024) {
+    const int k = b + threadIdx.x;
+    const uint32_t v = k < nblk ? w.slot_blk[k] : 0u;
+    uint32_t inc = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t t = __shfl_up(inc, off, 64);
+      if (lane >= off) inc += t;
+    }
+    if (lane == 63) s_w[wv] = inc;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+    for (int q = 0; q < 16; ++q) {
+      if (q < wv) pre += s_w[q];
+      tot += s_w[q];
+    }
+    __syncthreads();
+    if (k < nblk) w.slot_blk[k] = carry + pre + inc - v;
+    carry += tot;
+  }
+}
+
+// Sum of the adjoint rows, one wave per work item (a Gaussian and 64 of its
+// slots).  The lanes form 64/CW groups of CW columns; each group takes every
+// (64/CW)-th row of the item, so every row load of the item is in flight at
+// once, and a butterfly adds the groups.  Image terms go to grad2d (+=, which
+// the preprocess adjoint then consumes), features to d_feat (+=) when given; a
+// Gaussian with more than 64 slots has several items, which add atomically.
+template <int CW>
+__global__ __launch_bounds__(256) void k_adjoint_reduce(WsView w, int64_t P, int C,
+                                                        float* __restrict__ d_feat,
+                                                        uint32_t max_pairs) {
+  constexpr int RPI = 64 / CW;  // rows side by side in one load
+  const int lane = threadIdx.x & 63;
+  const int cl = lane & (CW - 1), rsub = lane / CW;
+  uint32_t cnt = *w.item_n;
+  if (cnt > w.item_cap) cnt = w.item_cap;
+  const int RW = w.row_width;
+  const int ncol = 10 + (d_feat ? C : 0);
+  const uint32_t nw = gridDim.x * 4u;
+  for (uint32_t e = blockIdx.x * 4u + (threadIdx.x >> 6); e < cnt; e += nw) {
+    const uint2 it = w.items[e];
+    const uint32_t gg = it.x, k0 = it.y;
+    if (gg >= (uint64_t)P) continue;
+    const uint32_t n = w.nslot[gg];
+    if (k0 >= n) continue;
+    const uint32_t m = n - k0 < 64u ? n - k0 : 64u;
+    const uint32_t sl = w.slot_blk[gg >> 8] + w.slot_local[gg] + k0 + (uint32_t)lane;
+    const uint32_t myrow = ((uint32_t)lane < m && sl < max_pairs) ? w.slots[sl] : 0xFFFFFFFFu;
+    const bool single = n <= 64u;
+    for (int c0 = 0; c0 < ncol; c0 += CW) {
+      const int col = c0 + cl;
+      float acc = 0.f;
+#pragma unroll
+      for (int u = 0; u < 64 / RPI; ++u) {
+        const int j = u * RPI + rsub;
+        const uint32_t r = (uint32_t)__shfl((int)myrow, j, 64);
+        const bool ok = r < w.row_cap && col < ncol;
+        const float v = w.rows[ok ? (int64_t)r * RW + col : 0];
+        acc += ok ? v : 0.f;
+      }
+#pragma unroll
+      for (int off = CW; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
+      if (rsub == 0 && col < ncol && acc != 0.f) {
+        float* dst = col < 10 ? w.grad2d + (int64_t)gg * 10 + col
+                              : d_feat + (int64_t)gg * C + (col - 10);
+        if (single) *dst += acc;
+        else unsafeAtomicAdd(dst, acc);
+      }
+    }
+  }
 }
 
 // Adjoint of project_gaussian followed by the pose terms of Eq. 4.
@@ -80,14 +185,17 @@ __global__ __launch_bounds__(kPoseBlock) void k_preprocess_bwd(DevGaussians g, D
   float pose[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   if (i < P) {
     const Proj p = project_gaussian(g, cam, st, V, i);
-    // consume the accumulated image-space gradients and re-arm them at zero,
-    // so another adjoint of the same forward starts from nothing
+    // consume the image-space gradients (the adjoint reduction has added
+    // the per-tile rows) and re-arm them at zero, so another adjoint of the
+    // same forward starts from nothing
     float* d2 = w.grad2d + i * 10;
     float d[10];
 #pragma unroll
     for (int k = 0; k < 10; ++k) d[k] = d2[k];
 #pragma unroll
     for (int k = 0; k < 10; ++k) d2[k] = 0.f;
+    w.nslot[i] = 0u;
+    if (i == 0) *w.item_n = 0u;
     float dmean[3] = {0.f, 0.f, 0.f}, dls[3] = {0.f, 0.f, 0.f}, dq[4] = {0.f, 0.f, 0.f, 0.f};
     float dlogit = 0.f;
     const float drgb[3] = {d[6], d[7], d[8]};
@@ -244,15 +352,31 @@ hipError_t launch_preprocess(const DevGaussians& g, const DevCamera& cam, const 
                              const Layout& L, const WsView& w, hipStream_t s) {
   const int64_t blocks = g.P > 0 ? (g.P + 255) / 256 : 1;
   hipLaunchKernelGGL(k_preprocess, dim3((unsigned)blocks), dim3(256), 0, s, g, cam, st, w);
+  if (g.P > 0)
+    hipLaunchKernelGGL(k_slot_scan, dim3(1), dim3(1024), 0, s, w, (int)blocks);
   return hipGetLastError();
 }
 
 hipError_t launch_preprocess_bwd(const DevGaussians& g, const DevCamera& cam,
                                  const DevSettings& st, const Layout& L, const WsView& w,
                                  const gsff_grads& out, int32_t accumulate, hipStream_t s) {
-  if (g.P > 0)
+  if (g.P > 0) {
+    const int64_t waves = (g.P + 63) / 64;
+    float* df = g.C > 0 ? out.feat : nullptr;
+    const int ncol = 10 + (df ? g.C : 0);
+    const unsigned nblk = (unsigned)std::min<int64_t>(std::max<int64_t>((waves + 3) / 4, 1), 2048);
+    if (ncol <= 16)
+      hipLaunchKernelGGL(k_adjoint_reduce<16>, dim3(nblk), dim3(256), 0, s, w, g.P, g.C, df,
+                         (uint32_t)L.max_pairs);
+    else if (ncol <= 32)
+      hipLaunchKernelGGL(k_adjoint_reduce<32>, dim3(nblk), dim3(256), 0, s, w, g.P, g.C, df,
+                         (uint32_t)L.max_pairs);
+    else
+      hipLaunchKernelGGL(k_adjoint_reduce<64>, dim3(nblk), dim3(256), 0, s, w, g.P, g.C, df,
+                         (uint32_t)L.max_pairs);
     hipLaunchKernelGGL(k_preprocess_bwd, dim3((unsigned)L.pose_blocks), dim3(kPoseBlock), 0, s,
                        g, cam, st, w, out, (int)accumulate);
+  }
   if (out.pose)
     hipLaunchKernelGGL(k_pose_final, dim3(1), dim3(256), 0, s, w.pose_part,
                        (int)(g.P > 0 ? L.pose_blocks : 0), out.pose, (int)accumulate);

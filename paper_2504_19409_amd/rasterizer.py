@@ -96,14 +96,14 @@ class Frame:
                                  0 if feat is None else feat.data_ptr())
         self.c = _capi.Camera(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy,
                               viewmat.data_ptr())
-        self.ws_bytes = _capi.workspace_size(P, self.max_pairs, cam.width, cam.height)
+        self.ws_bytes = _capi.workspace_size(P, C, self.max_pairs, cam.width, cam.height)
         if workspace is None or workspace.numel() < self.ws_bytes:
             # 256-byte alignment: the caching allocator hands out 512-byte aligned blocks
             workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         if workspace.data_ptr() % 256:
             raise ValueError("workspace must be 256-byte aligned")
         self.ws = workspace
-        self.layout = _capi.workspace_layout(P, self.max_pairs, cam.width, cam.height)
+        self.layout = _capi.workspace_layout(P, C, self.max_pairs, cam.width, cam.height)
 
     # -- argument tuples -------------------------------------------------
     def _head(self):

@@ -52,10 +52,10 @@ def test_version_and_defaults(capi):
 
 
 def test_workspace_layout_consistent(capi):
-    for P, M, W, H in [(1, 16, 1, 1), (2000, 24000, 64, 48), (200_000, 5_000_000, 640, 480),
-                       (1_000_000, 40_000_000, 1200, 680)]:
-        n = capi.workspace_size(P, M, W, H)
-        lay = capi.workspace_layout(P, M, W, H)
+    for P, C, M, W, H in [(1, 0, 16, 1, 1), (2000, 5, 24000, 64, 48),
+                          (200_000, 16, 5_000_000, 640, 480), (1_000_000, 64, 40_000_000, 1200, 680)]:
+        n = capi.workspace_size(P, C, M, W, H)
+        lay = capi.workspace_layout(P, C, M, W, H)
         assert lay.total_bytes == n
         offs = [lay.status, lay.records, lay.rects, lay.depth_keys, lay.depth_ids,
                 lay.pair_keys, lay.tile_ranges, lay.pix_T, lay.pix_end, lay.grad2d]
@@ -65,19 +65,21 @@ def test_workspace_layout_consistent(capi):
         assert lay.tiles_x == (W + 15) // 16 and lay.tiles_y == (H + 15) // 16
         assert lay.rank_bits >= max(1, (P - 1).bit_length())
         # monotone in every size
-        assert capi.workspace_size(P + 1, M, W, H) >= n
-        assert capi.workspace_size(P, M + 1000, W, H) >= n
+        assert capi.workspace_size(P + 1, C, M, W, H) >= n
+        assert capi.workspace_size(P, C + 1, M, W, H) >= n
+        assert capi.workspace_size(P, C, M + 1000, W, H) >= n
 
 
 def test_unrepresentable_sizes_rejected(capi):
     lib = capi.load()
     n = ctypes.c_size_t(0)
     # rank bits + tile bits > 32
-    assert lib.gsff_workspace_size(1 << 24, 100, 1 << 13, 1 << 13, ctypes.byref(n)) == \
+    assert lib.gsff_workspace_size(1 << 24, 0, 100, 1 << 13, 1 << 13, ctypes.byref(n)) == \
         capi.ERR_INVALID_ARGUMENT
-    assert lib.gsff_workspace_size(-1, 100, 64, 64, ctypes.byref(n)) == capi.ERR_INVALID_ARGUMENT
-    assert lib.gsff_workspace_size(10, 100, 0, 64, ctypes.byref(n)) == capi.ERR_INVALID_ARGUMENT
-    assert lib.gsff_workspace_size(10, 1 << 33, 64, 64, ctypes.byref(n)) == \
+    assert lib.gsff_workspace_size(-1, 0, 100, 64, 64, ctypes.byref(n)) == capi.ERR_INVALID_ARGUMENT
+    assert lib.gsff_workspace_size(10, -1, 100, 64, 64, ctypes.byref(n)) == capi.ERR_INVALID_ARGUMENT
+    assert lib.gsff_workspace_size(10, 0, 100, 0, 64, ctypes.byref(n)) == capi.ERR_INVALID_ARGUMENT
+    assert lib.gsff_workspace_size(10, 0, 1 << 33, 64, 64, ctypes.byref(n)) == \
         capi.ERR_INVALID_ARGUMENT
     assert b"representable" in lib.gsff_last_error()
 
