@@ -214,8 +214,9 @@ gsff_status gsff_backward_l1(const gsff_gaussians* g, const gsff_camera* cam,
  * sort_tiles, tile_ranges, composite_fwd in this order; the backward is
  * composite_bwd then preprocess_bwd.  Same arguments and conventions as the
  * two calls above; exposed for stage-by-stage testing and timing.  For tile
- * grids up to 4096 tiles `bin` writes every tile's list directly in depth
- * order and `sort_tiles` / `tile_ranges` have nothing left to do; larger grids
+ * grids of up to 4096 tiles whose 16 bytes per tile plus 32 bytes per tile row
+ * and column fit in 64 KiB, `bin` writes every tile's list directly in depth
+ * order and `sort_tiles` / `tile_ranges` have nothing left to do; other grids
  * sort (tile, rank) keys instead.  The compositing adjoints leave their
  * per-Gaussian sums (image-space terms and feature gradients) inside `ws` as
  * one row per walked (tile, Gaussian) pair, filed per Gaussian, plus direct

@@ -39,7 +39,10 @@ bool compute_layout(int64_t P, int32_t C, int64_t max_pairs, int32_t W, int32_t 
   l.ntiles = l.tiles_x * l.tiles_y;
   l.rank_bits = ceil_log2((uint64_t)(P < 2 ? 2 : P));
   l.tile_bits = ceil_log2((uint64_t)l.ntiles);
-  l.direct_bin = l.ntiles <= kMaxDirectTiles;
+  // direct binning keeps per-wave cursors (16 B per tile) and coverage masks
+  // (32 B per tile column and row) of a block in 64 KiB of LDS
+  l.direct_bin = l.ntiles <= kMaxDirectTiles &&
+                 16ll * l.ntiles + 32ll * (l.tiles_x + l.tiles_y) <= 65536;
   // the fallback path packs (tile, rank) into 32-bit keys
   if (!l.direct_bin && l.rank_bits + l.tile_bits > 32) return false;
   l.depth_chunks = (P + kDepthChunk - 1) / kDepthChunk;
@@ -87,6 +90,7 @@ bool compute_layout(int64_t P, int32_t C, int64_t max_pairs, int32_t W, int32_t 
   l.rows = take(4ull * (uint64_t)l.row_cap * (uint64_t)l.row_width);
   l.tile_walk = take(4ull * l.ntiles);
   l.walk_off = take(4ull * l.ntiles);
+  l.tile_order = take(4ull * l.ntiles);
   l.slot_local = take(4ull * P);
   l.slot_blk = take(4ull * (uint64_t)(l.pose_blocks + 1));
   l.nslot = take(4ull * P);
@@ -133,6 +137,7 @@ WsView make_view(void* ws, const Layout& L) {
   w.slot_blk = (uint32_t*)(b + L.slot_blk);
   w.nslot = (uint32_t*)(b + L.nslot);
   w.slots = (uint32_t*)(b + L.slots);
+  w.tile_order = (uint32_t*)(b + L.tile_order);
   w.item_n = (uint32_t*)(b + L.item_n);
   w.items = (uint2*)(b + L.items);
   w.row_cap = (uint32_t)L.row_cap;

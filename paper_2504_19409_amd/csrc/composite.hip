@@ -68,21 +68,45 @@ __device__ __forceinline__ uint32_t pair_gid(const WsView& w, uint32_t idx, uint
 
 // Gather the three record vectors of `gid`; an out-of-range id gets zero
 // opacity, so every pixel skips it.
+// Branch-free (an id past the end reads Gaussian 0 and keeps zeros): a
+// conditional assignment through the references made the compiler stage the
+// records in private memory.
+__device__ __forceinline__ float4 keep4(bool ok, float4 a) {
+  return make_float4(ok ? a.x : 0.f, ok ? a.y : 0.f, ok ? a.z : 0.f, ok ? a.w : 0.f);
+}
 __device__ __forceinline__ void load_record(const WsView& w, uint32_t gid, int64_t P, float4& r0,
                                             float4& r1, float4& r2) {
-  if (gid < (uint32_t)P) {
-    r0 = w.rec[gid];
-    r1 = w.rec[P + gid];
-    r2 = w.rec[2 * P + gid];
-  } else {
-    r0 = make_float4(0.f, 0.f, 0.f, 0.f);
-    r1 = r0;
-    r2 = r0;
-  }
+  const bool ok = gid < (uint32_t)P;
+  const int64_t g = ok ? (int64_t)gid : 0;
+  const float4 a = w.rec[g], b = w.rec[P + g], c = w.rec[2 * P + g];
+  r0 = keep4(ok, a);
+  r1 = keep4(ok, b);
+  r2 = keep4(ok, c);
 }
 
-// alpha of one (pixel, Gaussian) pair; forward and adjoint call this same
-// code so every skip decision and weight is reproduced bit for bit.
+// The Gaussian's exponent (Eq. 2's G) in base 2:
+//   log2(e) * (-1/2) (A dx^2 + 2 B dx dy + C dy^2) = dx (a dx + b dy) + c dy^2
+// with a = kConA A, b = kConB B, c = kConA C.  Both compositing kernels keep
+// the conic of a staged batch in this scaled form (the adjoint unscales it
+// for the mean and conic gradients).
+constexpr float kLn2 = 0.6931471805599453f;
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kConA = -0.5f * kLog2e, kConB = -kLog2e;
+constexpr float kConAInv = -2.f * kLn2, kConBInv = -kLn2;
+
+// A record as staged for eval_alpha: (u, v, a, b) (c, o, z, valid).  Applied
+// where a prefetched record is written to LDS, not where it is loaded, so the
+// load stays in flight while the current batch runs.
+__device__ __forceinline__ float4 scaled_r0(float4 r0) {
+  return make_float4(r0.x, r0.y, r0.z * kConA, r0.w * kConB);
+}
+__device__ __forceinline__ float4 scaled_r1(float4 r1) {
+  return make_float4(r1.x * kConA, r1.y, r1.z, r1.w);
+}
+
+// alpha of one (pixel, Gaussian) pair from a scaled record; forward and
+// adjoint call this same code so every skip decision and weight is
+// reproduced bit for bit.
 struct AlphaEval {
   float dx, dy, G, oG, alpha;
 };
@@ -93,12 +117,11 @@ __device__ __forceinline__ AlphaEval eval_alpha(const float4 r0, const float4 r1
   AlphaEval e;
   e.dx = r0.x - pxc;
   e.dy = r0.y - pyc;
-  // -1/2 (A dx^2 + 2 B dx dy + C dy^2), A = r0.z, B = r0.w, C = r1.x
-  const float q = __builtin_fmaf(r0.z * e.dx, e.dx,
-                                 __builtin_fmaf(2.f * r0.w * e.dx, e.dy, r1.x * e.dy * e.dy));
-  e.G = __expf(-0.5f * q);
+  const float q2 = __builtin_fmaf(e.dx, __builtin_fmaf(r0.z, e.dx, r0.w * e.dy),
+                                  (r1.x * e.dy) * e.dy);
+  e.G = __builtin_amdgcn_exp2f(q2);  // v_exp_f32
   e.oG = r1.y * e.G;
-  e.alpha = e.oG < alpha_max ? e.oG : alpha_max;
+  e.alpha = __builtin_fminf(e.oG, alpha_max);
   return e;
 }
 
@@ -106,6 +129,7 @@ __device__ __forceinline__ AlphaEval eval_alpha(const float4 r0, const float4 r1
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 // x = hi + lo + r with hi = bf16(x), lo = bf16(x - hi), |r| <= 2^-16 |x|.
 __device__ __forceinline__ void split8(const float4 a, const float4 b, bf16x8& hi, bf16x8& lo) {
@@ -144,7 +168,7 @@ __device__ __forceinline__ void lds_barrier() {
 // ------------------------------------------------------------ forward -----
 
 constexpr int kFwdNB = 16;       // Gaussians per batch
-constexpr int kFwdWStride = 20;  // LDS row stride (floats) of a pixel's batch weights
+constexpr int kFwdWStride = 40;  // LDS row (BF16): a pixel's batch weights, hi at 0, lo at 16
 constexpr int kFwdFStride = 24;  // LDS row stride (bf16) of a channel's batch features
 
 template <typename FT>
@@ -155,6 +179,18 @@ __device__ __forceinline__ void feat_split(const FT* p, int64_t i, __bf16& hi, _
 }
 __device__ __forceinline__ void feat_split(const uint16_t* p, int64_t i, __bf16& hi, __bf16& lo) {
   hi = __builtin_bit_cast(__bf16, p[i]);  // BF16 payload: exact
+  lo = (__bf16)0.f;
+}
+// the same split of an element already loaded
+__device__ __forceinline__ void split_value(float v, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)v;
+  lo = (__bf16)(v - (float)hi);
+}
+__device__ __forceinline__ void split_value(_Float16 v, __bf16& hi, __bf16& lo) {
+  split_value((float)v, hi, lo);
+}
+__device__ __forceinline__ void split_value(uint16_t v, __bf16& hi, __bf16& lo) {
+  hi = __builtin_bit_cast(__bf16, v);
   lo = (__bf16)0.f;
 }
 
@@ -190,7 +226,7 @@ void k_composite_fwd(
   constexpr bool EXACT = sizeof(FT) == 2 && !__is_same(FT, _Float16);  // BF16 payload
   constexpr int CPs = CP > 0 ? CP : 1;
   constexpr int FPT = CP > 0 ? (NB * CP + kBlock - 1) / kBlock : 0;  // features per thread
-  __shared__ __attribute__((aligned(16))) float s_w[kBlock][kFwdWStride];
+  __shared__ __attribute__((aligned(16))) __bf16 s_w[kBlock][kFwdWStride];
   __shared__ __attribute__((aligned(16))) __bf16 s_fh[2][CPs][kFwdFStride];
   __shared__ __attribute__((aligned(16))) __bf16 s_fl[EXACT ? 1 : 2][EXACT ? 1 : CPs][kFwdFStride];
   __shared__ float4 s_r0[2][NB], s_r1[2][NB], s_r2[2][NB];
@@ -228,7 +264,10 @@ void k_composite_fwd(
       const uint32_t idx = range.x + pf;
       const uint32_t gid = idx < range.y ? pair_gid(w, idx, rmask, P) : (uint32_t)P;
       s_ids[0][pf] = gid;
-      load_record(w, gid, P, s_r0[0][pf], s_r1[0][pf], s_r2[0][pf]);
+      float4 q0, q1;
+      load_record(w, gid, P, q0, q1, s_r2[0][pf]);
+      s_r0[0][pf] = scaled_r0(q0);
+      s_r1[0][pf] = scaled_r1(q1);
       const uint32_t nidx = range.x + NB + pf;
       if (nidx < range.y) g_next = w.pkeys_a[nidx];
     }
@@ -262,17 +301,18 @@ void k_composite_fwd(
       const uint32_t idx = b0 + 2 * NB + pf;
       if (idx < range.y) g_after = w.pkeys_a[idx];
     }
-    __bf16 fh[FPT > 0 ? FPT : 1], fl[FPT > 0 ? FPT : 1];
+    // features of the next batch, raw: split where they are staged, so the
+    // loads stay in flight while this batch runs
+    FT fraw[FPT > 0 ? FPT : 1];
     if constexpr (CP > 0) {
 #pragma unroll
       for (int k = 0; k < FPT; ++k) {
-        fh[k] = (__bf16)0.f;
-        fl[k] = (__bf16)0.f;
+        fraw[k] = FT(0);
         const int e = tid + kBlock * k;
         const int g = e / CP, c = e % CP;
         if (more && g < NB) {
           const uint32_t gid = s_ids[buf ^ 1][g];
-          if (c < cn && gid < (uint32_t)P) feat_split(feat, (int64_t)gid * C + c0 + c, fh[k], fl[k]);
+          if (c < cn && gid < (uint32_t)P) fraw[k] = feat[(int64_t)gid * C + c0 + c];
         }
       }
     }
@@ -298,8 +338,13 @@ void k_composite_fwd(
         T = use ? Tn : T;
         end = use ? b0 + (uint32_t)jj + 1u : end;
         wv[jj & 3] = wgt;
-        if (CP > 0 && (jj & 3) == 3)
-          reinterpret_cast<float4*>(&s_w[tid][0])[jj >> 2] = make_float4(wv[0], wv[1], wv[2], wv[3]);
+        if (CP > 0 && (jj & 3) == 3) {  // weight = hi + lo, both BF16, as the feature product's A
+          const f32x4 q = {wv[0], wv[1], wv[2], wv[3]};
+          const bf16x4 h = __builtin_convertvector(q, bf16x4);
+          const bf16x4 l = __builtin_convertvector(q - __builtin_convertvector(h, f32x4), bf16x4);
+          *reinterpret_cast<bf16x4*>(&s_w[tid][jj - 3]) = h;
+          *reinterpret_cast<bf16x4*>(&s_w[tid][16 + jj - 3]) = l;
+        }
       }
       if constexpr (CP > 0) {
         // the wave reads back only its own rows
@@ -310,11 +355,9 @@ void k_composite_fwd(
         const int gk = 8 * (lq & 1);  // Gaussians gk .. gk+7 of the batch
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb) {
-          const float* src = &s_w[64 * wave + 16 * rb + lj][gk];
-          bf16x8 hi, lo;
-          split8(*reinterpret_cast<const float4*>(src), *reinterpret_cast<const float4*>(src + 4),
-                 hi, lo);
-          const bf16x8 a = lq < 2 ? hi : lo;
+          // hi weights in lanes 0-31, lo in 32-63 (the K-concatenation of A)
+          const bf16x8 a = *reinterpret_cast<const bf16x8*>(
+              &s_w[64 * wave + 16 * rb + lj][(lq < 2 ? 0 : 16) + gk]);
 #pragma unroll
           for (int k = 0; k < NCB; ++k) {
             const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&s_fh[buf][16 * k + lj][gk]);
@@ -331,8 +374,8 @@ void k_composite_fwd(
     // ---- stage the next batch, report activity
     if (more) {
       if (pf_lane) {
-        s_r0[buf ^ 1][pf] = p0;
-        s_r1[buf ^ 1][pf] = p1;
+        s_r0[buf ^ 1][pf] = scaled_r0(p0);
+        s_r1[buf ^ 1][pf] = scaled_r1(p1);
         s_r2[buf ^ 1][pf] = p2;
         s_ids[buf][pf] = g_after;  // the slot of batch b + 2
       }
@@ -342,8 +385,10 @@ void k_composite_fwd(
           const int e = tid + kBlock * k;
           const int g = e / CP, c = e % CP;
           if (g < NB) {
-            s_fh[buf ^ 1][c][g] = fh[k];
-            if constexpr (!EXACT) s_fl[buf ^ 1][c][g] = fl[k];
+            __bf16 h, l;
+            split_value(fraw[k], h, l);
+            s_fh[buf ^ 1][c][g] = h;
+            if constexpr (!EXACT) s_fl[buf ^ 1][c][g] = l;
           }
         }
       }
@@ -433,6 +478,38 @@ __global__ __launch_bounds__(1024) void k_walk_scan(WsView w, int ntiles, uint32
     __syncthreads();
     if (i < ntiles) w.walk_off[i] = carry + pre + inc - v;
     carry += tot;
+  }
+  // The adjoint's launch order: tiles by decreasing walk length (counting
+  // sort on buckets of 4 list entries), so the tiles that start after the
+  // first round of resident workgroups are the short ones.
+  __shared__ uint32_t s_cnt[1024];
+  auto key_of = [&](int i) {
+    const uint2 r = clamp_range(w.tile_ranges[i], max_pairs);
+    const uint32_t v = min(max(w.tile_walk[i], r.x), r.y) - r.x;
+    return 1023u - min(v >> 2, 1023u);
+  };
+  s_cnt[threadIdx.x] = 0u;
+  __syncthreads();
+  for (int i = threadIdx.x; i < ntiles; i += 1024) atomicAdd(&s_cnt[key_of(i)], 1u);
+  __syncthreads();
+  {
+    const uint32_t c = s_cnt[threadIdx.x];
+    uint32_t inc = c;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t t = __shfl_up(inc, off, 64);
+      if (lane >= off) inc += t;
+    }
+    if (lane == 63) s_w[wv] = inc;
+    __syncthreads();
+    uint32_t pre = 0;
+    for (int k = 0; k < wv; ++k) pre += s_w[k];
+    s_cnt[threadIdx.x] = pre + inc - c;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < ntiles; i += 1024) {
+    const uint32_t pos = atomicAdd(&s_cnt[key_of(i)], 1u);
+    if (pos < (uint32_t)ntiles) w.tile_order[pos] = (uint32_t)i;
   }
 }
 
@@ -605,7 +682,9 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
   __shared__ float s_mom[kBwdNB][8];
   __shared__ uint32_t s_end;
   __shared__ float s_loss[kBlock / 64];
-  const int tile = xcd_tile(blockIdx.x, ntiles);
+  if (blockIdx.x >= (unsigned)ntiles) return;
+  const int tile = (int)w.tile_order[blockIdx.x];  // longest walks first
+  if ((unsigned)tile >= (unsigned)ntiles) return;  // (a permutation once the forward ran)
   if (tile >= ntiles) return;
   const int tx = tile % tiles_x, ty = tile / tiles_x;
   const int tid = threadIdx.x;
@@ -626,30 +705,54 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
   float gr = 0.f, gg = 0.f, gb = 0.f, gd = 0.f, ga = 0.f;  // geometry upstream (scaled)
   float ur = 0.f, ug = 0.f, ub = 0.f, ud = 0.f;           // same, as contraction operands
   float loss = 0.f;
-  if (inside) {
-    Tfin = w.pix_T[p];
-    pend = w.pix_end[p];
-    if (GEO) {
-      if (L1) {
-        if (l1.t_rgb) {
-          ur = l1_unit_sign(l1.out_rgb[p], l1.t_rgb[p], l1.s_rgb, loss);
-          ug = l1_unit_sign(l1.out_rgb[HW + p], l1.t_rgb[HW + p], l1.s_rgb, loss);
-          ub = l1_unit_sign(l1.out_rgb[2 * HW + p], l1.t_rgb[2 * HW + p], l1.s_rgb, loss);
+  // Every per-pixel load is issued up front, unconditionally (a pixel
+  // outside the image reads pixel 0 and masks the value), so the loads are
+  // in flight together instead of one round trip each.
+  const int64_t pq = inside ? p : 0;
+  {
+    const float tf = w.pix_T[pq];
+    const uint32_t pe = w.pix_end[pq];
+    Tfin = inside ? tf : 1.f;
+    pend = inside ? pe : range.x;
+  }
+  if constexpr (GEO) {
+    if constexpr (L1) {
+      float o[5] = {0.f, 0.f, 0.f, 0.f, 0.f}, t[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+      if (l1.t_rgb) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          o[k] = l1.out_rgb[k * HW + pq];
+          t[k] = l1.t_rgb[k * HW + pq];
         }
-        if (l1.t_depth) ud = l1_unit_sign(l1.out_depth[p], l1.t_depth[p], l1.s_depth, loss);
-        if (l1.t_alpha) ga = l1_unit_sign(l1.out_alpha[p], l1.t_alpha[p], l1.s_alpha, loss) *
-                             l1.s_alpha;
-        gr = ur * l1.s_rgb;
-        gg = ug * l1.s_rgb;
-        gb = ub * l1.s_rgb;
-        gd = ud * l1.s_depth;
-      } else {
-        gr = ur = g_rgb[p];
-        gg = ug = g_rgb[HW + p];
-        gb = ub = g_rgb[2 * HW + p];
-        gd = ud = g_depth[p];
-        ga = g_alpha[p];
       }
+      if (l1.t_depth) {
+        o[3] = l1.out_depth[pq];
+        t[3] = l1.t_depth[pq];
+      }
+      if (l1.t_alpha) {
+        o[4] = l1.out_alpha[pq];
+        t[4] = l1.t_alpha[pq];
+      }
+      const float m = inside ? 1.f : 0.f;
+      if (l1.t_rgb) {
+        ur = m * l1_unit_sign(o[0], t[0], m * l1.s_rgb, loss);
+        ug = m * l1_unit_sign(o[1], t[1], m * l1.s_rgb, loss);
+        ub = m * l1_unit_sign(o[2], t[2], m * l1.s_rgb, loss);
+      }
+      if (l1.t_depth) ud = m * l1_unit_sign(o[3], t[3], m * l1.s_depth, loss);
+      if (l1.t_alpha) ga = m * l1_unit_sign(o[4], t[4], m * l1.s_alpha, loss) * l1.s_alpha;
+      gr = ur * l1.s_rgb;
+      gg = ug * l1.s_rgb;
+      gb = ub * l1.s_rgb;
+      gd = ud * l1.s_depth;
+    } else {
+      const float a0 = g_rgb[pq], a1 = g_rgb[HW + pq], a2 = g_rgb[2 * HW + pq];
+      const float a3 = g_depth[pq], a4 = g_alpha[pq];
+      gr = ur = inside ? a0 : 0.f;
+      gg = ug = inside ? a1 : 0.f;
+      gb = ub = inside ? a2 : 0.f;
+      gd = ud = inside ? a3 : 0.f;
+      ga = inside ? a4 : 0.f;
     }
   }
   if (tid == 0) s_end = range.x;
@@ -661,20 +764,43 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
   bf16x8 bh[8], bl[8];
 #pragma unroll
   for (int cb = 0; cb < NCB; ++cb) {
+    // this block's feature upstream, all loads issued together (channels past
+    // cn and pixels outside the image read channel c0 / pixel 0, masked below)
+    float fo[16], ft[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      fo[j] = 0.f;
+      ft[j] = 0.f;
+    }
+    if (cn > 0) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int k = 16 * cb + j;
+        const int c = k - (GEO ? 4 : 0);
+        if (k < NL && c >= 0) {
+          const int64_t q = (int64_t)(c0 + (c < cn ? c : 0)) * HW + pq;
+          if constexpr (L1) {
+            fo[j] = l1.out_feat[q];
+            ft[j] = l1.t_feat[q];
+          } else {
+            fo[j] = g_feat[q];
+          }
+        }
+      }
+    }
     lds_barrier();  // s_W free
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       const int k = 16 * cb + j;
       float v = 0.f;
-      if (k < NL && inside) {
+      if (k < NL) {
         if (GEO && k < 4) {
           v = k == 0 ? ur : (k == 1 ? ug : (k == 2 ? ub : ud));
         } else {
           const int c = k - (GEO ? 4 : 0);
-          if (c < cn) {
-            const int64_t q = (int64_t)(c0 + c) * HW + p;
-            v = L1 ? l1_unit_sign(l1.out_feat[q], l1.t_feat[q], l1.s_feat, loss) : g_feat[q];
-          }
+          const bool on = inside && c < cn;
+          const float m = on ? 1.f : 0.f;
+          v = L1 ? m * l1_unit_sign(fo[j], ft[j], m * l1.s_feat, loss) : (on ? fo[j] : 0.f);
         }
       }
       s_W[j][tid] = v;
@@ -756,7 +882,10 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
     const uint32_t idx = b0 + pf;
     const uint32_t gid = idx < b1 ? pair_gid(w, idx, rmask, P) : (uint32_t)P;
     s_gid[0][pf] = gid;
-    load_record(w, gid, P, s_r0[0][pf], s_r1[0][pf], s_r2[0][pf]);
+    float4 q0, q1;
+    load_record(w, gid, P, q0, q1, s_r2[0][pf]);
+    s_r0[0][pf] = scaled_r0(q0);
+    s_r1[0][pf] = scaled_r1(q1);
   }
   uint32_t g_next = (uint32_t)P;  // ids of the next batch, per prefetch lane
   if (pf_lane && nb0 + pf < nb1) g_next = w.pkeys_a[nb0 + pf];
@@ -893,6 +1022,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
           const uint32_t gid = s_gid[buf][lane];
           if (gid < (uint32_t)P && (rows_ok ? (uint32_t)lane < b1 - b0 : true)) {
             const float4 r0 = s_r0[buf][lane], r1 = s_r1[buf][lane];
+            const float cA = r0.z * kConAInv, cB = r0.w * kConBInv, cC = r1.x * kConAInv;
             const float M0 = s_mom[lane][0], M1 = s_mom[lane][1], M2 = s_mom[lane][2];
             const float M3 = s_mom[lane][3], M4 = s_mom[lane][4], M5 = s_mom[lane][5];
             const float udx = r0.x - tcx, vdy = r0.y - tcy;  // mean relative to the tile centre
@@ -902,8 +1032,8 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
             const float Sxy = udx * vdy * M0 - udx * M2 - vdy * M1 + M4;
             const float Syy = vdy * vdy * M0 - 2.f * vdy * M2 + M5;
             float geo[6];
-            geo[0] = -(r0.z * Sx + r0.w * Sy);
-            geo[1] = -(r0.w * Sx + r1.x * Sy);
+            geo[0] = -(cA * Sx + cB * Sy);
+            geo[1] = -(cB * Sx + cC * Sy);
             geo[2] = -0.5f * Sxx;
             geo[3] = -Sxy;
             geo[4] = -0.5f * Syy;
@@ -940,8 +1070,8 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
     }
     if (more && pf_lane) {
       s_gid[buf ^ 1][pf] = pgid;
-      s_r0[buf ^ 1][pf] = p0;
-      s_r1[buf ^ 1][pf] = p1;
+      s_r0[buf ^ 1][pf] = scaled_r0(p0);
+      s_r1[buf ^ 1][pf] = scaled_r1(p1);
       s_r2[buf ^ 1][pf] = p2;
     }
     lds_barrier();  // products consumed, next records visible

@@ -46,7 +46,7 @@ struct Layout {
            pix_end = 0, grad2d = 0, hist = 0, hist_tot = 0, scan_part = 0, pose_part = 0,
            binhist = 0, tile_tot = 0, curbase = 0, rows = 0, tile_walk = 0, walk_off = 0,
            slot_local = 0, slot_blk = 0, nslot = 0, slots = 0, item_n = 0, items = 0,
-           total = 0;
+           tile_order = 0, total = 0;
 };
 
 // Returns false if the sizes are not representable (key bits, negative sizes).
@@ -82,6 +82,7 @@ struct WsView {
   float* rows;           // [row_cap][row_width]
   uint32_t* tile_walk;   // [ntiles] end of the forward's walk of every tile list
   uint32_t* walk_off;    // [ntiles] first row of every tile
+  uint32_t* tile_order;  // [ntiles] tiles by decreasing walk length (adjoint launch order)
   uint32_t* slot_local;  // [P] first slot of each Gaussian inside its 256-Gaussian block
   uint32_t* slot_blk;    // [P/256]: slot count of each block, then its first slot
   uint32_t* nslot;       // [P] slots filled per Gaussian

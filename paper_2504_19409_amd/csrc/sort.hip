@@ -322,56 +322,73 @@ __global__ __launch_bounds__(256) void k_emit(WsView w, int64_t P, int tiles_x, 
 
 // ------------------------------------------------------ direct binning ----
 
-// q = j / d for j < 2^16 and 1 <= d < 2^16, from a float reciprocal with
-// an exact one-step correction (d is wave-uniform).
-__device__ __forceinline__ uint32_t udiv_small(uint32_t j, uint32_t d, float rd) {
-  uint32_t q = (uint32_t)((float)j * rd);
-  const uint32_t r = j - q * d;
-  if ((int32_t)r < 0) --q;
-  else if (r >= d) ++q;
-  return q;
-}
-
-// Visit every (rank, tile) pair of the 64 ranks held by this wave's lanes, in
-// rank order; lanes split each rank's tiles.  fn(tile, gid) per pair.
-template <class Fn>
-__device__ __forceinline__ void wave_walk_pairs(const WsView& w, int64_t r, int64_t P,
-                                                int tiles_x, Fn&& fn) {
+// Coverage masks of the 64 consecutive depth ranks held by a wave's lanes:
+// bit L of col[x] is set when lane L's rectangle spans tile column x, bit L of
+// row[y] when it spans tile row y.  A rectangle is the product of its column
+// and row ranges, so lane L covers tile (x, y) exactly when bit L is set in
+// col[x] & row[y]: the wave's pair count on a tile is the popcount of that
+// word, and a pair's place among the wave's pairs of its tile (rank order) is
+// the popcount of the bits below its lane.  One ballot per tile column / row.
+__device__ __forceinline__ void wave_cover_masks(ushort4 rc, int tiles_x, int tiles_y,
+                                                 uint64_t* __restrict__ col,
+                                                 uint64_t* __restrict__ row) {
   const int lane = threadIdx.x & 63;
-  ushort4 rc = make_ushort4(1, 1, 0, 0);
-  uint32_t gid = 0;
-  if (r < P) {
-    gid = w.dids_a[r];
-    if (gid < (uint32_t)P) rc = w.rects[gid];
-  }
-  const uint32_t cnt = rect_count(rc);
-  const uint32_t x0 = rc.x, y0 = rc.y, wd = (uint32_t)(rc.z - rc.x) + 1u;
-  for (int src = 0; src < 64; ++src) {
-    const uint32_t n = __builtin_amdgcn_readlane(cnt, src);
-    if (n == 0u) continue;  // uniform
-    const uint32_t bx = __builtin_amdgcn_readlane(x0, src);
-    const uint32_t by = __builtin_amdgcn_readlane(y0, src);
-    const uint32_t bw = __builtin_amdgcn_readlane(wd, src);
-    const uint32_t g = __builtin_amdgcn_readlane(gid, src);
-    const float rbw = __builtin_amdgcn_rcpf((float)bw);
-    for (uint32_t j = lane; j < n; j += 64) {
-      const uint32_t q = udiv_small(j, bw, rbw);
-      fn((by + q) * (uint32_t)tiles_x + bx + (j - q * bw), g);
+  const uint32_t x0 = rc.x, x1 = rc.z, y0 = rc.y, y1 = rc.w;
+  for (int b = 0; b < tiles_x; b += 64) {
+    uint64_t mine = 0;
+    const int nb = tiles_x - b < 64 ? tiles_x - b : 64;
+    for (int k = 0; k < nb; ++k) {
+      const uint32_t x = (uint32_t)(b + k);
+      const uint64_t m = __ballot(x0 <= x && x <= x1);
+      mine = lane == k ? m : mine;
     }
+    if (lane < nb) col[b + lane] = mine;
+  }
+  for (int b = 0; b < tiles_y; b += 64) {
+    uint64_t mine = 0;
+    const int nb = tiles_y - b < 64 ? tiles_y - b : 64;
+    for (int k = 0; k < nb; ++k) {
+      const uint32_t y = (uint32_t)(b + k);
+      const uint64_t m = __ballot(y0 <= y && y <= y1);
+      mine = lane == k ? m : mine;
+    }
+    if (lane < nb) row[b + lane] = mine;
   }
 }
 
-// per-block, per-tile pair counts -> binhist[tile][block]
+// rectangle of the Gaussian at depth rank r, and its id (empty past the end)
+__device__ __forceinline__ ushort4 rank_rect(const WsView& w, int64_t r, int64_t P,
+                                             uint32_t* gid) {
+  ushort4 rc = make_ushort4(1, 1, 0, 0);
+  *gid = 0u;
+  if (r < P) {
+    *gid = w.dids_a[r];
+    if (*gid < (uint32_t)P) rc = w.rects[*gid];
+  }
+  return rc;
+}
+
+__device__ __forceinline__ uint32_t bits_below_lane(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// per-block, per-tile pair counts -> binhist[tile][block], from the masks
 __global__ __launch_bounds__(256) void k_bin_hist(WsView w, int64_t P, int ntiles, int tiles_x,
-                                                  int nblk) {
-  extern __shared__ uint32_t s_h[];
-  for (int t = threadIdx.x; t < ntiles; t += 256) s_h[t] = 0u;
+                                                  int tiles_y, int nblk) {
+  extern __shared__ uint64_t s_m[];  // [4][tiles_x + tiles_y]
+  const int wv = threadIdx.x >> 6, TM = tiles_x + tiles_y;
+  uint32_t gid;
+  const ushort4 rc = rank_rect(w, (int64_t)blockIdx.x * kBinBlock + threadIdx.x, P, &gid);
+  wave_cover_masks(rc, tiles_x, tiles_y, s_m + wv * TM, s_m + wv * TM + tiles_x);
   __syncthreads();
-  wave_walk_pairs(w, (int64_t)blockIdx.x * kBinBlock + threadIdx.x, P, tiles_x,
-                  [&](uint32_t t, uint32_t) { atomicAdd(&s_h[t], 1u); });
-  __syncthreads();
-  for (int t = threadIdx.x; t < ntiles; t += 256)
-    w.binhist[(int64_t)t * nblk + blockIdx.x] = s_h[t];
+  for (int t = threadIdx.x; t < ntiles; t += 256) {
+    const int y = t / tiles_x, x = t - y * tiles_x;
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) c += __popcll(s_m[k * TM + x] & s_m[k * TM + tiles_x + y]);
+    w.binhist[(int64_t)t * nblk + blockIdx.x] = c;
+  }
 }
 
 // One wave per tile: exclusive scan of its counts along the blocks, written
@@ -433,35 +450,47 @@ __global__ __launch_bounds__(1024) void k_bin_tilescan(WsView w, int ntiles, uin
 }
 
 // Stable scatter of Gaussian ids into their tiles' segments.  Wave wv owns
-// the block's ranks [64 wv, 64 wv + 64) and walks them in order; its cursors
-// start after the pairs of lower waves.  LDS atomics of one wave execute in
-// issue order, so the cursor bumps keep rank order without a dependency
-// chain, and the lanes of one rank always touch distinct tiles.
+// the block's ranks [64 wv, 64 wv + 64); its cursors start after the pairs of
+// lower waves, and every pair's place follows from the coverage masks, so each
+// lane walks its own rectangle with no ordering between lanes.
 __global__ __launch_bounds__(256) void k_bin_scatter(WsView w, int64_t P, int ntiles,
-                                                     int tiles_x, int nblk,
+                                                     int tiles_x, int tiles_y, int nblk,
                                                      uint32_t max_pairs) {
-  extern __shared__ uint32_t s_c[];  // [4][ntiles]: per-wave counts, then write cursors
+  extern __shared__ uint64_t s_m[];  // [4][tiles_x + tiles_y] masks, then [4][ntiles] cursors
   if (w.status[2] == 0u) return;     // nothing to write, or overflow (uniform)
-  const int wv = threadIdx.x >> 6;
-  for (int t = threadIdx.x; t < 4 * ntiles; t += 256) s_c[t] = 0u;
-  __syncthreads();
-  const int64_t r = (int64_t)blockIdx.x * kBinBlock + threadIdx.x;
-  uint32_t* cw = s_c + wv * ntiles;
-  wave_walk_pairs(w, r, P, tiles_x, [&](uint32_t t, uint32_t) { atomicAdd(&cw[t], 1u); });
+  const int wv = threadIdx.x >> 6, TM = tiles_x + tiles_y;
+  uint32_t* s_c = reinterpret_cast<uint32_t*>(s_m + 4 * TM);
+  uint32_t gid;
+  const ushort4 rc = rank_rect(w, (int64_t)blockIdx.x * kBinBlock + threadIdx.x, P, &gid);
+  const uint64_t* col = s_m + wv * TM;
+  const uint64_t* row = col + tiles_x;
+  wave_cover_masks(rc, tiles_x, tiles_y, s_m + wv * TM, s_m + wv * TM + tiles_x);
   __syncthreads();
   for (int t = threadIdx.x; t < ntiles; t += 256) {
+    const int y = t / tiles_x, x = t - y * tiles_x;
     uint32_t cur = w.tile_ranges[t].x + w.curbase[(int64_t)blockIdx.x * ntiles + t];
+#pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const uint32_t c = s_c[k * ntiles + t];
       s_c[k * ntiles + t] = cur;
-      cur += c;
+      cur += __popcll(s_m[k * TM + x] & s_m[k * TM + tiles_x + y]);
     }
   }
   __syncthreads();
-  wave_walk_pairs(w, r, P, tiles_x, [&](uint32_t t, uint32_t gid) {
-    const uint32_t pos = atomicAdd(&cw[t], 1u);
+  const uint32_t cnt = rect_count(rc);
+  if (cnt == 0u) return;
+  const uint32_t* cw = s_c + wv * ntiles;
+  const uint32_t x0 = rc.x, x1 = rc.z, y1 = rc.w;
+  uint32_t x = x0, y = rc.y;
+  uint64_t rm = row[y];
+  for (uint32_t j = 0; j < cnt; ++j) {
+    const uint32_t t = y * (uint32_t)tiles_x + x;
+    const uint32_t pos = cw[t] + bits_below_lane(col[x] & rm);
     if (pos < max_pairs) w.pkeys_a[pos] = gid;
-  });
+    const bool wrap = x == x1;
+    x = wrap ? x0 : x + 1u;
+    y = wrap && y < y1 ? y + 1u : y;
+    rm = row[y];
+  }
 }
 
 // fallback path: sorted (tile | rank) keys -> Gaussian ids, after the ranges
@@ -479,15 +508,15 @@ hipError_t launch_bin(const Layout& L, const WsView& w, hipStream_t s) {
     return hipSuccess;  // status was zeroed by the preprocess kernel
   }
   if (L.direct_bin) {
-    const size_t lds_h = 4ull * L.ntiles, lds_c = 16ull * L.ntiles;
-    hipLaunchKernelGGL(k_bin_hist, dim3((unsigned)L.bin_blocks), dim3(256), lds_h, s, w, L.P,
-                       L.ntiles, L.tiles_x, (int)L.bin_blocks);
+    const size_t lds_m = 32ull * (L.tiles_x + L.tiles_y), lds_c = lds_m + 16ull * L.ntiles;
+    hipLaunchKernelGGL(k_bin_hist, dim3((unsigned)L.bin_blocks), dim3(256), lds_m, s, w, L.P,
+                       L.ntiles, L.tiles_x, L.tiles_y, (int)L.bin_blocks);
     hipLaunchKernelGGL(k_bin_colscan, dim3((unsigned)((L.ntiles + 3) / 4)), dim3(256), 0, s, w,
                        L.ntiles, (int)L.bin_blocks);
     hipLaunchKernelGGL(k_bin_tilescan, dim3(1), dim3(1024), 0, s, w, L.ntiles,
                        (uint64_t)L.max_pairs);
     hipLaunchKernelGGL(k_bin_scatter, dim3((unsigned)L.bin_blocks), dim3(256), lds_c, s, w, L.P,
-                       L.ntiles, L.tiles_x, (int)L.bin_blocks, (uint32_t)L.max_pairs);
+                       L.ntiles, L.tiles_x, L.tiles_y, (int)L.bin_blocks, (uint32_t)L.max_pairs);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_count_reduce, dim3((unsigned)L.scan_blocks), dim3(256), 0, s, w, L.P);
