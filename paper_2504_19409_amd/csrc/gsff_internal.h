@@ -19,6 +19,7 @@ constexpr int kDepthChunk = 64 * kDepthIpt;  // small chunks: a 200k-key sort fi
 constexpr int kScanBlock = 1024;           // elements per block in the count scan
 constexpr int kPoseBlock = 256;            // Gaussians per preprocess-adjoint block
 constexpr int kMaxDirectTiles = 4096;      // tile grids binned without a pair sort
+constexpr int kBinBands = 4;               // tile-row bands of the direct scatter
 constexpr int kBinBlock = 256;             // depth ranks per direct-binning block
 
 inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }

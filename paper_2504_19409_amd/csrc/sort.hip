@@ -452,13 +452,20 @@ __global__ __launch_bounds__(1024) void k_bin_tilescan(WsView w, int ntiles, uin
 // Stable scatter of Gaussian ids into their tiles' segments.  Wave wv owns
 // the block's ranks [64 wv, 64 wv + 64); its cursors start after the pairs of
 // lower waves, and every pair's place follows from the coverage masks, so each
-// lane walks its own rectangle with no ordering between lanes.
+// lane walks its own rectangle with no ordering between lanes.  The rank
+// chunk's tile rows are split into gridDim.y bands, one workgroup each: the
+// nearest chunks hold the largest rectangles, and a band is a fraction of
+// their walk.
 __global__ __launch_bounds__(256) void k_bin_scatter(WsView w, int64_t P, int ntiles,
                                                      int tiles_x, int tiles_y, int nblk,
                                                      uint32_t max_pairs) {
-  extern __shared__ uint64_t s_m[];  // [4][tiles_x + tiles_y] masks, then [4][ntiles] cursors
+  extern __shared__ uint64_t s_m[];  // [4][tiles_x + tiles_y] masks, then [4][band tiles] cursors
   if (w.status[2] == 0u) return;     // nothing to write, or overflow (uniform)
   const int wv = threadIdx.x >> 6, TM = tiles_x + tiles_y;
+  const int nband = (int)gridDim.y;
+  const int y_lo = (int)blockIdx.y * tiles_y / nband, y_hi = ((int)blockIdx.y + 1) * tiles_y / nband;
+  const int t_lo = y_lo * tiles_x, nbt = (y_hi - y_lo) * tiles_x;
+  if (nbt == 0) return;  // uniform
   uint32_t* s_c = reinterpret_cast<uint32_t*>(s_m + 4 * TM);
   uint32_t gid;
   const ushort4 rc = rank_rect(w, (int64_t)blockIdx.x * kBinBlock + threadIdx.x, P, &gid);
@@ -466,21 +473,24 @@ __global__ __launch_bounds__(256) void k_bin_scatter(WsView w, int64_t P, int nt
   const uint64_t* row = col + tiles_x;
   wave_cover_masks(rc, tiles_x, tiles_y, s_m + wv * TM, s_m + wv * TM + tiles_x);
   __syncthreads();
-  for (int t = threadIdx.x; t < ntiles; t += 256) {
+  for (int b = threadIdx.x; b < nbt; b += 256) {
+    const int t = t_lo + b;
     const int y = t / tiles_x, x = t - y * tiles_x;
     uint32_t cur = w.tile_ranges[t].x + w.curbase[(int64_t)blockIdx.x * ntiles + t];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      s_c[k * ntiles + t] = cur;
+      s_c[k * nbt + b] = cur;
       cur += __popcll(s_m[k * TM + x] & s_m[k * TM + tiles_x + y]);
     }
   }
   __syncthreads();
-  const uint32_t cnt = rect_count(rc);
-  if (cnt == 0u) return;
-  const uint32_t* cw = s_c + wv * ntiles;
-  const uint32_t x0 = rc.x, x1 = rc.z, y1 = rc.w;
-  uint32_t x = x0, y = rc.y;
+  // this lane's rectangle, rows clipped to the band
+  const uint32_t ya = max((uint32_t)rc.y, (uint32_t)y_lo), yb = min((uint32_t)rc.w, (uint32_t)(y_hi - 1));
+  if (rc.x > rc.z || ya > yb) return;
+  const uint32_t cnt = (uint32_t)(rc.z - rc.x + 1) * (yb - ya + 1);
+  const uint32_t* cw = s_c + wv * nbt - t_lo;
+  const uint32_t x0 = rc.x, x1 = rc.z;
+  uint32_t x = x0, y = ya;
   uint64_t rm = row[y];
   for (uint32_t j = 0; j < cnt; ++j) {
     const uint32_t t = y * (uint32_t)tiles_x + x;
@@ -488,7 +498,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter(WsView w, int64_t P, int nt
     if (pos < max_pairs) w.pkeys_a[pos] = gid;
     const bool wrap = x == x1;
     x = wrap ? x0 : x + 1u;
-    y = wrap && y < y1 ? y + 1u : y;
+    y = wrap && y < yb ? y + 1u : y;
     rm = row[y];
   }
 }
@@ -508,14 +518,18 @@ hipError_t launch_bin(const Layout& L, const WsView& w, hipStream_t s) {
     return hipSuccess;  // status was zeroed by the preprocess kernel
   }
   if (L.direct_bin) {
-    const size_t lds_m = 32ull * (L.tiles_x + L.tiles_y), lds_c = lds_m + 16ull * L.ntiles;
+    // scatter bands: tile rows split over kBinBands workgroups per rank chunk
+    const int nband = L.tiles_y < kBinBands ? L.tiles_y : kBinBands;
+    const int band_rows = (L.tiles_y + nband - 1) / nband;
+    const size_t lds_m = 32ull * (L.tiles_x + L.tiles_y);
+    const size_t lds_c = lds_m + 16ull * band_rows * L.tiles_x;
     hipLaunchKernelGGL(k_bin_hist, dim3((unsigned)L.bin_blocks), dim3(256), lds_m, s, w, L.P,
                        L.ntiles, L.tiles_x, L.tiles_y, (int)L.bin_blocks);
     hipLaunchKernelGGL(k_bin_colscan, dim3((unsigned)((L.ntiles + 3) / 4)), dim3(256), 0, s, w,
                        L.ntiles, (int)L.bin_blocks);
     hipLaunchKernelGGL(k_bin_tilescan, dim3(1), dim3(1024), 0, s, w, L.ntiles,
                        (uint64_t)L.max_pairs);
-    hipLaunchKernelGGL(k_bin_scatter, dim3((unsigned)L.bin_blocks), dim3(256), lds_c, s, w, L.P,
+    hipLaunchKernelGGL(k_bin_scatter, dim3((unsigned)L.bin_blocks, (unsigned)nband), dim3(256), lds_c, s, w, L.P,
                        L.ntiles, L.tiles_x, L.tiles_y, (int)L.bin_blocks, (uint32_t)L.max_pairs);
     return hipGetLastError();
   }
