@@ -50,6 +50,9 @@ typedef int32_t gsff_status;
 
 /* status-word bits set by the device */
 #define GSFF_FLAG_PAIR_OVERFLOW 1u
+/* a depth-sort workgroup stopped waiting for an earlier one (not expected;
+ * the frame's results are not valid) */
+#define GSFF_FLAG_SORT_STALL 2u
 
 /* payload / output element types */
 #define GSFF_DTYPE_F32 0
@@ -153,7 +156,8 @@ gsff_status gsff_default_settings(gsff_settings* st);
 /* Workspace bytes for P Gaussians with `channels` feature channels (the C of
  * the gsff_gaussians the workspace will serve; 0..4096), a pair capacity of
  * max_pairs (Gaussian-tile overlaps), and a width x height image (host only).
- * Requires ceil(log2(max(P,2))) + ceil(log2(tiles)) <= 32.  The workspace
+ * Requires P < 2^30, max_pairs < 2^32 - 1, and for tile grids binned by the
+ * pair sort ceil(log2(max(P,2))) + ceil(log2(tiles)) <= 32.  The workspace
  * needs no initialisation. */
 gsff_status gsff_workspace_size(int64_t P, int32_t channels, int64_t max_pairs, int32_t width,
                                 int32_t height, size_t* bytes);

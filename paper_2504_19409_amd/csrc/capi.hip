@@ -26,7 +26,8 @@ static gsff_status hip_check(hipError_t e, const char* what) {
 
 bool compute_layout(int64_t P, int32_t C, int64_t max_pairs, int32_t W, int32_t H, Layout* L) {
   if (P < 0 || C < 0 || C > 4096 || max_pairs < 0 || W <= 0 || H <= 0) return false;
-  if (P > (int64_t)0x7FFFFFFF || max_pairs > (int64_t)0xFFFFFFFEu) return false;
+  // the depth sort's look-back words carry 30-bit counts
+  if (P >= ((int64_t)1 << 30) || max_pairs > (int64_t)0xFFFFFFFEu) return false;
   Layout l;
   l.C = C;
   l.P = P;
@@ -45,7 +46,7 @@ bool compute_layout(int64_t P, int32_t C, int64_t max_pairs, int32_t W, int32_t 
                  16ll * l.ntiles + 32ll * (l.tiles_x + l.tiles_y) <= 65536;
   // the fallback path packs (tile, rank) into 32-bit keys
   if (!l.direct_bin && l.rank_bits + l.tile_bits > 32) return false;
-  l.depth_chunks = (P + kDepthChunk - 1) / kDepthChunk;
+  l.sort_blocks = (P + kSortBlockKeys - 1) / kSortBlockKeys;
   l.pair_chunks = (max_pairs + kRadixChunk - 1) / kRadixChunk;
   l.scan_blocks = (P + kScanBlock - 1) / kScanBlock;
   l.pose_blocks = (P + kPoseBlock - 1) / kPoseBlock;
@@ -72,10 +73,13 @@ bool compute_layout(int64_t P, int32_t C, int64_t max_pairs, int32_t W, int32_t 
   l.pix_T = take(4ull * HW);
   l.pix_end = take(4ull * HW);
   l.grad2d = take(40ull * P);
-  const int64_t chunks = (l.direct_bin || l.depth_chunks > l.pair_chunks) ? l.depth_chunks
-                                                                          : l.pair_chunks;
-  l.hist = take(4ull * 256 * (uint64_t)(chunks > 0 ? chunks : 1));
+  // radix histograms of the (tile, rank) pair sort (larger tile grids only)
+  const int64_t chunks = l.direct_bin ? 1 : (l.pair_chunks > 0 ? l.pair_chunks : 1);
+  l.hist = take(4ull * 256 * (uint64_t)chunks);
   l.hist_tot = take(4ull * 256);
+  l.sort_part = take(4ull * kSortHistBlocks * 1024);
+  l.sort_lb = take(4ull * 4 * 256 * (uint64_t)(l.sort_blocks > 0 ? l.sort_blocks : 1));
+  l.sort_ctr = take(16);
   l.scan_part = take(4ull * (uint64_t)(l.scan_blocks + 1));
   l.pose_part = take(8ull * 6 * (uint64_t)(l.pose_blocks + 1));
   l.binhist = take(l.direct_bin ? 4ull * l.ntiles * (uint64_t)l.bin_blocks : 0ull);
@@ -125,6 +129,9 @@ WsView make_view(void* ws, const Layout& L) {
   w.grad2d = (float*)(b + L.grad2d);
   w.hist = (uint32_t*)(b + L.hist);
   w.hist_tot = (uint32_t*)(b + L.hist_tot);
+  w.sort_part = (uint32_t*)(b + L.sort_part);
+  w.sort_lb = (uint32_t*)(b + L.sort_lb);
+  w.sort_ctr = (uint32_t*)(b + L.sort_ctr);
   w.scan_part = (uint32_t*)(b + L.scan_part);
   w.pose_part = (double*)(b + L.pose_part);
   w.binhist = (uint32_t*)(b + L.binhist);

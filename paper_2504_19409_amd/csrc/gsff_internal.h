@@ -14,8 +14,9 @@ constexpr int kTile = GSFF_TILE;           // 16x16 pixel screen tiles
 constexpr int kBlock = kTile * kTile;      // one thread per pixel of a tile
 constexpr int kRadixIpt = 16;              // keys per lane in a pair-sort radix chunk
 constexpr int kRadixChunk = 64 * kRadixIpt;  // keys per wave chunk (pair sort)
-constexpr int kDepthIpt = 4;               // keys per lane in a depth-sort radix chunk
-constexpr int kDepthChunk = 64 * kDepthIpt;  // small chunks: a 200k-key sort fills the chip
+constexpr int kSortIpt = 8;                // depth sort: keys per lane
+constexpr int kSortBlockKeys = 256 * kSortIpt;  // keys per single-sweep workgroup
+constexpr int kSortHistBlocks = 64;        // workgroups of the 4-digit histogram
 constexpr int kScanBlock = 1024;           // elements per block in the count scan
 constexpr int kPoseBlock = 256;            // Gaussians per preprocess-adjoint block
 constexpr int kMaxDirectTiles = 4096;      // tile grids binned without a pair sort
@@ -41,13 +42,13 @@ struct Layout {
   int32_t W = 0, H = 0, tiles_x = 0, tiles_y = 0, ntiles = 0;
   int32_t rank_bits = 0, tile_bits = 0;
   bool direct_bin = false;
-  int64_t depth_chunks = 0, pair_chunks = 0, scan_blocks = 0, pose_blocks = 0, bin_blocks = 0;
+  int64_t sort_blocks = 0, pair_chunks = 0, scan_blocks = 0, pose_blocks = 0, bin_blocks = 0;
   uint64_t status = 0, records = 0, rects = 0, dkeys_a = 0, dkeys_b = 0, dids_a = 0,
            dids_b = 0, offsets = 0, pkeys_a = 0, pkeys_b = 0, tile_ranges = 0, pix_T = 0,
            pix_end = 0, grad2d = 0, hist = 0, hist_tot = 0, scan_part = 0, pose_part = 0,
            binhist = 0, tile_tot = 0, curbase = 0, rows = 0, tile_walk = 0, walk_off = 0,
            slot_local = 0, slot_blk = 0, nslot = 0, slots = 0, item_n = 0, items = 0,
-           tile_order = 0, total = 0;
+           tile_order = 0, sort_part = 0, sort_lb = 0, sort_ctr = 0, total = 0;
 };
 
 // Returns false if the sizes are not representable (key bits, negative sizes).
@@ -71,6 +72,9 @@ struct WsView {
   float* grad2d;         // [P][10]
   uint32_t* hist;        // radix chunk histograms [bins][chunks]
   uint32_t* hist_tot;    // radix digit totals [256]
+  uint32_t* sort_part;   // depth sort: per-workgroup 4-digit histograms [kSortHistBlocks][4][256]
+  uint32_t* sort_lb;     // depth sort look-back words [4 passes][sort_blocks][256]
+  uint32_t* sort_ctr;    // depth sort: workgroup tickets, one per pass
   uint32_t* scan_part;   // count-scan block partials
   double* pose_part;     // [pose_blocks][6]
   uint32_t* binhist;     // direct binning: per-tile counts per rank block [ntiles][blocks]

@@ -3,23 +3,27 @@
 //
 // Order of work:
 //   1. LSD radix sort of the P depth keys (float32 bits of camera z, culled
-//      Gaussians keyed 0xFFFFFFFF), values = Gaussian ids.  Stable, so equal
-//      keys keep index order.
-//   2. Binning in depth-rank order.  Ranks are cut into blocks of kScanBlock;
-//      every block counts its (Gaussian, tile) pairs per tile in LDS, the
-//      counts are scanned along the blocks for every tile and then across
-//      tiles, which gives every tile its [start, end) and every block its
-//      write cursor inside each tile.  A second pass over the block writes the
-//      Gaussian ids straight into their tiles' segments, wave by wave in rank
-//      order, so every tile's list comes out in depth order without sorting
-//      the pairs.  Needs 16 bytes of LDS per tile (kMaxDirectTiles).
-//   3. Larger tile grids fall back to emitting (tile << rank_bits | rank) keys
+//      Gaussians keyed 0xFFFFFFFF), values = Gaussian ids, stable, so equal
+//      keys keep index order: one histogram kernel for all four 8-bit digits,
+//      then one single-sweep kernel per digit (in-workgroup stable ranking,
+//      decoupled look-back across workgroups); see the depth sort section.
+//   2. Binning in depth-rank order (tile grids whose cursors fit in LDS).
+//      Ranks are cut into blocks of kBinBlock.  Each wave of 64 ranks builds
+//      coverage masks (one 64-bit word per tile column and per tile row) with
+//      ballots; a rank covers a tile iff its bit is set in both words, so a
+//      block's pair count per tile is a few popcounts.  The counts are
+//      scanned along the blocks for every tile and then across tiles, which
+//      gives every tile its [start, end) and every block its cursor inside
+//      each tile.  The scatter then writes every (rank, tile) pair at cursor +
+//      (set bits of the tile's mask below the rank's lane): every tile's list
+//      comes out in depth order, the pairs never sorted.
+//   3. Other tile grids fall back to emitting (tile << rank_bits | rank) keys
 //      in rank order, a stable LSD radix sort on the tile bits, a binary search
 //      for the tile ranges and a final rank -> id conversion.
 // Either way the pair buffer ends up holding Gaussian ids grouped by tile.
 //
-// Radix passes: every wave owns a chunk of 64 * IPT consecutive keys (256 for the
-// depth sort, 1024 for the pair sort).
+// Radix passes of the pair sort: every wave owns a chunk of 64 * IPT consecutive
+// keys (1024).
 //   hist    : per-chunk digit histogram (LDS atomics) -> hist[digit][chunk]
 //   rowscan : one block per digit, exclusive scan along the chunk axis,
 //             digit totals -> hist_tot
@@ -190,16 +194,172 @@ static hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t*
   return hipGetLastError();
 }
 
+// ------------------------------------------------------- depth sort ----
+//
+// Single-sweep LSD radix sort of the P depth keys, four passes of 8 bits:
+//   k_sort_hist4 : all four digit histograms in one read of the keys, as
+//                  kSortHistBlocks per-workgroup partials (nothing to clear
+//                  first); it also clears the look-back words and tickets.
+//   k_sort_pass  : a workgroup draws the next ticket b, ranks the keys of
+//                  chunk b stably in LDS (one ballot per digit bit per wave,
+//                  as the radix scatter), publishes its digit counts and then
+//                  finds each digit's count in chunks 0..b-1 by decoupled
+//                  look-back: chunk b-1, b-2, ... until one whose inclusive
+//                  prefix is already published.  A workgroup only waits on
+//                  chunks with earlier tickets, whose workgroups are running
+//                  or done, so every wait ends.
+// Look-back word: bits 31-30 = 0 not yet, 1 the chunk's own count, 2 the
+// inclusive prefix through the chunk; bits 29-0 the count.
+constexpr uint32_t kLbAgg = 1u << 30, kLbInc = 2u << 30, kLbMask = (1u << 30) - 1u;
+constexpr uint32_t kLbSpinMax = 1u << 22;  // polls before giving up (flags the frame)
+constexpr int kLbWindow = 16;              // predecessors read per look-back step
+
+__global__ __launch_bounds__(256) void k_sort_hist4(const uint32_t* __restrict__ keys, uint32_t n,
+                                                    WsView w, uint32_t lb_words) {
+  __shared__ uint32_t s_h[1024];
+  for (int j = threadIdx.x; j < 1024; j += 256) s_h[j] = 0u;
+  __syncthreads();
+#pragma unroll 4
+  for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const uint32_t k = keys[i];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) atomicAdd(&s_h[256 * p + ((k >> (8 * p)) & 255u)], 1u);
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < 1024; j += 256) w.sort_part[blockIdx.x * 1024 + j] = s_h[j];
+  for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < lb_words; i += gridDim.x * 256)
+    w.sort_lb[i] = 0u;
+  if (blockIdx.x == 0 && threadIdx.x < 4) w.sort_ctr[threadIdx.x] = 0u;
+}
+
+template <int IPT>
+__global__ __launch_bounds__(256) void k_sort_pass(const uint32_t* __restrict__ kin,
+                                                   const uint32_t* __restrict__ vin,
+                                                   uint32_t* __restrict__ kout,
+                                                   uint32_t* __restrict__ vout, uint32_t n,
+                                                   int pass, WsView w) {
+  __shared__ uint32_t s_cnt[4][256];  // per-wave digit counts, then per-wave digit offsets
+  __shared__ uint32_t s_base[256];
+  __shared__ uint32_t s_tmp[4];
+  __shared__ uint32_t s_bid;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int shift = 8 * pass;
+  uint32_t* lb = w.sort_lb + (uint64_t)pass * gridDim.x * 256;
+  if (tid == 0) s_bid = atomicAdd(&w.sort_ctr[pass], 1u);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) s_cnt[k][tid] = 0u;
+  // this pass's digit totals (thread = digit), from the histogram partials
+  uint32_t tot = 0;
+#pragma unroll 16
+  for (int g = 0; g < kSortHistBlocks; ++g) tot += w.sort_part[g * 1024 + 256 * pass + tid];
+  __syncthreads();
+  const uint32_t b = s_bid;
+  const uint64_t base = (uint64_t)b * (256 * IPT) + (uint64_t)wv * (64 * IPT);
+  uint32_t k[IPT], v[IPT], rank[IPT];
+#pragma unroll
+  for (int it = 0; it < IPT; ++it) {
+    const uint64_t idx = base + (uint64_t)it * 64 + lane;
+    k[it] = idx < n ? kin[idx] : 0u;
+    v[it] = idx < n ? vin[idx] : 0u;
+  }
+  // stable rank of every key among the wave's keys of its digit
+  const uint64_t lt = lanemask_lt(lane);
+#pragma unroll
+  for (int it = 0; it < IPT; ++it) {
+    const bool valid = base + (uint64_t)it * 64 + lane < n;
+    const uint32_t d = (k[it] >> shift) & 255u;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const bool on = (d >> bit) & 1u;
+      const uint64_t m = __ballot(on);
+      peers &= on ? m : ~m;
+    }
+    const uint32_t start = s_cnt[wv][d];
+    rank[it] = start + (uint32_t)__popcll(peers & lt);
+    if (valid && (peers & lt) == 0ull) s_cnt[wv][d] = start + (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+  // thread = digit: the chunk's count, published, then the earlier chunks' count
+  const uint32_t c0 = s_cnt[0][tid], c1 = s_cnt[1][tid], c2 = s_cnt[2][tid], c3 = s_cnt[3][tid];
+  const uint32_t cnt = c0 + c1 + c2 + c3;
+  uint32_t excl = 0;
+  if (b == 0) {
+    __hip_atomic_store(&lb[tid], kLbInc | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    __hip_atomic_store(&lb[b * 256 + tid], kLbAgg | cnt, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    // predecessors are read kLbWindow at a time (one round trip per window);
+    // chunks before chunk 0 count as an inclusive prefix of zero
+    int p = (int)b - 1;
+    uint32_t polls = 0;
+    while (true) {
+      uint32_t x[kLbWindow];
+#pragma unroll
+      for (int j = 0; j < kLbWindow; ++j)
+        x[j] = p - j >= 0 ? __hip_atomic_load(&lb[(p - j) * 256 + tid], __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT)
+                          : kLbInc;
+      int used = kLbWindow;  // words consumed before a chunk that is not ready
+      bool found = false;
+#pragma unroll
+      for (int j = 0; j < kLbWindow; ++j) {
+        if (!found && used == kLbWindow) {
+          const uint32_t f = x[j] >> 30;
+          if (f == 0u) {
+            used = j;
+          } else {
+            excl += x[j] & kLbMask;
+            found = f == 2u;
+          }
+        }
+      }
+      if (found) break;
+      p -= used;
+      if (used < kLbWindow) {  // chunk p has not published yet
+        if (++polls > kLbSpinMax) {
+          atomicOr(&w.status[0], GSFF_FLAG_SORT_STALL);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    __hip_atomic_store(&lb[b * 256 + tid], kLbInc | (excl + cnt), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  }
+  uint32_t all;
+  const uint32_t dbase = block_excl_scan256(tot, s_tmp, &all);
+  s_base[tid] = dbase + excl;
+  s_cnt[0][tid] = 0u;
+  s_cnt[1][tid] = c0;
+  s_cnt[2][tid] = c0 + c1;
+  s_cnt[3][tid] = c0 + c1 + c2;
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < IPT; ++it) {
+    if (base + (uint64_t)it * 64 + lane < n) {
+      const uint32_t d = (k[it] >> shift) & 255u;
+      const uint32_t pos = s_base[d] + s_cnt[wv][d] + rank[it];
+      if (pos < n) {
+        kout[pos] = k[it];
+        vout[pos] = v[it];
+      }
+    }
+  }
+}
+
 hipError_t launch_sort_depth(const Layout& L, const WsView& w, hipStream_t s) {
   if (L.P == 0) return hipSuccess;
+  const uint32_t n = (uint32_t)L.P;
+  hipLaunchKernelGGL(k_sort_hist4, dim3(kSortHistBlocks), dim3(256), 0, s, w.dkeys_a, n, w,
+                     (uint32_t)(4 * 256 * L.sort_blocks));
   uint32_t* ka = w.dkeys_a;
   uint32_t* kb = w.dkeys_b;
   uint32_t* va = w.dids_a;
   uint32_t* vb = w.dids_b;
   for (int pass = 0; pass < 4; ++pass) {
-    hipError_t e = radix_pass<kDepthIpt>(ka, va, kb, vb, nullptr, (uint32_t)L.P, pass * 8, 8,
-                                         (int)L.depth_chunks, (uint32_t)L.P, w, s);
-    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sort_pass<kSortIpt>, dim3((unsigned)L.sort_blocks), dim3(256), 0, s, ka,
+                       va, kb, vb, n, pass, w);
     uint32_t* t = ka;
     ka = kb;
     kb = t;
@@ -207,7 +367,7 @@ hipError_t launch_sort_depth(const Layout& L, const WsView& w, hipStream_t s) {
     va = vb;
     vb = t;
   }
-  return hipSuccess;  // four passes: the result is back in dkeys_a / dids_a
+  return hipGetLastError();  // four passes: the result is back in dkeys_a / dids_a
 }
 
 hipError_t launch_sort_tiles(const Layout& L, const WsView& w, hipStream_t s) {
@@ -399,13 +559,22 @@ __global__ __launch_bounds__(256) void k_bin_colscan(WsView w, int ntiles, int n
   const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (t >= ntiles) return;  // whole wave
   const uint32_t* col = w.binhist + (int64_t)t * nblk;
+  constexpr int G = 16;  // 64-block rows loaded together before they are scanned
   uint32_t carry = 0;
-  for (int b0 = 0; b0 < nblk; b0 += 64) {
-    const int b = b0 + lane;
-    const uint32_t v = b < nblk ? col[b] : 0u;
-    const uint32_t inc = wave_incl_scan(v, lane);
-    if (b < nblk) w.curbase[(int64_t)b * ntiles + t] = carry + inc - v;
-    carry += __shfl(inc, 63, 64);
+  for (int g0 = 0; g0 < nblk; g0 += 64 * G) {
+    uint32_t v[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const int b = g0 + 64 * k + lane;
+      v[k] = b < nblk ? col[b] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const int b = g0 + 64 * k + lane;
+      const uint32_t inc = wave_incl_scan(v[k], lane);
+      if (b < nblk) w.curbase[(int64_t)b * ntiles + t] = carry + inc - v[k];
+      carry += __shfl(inc, 63, 64);
+    }
   }
   if (lane == 0) w.tile_tot[t] = carry;
 }

@@ -194,6 +194,29 @@ def test_stage_depth_sort_and_tile_lists(orc, kind):
     assert extra <= 0.6 * npairs
 
 
+@pytest.mark.parametrize("P", [1, 2047, 2048, 2049, 6145, 50_000, 262_145])
+def test_depth_sort_exact_and_stable(P):
+    """The depth sort against numpy's stable argsort of the keys preprocess
+    wrote, at sizes around the 2048-key workgroup chunk and with many chunks
+    (the look-back between workgroups), on keys with heavy ties."""
+    rng = np.random.default_rng(P)
+    sc = sg.make_scene(P, 320, 240, 260.0, 260.0, 160.0, 120.0, 0, seed=P, rng=rng)
+    # depths from 37 distinct values: long runs of equal keys
+    sc.means[:, :] *= (rng.integers(0, 37, size=P) * 0.1 + 1.0) / sc.means[2]
+    fr, _ = H.make_frame(sc, torch)
+    fr.call_stage("gsff_preprocess")
+    torch.cuda.synchronize()
+    keys0 = fr.ws_view("depth_keys", torch.int32, P).cpu().numpy().view(np.uint32).copy()
+    fr.call_stage("gsff_sort_depth")
+    torch.cuda.synchronize()
+    assert fr.read_status()[0] == 0
+    keys = fr.ws_view("depth_keys", torch.int32, P).cpu().numpy().view(np.uint32)
+    ids = fr.ws_view("depth_ids", torch.int32, P).cpu().numpy().view(np.uint32)
+    order = np.argsort(keys0, kind="stable")
+    assert np.array_equal(ids.astype(np.int64), order)
+    assert np.array_equal(keys, keys0[order])
+
+
 # --------------------------------------------------------- forward/backward ----
 
 @pytest.mark.parametrize("kind,C", [("tiny", 16), ("tiny", 0), ("tiny", 1), ("ragged", 5),
