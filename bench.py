@@ -34,6 +34,8 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 # lane-instructions ("slots") per second = 78.6 TFLOP/s of non-packed FP32 FMA
 # (packed FP32 is disabled on these machines).
 VALU_PEAK_TSLOTS = 256 * 4 * 16 * 2.4e9 / 1e12
+# LDS delivery peak: 128 bytes per clock per CU x 256 CUs x 2.4 GHz, in TB/s
+LDS_PEAK_TBS = 128 * 256 * 2.4e9 / 1e12
 
 STAGES = ["preprocess", "sort_depth", "bin", "sort_tiles", "tile_ranges", "composite_fwd",
           "composite_bwd_l1", "preprocess_bwd"]
@@ -176,9 +178,14 @@ def main():
     step = Step(torch, fr, targets)
     log(f"pairs {n_pairs}, workspace {fr.ws_bytes / 1e6:.1f} MB")
     if args.profile_run:
+        # counter calibration: two plain streaming kernels of known size, an
+        # elementwise add (256 MiB read + 256 MiB written) and the runtime's
+        # buffer copy (the same)
         src = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
-        dst.copy_(src)  # calibration: 256 MiB read + 256 MiB written
+        torch.cuda.synchronize()
+        torch.add(src, 1.0, out=dst)
+        dst.copy_(src)
         for _ in range(args.steps):
             step.run()
         torch.cuda.synchronize()
@@ -288,25 +295,39 @@ def roofline_for(stage, ms, wc, sz):
     """Roofline entry of the dominant stage: algorithmic work per launch over the
     measured average launch time.  Work per unit is stated in the design notes.
 
-    The compositing kernels are bound by vector-ALU issue: work is counted in
-    VALU lane slots (a transcendental, issued at quarter rate, counts 4):
-      alpha evaluation (per pixel and Gaussian walked up to the pixel's stop): 15
-      forward, per contributing pair: transmittance, stop test, weight, colour
-        and depth sums: 8
-      adjoint, per contributing pair: transmittance recovery (a reciprocal),
-        weight, g . c, dL/dalpha, suffix sum, dL/dpower: 16
-    The feature and per-Gaussian sums run on the matrix cores and are not
-    counted."""
+    The compositing kernels have two candidate bounds; the limiting one is the
+    one whose time at peak is longer:
+      LDS lane delivery: every lane reads the record of every Gaussian its tile
+        walks (u, v, conic, opacity: 28 B; colour and depth: 12 B; C payload
+        channels at 4 B): W_tile * (40 + 4 C) bytes per launch, against
+        128 B per clock per CU.
+      vector-ALU issue, in lane slots (a transcendental, issued at quarter
+        rate, counts 4): alpha evaluation (per pixel and Gaussian walked up to
+        the pixel's stop) 15; forward, per contributing pair (transmittance,
+        stop test, weight, colour and depth sums) 8; adjoint, per contributing
+        pair (transmittance recovery, weight, g . c, dL/dalpha, suffix sum,
+        dL/dpower) 16.  The feature and per-Gaussian sums run on the matrix
+        cores and are not counted."""
     P, C, HW, M = sz["P"], sz["C"], sz["HW"], sz["n_pairs"]
     sec = ms * 1e-3
     if stage in ("composite_fwd", "composite_bwd_l1"):
         per_contrib = 8 if stage == "composite_fwd" else 16
         slots = wc["evals"] * 15 + wc["contribs"] * per_contrib
-        achieved = slots / sec / 1e12
+        lds_bytes = wc["tile_evals"] * (40 + 4 * C)
+        alu = slots / sec / 1e12
+        lds = lds_bytes / sec / 1e12
+        t_lds, t_alu = lds_bytes / (LDS_PEAK_TBS * 1e12), slots / (VALU_PEAK_TSLOTS * 1e12)
         traffic = measured_traffic() if stage == "composite_bwd_l1" else None
-        return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TSLOTS, 2),
-                "unit": "Tslot/s", "frac": round(achieved / VALU_PEAK_TSLOTS, 4),
-                "traffic": traffic, "stage": stage, "work_slots": int(slots)}
+        other = {"bound": "alu", "achieved": round(alu, 3), "peak": round(VALU_PEAK_TSLOTS, 2),
+                 "unit": "Tslot/s", "frac": round(alu / VALU_PEAK_TSLOTS, 4),
+                 "work": int(slots)}
+        main_ = {"bound": "lds", "achieved": round(lds, 3), "peak": round(LDS_PEAK_TBS, 2),
+                 "unit": "TB/s", "frac": round(lds / LDS_PEAK_TBS, 4), "work": int(lds_bytes)}
+        if t_alu > t_lds:
+            main_, other = other, main_
+        out = dict(main_)
+        out.update({"traffic": traffic, "stage": stage, "other_bound": other})
+        return out
     bytes_ = {
         "preprocess": P * (44 + 12) + P * (48 + 8 + 8),
         "sort_depth": 4 * P * 8 * 3,
