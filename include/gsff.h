@@ -64,8 +64,10 @@ typedef int32_t gsff_status;
  * adjoint's first pass, which also carries the geometry, takes at most 32) */
 #define GSFF_MAX_CHANNELS_PER_PASS 64
 
-/* Screen tiles are GSFF_TILE x GSFF_TILE pixels. */
+/* Screen tiles are GSFF_TILE x GSFF_TILE pixels; binning lists Gaussians per
+ * super-tile of GSFF_SUPER x GSFF_SUPER tiles. */
 #define GSFF_TILE 16
+#define GSFF_SUPER 4
 
 /* Rendering constants the paper does not print (it inherits them from the
  * 3D Gaussian splatting rasterizer it builds on, Sec. 3.1).  Defaults from
@@ -79,7 +81,9 @@ typedef struct gsff_settings {
   float alpha_max;        /* per-pixel alpha is clamped to this                  */
   float t_min;            /* blending stops before T would fall below this       */
   int32_t render_features;/* 0: feature map is zero and receives no gradient     */
-  int32_t reserved;
+  int32_t bin_mode;       /* 0: automatic; 1: bin by sorting (super-tile, rank)
+                             keys even where the direct scatter applies (same
+                             lists; for testing that path)                      */
 } gsff_settings;
 
 /* Pinhole camera.  viewmat is a DEVICE pointer to 12 floats, the row-major
@@ -130,18 +134,27 @@ typedef struct gsff_ws_layout {
   uint64_t rects;       /* uint16[4][P]: tile rect x0,y0,x1,y1 (inclusive); empty => x0>x1 */
   uint64_t depth_keys;  /* uint32[P]: sorted depth keys (float bits)           */
   uint64_t depth_ids;   /* uint32[P]: Gaussian index in depth order            */
-  uint64_t pair_keys;   /* uint32[max_pairs]: Gaussian ids grouped by tile, in
-                           depth order inside every tile                        */
-  uint64_t tile_ranges; /* uint32[2][ntiles]: [start, end) into pair_keys      */
+  uint64_t pair_keys;   /* uint32[max_pairs]: Gaussian ids grouped by super-tile
+                           (GSFF_SUPER x GSFF_SUPER tiles), in depth order inside
+                           every super-tile                                     */
+  uint64_t pair_masks;  /* uint16[max_pairs]: per pair, the tiles of its super-tile
+                           that the Gaussian's rectangle covers: bit
+                           GSFF_SUPER (ty % GSFF_SUPER) + (tx % GSFF_SUPER); a
+                           tile's list is its super-tile's pairs with its bit set */
+  uint64_t tile_ranges; /* uint32[2][super_x * super_y]: [start, end) into
+                           pair_keys / pair_masks of every super-tile            */
+  uint64_t tile_lists;  /* uint32: the per-tile lists the forward walked (ids in
+                           list order), tile t at tile_list_ranges[t]           */
+  uint64_t tile_list_ranges; /* uint32[2][ntiles]: [start, walk end) in tile_lists */
   uint64_t pix_T;       /* float[H*W]: final transmittance                     */
-  uint64_t pix_end;     /* uint32[H*W]: 1 + list position of last contributor  */
+  uint64_t pix_end;     /* uint32[H*W]: 1 + tile_lists position of the last contributor */
   uint64_t grad2d;      /* float[P][10]: du dv dA dB dC do dr dg db dz; cleared by
                            gsff_preprocess, accumulated by the compositing
                            adjoint, consumed and cleared by gsff_preprocess_bwd */
   uint64_t total_bytes;
   int32_t rank_bits;    /* bits of the depth rank inside a pair key            */
   int32_t tiles_x, tiles_y;
-  int32_t reserved;
+  int32_t super_x, super_y;
 } gsff_ws_layout;
 
 /* Library version (host only, no device work). */

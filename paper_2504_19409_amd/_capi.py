@@ -15,6 +15,7 @@ ERR_HIP = -3
 FLAG_PAIR_OVERFLOW = 1
 DTYPE_F32, DTYPE_BF16, DTYPE_F16 = 0, 1, 2
 TILE = 16
+SUPER = 4
 MAX_CHANNELS_PER_PASS = 64
 
 _vp = ctypes.c_void_p
@@ -24,7 +25,7 @@ class Settings(ctypes.Structure):
     _fields_ = [("near_plane", ctypes.c_float), ("guard", ctypes.c_float),
                 ("dilation", ctypes.c_float), ("alpha_min", ctypes.c_float),
                 ("alpha_max", ctypes.c_float), ("t_min", ctypes.c_float),
-                ("render_features", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("render_features", ctypes.c_int32), ("bin_mode", ctypes.c_int32)]
 
 
 class Camera(ctypes.Structure):
@@ -48,11 +49,13 @@ class WsLayout(ctypes.Structure):
     _fields_ = [("status", ctypes.c_uint64), ("records", ctypes.c_uint64),
                 ("rects", ctypes.c_uint64), ("depth_keys", ctypes.c_uint64),
                 ("depth_ids", ctypes.c_uint64), ("pair_keys", ctypes.c_uint64),
-                ("tile_ranges", ctypes.c_uint64), ("pix_T", ctypes.c_uint64),
+                ("pair_masks", ctypes.c_uint64), ("tile_ranges", ctypes.c_uint64),
+                ("tile_lists", ctypes.c_uint64), ("tile_list_ranges", ctypes.c_uint64),
+                ("pix_T", ctypes.c_uint64),
                 ("pix_end", ctypes.c_uint64), ("grad2d", ctypes.c_uint64),
                 ("total_bytes", ctypes.c_uint64), ("rank_bits", ctypes.c_int32),
                 ("tiles_x", ctypes.c_int32), ("tiles_y", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("super_x", ctypes.c_int32), ("super_y", ctypes.c_int32)]
 
 
 _G, _C, _S, _R = (ctypes.POINTER(Gaussians), ctypes.POINTER(Camera), ctypes.POINTER(Settings),

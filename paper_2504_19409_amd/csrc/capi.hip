@@ -38,14 +38,18 @@ bool compute_layout(int64_t P, int32_t C, int64_t max_pairs, int32_t W, int32_t 
   l.tiles_y = (H + kTile - 1) / kTile;
   if (l.tiles_x > 65535 || l.tiles_y > 65535) return false;
   l.ntiles = l.tiles_x * l.tiles_y;
+  l.super_x = (l.tiles_x + kSuper - 1) / kSuper;
+  l.super_y = (l.tiles_y + kSuper - 1) / kSuper;
+  l.nsuper = l.super_x * l.super_y;
   l.rank_bits = ceil_log2((uint64_t)(P < 2 ? 2 : P));
-  l.tile_bits = ceil_log2((uint64_t)l.ntiles);
-  // direct binning keeps per-wave cursors (16 B per tile) and coverage masks
-  // (32 B per tile column and row) of a block in 64 KiB of LDS
-  l.direct_bin = l.ntiles <= kMaxDirectTiles &&
-                 16ll * l.ntiles + 32ll * (l.tiles_x + l.tiles_y) <= 65536;
-  // the fallback path packs (tile, rank) into 32-bit keys
-  if (!l.direct_bin && l.rank_bits + l.tile_bits > 32) return false;
+  l.tile_bits = ceil_log2((uint64_t)l.nsuper);
+  // direct binning keeps per-wave cursors (16 B per super-tile) and coverage
+  // masks (32 B per super-tile column and row) of a block in 64 KiB of LDS
+  l.direct_bin = l.nsuper <= kMaxDirectTiles &&
+                 16ll * l.nsuper + 32ll * (l.super_x + l.super_y) <= 65536;
+  // the fallback path packs (super-tile, rank) into 32-bit keys
+  l.sort_fits = l.rank_bits + l.tile_bits <= 32;
+  if (!l.direct_bin && !l.sort_fits) return false;
   l.sort_blocks = (P + kSortBlockKeys - 1) / kSortBlockKeys;
   l.pair_chunks = (max_pairs + kRadixChunk - 1) / kRadixChunk;
   l.scan_blocks = (P + kScanBlock - 1) / kScanBlock;
@@ -68,13 +72,16 @@ bool compute_layout(int64_t P, int32_t C, int64_t max_pairs, int32_t W, int32_t 
   l.dids_b = take(4ull * P);
   l.offsets = take(4ull * (P + 1));
   l.pkeys_a = take(4ull * max_pairs);
-  l.pkeys_b = take(l.direct_bin ? 0ull : 4ull * max_pairs);
-  l.tile_ranges = take(8ull * l.ntiles);
+  l.pkeys_b = take(l.sort_fits ? 4ull * max_pairs : 0ull);  // key-sort binning (bin_mode 1 or large grids)
+  l.pmask = take(2ull * max_pairs);
+  l.tile_ranges = take(8ull * l.nsuper);
+  l.clist = take(4ull * kSuper * kSuper * (uint64_t)max_pairs);
+  l.crange = take(8ull * l.ntiles);
   l.pix_T = take(4ull * HW);
   l.pix_end = take(4ull * HW);
   l.grad2d = take(40ull * P);
   // radix histograms of the (tile, rank) pair sort (larger tile grids only)
-  const int64_t chunks = l.direct_bin ? 1 : (l.pair_chunks > 0 ? l.pair_chunks : 1);
+  const int64_t chunks = !l.sort_fits ? 1 : (l.pair_chunks > 0 ? l.pair_chunks : 1);
   l.hist = take(4ull * 256 * (uint64_t)chunks);
   l.hist_tot = take(4ull * 256);
   l.sort_part = take(4ull * kSortHistBlocks * 1024);
@@ -82,14 +89,14 @@ bool compute_layout(int64_t P, int32_t C, int64_t max_pairs, int32_t W, int32_t 
   l.sort_ctr = take(16);
   l.scan_part = take(4ull * (uint64_t)(l.scan_blocks + 1));
   l.pose_part = take(8ull * 6 * (uint64_t)(l.pose_blocks + 1));
-  l.binhist = take(l.direct_bin ? 4ull * l.ntiles * (uint64_t)l.bin_blocks : 0ull);
-  l.tile_tot = take(l.direct_bin ? 4ull * l.ntiles : 0ull);
-  l.curbase = take(l.direct_bin ? 4ull * l.ntiles * (uint64_t)l.bin_blocks : 0ull);
+  l.binhist = take(l.direct_bin ? 4ull * l.nsuper * (uint64_t)l.bin_blocks : 0ull);
+  l.tile_tot = take(l.direct_bin ? 4ull * l.nsuper : 0ull);
+  l.curbase = take(l.direct_bin ? 4ull * l.nsuper * (uint64_t)l.bin_blocks : 0ull);
   // adjoint partial rows: room for two walked pairs per Gaussian (a tile whose
   // rows do not fit falls back to atomic accumulation)
   l.row_width = 10 + C;
   l.row_cap = 2 * P + 4096;
-  if (l.row_cap > max_pairs + 4096) l.row_cap = max_pairs + 4096;
+  if (l.row_cap > kSuper * kSuper * max_pairs + 4096) l.row_cap = kSuper * kSuper * max_pairs + 4096;
   if (l.row_cap > 0xFFFFFFFFll) l.row_cap = 0xFFFFFFFFll;  // 32-bit row indices
   l.rows = take(4ull * (uint64_t)l.row_cap * (uint64_t)l.row_width);
   l.tile_walk = take(4ull * l.ntiles);
@@ -98,7 +105,11 @@ bool compute_layout(int64_t P, int32_t C, int64_t max_pairs, int32_t W, int32_t 
   l.slot_local = take(4ull * P);
   l.slot_blk = take(4ull * (uint64_t)(l.pose_blocks + 1));
   l.nslot = take(4ull * P);
-  l.slots = take(4ull * max_pairs);
+  // slots: a Gaussian's range is its rectangle's tile count, so all of them
+  // together are the tile pairs: at most kSuper^2 per super-tile pair
+  l.slot_cap = (int64_t)kSuper * kSuper * max_pairs;
+  if (l.slot_cap > 0xFFFFFFFFll) l.slot_cap = 0xFFFFFFFFll;
+  l.slots = take(4ull * (uint64_t)l.slot_cap);
   // a work item per Gaussian with rows, plus one per further full 64 rows
   l.item_cap = P + l.row_cap / 64 + 1;
   if (l.item_cap > 0xFFFFFFFFll) l.item_cap = 0xFFFFFFFFll;
@@ -124,6 +135,9 @@ WsView make_view(void* ws, const Layout& L) {
   w.pkeys_a = (uint32_t*)(b + L.pkeys_a);
   w.pkeys_b = (uint32_t*)(b + L.pkeys_b);
   w.tile_ranges = (uint2*)(b + L.tile_ranges);
+  w.pmask = (uint16_t*)(b + L.pmask);
+  w.clist = (uint32_t*)(b + L.clist);
+  w.crange = (uint2*)(b + L.crange);
   w.pix_T = (float*)(b + L.pix_T);
   w.pix_end = (uint32_t*)(b + L.pix_end);
   w.grad2d = (float*)(b + L.grad2d);
@@ -150,6 +164,7 @@ WsView make_view(void* ws, const Layout& L) {
   w.row_cap = (uint32_t)L.row_cap;
   w.row_width = L.row_width;
   w.item_cap = (uint32_t)L.item_cap;
+  w.slot_cap = (uint32_t)L.slot_cap;
   return w;
 }
 
@@ -194,6 +209,13 @@ gsff_status check_common(const gsff_gaussians* g, const gsff_camera* cam, const 
   c->g = DevGaussians{g->P, g->C, g->feat_dtype, g->means, g->log_scales, g->quats,
                       g->logit_opacity, g->rgb, g->feat};
   c->cam = DevCamera{cam->width, cam->height, cam->fx, cam->fy, cam->cx, cam->cy, cam->viewmat};
+  if (st->bin_mode != 0 && st->bin_mode != 1)
+    return fail(GSFF_ERR_INVALID_ARGUMENT, "bin_mode must be 0 or 1");
+  if (st->bin_mode == 1) {
+    if (!c->L.sort_fits)
+      return fail(GSFF_ERR_INVALID_ARGUMENT, "bin_mode 1: rank + super-tile bits exceed 32");
+    c->L.direct_bin = false;
+  }
   c->st = DevSettings{st->near_plane, st->guard, st->dilation, st->alpha_min,
                       st->alpha_max, st->t_min, st->render_features ? 1 : 0};
   c->s = (hipStream_t)stream;
@@ -239,7 +261,7 @@ gsff_status gsff_default_settings(gsff_settings* st) {
   st->alpha_max = 0.99f;
   st->t_min = 1e-4f;
   st->render_features = 1;
-  st->reserved = 0;
+  st->bin_mode = 0;
   return GSFF_OK;
 }
 
@@ -265,7 +287,10 @@ gsff_status gsff_workspace_layout(int64_t P, int32_t channels, int64_t max_pairs
   out->depth_keys = L.dkeys_a;
   out->depth_ids = L.dids_a;
   out->pair_keys = L.pkeys_a;
+  out->pair_masks = L.pmask;
   out->tile_ranges = L.tile_ranges;
+  out->tile_lists = L.clist;
+  out->tile_list_ranges = L.crange;
   out->pix_T = L.pix_T;
   out->pix_end = L.pix_end;
   out->grad2d = L.grad2d;
@@ -273,7 +298,8 @@ gsff_status gsff_workspace_layout(int64_t P, int32_t channels, int64_t max_pairs
   out->rank_bits = L.rank_bits;
   out->tiles_x = L.tiles_x;
   out->tiles_y = L.tiles_y;
-  out->reserved = 0;
+  out->super_x = L.super_x;
+  out->super_y = L.super_y;
   return GSFF_OK;
 }
 

@@ -57,15 +57,6 @@ __device__ __forceinline__ uint2 clamp_range(uint2 r, uint32_t max_pairs) {
   return make_uint2(min(r.x, e), e);
 }
 
-// Gaussian id of pair `idx` (the pair buffer holds ids grouped by tile);
-// returns P (an out-of-range marker) for an id that is not a valid index, so
-// no gather can leave the record arrays.
-__device__ __forceinline__ uint32_t pair_gid(const WsView& w, uint32_t idx, uint32_t,
-                                             int64_t P) {
-  const uint32_t gid = w.pkeys_a[idx];
-  return gid < (uint32_t)P ? gid : (uint32_t)P;
-}
-
 // Gather the three record vectors of `gid`; an out-of-range id gets zero
 // opacity, so every pixel skips it.
 // Branch-free (an id past the end reads Gaussian 0 and keeps zeros): a
@@ -167,7 +158,14 @@ __device__ __forceinline__ void lds_barrier() {
 
 // ------------------------------------------------------------ forward -----
 
-constexpr int kFwdNB = 16;       // Gaussians per batch
+// set bits of m below this lane
+__device__ __forceinline__ uint32_t bits_below_lane(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+constexpr int kFwdNB = 16;
+constexpr int kFwdQueue = 256;  // accepted-id ring of the forward's list scan       // Gaussians per batch
 constexpr int kFwdWStride = 40;  // LDS row (BF16): a pixel's batch weights, hi at 0, lo at 16
 constexpr int kFwdFStride = 24;  // LDS row stride (bf16) of a channel's batch features
 
@@ -231,47 +229,104 @@ void k_composite_fwd(
   __shared__ __attribute__((aligned(16))) __bf16 s_fl[EXACT ? 1 : 2][EXACT ? 1 : CPs][kFwdFStride];
   __shared__ float4 s_r0[2][NB], s_r1[2][NB], s_r2[2][NB];
   __shared__ uint32_t s_ids[2][NB];
+  __shared__ uint32_t s_nb[4], s_pos[4];  // size and list position of batch k, slot k % 4
+  __shared__ uint32_t s_q[kFwdQueue];     // ids accepted for this tile, not yet batched
   __shared__ int s_act[2][kBlock / 64];
   const int tile = xcd_tile(blockIdx.x, ntiles);
   if (tile >= ntiles) return;
   const int tid = threadIdx.x;
-  const int wave = tid >> 6, lane = tid & 63, lq = lane >> 4, lj = lane & 15;
+  // the wave index as a scalar: the scan wave's branches and counters stay uniform
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63, lq = lane >> 4,
+            lj = lane & 15;
   const int tx = tile % tiles_x, ty = tile / tiles_x;
   const int px = tx * kTile + (tid & (kTile - 1));
   const int py = ty * kTile + (tid / kTile);
   const bool inside = px < W && py < H;
   const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
-  const uint2 range = clamp_range(w.tile_ranges[tile], max_pairs);
-  const uint32_t rmask = (rank_bits >= 32) ? 0xFFFFFFFFu : ((1u << rank_bits) - 1u);
+  // the super-tile's list; this tile's Gaussians are its entries with the tile's bit
+  const int sx = (tiles_x + kSuper - 1) / kSuper;
+  const int lsub = (ty % kSuper) * kSuper + tx % kSuper;
+  const uint32_t bit = 1u << lsub;
+  const uint2 sr = clamp_range(w.tile_ranges[(ty / kSuper) * sx + tx / kSuper], max_pairs);
+  // the tile's walked list: kSuper^2 slots of the super-tile's length per super-tile entry
+  const uint32_t cbase = (uint32_t)(kSuper * kSuper) * sr.x + (uint32_t)lsub * (sr.y - sr.x);
   const int cn = CP > 0 ? min(CP, C - c0) : 0;
-  // loads are issued by the first 16 lanes of the last wave
+  // the last wave scans the list and batches the accepted ids; its first 16
+  // lanes load the records
   const int pf = tid - (kBlock - 64);
   const bool pf_lane = pf >= 0 && pf < NB;
+  const bool scan_wave = wave == kBlock / 64 - 1;
+  uint32_t sc = sr.x, qh = 0, qt = 0;  // scan position, queue head / tail (scan wave)
+  // Scan 128 list entries: lanes hold entries sc + lane and sc + 64 + lane.
+  auto scan_issue = [&](uint32_t& gA, uint32_t& mA, uint32_t& gB, uint32_t& mB) {
+    const uint32_t i0 = sc + (uint32_t)lane, i1 = i0 + 64u;
+    gA = i0 < sr.y ? w.pkeys_a[i0] : 0u;
+    mA = i0 < sr.y ? (uint32_t)w.pmask[i0] : 0u;
+    gB = i1 < sr.y ? w.pkeys_a[i1] : 0u;
+    mB = i1 < sr.y ? (uint32_t)w.pmask[i1] : 0u;
+  };
+  // append the accepted ones to the queue, in list order
+  auto scan_commit = [&](uint32_t gA, uint32_t mA, uint32_t gB, uint32_t mB) {
+    const bool a = (mA & bit) != 0u, b = (mB & bit) != 0u;
+    const uint64_t ba = __ballot(a), bb = __ballot(b);
+    if (a) s_q[(qt + bits_below_lane(ba)) & (kFwdQueue - 1)] = gA;
+    qt += (uint32_t)__popcll(ba);
+    if (b) s_q[(qt + bits_below_lane(bb)) & (kFwdQueue - 1)] = gB;
+    qt += (uint32_t)__popcll(bb);
+    sc = min(sc + 128u, sr.y);
+  };
+  // the next batch's ids (full unless the list is exhausted), recorded in the
+  // tile's walked list; returns the batch size
+  auto take_batch = [&](uint32_t& g, uint32_t& pos) {
+    while (qt - qh < (uint32_t)NB && sc < sr.y) {  // uniform in the scan wave
+      uint32_t gA, mA, gB, mB;
+      scan_issue(gA, mA, gB, mB);
+      scan_commit(gA, mA, gB, mB);
+    }
+    const uint32_t n = min((uint32_t)NB, qt - qh);
+    g = (uint32_t)P;
+    if ((uint32_t)lane < n) {
+      g = s_q[(qh + (uint32_t)lane) & (kFwdQueue - 1)];
+      if (write_geo) w.clist[cbase + qh + (uint32_t)lane] = g;
+    }
+    pos = qh;
+    qh += n;
+    return n;
+  };
 
   float T = 1.f, cr = 0.f, cg = 0.f, cb = 0.f, dep = 0.f;
   bool done = !inside;
-  uint32_t end = range.x;
+  uint32_t end = cbase;
   f32x4 acc[4][NCB > 0 ? NCB : 1];
 #pragma unroll
   for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
     for (int k = 0; k < (NCB > 0 ? NCB : 1); ++k) acc[rb][k] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  // ---- prologue: ids, records and features of batch 0, ids of batch 1
-  uint32_t g_next = (uint32_t)P;
-  if (range.x < range.y) {
+  // ---- prologue: ids of batches 0 and 1, records and features of batch 0
+  if (scan_wave) {
+    uint32_t g, pos;
+    const uint32_t n0 = take_batch(g, pos);
+    if (lane < NB) s_ids[0][lane] = g;
+    if (lane == 0) {
+      s_nb[0] = n0;
+      s_pos[0] = pos;
+    }
+    const uint32_t n1 = take_batch(g, pos);
+    if (lane < NB) s_ids[1][lane] = g;
+    if (lane == 0) {
+      s_nb[1] = n1;
+      s_pos[1] = pos;
+    }
+  }
+  lds_barrier();
+  if (s_nb[0] > 0u) {
     if (pf_lane) {
-      const uint32_t idx = range.x + pf;
-      const uint32_t gid = idx < range.y ? pair_gid(w, idx, rmask, P) : (uint32_t)P;
-      s_ids[0][pf] = gid;
       float4 q0, q1;
-      load_record(w, gid, P, q0, q1, s_r2[0][pf]);
+      load_record(w, s_ids[0][pf], P, q0, q1, s_r2[0][pf]);
       s_r0[0][pf] = scaled_r0(q0);
       s_r1[0][pf] = scaled_r1(q1);
-      const uint32_t nidx = range.x + NB + pf;
-      if (nidx < range.y) g_next = w.pkeys_a[nidx];
     }
-    lds_barrier();
     if constexpr (CP > 0) {
 #pragma unroll
       for (int k = 0; k < FPT; ++k) {
@@ -286,33 +341,38 @@ void k_composite_fwd(
         }
       }
     }
-    if (pf_lane) s_ids[1][pf] = g_next;
-    lds_barrier();
   }
+  lds_barrier();
 
   int buf = 0;
-  for (uint32_t b0 = range.x; b0 < range.y; b0 += NB) {
-    const bool more = b0 + NB < range.y;
-    // ---- loads for the next batch (ids already in LDS) and ids two ahead
-    float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f), p1 = p0, p2 = p0;
-    uint32_t g_after = (uint32_t)P;
-    if (more && pf_lane) {
-      load_record(w, s_ids[buf ^ 1][pf], P, p0, p1, p2);
-      const uint32_t idx = b0 + 2 * NB + pf;
-      if (idx < range.y) g_after = w.pkeys_a[idx];
+  for (uint32_t k = 0; s_nb[k & 3] > 0u; ++k) {
+    const bool more = s_nb[(k + 1) & 3] > 0u;  // batch k + 1 has ids
+    const uint32_t b0 = cbase + s_pos[k & 3];  // walked-list position of this batch
+    // ---- the scan wave: ids of batch k + 2 from the queue, a scan ahead if the
+    // queue runs short (committed at the end of the batch)
+    uint32_t g_after = (uint32_t)P, n_after = 0u, pos_after = 0u;
+    uint32_t gA = 0u, mA = 0u, gB = 0u, mB = 0u;
+    bool ahead = false;
+    if (scan_wave) {
+      n_after = more ? take_batch(g_after, pos_after) : 0u;
+      ahead = qt - qh < 3u * NB && sc < sr.y;
+      if (ahead) scan_issue(gA, mA, gB, mB);
     }
+    // ---- records of the next batch
+    float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f), p1 = p0, p2 = p0;
+    if (more && pf_lane) load_record(w, s_ids[buf ^ 1][pf], P, p0, p1, p2);
     // features of the next batch, raw: split where they are staged, so the
     // loads stay in flight while this batch runs
     FT fraw[FPT > 0 ? FPT : 1];
     if constexpr (CP > 0) {
 #pragma unroll
-      for (int k = 0; k < FPT; ++k) {
-        fraw[k] = FT(0);
-        const int e = tid + kBlock * k;
+      for (int kk = 0; kk < FPT; ++kk) {
+        fraw[kk] = FT(0);
+        const int e = tid + kBlock * kk;
         const int g = e / CP, c = e % CP;
         if (more && g < NB) {
           const uint32_t gid = s_ids[buf ^ 1][g];
-          if (c < cn && gid < (uint32_t)P) fraw[k] = feat[(int64_t)gid * C + c0 + c];
+          if (c < cn && gid < (uint32_t)P) fraw[kk] = feat[(int64_t)gid * C + c0 + c];
         }
       }
     }
@@ -359,13 +419,13 @@ void k_composite_fwd(
           const bf16x8 a = *reinterpret_cast<const bf16x8*>(
               &s_w[64 * wave + 16 * rb + lj][(lq < 2 ? 0 : 16) + gk]);
 #pragma unroll
-          for (int k = 0; k < NCB; ++k) {
-            const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&s_fh[buf][16 * k + lj][gk]);
-            acc[rb][k] = mfma16(a, bh, acc[rb][k]);
+          for (int kc = 0; kc < NCB; ++kc) {
+            const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&s_fh[buf][16 * kc + lj][gk]);
+            acc[rb][kc] = mfma16(a, bh, acc[rb][kc]);
             if constexpr (!EXACT) {
-              bf16x8 bl = *reinterpret_cast<const bf16x8*>(&s_fl[buf][16 * k + lj][gk]);
+              bf16x8 bl = *reinterpret_cast<const bf16x8*>(&s_fl[buf][16 * kc + lj][gk]);
               if (lq >= 2) bl = bf16x8{};
-              acc[rb][k] = mfma16(a, bl, acc[rb][k]);
+              acc[rb][kc] = mfma16(a, bl, acc[rb][kc]);
             }
           }
         }
@@ -377,21 +437,28 @@ void k_composite_fwd(
         s_r0[buf ^ 1][pf] = scaled_r0(p0);
         s_r1[buf ^ 1][pf] = scaled_r1(p1);
         s_r2[buf ^ 1][pf] = p2;
-        s_ids[buf][pf] = g_after;  // the slot of batch b + 2
       }
       if constexpr (CP > 0) {
 #pragma unroll
-        for (int k = 0; k < FPT; ++k) {
-          const int e = tid + kBlock * k;
+        for (int kk = 0; kk < FPT; ++kk) {
+          const int e = tid + kBlock * kk;
           const int g = e / CP, c = e % CP;
           if (g < NB) {
             __bf16 h, l;
-            split_value(fraw[k], h, l);
+            split_value(fraw[kk], h, l);
             s_fh[buf ^ 1][c][g] = h;
             if constexpr (!EXACT) s_fl[buf ^ 1][c][g] = l;
           }
         }
       }
+    }
+    if (scan_wave) {
+      if (lane < NB) s_ids[buf][lane] = g_after;  // the slot of batch k + 2
+      if (lane == 0) {
+        s_nb[(k + 2) & 3] = n_after;
+        s_pos[(k + 2) & 3] = pos_after;
+      }
+      if (ahead) scan_commit(gA, mA, gB, mB);
     }
     const bool still = __ballot(!done) != 0ull;
     if (lane == 0) s_act[buf][wave] = still ? 1 : 0;
@@ -403,11 +470,14 @@ void k_composite_fwd(
 
   if (write_geo) {  // uniform: end of the walk of this tile's list, for the adjoint
     __shared__ uint32_t s_wend;
-    if (tid == 0) s_wend = range.x;
+    if (tid == 0) s_wend = cbase;
     lds_barrier();
     if (inside) atomicMax(&s_wend, end);
     lds_barrier();
-    if (tid == 0) w.tile_walk[tile] = s_wend;
+    if (tid == 0) {
+      w.tile_walk[tile] = s_wend;
+      w.crange[tile] = make_uint2(cbase, s_wend);
+    }
   }
 
   const int64_t HW = (int64_t)W * H;
@@ -458,9 +528,8 @@ __global__ __launch_bounds__(1024) void k_walk_scan(WsView w, int ntiles, uint32
     const int i = b + threadIdx.x;
     uint32_t v = 0;
     if (i < ntiles) {
-      const uint2 r = clamp_range(w.tile_ranges[i], max_pairs);
-      const uint32_t e = min(max(w.tile_walk[i], r.x), r.y);
-      v = e - r.x;
+      const uint2 r = w.crange[i];  // [start, walk end) of the tile's walked list
+      v = r.y > r.x ? r.y - r.x : 0u;
     }
     uint32_t inc = v;
 #pragma unroll
@@ -484,8 +553,8 @@ __global__ __launch_bounds__(1024) void k_walk_scan(WsView w, int ntiles, uint32
   // first round of resident workgroups are the short ones.
   __shared__ uint32_t s_cnt[1024];
   auto key_of = [&](int i) {
-    const uint2 r = clamp_range(w.tile_ranges[i], max_pairs);
-    const uint32_t v = min(max(w.tile_walk[i], r.x), r.y) - r.x;
+    const uint2 r = w.crange[i];
+    const uint32_t v = r.y > r.x ? r.y - r.x : 0u;
     return 1023u - min(v >> 2, 1023u);
   };
   s_cnt[threadIdx.x] = 0u;
@@ -693,8 +762,10 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
   const int py = ty * kTile + (tid / kTile);
   const bool inside = px < W && py < H;
   const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
-  const uint2 range = clamp_range(w.tile_ranges[tile], max_pairs);
-  const uint32_t rmask = (rank_bits >= 32) ? 0xFFFFFFFFu : ((1u << rank_bits) - 1u);
+  // the tile's walked list (the forward's filtered walk of its super-tile
+  // list), kept inside the walked-list region
+  const uint64_t ccap = (uint64_t)(kSuper * kSuper) * max_pairs;
+  const uint2 range = clamp_range(w.crange[tile], (uint32_t)min(ccap, (uint64_t)0xFFFFFFFFu));
   const int cn = CP > 0 ? min(CP, C - c0) : 0;
   const int64_t HW = (int64_t)W * H;
   const int64_t p = (int64_t)py * W + px;
@@ -880,7 +951,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
   uint32_t nb1 = b0, nb0 = batch_start(nb1);
   if (pf_lane) {
     const uint32_t idx = b0 + pf;
-    const uint32_t gid = idx < b1 ? pair_gid(w, idx, rmask, P) : (uint32_t)P;
+    const uint32_t gid = idx < b1 ? w.clist[idx] : (uint32_t)P;
     s_gid[0][pf] = gid;
     float4 q0, q1;
     load_record(w, gid, P, q0, q1, s_r2[0][pf]);
@@ -888,7 +959,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
     s_r1[0][pf] = scaled_r1(q1);
   }
   uint32_t g_next = (uint32_t)P;  // ids of the next batch, per prefetch lane
-  if (pf_lane && nb0 + pf < nb1) g_next = w.pkeys_a[nb0 + pf];
+  if (pf_lane && nb0 + pf < nb1) g_next = w.clist[nb0 + pf];
   lds_barrier();
 
   float T = Tfin, D = 0.f;
@@ -903,7 +974,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
     const uint32_t mb1 = nb0, mb0 = batch_start(mb1);
     if (pf_lane) {
       if (more) load_record(w, pgid, P, p0, p1, p2);
-      g_next = (more && mb0 + pf < mb1) ? w.pkeys_a[mb0 + pf] : (uint32_t)P;
+      g_next = (more && mb0 + pf < mb1) ? w.clist[mb0 + pf] : (uint32_t)P;
     }
 
     // ---- phase A: per-pixel products, back to front
@@ -1061,7 +1132,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
         const uint32_t row = wstart + (b0 + (uint32_t)pf - range.x);
         const uint32_t k = atomicAdd(&w.nslot[gid], 1u);
         const uint32_t sl = w.slot_blk[gid >> 8] + w.slot_local[gid] + k;
-        if (sl < max_pairs) w.slots[sl] = row;
+        if (sl < w.slot_cap) w.slots[sl] = row;
         if ((k & 63u) == 0u) {
           const uint32_t t = atomicAdd(w.item_n, 1u);
           if (t < w.item_cap) w.items[t] = make_uint2(gid, k);

@@ -21,6 +21,8 @@ constexpr int kScanBlock = 1024;           // elements per block in the count sc
 constexpr int kPoseBlock = 256;            // Gaussians per preprocess-adjoint block
 constexpr int kMaxDirectTiles = 4096;      // tile grids binned without a pair sort
 constexpr int kBinBands = 4;               // tile-row bands of the direct scatter
+constexpr int kSuper = GSFF_SUPER;         // bin-grid cell: kSuper x kSuper tiles (16-bit masks)
+static_assert(kSuper == 4, "pair masks are 16 bits");
 constexpr int kBinBlock = 256;             // depth ranks per direct-binning block
 
 inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
@@ -39,11 +41,14 @@ struct Layout {
   int64_t row_cap = 0;      // adjoint partial rows (one per walked pair)
   int32_t row_width = 0;    // floats per row: 10 image-space terms + C features
   int64_t item_cap = 0;     // adjoint reduction work items (64-row chunks)
+  int64_t slot_cap = 0;     // adjoint slots: one per tile of every Gaussian's rectangle
   int32_t W = 0, H = 0, tiles_x = 0, tiles_y = 0, ntiles = 0;
+  int32_t super_x = 0, super_y = 0, nsuper = 0;  // bin grid: kSuper x kSuper tiles per cell
   int32_t rank_bits = 0, tile_bits = 0;
-  bool direct_bin = false;
+  bool direct_bin = false;  // bin by coverage masks (else by sorting (super-tile, rank) keys)
+  bool sort_fits = false;   // (super-tile, rank) keys fit 32 bits
   int64_t sort_blocks = 0, pair_chunks = 0, scan_blocks = 0, pose_blocks = 0, bin_blocks = 0;
-  uint64_t status = 0, records = 0, rects = 0, dkeys_a = 0, dkeys_b = 0, dids_a = 0,
+  uint64_t status = 0, records = 0, rects = 0, pmask = 0, clist = 0, crange = 0, dkeys_a = 0, dkeys_b = 0, dids_a = 0,
            dids_b = 0, offsets = 0, pkeys_a = 0, pkeys_b = 0, tile_ranges = 0, pix_T = 0,
            pix_end = 0, grad2d = 0, hist = 0, hist_tot = 0, scan_part = 0, pose_part = 0,
            binhist = 0, tile_tot = 0, curbase = 0, rows = 0, tile_walk = 0, walk_off = 0,
@@ -66,7 +71,12 @@ struct WsView {
   uint32_t* offsets;     // [P+1] exclusive scan of tile counts in depth order
   uint32_t* pkeys_a;     // [max_pairs] pair keys (sorted result lands here)
   uint32_t* pkeys_b;
-  uint2* tile_ranges;    // [ntiles]
+  uint2* tile_ranges;    // [nsuper] [start, end) of every super-tile's list in pkeys_a / pmask
+  uint16_t* pmask;       // [max_pairs] tiles of the super-tile the pair's rectangle covers
+                         //   (bit 4 (ty % 4) + (tx % 4))
+  uint32_t* clist;       // per-tile lists the forward walked (capacity: the super-tile's
+                         //   list length for each of its 16 tiles)
+  uint2* crange;         // [ntiles] [start, walk end) of every tile's walked list in clist
   float* pix_T;          // [H*W]
   uint32_t* pix_end;     // [H*W]
   float* grad2d;         // [P][10]
@@ -91,12 +101,13 @@ struct WsView {
   uint32_t* slot_local;  // [P] first slot of each Gaussian inside its 256-Gaussian block
   uint32_t* slot_blk;    // [P/256]: slot count of each block, then its first slot
   uint32_t* nslot;       // [P] slots filled per Gaussian
-  uint32_t* slots;       // [max_pairs] row index per filed (tile, Gaussian) pair
+  uint32_t* slots;       // [slot_cap] row index per filed (tile, Gaussian) pair
   uint32_t* item_n;      // [1] work items filed
   uint2* items;          // [item_cap] (Gaussian, first slot) of every 64-slot chunk
   uint32_t row_cap;
   int32_t row_width;
   uint32_t item_cap;
+  uint32_t slot_cap;
 };
 
 WsView make_view(void* ws, const Layout& L);

@@ -148,7 +148,7 @@ __global__ __launch_bounds__(256) void k_adjoint_reduce(WsView w, int64_t P, int
     if (k0 >= n) continue;
     const uint32_t m = n - k0 < 64u ? n - k0 : 64u;
     const uint32_t sl = w.slot_blk[gg >> 8] + w.slot_local[gg] + k0 + (uint32_t)lane;
-    const uint32_t myrow = ((uint32_t)lane < m && sl < max_pairs) ? w.slots[sl] : 0xFFFFFFFFu;
+    const uint32_t myrow = ((uint32_t)lane < m && sl < w.slot_cap) ? w.slots[sl] : 0xFFFFFFFFu;
     const bool single = n <= 64u;
     for (int c0 = 0; c0 < ncol; c0 += CW) {
       const int col = c0 + cl;

@@ -394,6 +394,25 @@ __device__ __forceinline__ uint32_t rect_count(ushort4 r) {
   return (uint32_t)(r.z - r.x + 1) * (uint32_t)(r.w - r.y + 1);
 }
 
+// Binning works on super-tiles of kSuper x kSuper tiles (the bin grid):
+// a tile rectangle's range of super-tiles (empty stays empty) ...
+__device__ __forceinline__ ushort4 super_rect(ushort4 r) {
+  if (r.x > r.z || r.y > r.w) return make_ushort4(1, 1, 0, 0);
+  return make_ushort4(r.x / kSuper, r.y / kSuper, r.z / kSuper, r.w / kSuper);
+}
+
+// ... and the tiles of super-tile (X, Y) that it covers: bit 4 (ty % 4) + (tx % 4)
+__device__ __forceinline__ uint32_t super_mask(ushort4 r, uint32_t X, uint32_t Y) {
+  const int xa = max((int)r.x - (int)(kSuper * X), 0), xb = min((int)r.z - (int)(kSuper * X), 3);
+  const int ya = max((int)r.y - (int)(kSuper * Y), 0), yb = min((int)r.w - (int)(kSuper * Y), 3);
+  if (xa > xb || ya > yb) return 0u;
+  const uint32_t cols = ((2u << xb) - 1u) & ~((1u << xa) - 1u);
+  uint32_t m = 0;
+#pragma unroll
+  for (int y = 0; y < 4; ++y) m |= (y >= ya && y <= yb) ? cols << (4 * y) : 0u;
+  return m;
+}
+
 // per-block sums of tile counts, ranks in depth order
 __global__ __launch_bounds__(256) void k_count_reduce(WsView w, int64_t P) {
   __shared__ uint32_t s_tmp[4];
@@ -402,7 +421,7 @@ __global__ __launch_bounds__(256) void k_count_reduce(WsView w, int64_t P) {
 #pragma unroll
   for (int k = 0; k < kScanBlock / 256; ++k) {
     const int64_t r = base + k * 256 + threadIdx.x;
-    if (r < P) sum += rect_count(ranked_rect(w, r, P));
+    if (r < P) sum += rect_count(super_rect(ranked_rect(w, r, P)));
   }
   uint32_t tot;
   block_excl_scan256(sum, s_tmp, &tot);
@@ -441,7 +460,7 @@ __global__ __launch_bounds__(1024) void k_count_top(WsView w, int nblocks, uint6
   }
 }
 
-// Offsets and pair emission: key = (tile << rank_bits) | rank.  After the
+// Offsets and pair emission: key = (super-tile << rank_bits) | rank.  After the
 // block scan every lane holds the offset, count and rectangle of its own rank;
 // each wave then walks its 64 ranks in order, broadcasting one rank's values
 // with readlane, and all lanes write consecutive keys of that rank's run.
@@ -455,7 +474,7 @@ __global__ __launch_bounds__(256) void k_emit(WsView w, int64_t P, int tiles_x, 
   for (int k = 0; k < kScanBlock / 256; ++k) {
     const int64_t r = base + k * 256 + threadIdx.x;
     ushort4 rc = make_ushort4(1, 1, 0, 0);
-    if (r < P) rc = ranked_rect(w, r, P);
+    if (r < P) rc = super_rect(ranked_rect(w, r, P));
     const uint32_t cnt = rect_count(rc);
     uint32_t tot;
     const uint32_t off = carry + block_excl_scan256(cnt, s_tmp, &tot);
@@ -533,13 +552,16 @@ __device__ __forceinline__ uint32_t bits_below_lane(uint64_t m) {
                                    __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-// per-block, per-tile pair counts -> binhist[tile][block], from the masks
+// Per-block, per-super-tile pair counts -> binhist[cell][block], from the
+// masks; the kernels below take the bin grid (cells = super-tiles) as
+// tiles_x x tiles_y / ntiles.
 __global__ __launch_bounds__(256) void k_bin_hist(WsView w, int64_t P, int ntiles, int tiles_x,
                                                   int tiles_y, int nblk) {
   extern __shared__ uint64_t s_m[];  // [4][tiles_x + tiles_y]
   const int wv = threadIdx.x >> 6, TM = tiles_x + tiles_y;
   uint32_t gid;
-  const ushort4 rc = rank_rect(w, (int64_t)blockIdx.x * kBinBlock + threadIdx.x, P, &gid);
+  const ushort4 rc =
+      super_rect(rank_rect(w, (int64_t)blockIdx.x * kBinBlock + threadIdx.x, P, &gid));
   wave_cover_masks(rc, tiles_x, tiles_y, s_m + wv * TM, s_m + wv * TM + tiles_x);
   __syncthreads();
   for (int t = threadIdx.x; t < ntiles; t += 256) {
@@ -637,7 +659,8 @@ __global__ __launch_bounds__(256) void k_bin_scatter(WsView w, int64_t P, int nt
   if (nbt == 0) return;  // uniform
   uint32_t* s_c = reinterpret_cast<uint32_t*>(s_m + 4 * TM);
   uint32_t gid;
-  const ushort4 rc = rank_rect(w, (int64_t)blockIdx.x * kBinBlock + threadIdx.x, P, &gid);
+  const ushort4 trc = rank_rect(w, (int64_t)blockIdx.x * kBinBlock + threadIdx.x, P, &gid);
+  const ushort4 rc = super_rect(trc);
   const uint64_t* col = s_m + wv * TM;
   const uint64_t* row = col + tiles_x;
   wave_cover_masks(rc, tiles_x, tiles_y, s_m + wv * TM, s_m + wv * TM + tiles_x);
@@ -664,7 +687,10 @@ __global__ __launch_bounds__(256) void k_bin_scatter(WsView w, int64_t P, int nt
   for (uint32_t j = 0; j < cnt; ++j) {
     const uint32_t t = y * (uint32_t)tiles_x + x;
     const uint32_t pos = cw[t] + bits_below_lane(col[x] & rm);
-    if (pos < max_pairs) w.pkeys_a[pos] = gid;
+    if (pos < max_pairs) {
+      w.pkeys_a[pos] = gid;
+      w.pmask[pos] = (uint16_t)super_mask(trc, x, y);
+    }
     const bool wrap = x == x1;
     x = wrap ? x0 : x + 1u;
     y = wrap && y < yb ? y + 1u : y;
@@ -672,13 +698,21 @@ __global__ __launch_bounds__(256) void k_bin_scatter(WsView w, int64_t P, int nt
   }
 }
 
-// fallback path: sorted (tile | rank) keys -> Gaussian ids, after the ranges
-__global__ __launch_bounds__(256) void k_keys_to_ids(WsView w, uint32_t rmask, int64_t P,
-                                                     uint32_t max_pairs) {
+// fallback path: sorted (super-tile | rank) keys -> Gaussian ids and tile
+// masks, after the ranges
+__global__ __launch_bounds__(256) void k_keys_to_ids(WsView w, uint32_t rmask, int rank_bits,
+                                                     int64_t P, int super_x, uint32_t max_pairs) {
   const uint32_t n = min(w.status[2], max_pairs);
   for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
-    const uint32_t r = w.pkeys_a[i] & rmask;
-    w.pkeys_a[i] = (r < (uint32_t)P) ? w.dids_a[r] : (uint32_t)P;
+    const uint32_t key = w.pkeys_a[i];
+    const uint32_t r = key & rmask;
+    const uint32_t cell = rank_bits >= 32 ? 0u : key >> rank_bits;
+    const uint32_t gid = (r < (uint32_t)P) ? w.dids_a[r] : (uint32_t)P;
+    uint32_t m = 0u;
+    if (gid < (uint32_t)P)
+      m = super_mask(w.rects[gid], cell % (uint32_t)super_x, cell / (uint32_t)super_x);
+    w.pkeys_a[i] = gid;
+    w.pmask[i] = (uint16_t)m;
   }
 }
 
@@ -687,25 +721,27 @@ hipError_t launch_bin(const Layout& L, const WsView& w, hipStream_t s) {
     return hipSuccess;  // status was zeroed by the preprocess kernel
   }
   if (L.direct_bin) {
-    // scatter bands: tile rows split over kBinBands workgroups per rank chunk
-    const int nband = L.tiles_y < kBinBands ? L.tiles_y : kBinBands;
-    const int band_rows = (L.tiles_y + nband - 1) / nband;
-    const size_t lds_m = 32ull * (L.tiles_x + L.tiles_y);
-    const size_t lds_c = lds_m + 16ull * band_rows * L.tiles_x;
+    // the bin grid is the super-tile grid; scatter bands split its rows over
+    // kBinBands workgroups per rank chunk
+    const int nband = L.super_y < kBinBands ? L.super_y : kBinBands;
+    const int band_rows = (L.super_y + nband - 1) / nband;
+    const size_t lds_m = 32ull * (L.super_x + L.super_y);
+    const size_t lds_c = lds_m + 16ull * band_rows * L.super_x;
     hipLaunchKernelGGL(k_bin_hist, dim3((unsigned)L.bin_blocks), dim3(256), lds_m, s, w, L.P,
-                       L.ntiles, L.tiles_x, L.tiles_y, (int)L.bin_blocks);
-    hipLaunchKernelGGL(k_bin_colscan, dim3((unsigned)((L.ntiles + 3) / 4)), dim3(256), 0, s, w,
-                       L.ntiles, (int)L.bin_blocks);
-    hipLaunchKernelGGL(k_bin_tilescan, dim3(1), dim3(1024), 0, s, w, L.ntiles,
+                       L.nsuper, L.super_x, L.super_y, (int)L.bin_blocks);
+    hipLaunchKernelGGL(k_bin_colscan, dim3((unsigned)((L.nsuper + 3) / 4)), dim3(256), 0, s, w,
+                       L.nsuper, (int)L.bin_blocks);
+    hipLaunchKernelGGL(k_bin_tilescan, dim3(1), dim3(1024), 0, s, w, L.nsuper,
                        (uint64_t)L.max_pairs);
-    hipLaunchKernelGGL(k_bin_scatter, dim3((unsigned)L.bin_blocks, (unsigned)nband), dim3(256), lds_c, s, w, L.P,
-                       L.ntiles, L.tiles_x, L.tiles_y, (int)L.bin_blocks, (uint32_t)L.max_pairs);
+    hipLaunchKernelGGL(k_bin_scatter, dim3((unsigned)L.bin_blocks, (unsigned)nband), dim3(256),
+                       lds_c, s, w, L.P, L.nsuper, L.super_x, L.super_y, (int)L.bin_blocks,
+                       (uint32_t)L.max_pairs);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_count_reduce, dim3((unsigned)L.scan_blocks), dim3(256), 0, s, w, L.P);
   hipLaunchKernelGGL(k_count_top, dim3(1), dim3(1024), 0, s, w, (int)L.scan_blocks,
                      (uint64_t)L.max_pairs);
-  hipLaunchKernelGGL(k_emit, dim3((unsigned)L.scan_blocks), dim3(256), 0, s, w, L.P, L.tiles_x,
+  hipLaunchKernelGGL(k_emit, dim3((unsigned)L.scan_blocks), dim3(256), 0, s, w, L.P, L.super_x,
                      L.rank_bits, (uint32_t)L.max_pairs);
   return hipGetLastError();
 }
@@ -736,14 +772,14 @@ __global__ __launch_bounds__(256) void k_tile_ranges(WsView w, int ntiles, int r
 
 hipError_t launch_tile_ranges(const Layout& L, const WsView& w, hipStream_t s) {
   if (L.direct_bin && L.P > 0) return hipSuccess;  // ranges came with the binning
-  hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)((L.ntiles + 255) / 256)), dim3(256), 0, s, w,
-                     L.ntiles, L.rank_bits, (uint32_t)L.max_pairs);
+  hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)((L.nsuper + 255) / 256)), dim3(256), 0, s, w,
+                     L.nsuper, L.rank_bits, (uint32_t)L.max_pairs);
   if (L.P > 0 && L.max_pairs > 0) {
     const uint32_t rmask = (L.rank_bits >= 32) ? 0xFFFFFFFFu : ((1u << L.rank_bits) - 1u);
     int64_t blocks = (L.max_pairs + 255) / 256;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_keys_to_ids, dim3((unsigned)blocks), dim3(256), 0, s, w, rmask, L.P,
-                       (uint32_t)L.max_pairs);
+    hipLaunchKernelGGL(k_keys_to_ids, dim3((unsigned)blocks), dim3(256), 0, s, w, rmask,
+                       L.rank_bits, L.P, L.super_x, (uint32_t)L.max_pairs);
   }
   return hipGetLastError();
 }

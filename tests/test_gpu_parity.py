@@ -171,27 +171,49 @@ def test_stage_depth_sort_and_tile_lists(orc, kind):
     ref = sel[np.lexsort((sel, okey[sel]))]
     assert np.array_equal(sel, ref)
     assert sorted(ids.tolist()) == list(range(P))  # a permutation
-    # tile lists: the oracle's exact support sets, in the same order
+    # tile lists: the oracle's exact support sets, in the same order.  The
+    # pair buffer holds super-tile lists (4x4 tiles); a tile's list is its
+    # super-tile's pairs whose mask has the tile's bit.
     flags, npairs = fr.read_status()
     assert flags == 0
     pk = fr.ws_view("pair_keys", torch.int32, npairs).cpu().numpy().view(np.uint32)
-    rng_ = fr.ws_view("tile_ranges", torch.int32, 2 * lay.tiles_x * lay.tiles_y)
+    pm = fr.ws_view("pair_masks", torch.int16, npairs).cpu().numpy().view(np.uint16)
+    sxn, syn = lay.super_x, lay.super_y
+    rng_ = fr.ws_view("tile_ranges", torch.int32, 2 * sxn * syn)
     rng_ = rng_.cpu().numpy().view(np.uint32).reshape(-1, 2)
     counts, oids = orc.tile_lists(p, c, 16)
     starts = np.concatenate([[0], np.cumsum(counts)])
-    extra = 0
-    # tiles partition the pair buffer in tile order
+    # super-tiles partition the pair buffer in order; every pair covers a tile
     assert rng_[0, 0] == 0 and np.all(rng_[1:, 0] == rng_[:-1, 1])
+    assert rng_[:, 1].max() == npairs
+    assert np.all(pm != 0)
+    # every mask is the Gaussian's tile rectangle inside its super-tile
+    rects = fr.ws_view("rects", torch.int16, 4 * P).cpu().numpy().view(np.uint16).reshape(P, 4)
+    for S in range(sxn * syn):
+        a, b = rng_[S]
+        X, Y = S % sxn, S // sxn
+        r = rects[pk[a:b].astype(np.int64)].astype(np.int64)
+        xa, xb = np.maximum(r[:, 0] - 4 * X, 0), np.minimum(r[:, 2] - 4 * X, 3)
+        ya, yb = np.maximum(r[:, 1] - 4 * Y, 0), np.minimum(r[:, 3] - 4 * Y, 3)
+        want = np.zeros(b - a, np.int64)
+        for yy in range(4):
+            for xx in range(4):
+                want |= ((xa <= xx) & (xx <= xb) & (ya <= yy) & (yy <= yb)).astype(np.int64) << (4 * yy + xx)
+        assert np.array_equal(pm[a:b].astype(np.int64), want), S
+    extra, total = 0, 0
     for t in range(len(counts)):
-        a, b = rng_[t]
-        gl = pk[a:b].astype(np.int64)  # Gaussian ids, depth order
+        tx, ty = t % lay.tiles_x, t // lay.tiles_x
+        S = (ty // 4) * sxn + tx // 4
+        a, b = rng_[S]
+        sel = (pm[a:b].astype(np.int64) >> (4 * (ty % 4) + tx % 4)) & 1 == 1
+        gl = pk[a:b][sel].astype(np.int64)  # Gaussian ids, depth order
         ol = oids[starts[t]:starts[t + 1]].astype(np.int64)
         inset = np.isin(gl, ol)
         assert np.array_equal(gl[inset], ol), t
         extra += int((~inset).sum())
-    assert rng_[:, 1].max() == npairs
+        total += len(gl)
     # conservative rectangles add some pairs, never drop one
-    assert extra <= 0.6 * npairs
+    assert extra <= 0.6 * total
 
 
 @pytest.mark.parametrize("P", [1, 2047, 2048, 2049, 6145, 50_000, 262_145])
@@ -230,14 +252,29 @@ def test_forward_backward_parity(orc, kind, C):
     _check_backward(res, o)
 
 
-def test_fallback_binning_large_tile_grid(orc):
-    """More than 4096 tiles: (tile, rank) keys are radix-sorted instead of the
-    direct per-tile scatter; results must not change."""
+def test_key_sort_binning_path(orc):
+    """Binning by radix-sorting (super-tile, rank) keys (what grids too large
+    for the direct scatter use, forced here with bin_mode = 1) gives the same
+    super-tile lists and masks as the direct scatter, and the same results."""
     sc = sg.make_scene(3000, 1040, 1040, 800.0, 800.0, 520.0, 520.0, 8, seed=21)
     sc.log_scales += 0.5
-    fr, _ = H.make_frame(sc, torch)
-    assert fr.layout.tiles_x * fr.layout.tiles_y > 4096
-    res = _run(sc, orc)
+    lists = []
+    for mode in (0, 1):
+        fr, _ = H.make_frame(sc, torch, settings=_settings(bin_mode=mode))
+        for st in ["gsff_preprocess", "gsff_sort_depth", "gsff_bin", "gsff_sort_tiles",
+                   "gsff_tile_ranges"]:
+            fr.call_stage(st)
+        torch.cuda.synchronize()
+        flags, n = fr.read_status()
+        assert flags == 0
+        lay = fr.layout
+        lists.append([fr.ws_view("pair_keys", torch.int32, n).cpu().numpy(),
+                      fr.ws_view("pair_masks", torch.int16, n).cpu().numpy(),
+                      fr.ws_view("tile_ranges", torch.int32,
+                                 2 * lay.super_x * lay.super_y).cpu().numpy()])
+    for a, b in zip(*lists):
+        assert np.array_equal(a, b)
+    res = _run(sc, orc, settings=_settings(bin_mode=1))
     o = _oracle(sc, orc, ups=res["ups"])
     _check_forward(res, o)
     _check_backward(res, o)
