@@ -251,11 +251,11 @@ void k_composite_fwd(
   // the tile's walked list: kSuper^2 slots of the super-tile's length per super-tile entry
   const uint32_t cbase = (uint32_t)(kSuper * kSuper) * sr.x + (uint32_t)lsub * (sr.y - sr.x);
   const int cn = CP > 0 ? min(CP, C - c0) : 0;
-  // the last wave scans the list and batches the accepted ids; its first 16
-  // lanes load the records
+  // wave 2 scans the list and batches the accepted ids; the first 16 lanes of
+  // the last wave load the records
   const int pf = tid - (kBlock - 64);
   const bool pf_lane = pf >= 0 && pf < NB;
-  const bool scan_wave = wave == kBlock / 64 - 1;
+  const bool scan_wave = wave == kBlock / 64 - 2;
   uint32_t sc = sr.x, qh = 0, qt = 0;  // scan position, queue head / tail (scan wave)
   // Scan 128 list entries: lanes hold entries sc + lane and sc + 64 + lane.
   auto scan_issue = [&](uint32_t& gA, uint32_t& mA, uint32_t& gB, uint32_t& mB) {
@@ -345,15 +345,18 @@ void k_composite_fwd(
   lds_barrier();
 
   int buf = 0;
+  // a scan ahead of the queue, issued in one batch and committed at the start
+  // of the next one, so its loads have a whole batch to arrive
+  uint32_t gA = 0u, mA = 0u, gB = 0u, mB = 0u;
+  bool ahead = false;
   for (uint32_t k = 0; s_nb[k & 3] > 0u; ++k) {
     const bool more = s_nb[(k + 1) & 3] > 0u;  // batch k + 1 has ids
     const uint32_t b0 = cbase + s_pos[k & 3];  // walked-list position of this batch
-    // ---- the scan wave: ids of batch k + 2 from the queue, a scan ahead if the
-    // queue runs short (committed at the end of the batch)
+    // ---- the scan wave: ids of batch k + 2 from the queue (a scan first if the
+    // queue runs short), then the next scan ahead
     uint32_t g_after = (uint32_t)P, n_after = 0u, pos_after = 0u;
-    uint32_t gA = 0u, mA = 0u, gB = 0u, mB = 0u;
-    bool ahead = false;
     if (scan_wave) {
+      if (ahead) scan_commit(gA, mA, gB, mB);
       n_after = more ? take_batch(g_after, pos_after) : 0u;
       ahead = qt - qh < 3u * NB && sc < sr.y;
       if (ahead) scan_issue(gA, mA, gB, mB);
@@ -458,7 +461,6 @@ void k_composite_fwd(
         s_nb[(k + 2) & 3] = n_after;
         s_pos[(k + 2) & 3] = pos_after;
       }
-      if (ahead) scan_commit(gA, mA, gB, mB);
     }
     const bool still = __ballot(!done) != 0ull;
     if (lane == 0) s_act[buf][wave] = still ? 1 : 0;
