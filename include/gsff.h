@@ -168,7 +168,8 @@ gsff_status gsff_default_settings(gsff_settings* st);
 
 /* Workspace bytes for P Gaussians with `channels` feature channels (the C of
  * the gsff_gaussians the workspace will serve; 0..4096), a pair capacity of
- * max_pairs (Gaussian-tile overlaps), and a width x height image (host only).
+ * max_pairs (Gaussian / super-tile overlaps; the count a frame needs is
+ * reported by gsff_read_status), and a width x height image (host only).
  * Requires P < 2^30, max_pairs < 2^32 - 1, and for tile grids binned by the
  * pair sort ceil(log2(max(P,2))) + ceil(log2(tiles)) <= 32.  The workspace
  * needs no initialisation. */
@@ -230,11 +231,15 @@ gsff_status gsff_backward_l1(const gsff_gaussians* g, const gsff_camera* cam,
 /* Stage entry points: the forward is exactly preprocess, sort_depth, bin,
  * sort_tiles, tile_ranges, composite_fwd in this order; the backward is
  * composite_bwd then preprocess_bwd.  Same arguments and conventions as the
- * two calls above; exposed for stage-by-stage testing and timing.  For tile
- * grids of up to 4096 tiles whose 16 bytes per tile plus 32 bytes per tile row
- * and column fit in 64 KiB, `bin` writes every tile's list directly in depth
- * order and `sort_tiles` / `tile_ranges` have nothing left to do; other grids
- * sort (tile, rank) keys instead.  The compositing adjoints leave their
+ * two calls above; exposed for stage-by-stage testing and timing.  Binning
+ * lists Gaussians per super-tile (GSFF_SUPER x GSFF_SUPER tiles) in depth
+ * order with a tile mask per entry (ws_layout.pair_keys / pair_masks); for
+ * super-tile grids whose 16 bytes per super-tile plus 32 per super-tile row
+ * and column fit in 64 KiB, `bin` writes the lists directly and `sort_tiles` /
+ * `tile_ranges` have nothing left to do, other grids (or bin_mode 1) sort
+ * (super-tile, rank) keys.  `composite_fwd` walks each tile's entries of its
+ * super-tile list and records the ids it walked (ws_layout.tile_lists), which
+ * the adjoint then walks back to front.  The compositing adjoints leave their
  * per-Gaussian sums (image-space terms and feature gradients) inside `ws` as
  * one row per walked (tile, Gaussian) pair, filed per Gaussian, plus direct
  * accumulation for tiles whose rows do not fit; `preprocess` resets them and
@@ -320,7 +325,7 @@ gsff_status gsff_l1_grad(const float* x, const float* y, int64_t n, float scale,
 
 /* Wait for `stream`, then copy the workspace status word (which starts at
  * byte 0 of every workspace) to the host: *flags receives the GSFF_FLAG_*
- * bits and *n_pairs the number of tile pairs the last forward needed (even
+ * bits and *n_pairs the number of super-tile pairs the last forward needed (even
  * when it exceeded max_pairs).  Host pointers; either may be NULL. */
 gsff_status gsff_read_status(const void* ws, uint32_t* flags, int64_t* n_pairs, void* stream);
 
