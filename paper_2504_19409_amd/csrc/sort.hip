@@ -36,6 +36,14 @@
 
 namespace gsff {
 
+// Workgroup barrier that orders LDS only: global loads issued before it stay
+// in flight (__syncthreads() also waits for every outstanding global access).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ __forceinline__ uint64_t lanemask_lt(int lane) {
   return (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 }
@@ -245,23 +253,30 @@ __global__ __launch_bounds__(256) void k_sort_pass(const uint32_t* __restrict__ 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int shift = 8 * pass;
   uint32_t* lb = w.sort_lb + (uint64_t)pass * gridDim.x * 256;
-  if (tid == 0) s_bid = atomicAdd(&w.sort_ctr[pass], 1u);
 #pragma unroll
   for (int k = 0; k < 4; ++k) s_cnt[k][tid] = 0u;
-  // this pass's digit totals (thread = digit), from the histogram partials
-  uint32_t tot = 0;
-#pragma unroll 16
-  for (int g = 0; g < kSortHistBlocks; ++g) tot += w.sort_part[g * 1024 + 256 * pass + tid];
-  __syncthreads();
-  const uint32_t b = s_bid;
-  const uint64_t base = (uint64_t)b * (256 * IPT) + (uint64_t)wv * (64 * IPT);
+  // the keys of chunk blockIdx.x are loaded while the ticket is in flight:
+  // workgroups nearly always draw their own index, otherwise they reload
   uint32_t k[IPT], v[IPT], rank[IPT];
+  auto load_chunk = [&](uint32_t bb) {
+    const uint64_t bs = (uint64_t)bb * (256 * IPT) + (uint64_t)wv * (64 * IPT);
 #pragma unroll
-  for (int it = 0; it < IPT; ++it) {
-    const uint64_t idx = base + (uint64_t)it * 64 + lane;
-    k[it] = idx < n ? kin[idx] : 0u;
-    v[it] = idx < n ? vin[idx] : 0u;
-  }
+    for (int it = 0; it < IPT; ++it) {
+      const uint64_t idx = bs + (uint64_t)it * 64 + lane;
+      k[it] = idx < n ? kin[idx] : 0u;
+      v[it] = idx < n ? vin[idx] : 0u;
+    }
+  };
+  load_chunk(blockIdx.x);
+  // this pass's digit totals (thread = digit), from the histogram partials
+  uint32_t part[kSortHistBlocks];
+#pragma unroll
+  for (int g = 0; g < kSortHistBlocks; ++g) part[g] = w.sort_part[g * 1024 + 256 * pass + tid];
+  if (tid == 0) s_bid = atomicAdd(&w.sort_ctr[pass], 1u);  // after the loads are issued
+  lds_barrier();  // the ticket and the zeroed counts; the loads stay in flight
+  const uint32_t b = s_bid;
+  if (b != blockIdx.x) load_chunk(b);  // uniform
+  const uint64_t base = (uint64_t)b * (256 * IPT) + (uint64_t)wv * (64 * IPT);
   // stable rank of every key among the wave's keys of its digit
   const uint64_t lt = lanemask_lt(lane);
 #pragma unroll
@@ -327,6 +342,9 @@ __global__ __launch_bounds__(256) void k_sort_pass(const uint32_t* __restrict__ 
     __hip_atomic_store(&lb[b * 256 + tid], kLbInc | (excl + cnt), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
   }
+  uint32_t tot = 0u;
+#pragma unroll
+  for (int g = 0; g < kSortHistBlocks; ++g) tot += part[g];
   uint32_t all;
   const uint32_t dbase = block_excl_scan256(tot, s_tmp, &all);
   s_base[tid] = dbase + excl;
