@@ -220,7 +220,7 @@ static hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t*
 // inclusive prefix through the chunk; bits 29-0 the count.
 constexpr uint32_t kLbAgg = 1u << 30, kLbInc = 2u << 30, kLbMask = (1u << 30) - 1u;
 constexpr uint32_t kLbSpinMax = 1u << 22;  // polls before giving up (flags the frame)
-constexpr int kLbWindow = 16;              // predecessors read per look-back step
+constexpr int kLbWindow = 8;               // predecessors read per look-back step
 
 __global__ __launch_bounds__(256) void k_sort_hist4(const uint32_t* __restrict__ keys, uint32_t n,
                                                     WsView w, uint32_t lb_words) {
