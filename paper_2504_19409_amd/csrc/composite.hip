@@ -989,19 +989,21 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
         const float4 r0 = s_r0[buf][jj], r1 = s_r1[buf][jj];
         const AlphaEval e = eval_alpha(r0, r1, pxc, pyc, st.alpha_max);
         const bool act = (b0 + (uint32_t)jj < pend) && (e.alpha >= st.alpha_min);
-        const float am = act ? 1.f : 0.f;
-        const float inv = __builtin_amdgcn_rcpf(1.f - e.alpha);  // v_rcp_f32, 1 ulp
+        // a pair the pixel does not use gets alpha 0: then 1 / (1 - alpha) is
+        // exactly 1, T passes through and the weight is 0
+        const float al = act ? e.alpha : 0.f;
+        const float inv = __builtin_amdgcn_rcpf(1.f - al);  // v_rcp_f32, 1 ulp; rcp(1) = 1
         const float Tb = T * inv;  // transmittance in front of this Gaussian
-        const float wv = am * (e.alpha * Tb);
+        const float wv = al * Tb;
         if constexpr (GEO) {
           const float4 r2 = s_r2[buf][jj];
           const float gc = gr * r2.x + gg * r2.y + gb * r2.z + gd * r1.z;
           const float dal = Tb * gc + (gaT - D) * inv;
-          const float og = (e.oG < st.alpha_max) ? am * e.oG : 0.f;
+          const float og = (act && e.oG < st.alpha_max) ? e.oG : 0.f;
           D = fmaf(wv, gc, D);
           s_DP[jj][tid] = dal * og;
         }
-        T = act ? Tb : T;
+        T = Tb;
         s_W[jj][tid] = wv;
       }
     } else {
