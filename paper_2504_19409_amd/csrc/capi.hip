@@ -101,7 +101,10 @@ bool compute_layout(int64_t P, int32_t C, int64_t max_pairs, int32_t W, int32_t 
   l.rows = take(4ull * (uint64_t)l.row_cap * (uint64_t)l.row_width);
   l.tile_walk = take(4ull * l.ntiles);
   l.walk_off = take(4ull * l.ntiles);
-  l.tile_order = take(4ull * l.ntiles);
+  l.seg_order = take(16ull * l.ntiles * kMaxSeg);
+  l.seg_n = take(4);
+  l.seg_state = take(4ull * l.ntiles * (kMaxSeg - 1) * 5 * kBlock);
+  l.seg_final = take(4ull * l.ntiles * 4 * kBlock);
   l.slot_local = take(4ull * P);
   l.slot_blk = take(4ull * (uint64_t)(l.pose_blocks + 1));
   l.nslot = take(4ull * P);
@@ -158,7 +161,10 @@ WsView make_view(void* ws, const Layout& L) {
   w.slot_blk = (uint32_t*)(b + L.slot_blk);
   w.nslot = (uint32_t*)(b + L.nslot);
   w.slots = (uint32_t*)(b + L.slots);
-  w.tile_order = (uint32_t*)(b + L.tile_order);
+  w.seg_order = (uint4*)(b + L.seg_order);
+  w.seg_n = (uint32_t*)(b + L.seg_n);
+  w.seg_state = (float*)(b + L.seg_state);
+  w.seg_final = (float*)(b + L.seg_final);
   w.item_n = (uint32_t*)(b + L.item_n);
   w.items = (uint2*)(b + L.items);
   w.row_cap = (uint32_t)L.row_cap;

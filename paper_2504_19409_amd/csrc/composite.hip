@@ -345,6 +345,7 @@ void k_composite_fwd(
   lds_barrier();
 
   int buf = 0;
+  int nseg_end = 0;  // segment-end states recorded
   // a scan ahead of the queue, issued in one batch and committed at the start
   // of the next one, so its loads have a whole batch to arrive
   uint32_t gA = 0u, mA = 0u, gB = 0u, mB = 0u;
@@ -380,6 +381,19 @@ void k_composite_fwd(
       }
     }
 
+    // ---- every kSegBatches batches, each pixel's transmittance and the
+    // colour and depth blended in front of this batch: the adjoint's segments
+    // that end here start from them.  Stored after this batch's loads are
+    // issued: waits for those loads do not include the stores.
+    if (write_geo && k > 0 && k % kSegBatches == 0 && nseg_end < kMaxSeg - 1) {
+      float* q = w.seg_state + ((int64_t)tile * (kMaxSeg - 1) + nseg_end) * 5 * kBlock + tid;
+      q[0] = T;
+      q[kBlock] = cr;
+      q[2 * kBlock] = cg;
+      q[3 * kBlock] = cb;
+      q[4 * kBlock] = dep;
+      ++nseg_end;
+    }
     const bool wave_active = __ballot(!done) != 0ull;
     if (wave_active) {
       // ---- phase A: weights, transmittance, colour and depth, front to back
@@ -482,6 +496,15 @@ void k_composite_fwd(
     }
   }
 
+  // a split tile also keeps its final colour and depth: the adjoint takes
+  // what is blended behind a segment's end as final minus recorded
+  if (nseg_end > 0) {
+    float* q = w.seg_final + (int64_t)tile * 4 * kBlock + tid;
+    q[0] = cr;
+    q[kBlock] = cg;
+    q[2 * kBlock] = cb;
+    q[3 * kBlock] = dep;
+  }
   const int64_t HW = (int64_t)W * H;
   if (inside && write_geo) {
     const int64_t p = (int64_t)py * W + px;
@@ -521,18 +544,47 @@ __global__ void k_fill_zero(OT* p, int64_t n) {
 }
 
 // One block: the adjoint's first row of every tile, an exclusive scan of the
-// walk lengths (the list prefix the forward visited) over the tiles.
+// walk lengths (the list prefix the forward visited) over the tiles, and the
+// adjoint's work items.  The tiles' walk ranges are read once, into LDS (the
+// first kWalkCache tiles; any further ones are read where needed).
+constexpr int kWalkCache = 8192;
 __global__ __launch_bounds__(1024) void k_walk_scan(WsView w, int ntiles, uint32_t max_pairs) {
   __shared__ uint32_t s_w[16];
+  __shared__ uint2 s_rng[kWalkCache];     // [start, walk end) of each tile's walked list
+  __shared__ uint32_t s_off[kWalkCache];  // first row of each tile
+  __shared__ uint32_t s_ok[kWalkCache];   // the forward's walk end matches (rows usable)
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int ncache = min(ntiles, kWalkCache);
+  {
+    uint2 r[kWalkCache / 1024];
+    uint32_t t[kWalkCache / 1024];
+#pragma unroll
+    for (int m = 0; m < kWalkCache / 1024; ++m) {
+      const int i = threadIdx.x + 1024 * m;
+      if (i < ncache) {
+        r[m] = w.crange[i];
+        t[m] = w.tile_walk[i];
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < kWalkCache / 1024; ++m) {
+      const int i = threadIdx.x + 1024 * m;
+      if (i < ncache) {
+        s_rng[i] = r[m];
+        s_ok[i] = t[m] == r[m].y ? 1u : 0u;
+      }
+    }
+  }
+  __syncthreads();
+  auto rng_of = [&](int i) { return i < kWalkCache ? s_rng[i] : w.crange[i]; };
+  auto walk_of = [&](int i) {
+    const uint2 r = rng_of(i);
+    return r.y > r.x ? r.y - r.x : 0u;
+  };
   uint32_t carry = 0;
   for (int b = 0; b < ntiles; b += 1024) {
     const int i = b + threadIdx.x;
-    uint32_t v = 0;
-    if (i < ntiles) {
-      const uint2 r = w.crange[i];  // [start, walk end) of the tile's walked list
-      v = r.y > r.x ? r.y - r.x : 0u;
-    }
+    const uint32_t v = i < ntiles ? walk_of(i) : 0u;
     uint32_t inc = v;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
@@ -547,21 +599,55 @@ __global__ __launch_bounds__(1024) void k_walk_scan(WsView w, int ntiles, uint32
       tot += s_w[k];
     }
     __syncthreads();
-    if (i < ntiles) w.walk_off[i] = carry + pre + inc - v;
+    if (i < ntiles) {
+      const uint32_t off = carry + pre + inc - v;
+      w.walk_off[i] = off;
+      if (i < kWalkCache) s_off[i] = off;
+    }
     carry += tot;
   }
-  // The adjoint's launch order: tiles by decreasing walk length (counting
-  // sort on buckets of 4 list entries), so the tiles that start after the
-  // first round of resident workgroups are the short ones.
+  // The adjoint's work items: each tile's walked list in segments of
+  // kSegLen entries (at most kMaxSeg, the last takes the rest; a tile with an
+  // empty walk keeps one item for its loss), ordered by decreasing length
+  // (counting sort on buckets of 4 entries), so the items that start after
+  // the first round of resident workgroups are the short ones.
   __shared__ uint32_t s_cnt[1024];
-  auto key_of = [&](int i) {
-    const uint2 r = w.crange[i];
-    const uint32_t v = r.y > r.x ? r.y - r.x : 0u;
-    return 1023u - min(v >> 2, 1023u);
+  __shared__ uint32_t s_total;
+  auto nseg_of = [](uint32_t v) {
+    return v == 0u ? 1u : min((uint32_t)kMaxSeg, (v + kSegLen - 1) / kSegLen);
+  };
+  auto key_of = [](uint32_t v, uint32_t j, uint32_t ns) {
+    const uint32_t len = j + 1 < ns ? (uint32_t)kSegLen : v - j * kSegLen;
+    return 1023u - min(len >> 2, 1023u);
+  };
+  // every segment but a tile's last has kSegLen entries, so one key: those
+  // are counted and placed one wave at a time (a wave scan of the tiles'
+  // counts and one atomic), the last segments one at a time
+  const uint32_t key_inner = key_of(kSegLen, 0u, 2u);
+  auto wave_excl = [&](uint32_t v, uint32_t& total) {
+    uint32_t inc = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t t = __shfl_up(inc, off, 64);
+      if (lane >= off) inc += t;
+    }
+    total = __shfl(inc, 63, 64);
+    return inc - v;
   };
   s_cnt[threadIdx.x] = 0u;
   __syncthreads();
-  for (int i = threadIdx.x; i < ntiles; i += 1024) atomicAdd(&s_cnt[key_of(i)], 1u);
+  for (int b = 0; b < ntiles; b += 1024) {
+    const int i = b + threadIdx.x;
+    uint32_t ninner = 0u;
+    if (i < ntiles) {
+      const uint32_t v = walk_of(i), ns = nseg_of(v);
+      atomicAdd(&s_cnt[key_of(v, ns - 1u, ns)], 1u);
+      ninner = ns - 1u;
+    }
+    uint32_t wtot;
+    wave_excl(ninner, wtot);
+    if (lane == 0 && wtot > 0u) atomicAdd(&s_cnt[key_inner], wtot);
+  }
   __syncthreads();
   {
     const uint32_t c = s_cnt[threadIdx.x];
@@ -573,15 +659,49 @@ __global__ __launch_bounds__(1024) void k_walk_scan(WsView w, int ntiles, uint32
     }
     if (lane == 63) s_w[wv] = inc;
     __syncthreads();
-    uint32_t pre = 0;
-    for (int k = 0; k < wv; ++k) pre += s_w[k];
+    uint32_t pre = 0, tot = 0;
+    for (int k = 0; k < 16; ++k) {
+      if (k < wv) pre += s_w[k];
+      tot += s_w[k];
+    }
     s_cnt[threadIdx.x] = pre + inc - c;
+    if (threadIdx.x == 0) s_total = tot;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < ntiles; i += 1024) {
-    const uint32_t pos = atomicAdd(&s_cnt[key_of(i)], 1u);
-    if (pos < (uint32_t)ntiles) w.tile_order[pos] = (uint32_t)i;
+  // an item: tile | segment << 24 | (a later segment follows) << 30 |
+  // (the tile's rows fit) << 31, its list range [q1, q2) and the row of list
+  // position 0 (rows are indexed by list position)
+  const uint32_t cap = (uint32_t)ntiles * (uint32_t)kMaxSeg;
+  const uint64_t ccap = min((uint64_t)(kSuper * kSuper) * max_pairs, (uint64_t)0xFFFFFFFFu);
+  for (int b = 0; b < ntiles; b += 1024) {
+    const int i = b + threadIdx.x;
+    const bool on = i < ntiles;
+    const uint2 cr = on ? rng_of(i) : make_uint2(0u, 0u);
+    const uint2 r = clamp_range(cr, (uint32_t)ccap);
+    const uint32_t v = cr.y > cr.x ? cr.y - cr.x : 0u, ns = on ? nseg_of(v) : 0u;
+    // places of this tile's inner segments: the wave's block plus the offset
+    uint32_t wtot;
+    const uint32_t woff = wave_excl(ns > 0u ? ns - 1u : 0u, wtot);
+    uint32_t wbase = 0u;
+    if (lane == 0 && wtot > 0u) wbase = atomicAdd(&s_cnt[key_inner], wtot);
+    wbase = __shfl(wbase, 0, 64);
+    if (!on) continue;
+    const uint32_t wstart = i < kWalkCache ? s_off[i] : w.walk_off[i];
+    const bool walk_ok = i < kWalkCache ? s_ok[i] != 0u : w.tile_walk[i] == cr.y;
+    const bool rows_ok = walk_ok && cr.y == r.y &&
+                         (uint64_t)wstart + (r.y - r.x) <= (uint64_t)w.row_cap;
+    for (uint32_t j = 0; j < ns; ++j) {
+      const bool inner = j + 1 < ns;
+      const uint32_t pos = inner ? wbase + woff + j : atomicAdd(&s_cnt[key_of(v, j, ns)], 1u);
+      const uint32_t q1 = min(r.x + j * kSegLen, r.y);
+      const uint32_t q2 = inner ? min(q1 + kSegLen, r.y) : r.y;
+      if (pos < cap)
+        w.seg_order[pos] = make_uint4((uint32_t)i | (j << 24) | ((inner ? 1u : 0u) << 30) |
+                                          ((rows_ok ? 1u : 0u) << 31),
+                                      q1, q2, wstart - r.x);
+    }
   }
+  if (threadIdx.x == 0) w.seg_n[0] = min(s_total, cap);
 }
 
 template <int CP, typename FT, typename OT>
@@ -751,11 +871,15 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
   __shared__ float4 s_r0[2][kBwdNB], s_r1[2][kBwdNB], s_r2[2][kBwdNB];
   __shared__ uint32_t s_gid[2][kBwdNB];
   __shared__ float s_mom[kBwdNB][8];
-  __shared__ uint32_t s_end;
   __shared__ float s_loss[kBlock / 64];
-  if (blockIdx.x >= (unsigned)ntiles) return;
-  const int tile = (int)w.tile_order[blockIdx.x];  // longest walks first
-  if ((unsigned)tile >= (unsigned)ntiles) return;  // (a permutation once the forward ran)
+  // work item: a segment [q1, q2) of a tile's walked list (longest first)
+  if (blockIdx.x >= min(w.seg_n[0], (uint32_t)ntiles * (uint32_t)kMaxSeg)) return;
+  const uint4 item = w.seg_order[blockIdx.x];
+  const int tile = (int)(item.x & 0xFFFFFFu), seg = (int)((item.x >> 24) & 63u);
+  const bool inner = ((item.x >> 30) & 1u) != 0u;  // a later segment follows
+  const bool rows_ok = (item.x >> 31) != 0u;       // the tile's rows fit
+  const uint32_t q1 = item.y, q2 = item.z;
+  const uint32_t rowbase = item.w;  // row of list position p: rowbase + p
   if (tile >= ntiles) return;
   const int tx = tile % tiles_x, ty = tile / tiles_x;
   const int tid = threadIdx.x;
@@ -764,17 +888,36 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
   const int py = ty * kTile + (tid / kTile);
   const bool inside = px < W && py < H;
   const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
-  // the tile's walked list (the forward's filtered walk of its super-tile
-  // list), kept inside the walked-list region
-  const uint64_t ccap = (uint64_t)(kSuper * kSuper) * max_pairs;
-  const uint2 range = clamp_range(w.crange[tile], (uint32_t)min(ccap, (uint64_t)0xFFFFFFFFu));
   const int cn = CP > 0 ? min(CP, C - c0) : 0;
   const int64_t HW = (int64_t)W * H;
   const int64_t p = (int64_t)py * W + px;
 
+  // Batches run back to front: [b0, b1), then [nb0, nb1 = b0), then
+  // [mb0, mb1 = nb0), ...; only the front-most one can be shorter than 16.
+  // Loads are pipelined: while batch b is processed, the records of b+1
+  // (whose ids arrived during b-1) and the ids of b+2 are in flight.
+  const uint32_t rx = q1;
+  auto batch_start = [rx](uint32_t end) {
+    return end > rx ? end - min((uint32_t)kBwdNB, end - rx) : end;
+  };
+  // The loads are issued by the first 16 lanes of the last wave, which has no
+  // output block when NT < 4 (its memory queue then holds no gradient atomics).
+  // Ids stay unchecked until use: load_record and the atomics test id < P.
+  // The ids of the first two batches are the first loads of the item.
+  const int pf = tid - (kBlock - 64);
+  const bool pf_lane = pf >= 0 && pf < kBwdNB;
+  uint32_t b1 = q2, b0 = batch_start(b1);
+  uint32_t nb1 = b0, nb0 = batch_start(nb1);
+  uint32_t gid0 = (uint32_t)P, g_next = (uint32_t)P;  // per prefetch lane
+  if (pf_lane) {
+    if (b0 + pf < b1) gid0 = w.clist[b0 + pf];
+    if (nb0 + pf < nb1) g_next = w.clist[nb0 + pf];
+  }
+
+
   // ---- per-pixel state and upstream gradients
   float Tfin = 1.f;
-  uint32_t pend = range.x;
+  uint32_t pend = q1;
   float gr = 0.f, gg = 0.f, gb = 0.f, gd = 0.f, ga = 0.f;  // geometry upstream (scaled)
   float ur = 0.f, ug = 0.f, ub = 0.f, ud = 0.f;           // same, as contraction operands
   float loss = 0.f;
@@ -786,7 +929,57 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
     const float tf = w.pix_T[pq];
     const uint32_t pe = w.pix_end[pq];
     Tfin = inside ? tf : 1.f;
-    pend = inside ? pe : range.x;
+    pend = inside ? pe : q1;
+  }
+  // the feature upstream of the first staging round (RS 16-column blocks),
+  // issued with the per-pixel loads: channels past cn and pixels outside the
+  // image read channel c0 / pixel 0, masked where the values are formed
+  constexpr int RS = GEO ? 2 : 1;
+  float fo[RS][16], ft[RS][16];
+  auto load_round = [&](int r) {
+#pragma unroll
+    for (int u = 0; u < RS; ++u)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        fo[u][j] = 0.f;
+        ft[u][j] = 0.f;
+      }
+    if constexpr (CP > 0) {  // (launched with CP > 0 only when cn >= 1)
+#pragma unroll
+      for (int u = 0; u < RS; ++u)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const int k = 16 * (r * RS + u) + j;
+          const int c = k - (GEO ? 4 : 0);
+          if (k < NL && c >= 0) {
+            const int64_t q = (int64_t)(c0 + (c < cn ? c : 0)) * HW + pq;
+            if constexpr (L1) {
+              fo[u][j] = l1.out_feat[q];
+              ft[u][j] = l1.t_feat[q];
+            } else {
+              fo[u][j] = g_feat[q];
+            }
+          }
+        }
+    }
+  };
+  load_round(0);
+  // the records of the first batch, once their ids (the first loads) arrive:
+  // every lane loads, with no branch to hold the wait (lanes that stage no
+  // record and ids past the end read Gaussian 0, masked where staged)
+  const int64_t g0 = gid0 < (uint32_t)P ? (int64_t)gid0 : 0;
+  const float4 f0 = w.rec[g0], f1 = w.rec[P + g0], f2 = w.rec[2 * P + g0];
+  // the state at this segment's end as the forward recorded it (when a later
+  // segment follows): T and the colour and depth blended in front of it, and
+  // the tile's final colour and depth
+  float sst[5] = {1.f, 0.f, 0.f, 0.f, 0.f}, sfin[4] = {0.f, 0.f, 0.f, 0.f};
+  if (inner) {
+    const float* q = w.seg_state + ((int64_t)tile * (kMaxSeg - 1) + seg) * 5 * kBlock + tid;
+    const float* f = w.seg_final + (int64_t)tile * 4 * kBlock + tid;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) sst[k] = q[k * kBlock];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sfin[k] = f[k * kBlock];
   }
   if constexpr (GEO) {
     if constexpr (L1) {
@@ -828,61 +1021,63 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
       ga = inside ? a4 : 0.f;
     }
   }
-  if (tid == 0) s_end = range.x;
+  // transmittance and D at the segment's end: the final values for the last
+  // segment, the recorded ones for the others
+  float T = Tfin, D = 0.f;
+  if (inner) {
+    T = inside ? sst[0] : 1.f;
+    if constexpr (GEO)
+      D = inside ? gr * (sfin[0] - sst[1]) + gg * (sfin[1] - sst[2]) + gb * (sfin[2] - sst[3]) +
+                       gd * (sfin[3] - sst[4])
+                 : 0.f;
+  }
 
   // ---- right operands, kept in registers for the tile: wave b < NCB holds
   // G[pixels 32s + 8 lq .. +7][channel 16 b + lj] for s = 0..7, the moments
   // wave (b = NCB) the moment values of the same pixels.
-  // The per-pixel values are staged through s_W one 16-channel block at a time.
+  // The per-pixel values are staged through LDS, RS 16-channel blocks at a
+  // time (s_W, and s_DP when the geometry terms are on).
   bf16x8 bh[8], bl[8];
 #pragma unroll
-  for (int cb = 0; cb < NCB; ++cb) {
-    // this block's feature upstream, all loads issued together (channels past
-    // cn and pixels outside the image read channel c0 / pixel 0, masked below)
-    float fo[16], ft[16];
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      fo[j] = 0.f;
-      ft[j] = 0.f;
+  for (int r = 0; r < (NCB + RS - 1) / RS; ++r) {
+    if (r > 0) {
+      load_round(r);
+      lds_barrier();  // the staging rows are free again
     }
-    if (cn > 0) {
+#pragma unroll
+    for (int u = 0; u < RS; ++u) {
+      float* rows_u = u == 0 ? &s_W[0][0] : &s_DP[0][0];
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
-        const int k = 16 * cb + j;
-        const int c = k - (GEO ? 4 : 0);
-        if (k < NL && c >= 0) {
-          const int64_t q = (int64_t)(c0 + (c < cn ? c : 0)) * HW + pq;
-          if constexpr (L1) {
-            fo[j] = l1.out_feat[q];
-            ft[j] = l1.t_feat[q];
+        const int k = 16 * (r * RS + u) + j;
+        float v = 0.f;
+        if (k < NL) {
+          if (GEO && k < 4) {
+            v = k == 0 ? ur : (k == 1 ? ug : (k == 2 ? ub : ud));
           } else {
-            fo[j] = g_feat[q];
+            const int c = k - (GEO ? 4 : 0);
+            const bool on = inside && c < cn;
+            const float m = on ? 1.f : 0.f;
+            v = L1 ? m * l1_unit_sign(fo[u][j], ft[u][j], m * l1.s_feat, loss)
+                   : (on ? fo[u][j] : 0.f);
           }
         }
+        if (r * RS + u < NCB) rows_u[j * kBwdStride + tid] = v;
       }
     }
-    lds_barrier();  // s_W free
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const int k = 16 * cb + j;
-      float v = 0.f;
-      if (k < NL) {
-        if (GEO && k < 4) {
-          v = k == 0 ? ur : (k == 1 ? ug : (k == 2 ? ub : ud));
-        } else {
-          const int c = k - (GEO ? 4 : 0);
-          const bool on = inside && c < cn;
-          const float m = on ? 1.f : 0.f;
-          v = L1 ? m * l1_unit_sign(fo[j], ft[j], m * l1.s_feat, loss) : (on ? fo[j] : 0.f);
-        }
-      }
-      s_W[j][tid] = v;
+    if (r == 0 && pf_lane) {  // the first batch's records have arrived by now
+      const bool ok = gid0 < (uint32_t)P;
+      s_gid[0][pf] = gid0;
+      s_r0[0][pf] = scaled_r0(keep4(ok, f0));
+      s_r1[0][pf] = scaled_r1(keep4(ok, f1));
+      s_r2[0][pf] = keep4(ok, f2);
     }
     lds_barrier();
-    if (wave == cb) {
+    if (wave >= r * RS && wave < r * RS + RS && wave < NCB) {
+      const float* rows_w = wave == r * RS ? &s_W[0][0] : &s_DP[0][0];
 #pragma unroll
       for (int s = 0; s < 8; ++s) {
-        const float* src = &s_W[lj][32 * s + 8 * lq];
+        const float* src = rows_w + lj * kBwdStride + 32 * s + 8 * lq;
         const float4 a = *reinterpret_cast<const float4*>(src);
         const float4 b = *reinterpret_cast<const float4*>(src + 4);
         if (L1) {
@@ -920,51 +1115,17 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
     const float v = wave_sum(loss);
     if (lane == 0) s_loss[wave] = v;
   }
-  if (inside && pend > range.x) atomicMax(&s_end, pend);
   lds_barrier();
-  if (L1 && l1.loss && tid == 0) {
+  if (L1 && l1.loss && tid == 0 && seg == 0) {  // once per tile
     const float v = (s_loss[0] + s_loss[1]) + (s_loss[2] + s_loss[3]);
     if (v != 0.f) unsafeAtomicAdd(l1.loss, v);
   }
-  const uint32_t blk_end = min(s_end, range.y);
-  if (blk_end <= range.x) return;  // uniform: no pixel of the tile uses any Gaussian
+  if (q1 >= q2) return;  // uniform: an empty walk (the item only carried the loss)
   // The tile's results go to one row per walked list position (the rows of
   // the tiles follow each other in tile order) when they fit; otherwise they
   // are added to the per-Gaussian gradients with atomics.
-  const uint32_t wstart = w.walk_off[tile];
-  const bool rows_ok = w.tile_walk[tile] == blk_end &&
-                       (uint64_t)wstart + (blk_end - range.x) <= (uint64_t)w.row_cap;
   const int RW = w.row_width;
 
-  // Batches run back to front: [b0, b1), then [nb0, nb1 = b0), then
-  // [mb0, mb1 = nb0), ...; only the front-most one can be shorter than 16.
-  // Loads are pipelined: while batch b is processed, the records of b+1
-  // (whose ids arrived during b-1) and the ids of b+2 are in flight.
-  const uint32_t rx = range.x;
-  auto batch_start = [rx](uint32_t end) {
-    return end > rx ? end - min((uint32_t)kBwdNB, end - rx) : end;
-  };
-  // The loads are issued by the first 16 lanes of the last wave, which has no
-  // output block when NT < 4 (its memory queue then holds no gradient atomics).
-  // Ids stay unchecked until use: load_record and the atomics test id < P.
-  const int pf = tid - (kBlock - 64);
-  const bool pf_lane = pf >= 0 && pf < kBwdNB;
-  uint32_t b1 = blk_end, b0 = batch_start(b1);
-  uint32_t nb1 = b0, nb0 = batch_start(nb1);
-  if (pf_lane) {
-    const uint32_t idx = b0 + pf;
-    const uint32_t gid = idx < b1 ? w.clist[idx] : (uint32_t)P;
-    s_gid[0][pf] = gid;
-    float4 q0, q1;
-    load_record(w, gid, P, q0, q1, s_r2[0][pf]);
-    s_r0[0][pf] = scaled_r0(q0);
-    s_r1[0][pf] = scaled_r1(q1);
-  }
-  uint32_t g_next = (uint32_t)P;  // ids of the next batch, per prefetch lane
-  if (pf_lane && nb0 + pf < nb1) g_next = w.clist[nb0 + pf];
-  lds_barrier();
-
-  float T = Tfin, D = 0.f;
   const float gaT = ga * Tfin;
   const float tcx = (float)(tx * kTile) + 0.5f * kTile, tcy = (float)(ty * kTile) + 0.5f * kTile;
   int buf = 0;
@@ -1056,7 +1217,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
         for (int r = 0; r < 4; ++r) {
           const uint32_t g = 4 * lq + r;
           if (g < nb) {
-            float* row = w.rows + (int64_t)(wstart + (b0 + g - range.x)) * RW;
+            float* row = w.rows + (int64_t)(rowbase + b0 + g) * RW;
             if (col >= 0) row[col] = acc[r] * scale;
             if (wave == 0 && first_pass) {  // columns no pass of this call writes
               if (zero_geo && lj < 10) row[lj] = 0.f;
@@ -1114,7 +1275,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
             geo[4] = -0.5f * Syy;
             geo[5] = r1.y > 0.f ? M0 * __builtin_amdgcn_rcpf(r1.y) : 0.f;
             if (rows_ok) {
-              float* row = w.rows + (int64_t)(wstart + (b0 + (uint32_t)lane - range.x)) * RW;
+              float* row = w.rows + (int64_t)(rowbase + b0 + (uint32_t)lane) * RW;
 #pragma unroll
               for (int f = 0; f < 6; ++f) row[f] = geo[f];
             } else {
@@ -1133,7 +1294,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
     if (first_pass && rows_ok && pf_lane) {
       const uint32_t gid = s_gid[buf][pf];
       if ((uint32_t)pf < b1 - b0 && gid < (uint32_t)P) {
-        const uint32_t row = wstart + (b0 + (uint32_t)pf - range.x);
+        const uint32_t row = rowbase + b0 + (uint32_t)pf;
         const uint32_t k = atomicAdd(&w.nslot[gid], 1u);
         const uint32_t sl = w.slot_blk[gid >> 8] + w.slot_local[gid] + k;
         if (sl < w.slot_cap) w.slots[sl] = row;
@@ -1170,7 +1331,7 @@ static void launch_bwd_t(const DevSettings& st, const DevGaussians& g, const Lay
                          const WsView& w, int c0, const float* g_rgb, const float* g_depth,
                          const float* g_alpha, const float* g_feat, float* d_feat,
                          const L1Upstream& l1, const PassFlags& pf, hipStream_t s) {
-  const int grid = ((L.ntiles + kNumXcd - 1) / kNumXcd) * kNumXcd;
+  const int grid = (int)L.ntiles * kMaxSeg;  // work items beyond the filed ones return
   hipLaunchKernelGGL((k_composite_bwd<CP, GEO, L1>), dim3(grid), dim3(kBlock), 0, s, st, g.P,
                      g.C, c0, L.W, L.H, L.tiles_x, L.ntiles, L.rank_bits, (uint32_t)L.max_pairs,
                      w, g_rgb, g_depth, g_alpha, g_feat, d_feat, l1, pf.first, pf.zero_geo,

@@ -24,6 +24,9 @@ constexpr int kBinBands = 4;               // tile-row bands of the direct scatt
 constexpr int kSuper = GSFF_SUPER;         // bin-grid cell: kSuper x kSuper tiles (16-bit masks)
 static_assert(kSuper == 4, "pair masks are 16 bits");
 constexpr int kBinBlock = 256;             // depth ranks per direct-binning block
+constexpr int kSegBatches = 4;             // adjoint segment: batches of 16 walked entries
+constexpr int kSegLen = 16 * kSegBatches;  // walked-list entries per adjoint segment
+constexpr int kMaxSeg = 8;                 // adjoint segments per tile (the last one takes the rest)
 
 inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
@@ -53,7 +56,7 @@ struct Layout {
            pix_end = 0, grad2d = 0, hist = 0, hist_tot = 0, scan_part = 0, pose_part = 0,
            binhist = 0, tile_tot = 0, curbase = 0, rows = 0, tile_walk = 0, walk_off = 0,
            slot_local = 0, slot_blk = 0, nslot = 0, slots = 0, item_n = 0, items = 0,
-           tile_order = 0, sort_part = 0, sort_lb = 0, sort_ctr = 0, total = 0;
+           seg_order = 0, seg_n = 0, seg_state = 0, seg_final = 0, sort_part = 0, sort_lb = 0, sort_ctr = 0, total = 0;
 };
 
 // Returns false if the sizes are not representable (key bits, negative sizes).
@@ -97,7 +100,12 @@ struct WsView {
   float* rows;           // [row_cap][row_width]
   uint32_t* tile_walk;   // [ntiles] end of the forward's walk of every tile list
   uint32_t* walk_off;    // [ntiles] first row of every tile
-  uint32_t* tile_order;  // [ntiles] tiles by decreasing walk length (adjoint launch order)
+  uint4* seg_order;      // [ntiles * kMaxSeg] adjoint work items, longest first: tile |
+                         // segment << 24 | inner << 30 | rows fit << 31, q1, q2, row base
+  uint32_t* seg_n;       // [1] adjoint work items
+  float* seg_state;      // [ntiles][kMaxSeg - 1][5][256] per-pixel state at the segment
+                         // ends: T, then the colour and depth blended in front of the end
+  float* seg_final;      // [ntiles][4][256] final colour and depth of the split tiles
   uint32_t* slot_local;  // [P] first slot of each Gaussian inside its 256-Gaussian block
   uint32_t* slot_blk;    // [P/256]: slot count of each block, then its first slot
   uint32_t* nslot;       // [P] slots filled per Gaussian
