@@ -38,7 +38,7 @@ VALU_PEAK_TSLOTS = 256 * 4 * 16 * 2.4e9 / 1e12
 LDS_PEAK_TBS = 128 * 256 * 2.4e9 / 1e12
 
 STAGES = ["preprocess", "sort_depth", "bin", "sort_tiles", "tile_ranges", "composite_fwd",
-          "composite_bwd_l1", "preprocess_bwd"]
+          "adjoint_items", "composite_bwd_l1", "preprocess_bwd"]
 L1_WEIGHTS = (1.0, 1.0, 0.0, 1.0)  # rgb, depth, alpha, feature
 
 
@@ -113,16 +113,19 @@ class Step:
         fr.call_stage("gsff_tile_ranges")
         rec(5)
         fr.composite_fwd(self.outs)
-        # the adjoint accumulates the loss and the feature gradient: cleared
-        # here so the stage below is the compositing adjoint kernel alone
+        rec(6)
+        # the adjoint's work items; the adjoint accumulates the loss and the
+        # feature gradient, cleared here so the next stage is the compositing
+        # adjoint kernel alone
+        fr.call_stage("gsff_adjoint_items")
         self.loss.zero_()
         self.grads["feat"].zero_()
-        rec(6)
-        fr.composite_bwd_l1(self.outs, self.targets, L1_WEIGHTS, self.grads, self.loss,
-                            accumulate=True)
         rec(7)
-        fr.preprocess_bwd(self.grads)
+        fr.composite_bwd_l1(self.outs, self.targets, L1_WEIGHTS, self.grads, self.loss,
+                            accumulate=True, items=False)
         rec(8)
+        fr.preprocess_bwd(self.grads)
+        rec(9)
 
 
 def algorithmic_work(scene, n_pairs, torch):
@@ -334,6 +337,7 @@ def roofline_for(stage, ms, wc, sz):
         "bin": P * 8 * 2 + M * 4,
         "sort_tiles": 2 * M * 4 * 3,
         "tile_ranges": 8 * 1200,
+        "adjoint_items": 16 * 1200,
         "preprocess_bwd": P * (44 + 40) + P * 56,
     }[stage]
     achieved = bytes_ / sec / 1e9

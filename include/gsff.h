@@ -245,7 +245,13 @@ gsff_status gsff_backward_l1(const gsff_gaussians* g, const gsff_camera* cam,
  * accumulation for tiles whose rows do not fit; `preprocess` resets them and
  * `preprocess_bwd` adds them up, writes the feature gradient (out->feat, +=)
  * and resets them again: each composite_bwd (or composite_bwd_l1) is followed
- * by one preprocess_bwd with the same `out`. */
+ * by one preprocess_bwd with the same `out`.  `adjoint_items` turns the walks
+ * of the last composite_fwd into the adjoint's work items (each tile's walked
+ * list in segments of 64 entries, at most 8 per tile, longest first; the
+ * forward recorded each pixel's state at every segment end) and the first
+ * adjoint row of every tile: it runs after composite_fwd and before the
+ * first composite_bwd / composite_bwd_l1 that follows it (gsff_backward and
+ * gsff_backward_l1 run it themselves). */
 gsff_status gsff_preprocess(const gsff_gaussians* g, const gsff_camera* cam,
                             const gsff_settings* st, void* ws, size_t ws_bytes,
                             int64_t max_pairs, void* stream);
@@ -266,6 +272,9 @@ gsff_status gsff_composite_fwd(const gsff_gaussians* g, const gsff_camera* cam,
                                int64_t max_pairs, float* out_rgb, float* out_depth,
                                float* out_alpha, void* out_feat, int32_t out_feat_dtype,
                                void* stream);
+gsff_status gsff_adjoint_items(const gsff_gaussians* g, const gsff_camera* cam,
+                               const gsff_settings* st, void* ws, size_t ws_bytes,
+                               int64_t max_pairs, void* stream);
 gsff_status gsff_composite_bwd(const gsff_gaussians* g, const gsff_camera* cam,
                                const gsff_settings* st, void* ws, size_t ws_bytes,
                                int64_t max_pairs, const float* g_rgb,

@@ -80,6 +80,7 @@ SIGNATURES = {
     "gsff_bin": (_i32, [_G, _C, _S, _vp, _sz, _i64, _vp]),
     "gsff_sort_tiles": (_i32, [_G, _C, _S, _vp, _sz, _i64, _vp]),
     "gsff_tile_ranges": (_i32, [_G, _C, _S, _vp, _sz, _i64, _vp]),
+    "gsff_adjoint_items": (_i32, [_G, _C, _S, _vp, _sz, _i64, _vp]),
     "gsff_composite_fwd": (_i32, [_G, _C, _S, _vp, _sz, _i64, _vp, _vp, _vp, _vp, _i32, _vp]),
     "gsff_composite_bwd": (_i32, [_G, _C, _S, _vp, _sz, _i64, _vp, _vp, _vp, _vp, _R, _i32,
                                   _vp]),

@@ -381,6 +381,13 @@ gsff_status gsff_forward(const gsff_gaussians* g, const gsff_camera* cam, const 
                    "composite_fwd");
 }
 
+gsff_status gsff_adjoint_items(const gsff_gaussians* g, const gsff_camera* cam,
+                               const gsff_settings* st, void* ws, size_t ws_bytes,
+                               int64_t max_pairs, void* stream) {
+  GSFF_PRELUDE
+  return hip_check(launch_adjoint_items(c.L, c.w, c.s), "adjoint_items");
+}
+
 gsff_status gsff_composite_bwd(const gsff_gaussians* g, const gsff_camera* cam,
                                const gsff_settings* st, void* ws, size_t ws_bytes,
                                int64_t max_pairs, const float* g_rgb, const float* g_depth,
@@ -419,9 +426,11 @@ gsff_status gsff_backward(const gsff_gaussians* g, const gsff_camera* cam,
   if (geo && (!g_rgb || !g_depth || !g_alpha))
     return fail(GSFF_ERR_INVALID_ARGUMENT, "NULL upstream gradient");
   if (out->feat && g->C == 0) return fail(GSFF_ERR_INVALID_ARGUMENT, "feat grad with C == 0");
-  gsff_status rc = hip_check(launch_composite_bwd(c.g, c.st, c.L, c.w, g_rgb, g_depth, g_alpha,
-                                                  g_feat, geo, out->feat, accumulate, c.s),
-                             "composite_bwd");
+  gsff_status rc = hip_check(launch_adjoint_items(c.L, c.w, c.s), "adjoint_items");
+  if (rc != GSFF_OK) return rc;
+  rc = hip_check(launch_composite_bwd(c.g, c.st, c.L, c.w, g_rgb, g_depth, g_alpha, g_feat, geo,
+                                      out->feat, accumulate, c.s),
+                 "composite_bwd");
   // the preprocess adjoint also turns the adjoint's rows into out->feat, so it
   // runs for a feature-only gradient too
   if (rc != GSFF_OK) return rc;
@@ -450,9 +459,13 @@ static gsff_status backward_l1_impl(const gsff_gaussians* g, const gsff_camera* 
   const bool geo = any_geometry(out);
   L1Args a{out_rgb, out_depth, out_alpha, out_feat, t_rgb, t_depth, t_alpha, t_feat,
            (double)weights[0], (double)weights[1], (double)weights[2], (double)weights[3], loss};
-  gsff_status rc = hip_check(launch_composite_bwd_l1(c.g, c.st, c.L, c.w, a, geo, out->feat,
-                                                     accumulate, c.s),
-                             "composite_bwd_l1");
+  gsff_status rc = GSFF_OK;
+  if (with_preprocess) {  // the whole adjoint: its work items first
+    rc = hip_check(launch_adjoint_items(c.L, c.w, c.s), "adjoint_items");
+    if (rc != GSFF_OK) return rc;
+  }
+  rc = hip_check(launch_composite_bwd_l1(c.g, c.st, c.L, c.w, a, geo, out->feat, accumulate, c.s),
+                 "composite_bwd_l1");
   if (rc != GSFF_OK || !with_preprocess) return rc;
   return hip_check(launch_preprocess_bwd(c.g, c.cam, c.st, c.L, c.w, *out, accumulate, c.s),
                    "preprocess_bwd");

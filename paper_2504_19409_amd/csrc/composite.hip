@@ -704,6 +704,11 @@ __global__ __launch_bounds__(1024) void k_walk_scan(WsView w, int ntiles, uint32
   if (threadIdx.x == 0) w.seg_n[0] = min(s_total, cap);
 }
 
+hipError_t launch_adjoint_items(const Layout& L, const WsView& w, hipStream_t s) {
+  hipLaunchKernelGGL(k_walk_scan, dim3(1), dim3(1024), 0, s, w, L.ntiles, (uint32_t)L.max_pairs);
+  return hipGetLastError();
+}
+
 template <int CP, typename FT, typename OT>
 static void launch_fwd_t(const DevSettings& st, const DevGaussians& g, const Layout& L,
                          const WsView& w, int c0, float* out_rgb, float* out_depth,
@@ -776,7 +781,6 @@ hipError_t launch_composite_fwd(const DevGaussians& g, const DevSettings& st, co
                                           out_feat, wg, s);
     }
   }
-  hipLaunchKernelGGL(k_walk_scan, dim3(1), dim3(1024), 0, s, w, L.ntiles, (uint32_t)L.max_pairs);
   return hipGetLastError();
 }
 

@@ -156,6 +156,9 @@ hipError_t launch_composite_fwd(const DevGaussians& g, const DevSettings& st,
                                 const Layout& L, const WsView& w, float* out_rgb,
                                 float* out_depth, float* out_alpha, void* out_feat,
                                 int32_t out_feat_dtype, hipStream_t s);
+// The adjoint's work items (tile list segments, longest first) and the first
+// adjoint row of every tile, from the walks the last forward recorded.
+hipError_t launch_adjoint_items(const Layout& L, const WsView& w, hipStream_t s);
 hipError_t launch_composite_bwd(const DevGaussians& g, const DevSettings& st,
                                 const Layout& L, const WsView& w, const float* g_rgb,
                                 const float* g_depth, const float* g_alpha,

@@ -179,9 +179,13 @@ class Frame:
                     "gsff_backward_l1")
         return grads
 
-    def composite_bwd_l1(self, outs, targets, weights, grads, loss=None, accumulate=False):
+    def composite_bwd_l1(self, outs, targets, weights, grads, loss=None, accumulate=False,
+                         items=True):
         """Only the compositing adjoint of backward_l1 (the preprocess adjoint
-        follows with preprocess_bwd); used to time the stages separately."""
+        follows with preprocess_bwd); used to time the stages separately.
+        items=False: the adjoint_items stage already ran for this forward."""
+        if items:
+            self.call_stage("gsff_adjoint_items")
         gs = self._grads_struct(grads)
         w = (ctypes.c_float * 4)(*[float(x) for x in weights])
         o = [(None if t is None else x) for x, t in zip(outs, targets)]
@@ -191,7 +195,10 @@ class Frame:
                                             ctypes.byref(gs), int(accumulate), _stream()),
                     "gsff_composite_bwd_l1")
 
-    def composite_bwd(self, g_rgb, g_depth, g_alpha, g_feat, grads, accumulate=False):
+    def composite_bwd(self, g_rgb, g_depth, g_alpha, g_feat, grads, accumulate=False,
+                      items=True):
+        if items:
+            self.call_stage("gsff_adjoint_items")
         gs = self._grads_struct(grads)
         L = _capi.load()
         _capi.check(L.gsff_composite_bwd(*self._head(), _ptr(g_rgb), _ptr(g_depth),
