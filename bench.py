@@ -273,14 +273,17 @@ def main():
 # Measured HBM traffic of the dominant kernel, from the rocprofv3 counter
 # summary committed beside the kernel profiles.  It is used only while the
 # kernel source still hashes to the value recorded with the counters.
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "composite_bwd_640x480_200k_traffic.md")
+TRAFFIC_PROFILE = {
+    "composite_fwd": os.path.join(ROOT, "profiles", "composite_fwd_640x480_200k_traffic.md"),
+    "composite_bwd_l1": os.path.join(ROOT, "profiles", "composite_bwd_640x480_200k_traffic.md"),
+}
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2504_19409_amd", "csrc", "composite.hip")
 
 
-def measured_traffic():
+def measured_traffic(stage):
     import hashlib
     try:
-        text = open(TRAFFIC_PROFILE).read()
+        text = open(TRAFFIC_PROFILE[stage]).read()
         src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
     except OSError:
         return None
@@ -320,7 +323,7 @@ def roofline_for(stage, ms, wc, sz):
         alu = slots / sec / 1e12
         lds = lds_bytes / sec / 1e12
         t_lds, t_alu = lds_bytes / (LDS_PEAK_TBS * 1e12), slots / (VALU_PEAK_TSLOTS * 1e12)
-        traffic = measured_traffic() if stage == "composite_bwd_l1" else None
+        traffic = measured_traffic(stage)
         other = {"bound": "alu", "achieved": round(alu, 3), "peak": round(VALU_PEAK_TSLOTS, 2),
                  "unit": "Tslot/s", "frac": round(alu / VALU_PEAK_TSLOTS, 4),
                  "work": int(slots)}

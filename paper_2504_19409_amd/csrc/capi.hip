@@ -105,6 +105,8 @@ bool compute_layout(int64_t P, int32_t C, int64_t max_pairs, int32_t W, int32_t 
   l.seg_n = take(4);
   l.seg_state = take(4ull * l.ntiles * (kMaxSeg - 1) * 5 * kBlock);
   l.seg_final = take(4ull * l.ntiles * 4 * kBlock);
+  l.l1_codes = take(4ull * (1 + (C + 15) / 16) * HW);
+  l.loss_part = take(4ull * ((HW + 255) / 256));
   l.slot_local = take(4ull * P);
   l.slot_blk = take(4ull * (uint64_t)(l.pose_blocks + 1));
   l.nslot = take(4ull * P);
@@ -165,6 +167,8 @@ WsView make_view(void* ws, const Layout& L) {
   w.seg_n = (uint32_t*)(b + L.seg_n);
   w.seg_state = (float*)(b + L.seg_state);
   w.seg_final = (float*)(b + L.seg_final);
+  w.l1_codes = (uint32_t*)(b + L.l1_codes);
+  w.loss_part = (float*)(b + L.loss_part);
   w.item_n = (uint32_t*)(b + L.item_n);
   w.items = (uint2*)(b + L.items);
   w.row_cap = (uint32_t)L.row_cap;

@@ -608,14 +608,12 @@ __global__ __launch_bounds__(1024) void k_walk_scan(WsView w, int ntiles, uint32
   }
   // The adjoint's work items: each tile's walked list in segments of
   // kSegLen entries (at most kMaxSeg, the last takes the rest; a tile with an
-  // empty walk keeps one item for its loss), ordered by decreasing length
+  // empty walk has none), ordered by decreasing length
   // (counting sort on buckets of 4 entries), so the items that start after
   // the first round of resident workgroups are the short ones.
   __shared__ uint32_t s_cnt[1024];
   __shared__ uint32_t s_total;
-  auto nseg_of = [](uint32_t v) {
-    return v == 0u ? 1u : min((uint32_t)kMaxSeg, (v + kSegLen - 1) / kSegLen);
-  };
+  auto nseg_of = [](uint32_t v) { return min((uint32_t)kMaxSeg, (v + kSegLen - 1) / kSegLen); };
   auto key_of = [](uint32_t v, uint32_t j, uint32_t ns) {
     const uint32_t len = j + 1 < ns ? (uint32_t)kSegLen : v - j * kSegLen;
     return 1023u - min(len >> 2, 1023u);
@@ -641,8 +639,10 @@ __global__ __launch_bounds__(1024) void k_walk_scan(WsView w, int ntiles, uint32
     uint32_t ninner = 0u;
     if (i < ntiles) {
       const uint32_t v = walk_of(i), ns = nseg_of(v);
-      atomicAdd(&s_cnt[key_of(v, ns - 1u, ns)], 1u);
-      ninner = ns - 1u;
+      if (ns > 0u) {
+        atomicAdd(&s_cnt[key_of(v, ns - 1u, ns)], 1u);
+        ninner = ns - 1u;
+      }
     }
     uint32_t wtot;
     wave_excl(ninner, wtot);
@@ -817,12 +817,95 @@ struct L1Upstream {
   float* loss;                            // += the loss (may be NULL)
 };
 
-// sign(o - t) in {-1, 0, 1}; l += |o - t| * scale
-__device__ __forceinline__ float l1_unit_sign(float o, float t, float scale, float& l) {
+// The L1 upstream of every pixel in 2-bit codes (0: zero, 1: +1, 2: -1),
+// formed once per adjoint call: plane 0 holds r, g, b, depth, alpha at bits
+// 0-9, plane 1 + k the feature channels 16 k .. 16 k + 15.  Groups without a
+// target are zero.  The pass also adds the loss.
+__device__ __forceinline__ uint32_t l1_code(float o, float t, float scale, float& l) {
   const float d = o - t;
   l += fabsf(d) * scale;
-  return d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
+  return d > 0.f ? 1u : (d < 0.f ? 2u : 0u);
 }
+__device__ __forceinline__ float l1_decode(uint32_t word, int slot) {
+  const uint32_t c = (word >> (2 * slot)) & 3u;
+  return c == 1u ? 1.f : (c == 2u ? -1.f : 0.f);
+}
+__global__ __launch_bounds__(256) void k_l1_codes(L1Upstream l1, int64_t HW, int C,
+                                                  uint32_t* __restrict__ codes,
+                                                  float* __restrict__ loss_part) {
+  __shared__ float s_l[4];
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  float loss = 0.f;
+  if (p < HW) {
+    // every load of the pixel is issued before any code is formed
+    float o[5] = {0.f, 0.f, 0.f, 0.f, 0.f}, t[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    if (l1.t_rgb) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        o[k] = l1.out_rgb[k * HW + p];
+        t[k] = l1.t_rgb[k * HW + p];
+      }
+    }
+    if (l1.t_depth) {
+      o[3] = l1.out_depth[p];
+      t[3] = l1.t_depth[p];
+    }
+    if (l1.t_alpha) {
+      o[4] = l1.out_alpha[p];
+      t[4] = l1.t_alpha[p];
+    }
+    const bool feat = l1.t_feat != nullptr && C > 0;
+    float fo[16], ft[16];
+    if (feat) {  // the first 16 channels with the rest (channels past C read channel C - 1)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int64_t q = (int64_t)min(j, C - 1) * HW + p;
+        fo[j] = l1.out_feat[q];
+        ft[j] = l1.t_feat[q];
+      }
+    }
+    uint32_t w0 = 0u;
+    if (l1.t_rgb) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) w0 |= l1_code(o[k], t[k], l1.s_rgb, loss) << (2 * k);
+    }
+    if (l1.t_depth) w0 |= l1_code(o[3], t[3], l1.s_depth, loss) << 6;
+    if (l1.t_alpha) w0 |= l1_code(o[4], t[4], l1.s_alpha, loss) << 8;
+    codes[p] = w0;
+    if (feat) {
+      for (int cb = 0; cb < C; cb += 16) {
+        if (cb > 0) {
+#pragma unroll
+          for (int j = 0; j < 16; ++j) {
+            const int64_t q = (int64_t)min(cb + j, C - 1) * HW + p;
+            fo[j] = l1.out_feat[q];
+            ft[j] = l1.t_feat[q];
+          }
+        }
+        uint32_t wf = 0u;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          float l = 0.f;
+          const uint32_t c = l1_code(fo[j], ft[j], l1.s_feat, l);
+          if (cb + j < C) {
+            wf |= c << (2 * j);
+            loss += l;
+          }
+        }
+        codes[(int64_t)(1 + cb / 16) * HW + p] = wf;
+      }
+    }
+  }
+  // the workgroup's share of the loss; the adjoint's first workgroup adds
+  // the shares up (one atomic instead of one per workgroup on one address)
+  if (l1.loss) {
+    const float v = wave_sum(loss);
+    if ((threadIdx.x & 63) == 0) s_l[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) loss_part[blockIdx.x] = (s_l[0] + s_l[1]) + (s_l[2] + s_l[3]);
+  }
+}
+
 
 // The per-pixel adjoint of a tile, with the per-Gaussian sums as matrix
 // products on the matrix cores.
@@ -875,7 +958,20 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
   __shared__ float4 s_r0[2][kBwdNB], s_r1[2][kBwdNB], s_r2[2][kBwdNB];
   __shared__ uint32_t s_gid[2][kBwdNB];
   __shared__ float s_mom[kBwdNB][8];
-  __shared__ float s_loss[kBlock / 64];
+  if (L1 && first_pass && l1.loss && blockIdx.x == 0) {
+    // the L1 loss: the shares the code pass left, one per 256 pixels
+    __shared__ float s_part[kBlock / 64];
+    const int nparts = (W * H + 255) / 256;
+    float v = 0.f;
+    for (int i = threadIdx.x; i < nparts; i += kBlock) v += w.loss_part[i];
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const float t = (s_part[0] + s_part[1]) + (s_part[2] + s_part[3]);
+      if (t != 0.f) unsafeAtomicAdd(l1.loss, t);
+    }
+  }
   // work item: a segment [q1, q2) of a tile's walked list (longest first)
   if (blockIdx.x >= min(w.seg_n[0], (uint32_t)ntiles * (uint32_t)kMaxSeg)) return;
   const uint4 item = w.seg_order[blockIdx.x];
@@ -924,7 +1020,6 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
   uint32_t pend = q1;
   float gr = 0.f, gg = 0.f, gb = 0.f, gd = 0.f, ga = 0.f;  // geometry upstream (scaled)
   float ur = 0.f, ug = 0.f, ub = 0.f, ud = 0.f;           // same, as contraction operands
-  float loss = 0.f;
   // Every per-pixel load is issued up front, unconditionally (a pixel
   // outside the image reads pixel 0 and masks the value), so the loads are
   // in flight together instead of one round trip each.
@@ -939,16 +1034,33 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
   // issued with the per-pixel loads: channels past cn and pixels outside the
   // image read channel c0 / pixel 0, masked where the values are formed
   constexpr int RS = GEO ? 2 : 1;
-  float fo[RS][16], ft[RS][16];
+  float fo[RS][16];
   auto load_round = [&](int r) {
 #pragma unroll
     for (int u = 0; u < RS; ++u)
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
         fo[u][j] = 0.f;
-        ft[u][j] = 0.f;
       }
-    if constexpr (CP > 0) {  // (launched with CP > 0 only when cn >= 1)
+    if constexpr (CP > 0 && L1) {
+      // the block's channels lie in two code planes at most: both loaded
+#pragma unroll
+      for (int u = 0; u < RS; ++u) {
+        const int first = c0 + 16 * (r * RS + u) - (GEO ? 4 : 0);  // channel of column 0
+        const int plane = (first > 0 ? first : 0) >> 4;
+        const uint32_t wa = w.l1_codes[(int64_t)(1 + plane) * HW + pq];
+        const uint32_t wb = (plane + 1) * 16 < C ? w.l1_codes[(int64_t)(2 + plane) * HW + pq] : 0u;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const int k = 16 * (r * RS + u) + j;
+          const int c = k - (GEO ? 4 : 0);
+          if (k < NL && c >= 0) {
+            const int gch = c0 + c;
+            fo[u][j] = l1_decode((gch >> 4) == plane ? wa : wb, gch & 15);
+          }
+        }
+      }
+    } else if constexpr (CP > 0) {  // (launched with CP > 0 only when cn >= 1)
 #pragma unroll
       for (int u = 0; u < RS; ++u)
 #pragma unroll
@@ -957,12 +1069,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
           const int c = k - (GEO ? 4 : 0);
           if (k < NL && c >= 0) {
             const int64_t q = (int64_t)(c0 + (c < cn ? c : 0)) * HW + pq;
-            if constexpr (L1) {
-              fo[u][j] = l1.out_feat[q];
-              ft[u][j] = l1.t_feat[q];
-            } else {
-              fo[u][j] = g_feat[q];
-            }
+            fo[u][j] = g_feat[q];
           }
         }
     }
@@ -987,30 +1094,13 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
   }
   if constexpr (GEO) {
     if constexpr (L1) {
-      float o[5] = {0.f, 0.f, 0.f, 0.f, 0.f}, t[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-      if (l1.t_rgb) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          o[k] = l1.out_rgb[k * HW + pq];
-          t[k] = l1.t_rgb[k * HW + pq];
-        }
-      }
-      if (l1.t_depth) {
-        o[3] = l1.out_depth[pq];
-        t[3] = l1.t_depth[pq];
-      }
-      if (l1.t_alpha) {
-        o[4] = l1.out_alpha[pq];
-        t[4] = l1.t_alpha[pq];
-      }
+      const uint32_t w0 = w.l1_codes[pq];
       const float m = inside ? 1.f : 0.f;
-      if (l1.t_rgb) {
-        ur = m * l1_unit_sign(o[0], t[0], m * l1.s_rgb, loss);
-        ug = m * l1_unit_sign(o[1], t[1], m * l1.s_rgb, loss);
-        ub = m * l1_unit_sign(o[2], t[2], m * l1.s_rgb, loss);
-      }
-      if (l1.t_depth) ud = m * l1_unit_sign(o[3], t[3], m * l1.s_depth, loss);
-      if (l1.t_alpha) ga = m * l1_unit_sign(o[4], t[4], m * l1.s_alpha, loss) * l1.s_alpha;
+      ur = m * l1_decode(w0, 0);
+      ug = m * l1_decode(w0, 1);
+      ub = m * l1_decode(w0, 2);
+      ud = m * l1_decode(w0, 3);
+      ga = m * l1_decode(w0, 4) * l1.s_alpha;
       gr = ur * l1.s_rgb;
       gg = ug * l1.s_rgb;
       gb = ub * l1.s_rgb;
@@ -1061,9 +1151,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
           } else {
             const int c = k - (GEO ? 4 : 0);
             const bool on = inside && c < cn;
-            const float m = on ? 1.f : 0.f;
-            v = L1 ? m * l1_unit_sign(fo[u][j], ft[u][j], m * l1.s_feat, loss)
-                   : (on ? fo[u][j] : 0.f);
+            v = on ? fo[u][j] : 0.f;
           }
         }
         if (r * RS + u < NCB) rows_u[j * kBwdStride + tid] = v;
@@ -1115,16 +1203,8 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
       }
     }
   }
-  if (L1 && l1.loss) {
-    const float v = wave_sum(loss);
-    if (lane == 0) s_loss[wave] = v;
-  }
   lds_barrier();
-  if (L1 && l1.loss && tid == 0 && seg == 0) {  // once per tile
-    const float v = (s_loss[0] + s_loss[1]) + (s_loss[2] + s_loss[3]);
-    if (v != 0.f) unsafeAtomicAdd(l1.loss, v);
-  }
-  if (q1 >= q2) return;  // uniform: an empty walk (the item only carried the loss)
+  if (q1 >= q2) return;  // uniform: an empty segment
   // The tile's results go to one row per walked list position (the rows of
   // the tiles follow each other in tile order) when they fit; otherwise they
   // are added to the per-Gaussian gradients with atomics.
@@ -1446,6 +1526,11 @@ hipError_t launch_composite_bwd_l1(const DevGaussians& g, const DevSettings& st,
   u.s_alpha = (float)(a.w_alpha / HW);
   u.s_feat = (float)(g.C > 0 ? a.w_feat / ((double)g.C * HW) : 0.0);
   u.loss = a.loss;
+  // the upstream codes and the loss, once for every channel pass
+  const int64_t npx = (int64_t)L.W * L.H;
+  if (npx > 0)
+    hipLaunchKernelGGL(k_l1_codes, dim3((unsigned)((npx + 255) / 256)), dim3(256), 0, s, u, npx,
+                       g.C, w.l1_codes, w.loss_part);
   return launch_composite_bwd_impl(g, st, L, w, nullptr, nullptr, nullptr, nullptr, geometry,
                                    d_feat, accumulate, &u, s);
 }
