@@ -546,6 +546,48 @@ def test_backward_l1_fused_upstream(orc, kind, C, weights):
         assert H.rel_l2(grads[k].cpu().numpy(), ob[k]) <= H.TOL_GRAD, k
 
 
+@pytest.mark.parametrize("kind,C", [("ragged", 5), ("dense", 16)])
+def test_stage_split_matches_whole_pass(kind, C):
+    """The stages one at a time (forward compositing, adjoint work items,
+    compositing adjoint, preprocess adjoint) give what gsff_forward +
+    gsff_backward_l1 give in one call: outputs bit for bit; gradients and loss
+    up to the summation order of atomics."""
+    sc = _scene(kind, C=C)
+    rng = np.random.default_rng(23)
+    W, Hh = sc.camera.width, sc.camera.height
+    t_rgb, t_depth, t_feat = sg.make_targets(rng, W, Hh, C)
+    t_alpha = rng.random((Hh, W)).astype(np.float32)
+    targets = [torch.from_numpy(t).cuda() for t in (t_rgb, t_depth, t_alpha, t_feat)]
+    weights = (1.0, 0.5, 0.25, 1.0)
+    fa, _ = H.make_frame(sc, torch)
+    outs_a = fa.forward()
+    assert fa.read_status()[0] == 0
+    loss_a = torch.zeros(1, device="cuda")
+    grads_a = fa.make_grads()
+    fa.backward_l1(outs_a, targets, weights, grads_a, loss_a)
+    fb, _ = H.make_frame(sc, torch)
+    outs_b = fb.alloc_outputs()
+    for st in ["gsff_preprocess", "gsff_sort_depth", "gsff_bin", "gsff_sort_tiles",
+               "gsff_tile_ranges"]:
+        fb.call_stage(st)
+    fb.composite_fwd(outs_b)
+    fb.call_stage("gsff_adjoint_items")
+    loss_b = torch.zeros(1, device="cuda")
+    grads_b = fb.make_grads()
+    fb.composite_bwd_l1(outs_b, targets, weights, grads_b, loss_b, items=False)
+    fb.preprocess_bwd(grads_b)
+    torch.cuda.synchronize()
+    for a, b in zip(outs_a, outs_b):
+        assert torch.equal(a, b)
+    assert loss_b.item() == pytest.approx(loss_a.item(), rel=1e-6)
+    for k in grads_a:
+        a, b = grads_a[k].cpu().numpy(), grads_b[k].cpu().numpy()
+        if not np.any(a):
+            assert not np.any(b), k
+            continue
+        assert H.rel_l2(b, a) <= 1e-5, (k, H.rel_l2(b, a))
+
+
 def test_backward_l1_feature_only(orc):
     sc = _scene("tiny", C=16)
     fr, _ = H.make_frame(sc, torch)
