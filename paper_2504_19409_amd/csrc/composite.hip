@@ -139,6 +139,15 @@ __device__ __forceinline__ bf16x8 to_bf16x8(const float4 a, const float4 b) {
   return h;
 }
 
+// Sixteen 4x4x4 BF16 products at once (FP32 accumulate): block b = lanes
+// 4b .. 4b+3; lane 4b + i holds row i of A (k = 0..3 in element order), lane
+// 4b + j column j of B, and D[i][j] for i = 0..3 lands in lane 4b + j.
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ f32x4 mfma4(const bf16x4 a, const bf16x4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(__builtin_bit_cast(s16x4, a),
+                                                 __builtin_bit_cast(s16x4, b), c, 0, 0, 0);
+}
+
 // D += A B for one 16x16x32 BF16 tile (FP32 accumulate).  Lane l holds
 // A[l % 16][8 (l / 16) .. +7], B[8 (l / 16) .. +7][l % 16] and
 // D[4 (l / 16) + r][l % 16] in acc[r].
@@ -227,7 +236,10 @@ void k_composite_fwd(
   __shared__ __attribute__((aligned(16))) __bf16 s_w[kBlock][kFwdWStride];
   __shared__ __attribute__((aligned(16))) __bf16 s_fh[2][CPs][kFwdFStride];
   __shared__ __attribute__((aligned(16))) __bf16 s_fl[EXACT ? 1 : 2][EXACT ? 1 : CPs][kFwdFStride];
-  __shared__ float4 s_r0[2][NB], s_r1[2][NB], s_r2[2][NB];
+  __shared__ float4 s_r0[2][NB], s_r1[2][NB];
+  // colour and depth of the batch as the B operand of the 4x4x4 products:
+  // [buffer][hi, lo][group of 4 Gaussians][channel r, g, b, depth][Gaussian]
+  __shared__ __attribute__((aligned(8))) __bf16 s_cc[2][2][NB / 4][4][4];
   __shared__ uint32_t s_ids[2][NB];
   __shared__ uint32_t s_nb[4], s_pos[4];  // size and list position of batch k, slot k % 4
   __shared__ uint32_t s_q[kFwdQueue];     // ids accepted for this tile, not yet batched
@@ -294,7 +306,20 @@ void k_composite_fwd(
     return n;
   };
 
-  float T = 1.f, cr = 0.f, cg = 0.f, cb = 0.f, dep = 0.f;
+  float T = 1.f;
+  // colour and depth sums of pixels 4 (lane / 4) + r of the wave, channel
+  // lane % 4 (r, g, b, depth): the 4x4x4 products' accumulator
+  f32x4 acc_c = {0.f, 0.f, 0.f, 0.f};
+  // a prefetch lane writes its Gaussian's colour and depth, split hi + lo
+  auto stage_colour = [&](int sb, float4 rec1, float4 rec2) {
+    const float v[4] = {rec2.x, rec2.y, rec2.z, rec1.z};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const __bf16 h = (__bf16)v[c];
+      s_cc[sb][0][pf >> 2][c][pf & 3] = h;
+      s_cc[sb][1][pf >> 2][c][pf & 3] = (__bf16)(v[c] - (float)h);
+    }
+  };
   bool done = !inside;
   uint32_t end = cbase;
   f32x4 acc[4][NCB > 0 ? NCB : 1];
@@ -322,10 +347,11 @@ void k_composite_fwd(
   lds_barrier();
   if (s_nb[0] > 0u) {
     if (pf_lane) {
-      float4 q0, q1;
-      load_record(w, s_ids[0][pf], P, q0, q1, s_r2[0][pf]);
+      float4 q0, q1, q2;
+      load_record(w, s_ids[0][pf], P, q0, q1, q2);
       s_r0[0][pf] = scaled_r0(q0);
       s_r1[0][pf] = scaled_r1(q1);
+      stage_colour(0, q1, q2);
     }
     if constexpr (CP > 0) {
 #pragma unroll
@@ -376,7 +402,12 @@ void k_composite_fwd(
         const int g = e / CP, c = e % CP;
         if (more && g < NB) {
           const uint32_t gid = s_ids[buf ^ 1][g];
-          if (c < cn && gid < (uint32_t)P) fraw[kk] = feat[(int64_t)gid * C + c0 + c];
+          // the channel offset is re-formed every batch (an empty asm keeps the
+          // compiler from holding a 64-bit base across the loop in a register
+          // it does not have)
+          int coff = c0 + c;
+          asm volatile("" : "+v"(coff));
+          if (c < cn && gid < (uint32_t)P) fraw[kk] = feat[(int64_t)gid * C + coff];
         }
       }
     }
@@ -386,12 +417,11 @@ void k_composite_fwd(
     // that end here start from them.  Stored after this batch's loads are
     // issued: waits for those loads do not include the stores.
     if (write_geo && k > 0 && k % kSegBatches == 0 && nseg_end < kMaxSeg - 1) {
-      float* q = w.seg_state + ((int64_t)tile * (kMaxSeg - 1) + nseg_end) * 5 * kBlock + tid;
-      q[0] = T;
-      q[kBlock] = cr;
-      q[2 * kBlock] = cg;
-      q[3 * kBlock] = cb;
-      q[4 * kBlock] = dep;
+      float* q = w.seg_state + ((int64_t)tile * (kMaxSeg - 1) + nseg_end) * 5 * kBlock;
+      q[tid] = T;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        q[(1 + (lane & 3)) * kBlock + 64 * wave + 4 * (lane >> 2) + r] = acc_c[r];
       ++nseg_end;
     }
     const bool wave_active = __ballot(!done) != 0ull;
@@ -400,7 +430,7 @@ void k_composite_fwd(
       float wv[4];
 #pragma unroll
       for (int jj = 0; jj < NB; ++jj) {
-        const float4 r0 = s_r0[buf][jj], r1 = s_r1[buf][jj], r2 = s_r2[buf][jj];
+        const float4 r0 = s_r0[buf][jj], r1 = s_r1[buf][jj];
         const AlphaEval e = eval_alpha(r0, r1, pxc, pyc, st.alpha_max);
         const bool valid = !done && e.alpha >= st.alpha_min;
         const float Tn = T * (1.f - e.alpha);
@@ -408,14 +438,10 @@ void k_composite_fwd(
         const bool use = valid && !stop;
         done = done || stop;
         const float wgt = use ? e.alpha * T : 0.f;
-        cr += wgt * r2.x;
-        cg += wgt * r2.y;
-        cb += wgt * r2.z;
-        dep += wgt * r1.z;
         T = use ? Tn : T;
         end = use ? b0 + (uint32_t)jj + 1u : end;
         wv[jj & 3] = wgt;
-        if (CP > 0 && (jj & 3) == 3) {  // weight = hi + lo, both BF16, as the feature product's A
+        if ((jj & 3) == 3) {  // weight = hi + lo, both BF16: the products' A operands
           const f32x4 q = {wv[0], wv[1], wv[2], wv[3]};
           const bf16x4 h = __builtin_convertvector(q, bf16x4);
           const bf16x4 l = __builtin_convertvector(q - __builtin_convertvector(h, f32x4), bf16x4);
@@ -423,12 +449,23 @@ void k_composite_fwd(
           *reinterpret_cast<bf16x4*>(&s_w[tid][16 + jj - 3]) = l;
         }
       }
+      // ---- phase B: colour and depth, and the feature sums, on the matrix cores
+      // (the wave reads back only its own rows)
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+#pragma unroll
+      for (int g4 = 0; g4 < NB / 4; ++g4) {
+        // A: this lane's pixel, Gaussians 4 g4 .. +3; B: channel lane % 4
+        const bf16x4 h = *reinterpret_cast<const bf16x4*>(&s_w[tid][4 * g4]);
+        const bf16x4 l = *reinterpret_cast<const bf16x4*>(&s_w[tid][16 + 4 * g4]);
+        const bf16x4 ch = *reinterpret_cast<const bf16x4*>(&s_cc[buf][0][g4][lane & 3][0]);
+        const bf16x4 cl = *reinterpret_cast<const bf16x4*>(&s_cc[buf][1][g4][lane & 3][0]);
+        acc_c = mfma4(h, ch, acc_c);
+        acc_c = mfma4(l, ch, acc_c);
+        acc_c = mfma4(h, cl, acc_c);
+      }
       if constexpr (CP > 0) {
-        // the wave reads back only its own rows
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
-        // ---- phase B: feature sums on the matrix cores
         const int gk = 8 * (lq & 1);  // Gaussians gk .. gk+7 of the batch
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb) {
@@ -453,7 +490,7 @@ void k_composite_fwd(
       if (pf_lane) {
         s_r0[buf ^ 1][pf] = scaled_r0(p0);
         s_r1[buf ^ 1][pf] = scaled_r1(p1);
-        s_r2[buf ^ 1][pf] = p2;
+        stage_colour(buf ^ 1, p1, p2);
       }
       if constexpr (CP > 0) {
 #pragma unroll
@@ -499,19 +536,26 @@ void k_composite_fwd(
   // a split tile also keeps its final colour and depth: the adjoint takes
   // what is blended behind a segment's end as final minus recorded
   if (nseg_end > 0) {
-    float* q = w.seg_final + (int64_t)tile * 4 * kBlock + tid;
-    q[0] = cr;
-    q[kBlock] = cg;
-    q[2 * kBlock] = cb;
-    q[3 * kBlock] = dep;
+    float* q = w.seg_final + (int64_t)tile * 4 * kBlock;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      q[(lane & 3) * kBlock + 64 * wave + 4 * (lane >> 2) + r] = acc_c[r];
   }
   const int64_t HW = (int64_t)W * H;
+  if (write_geo) {
+    // colour and depth from the accumulator lanes: channel lane % 4 of pixels
+    // 64 wave + 4 (lane / 4) + r of the tile
+    const int ch = lane & 3;
+    float* dst = ch < 3 ? out_rgb + (int64_t)ch * HW : out_depth;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int tp = 64 * wave + 4 * (lane >> 2) + r;
+      const int qx = tx * kTile + (tp & (kTile - 1)), qy = ty * kTile + tp / kTile;
+      if (qx < W && qy < H) dst[(int64_t)qy * W + qx] = acc_c[r];
+    }
+  }
   if (inside && write_geo) {
     const int64_t p = (int64_t)py * W + px;
-    out_rgb[p] = cr;
-    out_rgb[HW + p] = cg;
-    out_rgb[2 * HW + p] = cb;
-    out_depth[p] = dep;
     out_alpha[p] = 1.f - T;
     w.pix_T[p] = T;
     w.pix_end[p] = end;
