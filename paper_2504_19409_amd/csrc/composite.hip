@@ -378,7 +378,8 @@ void k_composite_fwd(
   bool ahead = false;
   for (uint32_t k = 0; s_nb[k & 3] > 0u; ++k) {
     const bool more = s_nb[(k + 1) & 3] > 0u;  // batch k + 1 has ids
-    const uint32_t b0 = cbase + s_pos[k & 3];  // walked-list position of this batch
+    // walked-list position of this batch (uniform: a scalar register)
+    const uint32_t b0 = __builtin_amdgcn_readfirstlane(cbase + s_pos[k & 3]);
     // ---- the scan wave: ids of batch k + 2 from the queue (a scan first if the
     // queue runs short), then the next scan ahead
     uint32_t g_after = (uint32_t)P, n_after = 0u, pos_after = 0u;
@@ -433,11 +434,12 @@ void k_composite_fwd(
         const float4 r0 = s_r0[buf][jj], r1 = s_r1[buf][jj];
         const AlphaEval e = eval_alpha(r0, r1, pxc, pyc, st.alpha_max);
         const bool valid = !done && e.alpha >= st.alpha_min;
-        const float Tn = T * (1.f - e.alpha);
+        const float aT = e.alpha * T;
+        const float Tn = __builtin_fmaf(-e.alpha, T, T);  // T (1 - alpha), one rounding
         const bool stop = valid && Tn < st.t_min;
         const bool use = valid && !stop;
         done = done || stop;
-        const float wgt = use ? e.alpha * T : 0.f;
+        const float wgt = use ? aT : 0.f;
         T = use ? Tn : T;
         end = use ? b0 + (uint32_t)jj + 1u : end;
         wv[jj & 3] = wgt;
