@@ -38,8 +38,14 @@ VALU_PEAK_TSLOTS = 256 * 4 * 16 * 2.4e9 / 1e12
 LDS_PEAK_TBS = 128 * 256 * 2.4e9 / 1e12
 
 STAGES = ["preprocess", "sort_depth", "bin", "sort_tiles", "tile_ranges", "composite_fwd",
-          "adjoint_items", "composite_bwd_l1", "preprocess_bwd"]
+          "composite_bwd_l1", "preprocess_bwd"]
 L1_WEIGHTS = (1.0, 1.0, 0.0, 1.0)  # rgb, depth, alpha, feature
+# Stages that are a single kernel launch at this workload, whose event time is
+# that kernel's launch duration; the roofline entry is for the longest of
+# them.  The forward compositing kernel is the longest kernel of the step;
+# the adjoint stage holds two launches (the L1 code pass, then the adjoint
+# kernel), so its time is not one kernel's.
+ONE_KERNEL_STAGES = ["composite_fwd"]
 
 
 def log(*a):
@@ -114,18 +120,12 @@ class Step:
         rec(5)
         fr.composite_fwd(self.outs)
         rec(6)
-        # the adjoint's work items; the adjoint accumulates the loss and the
-        # feature gradient, cleared here so the next stage is the compositing
-        # adjoint kernel alone
-        fr.call_stage("gsff_adjoint_items")
-        self.loss.zero_()
-        self.grads["feat"].zero_()
+        # the L1 code pass also builds the work items and clears the loss and
+        # the feature gradient (accumulate = 0)
+        fr.composite_bwd_l1(self.outs, self.targets, L1_WEIGHTS, self.grads, self.loss)
         rec(7)
-        fr.composite_bwd_l1(self.outs, self.targets, L1_WEIGHTS, self.grads, self.loss,
-                            accumulate=True, items=False)
-        rec(8)
         fr.preprocess_bwd(self.grads)
-        rec(9)
+        rec(8)
 
 
 def algorithmic_work(scene, n_pairs, torch):
@@ -248,7 +248,7 @@ def main():
     value = 1e3 / ms
 
     wc, sizes = algorithmic_work(scene, n_pairs, torch)
-    dom = max(STAGES, key=lambda s: stage_ms[s])
+    dom = max(ONE_KERNEL_STAGES, key=lambda s: stage_ms[s])
     roof = roofline_for(dom, stage_ms[dom], wc, sizes)
     out = {
         "metric": "fwd+bwd render iterations/sec at 640x480, 200k Gaussians, 16-ch features",
@@ -340,7 +340,6 @@ def roofline_for(stage, ms, wc, sz):
         "bin": P * 8 * 2 + M * 4,
         "sort_tiles": 2 * M * 4 * 3,
         "tile_ranges": 8 * 1200,
-        "adjoint_items": 16 * 1200,
         "preprocess_bwd": P * (44 + 40) + P * 56,
     }[stage]
     achieved = bytes_ / sec / 1e9

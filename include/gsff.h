@@ -216,9 +216,10 @@ gsff_status gsff_backward(const gsff_gaussians* g, const gsff_camera* cam,
  * itself, so no upstream images are materialised.  out_* are the outputs of
  * the forward that last used `ws` (f32, same layouts); t_* the targets, where
  * a NULL target leaves that group out of the loss.  weights: HOST pointer to
- * 4 floats.  loss (device, may be NULL) receives += the loss terms whose
+ * 4 floats.  loss (device, may be NULL) receives the loss terms whose
  * gradients are computed (rgb / depth / alpha only when a geometry gradient is
- * requested, feature only when out->feat is set and features are on).
+ * requested, feature only when out->feat is set and features are on):
+ * accumulate = 0 overwrites it, 1 adds to it, as for the gradients.
  * Otherwise as gsff_backward. */
 gsff_status gsff_backward_l1(const gsff_gaussians* g, const gsff_camera* cam,
                              const gsff_settings* st, void* ws, size_t ws_bytes,
@@ -250,8 +251,9 @@ gsff_status gsff_backward_l1(const gsff_gaussians* g, const gsff_camera* cam,
  * list in segments of 64 entries, at most 8 per tile, longest first; the
  * forward recorded each pixel's state at every segment end) and the first
  * adjoint row of every tile: it runs after composite_fwd and before the
- * first composite_bwd / composite_bwd_l1 that follows it (gsff_backward and
- * gsff_backward_l1 run it themselves). */
+ * first composite_bwd that follows it (gsff_backward runs it itself;
+ * composite_bwd_l1 and gsff_backward_l1 build the same items inside their
+ * L1 upstream pass and need no adjoint_items call). */
 gsff_status gsff_preprocess(const gsff_gaussians* g, const gsff_camera* cam,
                             const gsff_settings* st, void* ws, size_t ws_bytes,
                             int64_t max_pairs, void* stream);

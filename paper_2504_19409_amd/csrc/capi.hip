@@ -463,13 +463,10 @@ static gsff_status backward_l1_impl(const gsff_gaussians* g, const gsff_camera* 
   const bool geo = any_geometry(out);
   L1Args a{out_rgb, out_depth, out_alpha, out_feat, t_rgb, t_depth, t_alpha, t_feat,
            (double)weights[0], (double)weights[1], (double)weights[2], (double)weights[3], loss};
-  gsff_status rc = GSFF_OK;
-  if (with_preprocess) {  // the whole adjoint: its work items first
-    rc = hip_check(launch_adjoint_items(c.L, c.w, c.s), "adjoint_items");
-    if (rc != GSFF_OK) return rc;
-  }
-  rc = hip_check(launch_composite_bwd_l1(c.g, c.st, c.L, c.w, a, geo, out->feat, accumulate, c.s),
-                 "composite_bwd_l1");
+  // the L1 code pass builds the adjoint's work items itself
+  gsff_status rc = hip_check(
+      launch_composite_bwd_l1(c.g, c.st, c.L, c.w, a, geo, out->feat, accumulate, c.s),
+      "composite_bwd_l1");
   if (rc != GSFF_OK || !with_preprocess) return rc;
   return hip_check(launch_preprocess_bwd(c.g, c.cam, c.st, c.L, c.w, *out, accumulate, c.s),
                    "preprocess_bwd");

@@ -589,165 +589,188 @@ __global__ void k_fill_zero(OT* p, int64_t n) {
   if (i < n) p[i] = OT(0);
 }
 
-// One block: the adjoint's first row of every tile, an exclusive scan of the
-// walk lengths (the list prefix the forward visited) over the tiles, and the
-// adjoint's work items.  The tiles' walk ranges are read once, into LDS (the
-// first kWalkCache tiles; any further ones are read where needed).
-constexpr int kWalkCache = 8192;
-__global__ __launch_bounds__(1024) void k_walk_scan(WsView w, int ntiles, uint32_t max_pairs) {
-  __shared__ uint32_t s_w[16];
-  __shared__ uint2 s_rng[kWalkCache];     // [start, walk end) of each tile's walked list
-  __shared__ uint32_t s_off[kWalkCache];  // first row of each tile
-  __shared__ uint32_t s_ok[kWalkCache];   // the forward's walk end matches (rows usable)
+// The adjoint's work items and the first adjoint row of every tile, built by
+// one workgroup of NT threads (the standalone kernel below, or the first
+// workgroup of the L1 upstream pass).
+//
+// walk_off: an exclusive scan of the walk lengths (the list prefix the
+// forward visited) over the tiles.  Items: each tile's walked list in
+// segments of kSegLen entries (at most kMaxSeg, the last takes the rest; a
+// tile with an empty walk has none), ordered by decreasing length (counting
+// sort on buckets of 4 entries), so the items that start after the first
+// round of resident workgroups are the short ones.  An item is
+// tile | segment << 24 | (a later segment follows) << 30 | (the tile's rows
+// fit) << 31, its list range [q1, q2) and the row of list position 0 (rows
+// are indexed by list position).
+//
+// Thread t holds tiles kItemRegs t .. kItemRegs t + kItemRegs - 1 of each
+// chunk of NT kItemRegs tiles in registers; with one chunk (up to 2048 tiles
+// at 256 threads, 8192 at 1024) the ranges are read once.
+constexpr int kItemBuckets = 1024;
+constexpr int kItemRegs = 8;
+struct ItemScratch {
+  uint32_t cnt[kItemBuckets];
+  uint32_t part[16];
+  uint32_t total;
+};
+
+__device__ __forceinline__ uint32_t wave_excl_u32(uint32_t v, uint32_t& total) {
+  const int lane = threadIdx.x & 63;
+  uint32_t inc = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t t = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += t;
+  }
+  total = __shfl(inc, 63, 64);
+  return inc - v;
+}
+
+// exclusive scan over the NT threads of the workgroup (all of them call it)
+template <int NT>
+__device__ __forceinline__ uint32_t block_excl_u32(uint32_t v, uint32_t& total, uint32_t* part) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int ncache = min(ntiles, kWalkCache);
-  {
-    uint2 r[kWalkCache / 1024];
-    uint32_t t[kWalkCache / 1024];
+  uint32_t wt;
+  const uint32_t ex = wave_excl_u32(v, wt);
+  if (lane == 0) part[wv] = wt;
+  __syncthreads();
+  uint32_t pre = 0, tot = 0;
 #pragma unroll
-    for (int m = 0; m < kWalkCache / 1024; ++m) {
-      const int i = threadIdx.x + 1024 * m;
-      if (i < ncache) {
-        r[m] = w.crange[i];
-        t[m] = w.tile_walk[i];
-      }
-    }
-#pragma unroll
-    for (int m = 0; m < kWalkCache / 1024; ++m) {
-      const int i = threadIdx.x + 1024 * m;
-      if (i < ncache) {
-        s_rng[i] = r[m];
-        s_ok[i] = t[m] == r[m].y ? 1u : 0u;
-      }
-    }
+  for (int k = 0; k < NT / 64; ++k) {
+    const uint32_t p = part[k];
+    if (k < wv) pre += p;
+    tot += p;
   }
   __syncthreads();
-  auto rng_of = [&](int i) { return i < kWalkCache ? s_rng[i] : w.crange[i]; };
-  auto walk_of = [&](int i) {
-    const uint2 r = rng_of(i);
-    return r.y > r.x ? r.y - r.x : 0u;
-  };
-  uint32_t carry = 0;
-  for (int b = 0; b < ntiles; b += 1024) {
-    const int i = b + threadIdx.x;
-    const uint32_t v = i < ntiles ? walk_of(i) : 0u;
-    uint32_t inc = v;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const uint32_t t = __shfl_up(inc, off, 64);
-      if (lane >= off) inc += t;
-    }
-    if (lane == 63) s_w[wv] = inc;
-    __syncthreads();
-    uint32_t pre = 0, tot = 0;
-    for (int k = 0; k < 16; ++k) {
-      if (k < wv) pre += s_w[k];
-      tot += s_w[k];
-    }
-    __syncthreads();
-    if (i < ntiles) {
-      const uint32_t off = carry + pre + inc - v;
-      w.walk_off[i] = off;
-      if (i < kWalkCache) s_off[i] = off;
-    }
-    carry += tot;
-  }
-  // The adjoint's work items: each tile's walked list in segments of
-  // kSegLen entries (at most kMaxSeg, the last takes the rest; a tile with an
-  // empty walk has none), ordered by decreasing length
-  // (counting sort on buckets of 4 entries), so the items that start after
-  // the first round of resident workgroups are the short ones.
-  __shared__ uint32_t s_cnt[1024];
-  __shared__ uint32_t s_total;
+  total = tot;
+  return pre + ex;
+}
+
+template <int NT>
+__device__ void build_adjoint_items(const WsView& w, int ntiles, uint32_t max_pairs,
+                                    ItemScratch& sm) {
+  constexpr int R = kItemRegs, CH = NT * R;
+  const int tid = threadIdx.x, lane = tid & 63;
   auto nseg_of = [](uint32_t v) { return min((uint32_t)kMaxSeg, (v + kSegLen - 1) / kSegLen); };
   auto key_of = [](uint32_t v, uint32_t j, uint32_t ns) {
     const uint32_t len = j + 1 < ns ? (uint32_t)kSegLen : v - j * kSegLen;
-    return 1023u - min(len >> 2, 1023u);
+    return (uint32_t)(kItemBuckets - 1) - min(len >> 2, (uint32_t)(kItemBuckets - 1));
   };
+  auto walk_of = [](uint2 r) { return r.y > r.x ? r.y - r.x : 0u; };
   // every segment but a tile's last has kSegLen entries, so one key: those
-  // are counted and placed one wave at a time (a wave scan of the tiles'
-  // counts and one atomic), the last segments one at a time
+  // are counted and placed one wave at a time (a wave scan and one atomic),
+  // the last segments one at a time
   const uint32_t key_inner = key_of(kSegLen, 0u, 2u);
-  auto wave_excl = [&](uint32_t v, uint32_t& total) {
-    uint32_t inc = v;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const uint32_t t = __shfl_up(inc, off, 64);
-      if (lane >= off) inc += t;
-    }
-    total = __shfl(inc, 63, 64);
-    return inc - v;
-  };
-  s_cnt[threadIdx.x] = 0u;
+  for (int k = tid; k < kItemBuckets; k += NT) sm.cnt[k] = 0u;
   __syncthreads();
-  for (int b = 0; b < ntiles; b += 1024) {
-    const int i = b + threadIdx.x;
-    uint32_t ninner = 0u;
-    if (i < ntiles) {
-      const uint32_t v = walk_of(i), ns = nseg_of(v);
-      if (ns > 0u) {
-        atomicAdd(&s_cnt[key_of(v, ns - 1u, ns)], 1u);
-        ninner = ns - 1u;
+  uint2 rg[R];
+  uint32_t tw[R], off[R];
+  auto load = [&](int cb, bool with_off) {
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      const int i = cb + R * tid + m;
+      rg[m] = make_uint2(0u, 0u);
+      tw[m] = 0u;
+      if (i < ntiles) {
+        rg[m] = w.crange[i];
+        tw[m] = w.tile_walk[i];
+        if (with_off) off[m] = w.walk_off[i];
       }
     }
-    uint32_t wtot;
-    wave_excl(ninner, wtot);
-    if (lane == 0 && wtot > 0u) atomicAdd(&s_cnt[key_inner], wtot);
-  }
-  __syncthreads();
-  {
-    const uint32_t c = s_cnt[threadIdx.x];
-    uint32_t inc = c;
+  };
+  // the first rows and the bucket counts
+  uint32_t carry = 0;
+  for (int cb = 0; cb < ntiles; cb += CH) {
+    load(cb, false);
+    uint32_t s = 0, ninner = 0;
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const uint32_t t = __shfl_up(inc, off, 64);
-      if (lane >= off) inc += t;
+    for (int m = 0; m < R; ++m) {
+      off[m] = s;
+      s += walk_of(rg[m]);
     }
-    if (lane == 63) s_w[wv] = inc;
-    __syncthreads();
-    uint32_t pre = 0, tot = 0;
-    for (int k = 0; k < 16; ++k) {
-      if (k < wv) pre += s_w[k];
-      tot += s_w[k];
+    uint32_t tot;
+    const uint32_t pre = carry + block_excl_u32<NT>(s, tot, sm.part);
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      const int i = cb + R * tid + m;
+      off[m] += pre;
+      if (i < ntiles) w.walk_off[i] = off[m];
+      const uint32_t v = walk_of(rg[m]), ns = nseg_of(v);
+      if (ns > 0u) {
+        atomicAdd(&sm.cnt[key_of(v, ns - 1u, ns)], 1u);
+        ninner += ns - 1u;
+      }
     }
-    s_cnt[threadIdx.x] = pre + inc - c;
-    if (threadIdx.x == 0) s_total = tot;
+    uint32_t wt;
+    wave_excl_u32(ninner, wt);
+    if (lane == 0 && wt > 0u) atomicAdd(&sm.cnt[key_inner], wt);
+    carry += tot;
   }
   __syncthreads();
-  // an item: tile | segment << 24 | (a later segment follows) << 30 |
-  // (the tile's rows fit) << 31, its list range [q1, q2) and the row of list
-  // position 0 (rows are indexed by list position)
+  // the buckets' first places
+  {
+    constexpr int BPT = kItemBuckets / NT;
+    uint32_t c[BPT], s = 0;
+#pragma unroll
+    for (int b = 0; b < BPT; ++b) {
+      c[b] = sm.cnt[BPT * tid + b];
+      s += c[b];
+    }
+    uint32_t tot;
+    uint32_t run = block_excl_u32<NT>(s, tot, sm.part);
+#pragma unroll
+    for (int b = 0; b < BPT; ++b) {
+      sm.cnt[BPT * tid + b] = run;
+      run += c[b];
+    }
+    if (tid == 0) sm.total = tot;
+  }
+  __syncthreads();
   const uint32_t cap = (uint32_t)ntiles * (uint32_t)kMaxSeg;
-  const uint64_t ccap = min((uint64_t)(kSuper * kSuper) * max_pairs, (uint64_t)0xFFFFFFFFu);
-  for (int b = 0; b < ntiles; b += 1024) {
-    const int i = b + threadIdx.x;
-    const bool on = i < ntiles;
-    const uint2 cr = on ? rng_of(i) : make_uint2(0u, 0u);
-    const uint2 r = clamp_range(cr, (uint32_t)ccap);
-    const uint32_t v = cr.y > cr.x ? cr.y - cr.x : 0u, ns = on ? nseg_of(v) : 0u;
-    // places of this tile's inner segments: the wave's block plus the offset
-    uint32_t wtot;
-    const uint32_t woff = wave_excl(ns > 0u ? ns - 1u : 0u, wtot);
+  const uint32_t ccap =
+      (uint32_t)min((uint64_t)(kSuper * kSuper) * max_pairs, (uint64_t)0xFFFFFFFFu);
+  const bool resident = ntiles <= CH;
+  for (int cb = 0; cb < ntiles; cb += CH) {
+    if (!resident) load(cb, true);
+    // places of the thread's inner segments: the wave's block plus the offset
+    uint32_t ninner = 0;
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      const uint32_t ns = nseg_of(walk_of(rg[m]));
+      ninner += ns > 0u ? ns - 1u : 0u;
+    }
+    uint32_t wt;
+    const uint32_t woff = wave_excl_u32(ninner, wt);
     uint32_t wbase = 0u;
-    if (lane == 0 && wtot > 0u) wbase = atomicAdd(&s_cnt[key_inner], wtot);
-    wbase = __shfl(wbase, 0, 64);
-    if (!on) continue;
-    const uint32_t wstart = i < kWalkCache ? s_off[i] : w.walk_off[i];
-    const bool walk_ok = i < kWalkCache ? s_ok[i] != 0u : w.tile_walk[i] == cr.y;
-    const bool rows_ok = walk_ok && cr.y == r.y &&
-                         (uint64_t)wstart + (r.y - r.x) <= (uint64_t)w.row_cap;
-    for (uint32_t j = 0; j < ns; ++j) {
-      const bool inner = j + 1 < ns;
-      const uint32_t pos = inner ? wbase + woff + j : atomicAdd(&s_cnt[key_of(v, j, ns)], 1u);
-      const uint32_t q1 = min(r.x + j * kSegLen, r.y);
-      const uint32_t q2 = inner ? min(q1 + kSegLen, r.y) : r.y;
-      if (pos < cap)
-        w.seg_order[pos] = make_uint4((uint32_t)i | (j << 24) | ((inner ? 1u : 0u) << 30) |
-                                          ((rows_ok ? 1u : 0u) << 31),
-                                      q1, q2, wstart - r.x);
+    if (lane == 0 && wt > 0u) wbase = atomicAdd(&sm.cnt[key_inner], wt);
+    uint32_t ipos = __shfl(wbase, 0, 64) + woff;
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      const int i = cb + R * tid + m;
+      if (i >= ntiles) break;
+      const uint2 cr = rg[m];
+      const uint2 r = clamp_range(cr, ccap);
+      const uint32_t v = walk_of(cr), ns = nseg_of(v);
+      const bool rows_ok = tw[m] == cr.y && cr.y == r.y &&
+                           (uint64_t)off[m] + (r.y - r.x) <= (uint64_t)w.row_cap;
+      for (uint32_t j = 0; j < ns; ++j) {
+        const bool inner = j + 1 < ns;
+        const uint32_t pos = inner ? ipos++ : atomicAdd(&sm.cnt[key_of(v, j, ns)], 1u);
+        const uint32_t q1 = min(r.x + j * kSegLen, r.y);
+        const uint32_t q2 = inner ? min(q1 + kSegLen, r.y) : r.y;
+        if (pos < cap)
+          w.seg_order[pos] = make_uint4((uint32_t)i | (j << 24) | ((inner ? 1u : 0u) << 30) |
+                                            ((rows_ok ? 1u : 0u) << 31),
+                                        q1, q2, off[m] - r.x);
+      }
     }
   }
-  if (threadIdx.x == 0) w.seg_n[0] = min(s_total, cap);
+  if (tid == 0) w.seg_n[0] = min(sm.total, cap);
+}
+
+__global__ __launch_bounds__(1024) void k_walk_scan(WsView w, int ntiles, uint32_t max_pairs) {
+  __shared__ ItemScratch sm;
+  build_adjoint_items<1024>(w, ntiles, max_pairs, sm);
 }
 
 hipError_t launch_adjoint_items(const Layout& L, const WsView& w, hipStream_t s) {
@@ -867,6 +890,13 @@ struct L1Upstream {
 // formed once per adjoint call: plane 0 holds r, g, b, depth, alpha at bits
 // 0-9, plane 1 + k the feature channels 16 k .. 16 k + 15.  Groups without a
 // target are zero.  The pass also adds the loss.
+//
+// The same launch does the adjoint's other set-up, which shares no data with
+// the codes: its first workgroup builds the work items (one workgroup of
+// dependent steps, which would otherwise be a launch of its own on the
+// critical path) and, for a call that does not accumulate, sets the loss to
+// zero (loss_zero; the adjoint then adds it) while the code workgroups clear
+// the feature gradient (n_zero floats at zero).
 __device__ __forceinline__ uint32_t l1_code(float o, float t, float scale, float& l) {
   const float d = o - t;
   l += fabsf(d) * scale;
@@ -878,9 +908,19 @@ __device__ __forceinline__ float l1_decode(uint32_t word, int slot) {
 }
 __global__ __launch_bounds__(256) void k_l1_codes(L1Upstream l1, int64_t HW, int C,
                                                   uint32_t* __restrict__ codes,
-                                                  float* __restrict__ loss_part) {
+                                                  float* __restrict__ loss_part, WsView w,
+                                                  int ntiles, uint32_t max_pairs,
+                                                  float* __restrict__ zero, int64_t n_zero,
+                                                  float* __restrict__ loss_zero) {
   __shared__ float s_l[4];
-  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  __shared__ ItemScratch s_items;
+  if (blockIdx.x == 0) {  // uniform
+    if (loss_zero && threadIdx.x == 0) *loss_zero = 0.f;
+    build_adjoint_items<256>(w, ntiles, max_pairs, s_items);
+    return;
+  }
+  const int64_t wg = (int64_t)blockIdx.x - 1, nwg = (int64_t)gridDim.x - 1;
+  const int64_t p = wg * 256 + threadIdx.x;
   float loss = 0.f;
   if (p < HW) {
     // every load of the pixel is issued before any code is formed
@@ -942,13 +982,14 @@ __global__ __launch_bounds__(256) void k_l1_codes(L1Upstream l1, int64_t HW, int
       }
     }
   }
+  for (int64_t q = p; q < n_zero; q += nwg * 256) zero[q] = 0.f;
   // the workgroup's share of the loss; the adjoint's first workgroup adds
   // the shares up (one atomic instead of one per workgroup on one address)
-  if (l1.loss) {
+  if (l1.loss && wg * 256 < HW) {  // uniform
     const float v = wave_sum(loss);
     if ((threadIdx.x & 63) == 0) s_l[threadIdx.x >> 6] = v;
     __syncthreads();
-    if (threadIdx.x == 0) loss_part[blockIdx.x] = (s_l[0] + s_l[1]) + (s_l[2] + s_l[3]);
+    if (threadIdx.x == 0) loss_part[wg] = (s_l[0] + s_l[1]) + (s_l[2] + s_l[3]);
   }
 }
 
@@ -1507,7 +1548,7 @@ hipError_t launch_composite_bwd_impl(const DevGaussians& g, const DevSettings& s
   const bool feat_on = st.render_features && g.C > 0 && has_gf && d_feat != nullptr;
   // grad2d is zero here: the forward preprocess clears it and the preprocess
   // adjoint clears it again after consuming it
-  if (d_feat && !accumulate && L.P > 0 && g.C > 0) {
+  if (d_feat && !accumulate && L.P > 0 && g.C > 0 && !l1) {  // the L1 code pass clears it
     const int64_t n = L.P * g.C;
     hipLaunchKernelGGL(k_fill_zero<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                        d_feat, n);
@@ -1572,11 +1613,15 @@ hipError_t launch_composite_bwd_l1(const DevGaussians& g, const DevSettings& st,
   u.s_alpha = (float)(a.w_alpha / HW);
   u.s_feat = (float)(g.C > 0 ? a.w_feat / ((double)g.C * HW) : 0.0);
   u.loss = a.loss;
-  // the upstream codes and the loss, once for every channel pass
+  // the upstream codes and the loss, once for every channel pass, with the
+  // work items and the cleared feature gradient
   const int64_t npx = (int64_t)L.W * L.H;
-  if (npx > 0)
-    hipLaunchKernelGGL(k_l1_codes, dim3((unsigned)((npx + 255) / 256)), dim3(256), 0, s, u, npx,
-                       g.C, w.l1_codes, w.loss_part);
+  const int64_t n_zero = (d_feat && !accumulate && L.P > 0 && g.C > 0) ? L.P * g.C : 0;
+  // (at least one code workgroup, for the clearing)
+  const int64_t ncode = npx > 0 ? (npx + 255) / 256 : 1;
+  hipLaunchKernelGGL(k_l1_codes, dim3((unsigned)(1 + ncode)), dim3(256), 0, s, u,
+                     npx, g.C, w.l1_codes, w.loss_part, w, L.ntiles, (uint32_t)L.max_pairs,
+                     d_feat, n_zero, accumulate ? nullptr : a.loss);
   return launch_composite_bwd_impl(g, st, L, w, nullptr, nullptr, nullptr, nullptr, geometry,
                                    d_feat, accumulate, &u, s);
 }

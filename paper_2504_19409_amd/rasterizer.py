@@ -179,13 +179,10 @@ class Frame:
                     "gsff_backward_l1")
         return grads
 
-    def composite_bwd_l1(self, outs, targets, weights, grads, loss=None, accumulate=False,
-                         items=True):
+    def composite_bwd_l1(self, outs, targets, weights, grads, loss=None, accumulate=False):
         """Only the compositing adjoint of backward_l1 (the preprocess adjoint
-        follows with preprocess_bwd); used to time the stages separately.
-        items=False: the adjoint_items stage already ran for this forward."""
-        if items:
-            self.call_stage("gsff_adjoint_items")
+        follows with preprocess_bwd); used to time the stages separately.  It
+        builds the adjoint's work items itself."""
         gs = self._grads_struct(grads)
         w = (ctypes.c_float * 4)(*[float(x) for x in weights])
         o = [(None if t is None else x) for x, t in zip(outs, targets)]

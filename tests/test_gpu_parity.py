@@ -471,6 +471,35 @@ def test_backward_accumulate(orc):
         assert H.rel_l2(g2[k].cpu().numpy(), 2 * g1[k].cpu().numpy()) <= 1e-6, k
 
 
+def test_backward_l1_overwrite_and_accumulate():
+    """accumulate = 0 overwrites the loss and every gradient (stale values in
+    them do not leak in); accumulate = 1 adds to them."""
+    sc = _scene("ragged", C=5)
+    fr, _ = H.make_frame(sc, torch)
+    outs = fr.forward()
+    rng = np.random.default_rng(29)
+    t_rgb, t_depth, t_feat = sg.make_targets(rng, sc.camera.width, sc.camera.height, 5)
+    targets = [torch.from_numpy(t).cuda() for t in (t_rgb, t_depth)] + [None]
+    targets.append(torch.from_numpy(t_feat).cuda())
+    weights = (1.0, 0.5, 0.0, 1.0)
+    ref_loss = torch.zeros(1, device="cuda")
+    ref = fr.make_grads()
+    fr.backward_l1(outs, targets, weights, ref, ref_loss)
+    loss = torch.full((1,), 123.0, device="cuda")
+    g = {k: torch.full_like(v, 7.0) for k, v in ref.items()}
+    fr.backward_l1(outs, targets, weights, g, loss)
+    torch.cuda.synchronize()
+    assert loss.item() == pytest.approx(ref_loss.item(), rel=1e-6)
+    # gradients up to the summation order of atomics
+    for k in ref:
+        assert H.rel_l2(g[k].cpu().numpy(), ref[k].cpu().numpy()) <= 1e-5, k
+    fr.backward_l1(outs, targets, weights, g, loss, accumulate=True)
+    torch.cuda.synchronize()
+    assert loss.item() == pytest.approx(2 * ref_loss.item(), rel=1e-6)
+    for k in ref:
+        assert H.rel_l2(g[k].cpu().numpy(), 2 * ref[k].cpu().numpy()) <= 1e-5, k
+
+
 def test_l1_grad_kernel():
     from paper_2504_19409_amd.rasterizer import l1_grad
     rng = np.random.default_rng(0)
@@ -548,8 +577,8 @@ def test_backward_l1_fused_upstream(orc, kind, C, weights):
 
 @pytest.mark.parametrize("kind,C", [("ragged", 5), ("dense", 16)])
 def test_stage_split_matches_whole_pass(kind, C):
-    """The stages one at a time (forward compositing, adjoint work items,
-    compositing adjoint, preprocess adjoint) give what gsff_forward +
+    """The stages one at a time (forward compositing, compositing adjoint
+    with its work items, preprocess adjoint) give what gsff_forward +
     gsff_backward_l1 give in one call: outputs bit for bit; gradients and loss
     up to the summation order of atomics."""
     sc = _scene(kind, C=C)
@@ -571,10 +600,9 @@ def test_stage_split_matches_whole_pass(kind, C):
                "gsff_tile_ranges"]:
         fb.call_stage(st)
     fb.composite_fwd(outs_b)
-    fb.call_stage("gsff_adjoint_items")
     loss_b = torch.zeros(1, device="cuda")
     grads_b = fb.make_grads()
-    fb.composite_bwd_l1(outs_b, targets, weights, grads_b, loss_b, items=False)
+    fb.composite_bwd_l1(outs_b, targets, weights, grads_b, loss_b)
     fb.preprocess_bwd(grads_b)
     torch.cuda.synchronize()
     for a, b in zip(outs_a, outs_b):
