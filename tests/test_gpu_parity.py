@@ -543,15 +543,17 @@ def test_autograd_function(orc):
                                             ("tiny", 80, (1.0, 0.5, 0.0, 1.0))])
 def test_backward_l1_fused_upstream(orc, kind, C, weights):
     """gsff_backward_l1 forms (w_k / numel_k) sign(out - target) inside the
-    adjoint; the oracle gets that same upstream explicitly."""
+    adjoint; the oracle gets that same upstream explicitly, formed from its
+    own render.  Targets keep a margin from the outputs so that no sign
+    depends on the rounding of either side."""
     sc = _scene(kind, C=C)
+    p, c = orc.scene_dicts(sc)
+    ref = orc.render(p, c)
+    o = [ref["rgb"], ref["depth"], ref["alpha"], ref["feat"]]
+    rng = np.random.default_rng(17)
+    targets_np = [H.targets_away(rng, x) for x in o]
     fr, _ = H.make_frame(sc, torch)
     outs = fr.forward()
-    W, Hh = sc.camera.width, sc.camera.height
-    rng = np.random.default_rng(17)
-    t_rgb, t_depth, t_feat = sg.make_targets(rng, W, Hh, C)
-    t_alpha = rng.random((Hh, W)).astype(np.float32)
-    targets_np = [t_rgb, t_depth, t_alpha, t_feat]
     targets = [torch.from_numpy(t).cuda() for t in targets_np]
     if weights[2] == 0.0:
         targets[2] = None
@@ -559,7 +561,6 @@ def test_backward_l1_fused_upstream(orc, kind, C, weights):
     grads = fr.make_grads()
     fr.backward_l1(outs, targets, weights, grads, loss)
     torch.cuda.synchronize()
-    o = [x.cpu().numpy().astype(np.float64) for x in outs]
     ups, ref_loss = [], 0.0
     for k, (x, t) in enumerate(zip(o, targets_np)):
         if targets[k] is None or weights[k] == 0.0:
@@ -569,7 +570,6 @@ def test_backward_l1_fused_upstream(orc, kind, C, weights):
         ups.append(scale * np.sign(x - t))
         ref_loss += scale * np.abs(x - t).sum()
     assert loss.item() == pytest.approx(ref_loss, rel=2e-5)
-    p, c = orc.scene_dicts(sc)
     ob = orc.backward(p, c, dict(g_rgb=ups[0], g_depth=ups[1], g_alpha=ups[2], g_feat=ups[3]))
     for k in GRAD_KEYS:
         assert H.rel_l2(grads[k].cpu().numpy(), ob[k]) <= H.TOL_GRAD, k
@@ -618,18 +618,18 @@ def test_stage_split_matches_whole_pass(kind, C):
 
 def test_backward_l1_feature_only(orc):
     sc = _scene("tiny", C=16)
+    p, c = orc.scene_dicts(sc)
+    of = orc.render(p, c)["feat"]
+    rng = np.random.default_rng(19)
+    t_feat = H.targets_away(rng, of)
     fr, _ = H.make_frame(sc, torch)
     outs = fr.forward()
-    rng = np.random.default_rng(19)
-    _, _, t_feat = sg.make_targets(rng, sc.camera.width, sc.camera.height, 16)
     tf = torch.from_numpy(t_feat).cuda()
     grads = {"feat": torch.empty((sc.P, 16), device="cuda")}
     loss = torch.zeros(1, device="cuda")
     fr.backward_l1(outs, [None, None, None, tf], (0.0, 0.0, 0.0, 1.0), grads, loss)
     torch.cuda.synchronize()
-    of = outs[3].cpu().numpy().astype(np.float64)
     up = np.sign(of - t_feat) / of.size
-    p, c = orc.scene_dicts(sc)
     z = np.zeros((sc.camera.height, sc.camera.width))
     ob = orc.backward(p, c, dict(g_rgb=np.zeros((3,) + z.shape), g_depth=z, g_alpha=z,
                                  g_feat=up))
