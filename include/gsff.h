@@ -229,6 +229,55 @@ gsff_status gsff_backward_l1(const gsff_gaussians* g, const gsff_camera* cam,
                              const float* weights, float* loss, const gsff_grads* out,
                              int32_t accumulate, void* stream);
 
+/* Tracking backward (Sec. 3.3 tracking loss, Eq. 5; pose terms Eq. 4): with
+ * the Gaussians frozen, the gradient of
+ *   L = lambda_t mean(m_v m_e |rgb - t_rgb|) + (1 - lambda_t) mean(m_v |depth - t_depth|)
+ * with respect to the pose perturbation only (d_pose [6], rho then theta, as
+ * gsff_grads.pose).  The means run over all 3HW colour and HW depth elements;
+ * a masked-out pixel contributes zero.  mask_v [H,W] (the visibility mask)
+ * and mask_e [H,W] (the edge mask), uint8 on the device, non-zero = kept;
+ * NULL keeps every pixel.  A NULL target leaves its term out.  out_rgb and
+ * out_depth are the forward outputs of the same frame.  loss (device, may be
+ * NULL) receives L: accumulate = 0 overwrites it and d_pose, 1 adds to them.
+ * Errors: GSFF_ERR_INVALID_ARGUMENT for a NULL d_pose or a non-finite
+ * lambda_t; otherwise as gsff_backward_l1. */
+gsff_status gsff_backward_tracking(const gsff_gaussians* g, const gsff_camera* cam,
+                                   const gsff_settings* st, void* ws, size_t ws_bytes,
+                                   int64_t max_pairs, const float* out_rgb,
+                                   const float* out_depth, const float* t_rgb,
+                                   const float* t_depth, const uint8_t* mask_v,
+                                   const uint8_t* mask_e, float lambda_t, float* loss,
+                                   float* d_pose, int32_t accumulate, void* stream);
+
+/* The masks of the tracking loss (Sec. 3.3, Eq. 5), uint8 [H,W] on the
+ * device, 1 = kept.  mask_e: the edge mask of the target colour image t_rgb
+ * [3,H,W] f32: the Sobel gradient of the grey image (mean of the three
+ * channels), scaled by 1/8 so that a ramp of slope a per pixel has magnitude
+ * a, the border replicated; kept where the magnitude exceeds edge_threshold
+ * (>= 0).  mask_v: the visibility mask, kept where alpha [H,W] f32 (the
+ * accumulated opacity of the render at the frozen Gaussians) exceeds
+ * vis_threshold.  Either output may be NULL (its input may then be NULL).
+ * Errors: GSFF_ERR_INVALID_ARGUMENT for a non-positive size, a missing input
+ * or a non-finite or negative threshold. */
+gsff_status gsff_tracking_masks(const float* t_rgb, const float* alpha, int32_t width,
+                                int32_t height, float edge_threshold, float vis_threshold,
+                                uint8_t* mask_v, uint8_t* mask_e, void* stream);
+
+/* One pose step of the tracking loop (Sec. 3.3; the increment is the left
+ * perturbation of Eq. 4).  d_pose [6] (rho, theta) is the gradient from
+ * gsff_backward_tracking; state [12] holds Adam's first and second moments
+ * (zero before step 1); step counts from 1.  The increment
+ * delta_k = -lr_k mhat_k / (sqrt(vhat_k) + eps) (lr_trans for rho, lr_rot for
+ * theta) is applied as viewmat <- Exp(delta) viewmat with the closed-form
+ * SE(3) exponential, in FP64, and written to delta [6] if that is not NULL:
+ * its two halves are the translation and rotation changes whose norms the
+ * caller tests for convergence.  All pointers are device pointers; viewmat
+ * is updated in place.  Errors: GSFF_ERR_INVALID_ARGUMENT for a NULL
+ * pointer, step < 1, betas outside [0, 1), eps <= 0 or a non-finite rate. */
+gsff_status gsff_pose_adam_step(float* viewmat, const float* d_pose, float* state,
+                                int32_t step, float lr_trans, float lr_rot, float beta1,
+                                float beta2, float eps, float* delta, void* stream);
+
 /* Stage entry points: the forward is exactly preprocess, sort_depth, bin,
  * sort_tiles, tile_ranges, composite_fwd in this order; the backward is
  * composite_bwd then preprocess_bwd.  Same arguments and conventions as the

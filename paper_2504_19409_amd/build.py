@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgsff.so")
-SOURCES = ["capi.hip", "preprocess.hip", "sort.hip", "composite.hip", "decoder.hip"]
+SOURCES = ["capi.hip", "preprocess.hip", "sort.hip", "composite.hip", "decoder.hip",
+           "tracking.hip"]
 ARCH = "gfx950"
 
 

@@ -450,7 +450,8 @@ static gsff_status backward_l1_impl(const gsff_gaussians* g, const gsff_camera* 
                                     const float* t_depth, const float* t_alpha,
                                     const float* t_feat, const float* weights, float* loss,
                                     const gsff_grads* out, int32_t accumulate, void* stream,
-                                    bool with_preprocess) {
+                                    bool with_preprocess, const uint8_t* mask_v = nullptr,
+                                    const uint8_t* mask_e = nullptr) {
   GSFF_PRELUDE
   if (!out) return fail(GSFF_ERR_INVALID_ARGUMENT, "NULL grads");
   if (!weights) return fail(GSFF_ERR_INVALID_ARGUMENT, "NULL weights");
@@ -462,7 +463,8 @@ static gsff_status backward_l1_impl(const gsff_gaussians* g, const gsff_camera* 
   if (out->feat && g->C == 0) return fail(GSFF_ERR_INVALID_ARGUMENT, "feat grad with C == 0");
   const bool geo = any_geometry(out);
   L1Args a{out_rgb, out_depth, out_alpha, out_feat, t_rgb, t_depth, t_alpha, t_feat,
-           (double)weights[0], (double)weights[1], (double)weights[2], (double)weights[3], loss};
+           (double)weights[0], (double)weights[1], (double)weights[2], (double)weights[3], loss,
+           mask_v, mask_e};
   // the L1 code pass builds the adjoint's work items itself
   gsff_status rc = hip_check(
       launch_composite_bwd_l1(c.g, c.st, c.L, c.w, a, geo, out->feat, accumulate, c.s),
@@ -482,6 +484,24 @@ gsff_status gsff_backward_l1(const gsff_gaussians* g, const gsff_camera* cam,
   return backward_l1_impl(g, cam, st, ws, ws_bytes, max_pairs, out_rgb, out_depth, out_alpha,
                           out_feat, t_rgb, t_depth, t_alpha, t_feat, weights, loss, out,
                           accumulate, stream, true);
+}
+
+gsff_status gsff_backward_tracking(const gsff_gaussians* g, const gsff_camera* cam,
+                                   const gsff_settings* st, void* ws, size_t ws_bytes,
+                                   int64_t max_pairs, const float* out_rgb,
+                                   const float* out_depth, const float* t_rgb,
+                                   const float* t_depth, const uint8_t* mask_v,
+                                   const uint8_t* mask_e, float lambda_t, float* loss,
+                                   float* d_pose, int32_t accumulate, void* stream) {
+  if (!d_pose) return fail(GSFF_ERR_INVALID_ARGUMENT, "NULL d_pose");
+  if (!std::isfinite(lambda_t)) return fail(GSFF_ERR_INVALID_ARGUMENT, "lambda_t not finite");
+  // the Gaussians are frozen: the pose is the only gradient
+  gsff_grads out{};
+  out.pose = d_pose;
+  const float weights[4] = {lambda_t, 1.f - lambda_t, 0.f, 0.f};
+  return backward_l1_impl(g, cam, st, ws, ws_bytes, max_pairs, out_rgb, out_depth, nullptr,
+                          nullptr, t_rgb, t_depth, nullptr, nullptr, weights, loss, &out,
+                          accumulate, stream, true, mask_v, mask_e);
 }
 
 gsff_status gsff_composite_bwd_l1(const gsff_gaussians* g, const gsff_camera* cam,

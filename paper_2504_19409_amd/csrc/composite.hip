@@ -884,12 +884,16 @@ struct L1Upstream {
   const float* t_feat;
   float s_rgb, s_depth, s_alpha, s_feat;  // w_k / numel_k
   float* loss;                            // += the loss (may be NULL)
+  const uint8_t* mask_v;                  // zero: no colour or depth term here
+  const uint8_t* mask_e;                  // zero: no colour term here
 };
 
 // The L1 upstream of every pixel in 2-bit codes (0: zero, 1: +1, 2: -1),
 // formed once per adjoint call: plane 0 holds r, g, b, depth, alpha at bits
 // 0-9, plane 1 + k the feature channels 16 k .. 16 k + 15.  Groups without a
-// target are zero.  The pass also adds the loss.
+// target are zero, and so are the colour and depth groups of a pixel the
+// tracking masks leave out (Eq. 5: m_v m_e on colour, m_v on depth).  The
+// pass also adds the loss.
 //
 // The same launch does the adjoint's other set-up, which shares no data with
 // the codes: its first workgroup builds the work items (one workgroup of
@@ -950,12 +954,14 @@ __global__ __launch_bounds__(256) void k_l1_codes(L1Upstream l1, int64_t HW, int
         ft[j] = l1.t_feat[q];
       }
     }
+    const bool in_v = !l1.mask_v || l1.mask_v[p] != 0;
+    const bool in_c = in_v && (!l1.mask_e || l1.mask_e[p] != 0);
     uint32_t w0 = 0u;
-    if (l1.t_rgb) {
+    if (l1.t_rgb && in_c) {
 #pragma unroll
       for (int k = 0; k < 3; ++k) w0 |= l1_code(o[k], t[k], l1.s_rgb, loss) << (2 * k);
     }
-    if (l1.t_depth) w0 |= l1_code(o[3], t[3], l1.s_depth, loss) << 6;
+    if (l1.t_depth && in_v) w0 |= l1_code(o[3], t[3], l1.s_depth, loss) << 6;
     if (l1.t_alpha) w0 |= l1_code(o[4], t[4], l1.s_alpha, loss) << 8;
     codes[p] = w0;
     if (feat) {
@@ -1613,6 +1619,8 @@ hipError_t launch_composite_bwd_l1(const DevGaussians& g, const DevSettings& st,
   u.s_alpha = (float)(a.w_alpha / HW);
   u.s_feat = (float)(g.C > 0 ? a.w_feat / ((double)g.C * HW) : 0.0);
   u.loss = a.loss;
+  u.mask_v = a.mask_v;
+  u.mask_e = a.mask_e;
   // the upstream codes and the loss, once for every channel pass, with the
   // work items and the cleared feature gradient
   const int64_t npx = (int64_t)L.W * L.H;

@@ -173,6 +173,10 @@ struct L1Args {
   const float *t_rgb, *t_depth, *t_alpha, *t_feat;
   double w_rgb, w_depth, w_alpha, w_feat;
   float* loss;
+  // per-pixel masks of the tracking loss (NULL: every pixel): mask_v gates
+  // the colour and depth terms, mask_e the colour term
+  const uint8_t* mask_v = nullptr;
+  const uint8_t* mask_e = nullptr;
 };
 hipError_t launch_composite_bwd_l1(const DevGaussians& g, const DevSettings& st,
                                    const Layout& L, const WsView& w, const L1Args& a,

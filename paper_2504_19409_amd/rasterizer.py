@@ -179,6 +179,20 @@ class Frame:
                     "gsff_backward_l1")
         return grads
 
+    def backward_tracking(self, outs, t_rgb, t_depth, mask_v, mask_e, lambda_t, d_pose,
+                          loss=None, accumulate=False):
+        """Pose gradient of the tracking loss (Eq. 5) with the Gaussians frozen:
+        lambda_t mean(m_v m_e |rgb - t_rgb|) + (1 - lambda_t) mean(m_v |depth -
+        t_depth|).  Masks are uint8 [H, W] (None keeps every pixel); d_pose [6]
+        receives (rho, theta)."""
+        L = _capi.load()
+        _capi.check(L.gsff_backward_tracking(*self._head(), _ptr(outs[0]), _ptr(outs[1]),
+                                             _ptr(t_rgb), _ptr(t_depth), _ptr(mask_v),
+                                             _ptr(mask_e), float(lambda_t), _ptr(loss),
+                                             _ptr(d_pose), int(accumulate), _stream()),
+                    "gsff_backward_tracking")
+        return d_pose
+
     def composite_bwd_l1(self, outs, targets, weights, grads, loss=None, accumulate=False):
         """Only the compositing adjoint of backward_l1 (the preprocess adjoint
         follows with preprocess_bwd); used to time the stages separately.  It
