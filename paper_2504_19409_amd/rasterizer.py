@@ -132,6 +132,7 @@ class Frame:
                     "gsff_composite_fwd")
 
     def forward(self, out_feat_dtype=torch.float32, outs=None):
+        """outs[3] may be None when the settings turn features off."""
         outs = outs or self.alloc_outputs(out_feat_dtype)
         rgb, depth, alpha, feat = outs
         L = _capi.load()

@@ -59,14 +59,17 @@ class TrackingConfig:
 class Tracker:
     """Tracks one frame: ``frame`` renders at its own viewmat tensor, which the
     loop updates in place; targets are the frame's colour [3, H, W] and depth
-    [H, W] images."""
+    [H, W] images.  The loop renders without features (the tracking loss does
+    not use them; skipping them is what makes tracking fast) and restores the
+    frame's feature setting afterwards."""
 
     def __init__(self, frame: Frame, t_rgb, t_depth, cfg: TrackingConfig | None = None):
         self.fr, self.t_rgb, self.t_depth = frame, t_rgb, t_depth
         self.cfg = cfg or TrackingConfig()
         dev = frame.device
         self.viewmat = frame.tensors[-1]
-        self.outs = frame.alloc_outputs()
+        rgb, depth, alpha, _ = frame.alloc_outputs()
+        self.outs = (rgb, depth, alpha, None)
         self.d_pose = torch.zeros(6, device=dev)
         self.state = torch.zeros(12, device=dev)
         self.delta = torch.zeros(6, device=dev)
@@ -76,6 +79,15 @@ class Tracker:
     def run(self):
         """Returns (iterations, converged, first loss, last loss); the losses
         are those of the poses the gradients were taken at."""
+        st = self.fr.settings
+        keep = st.render_features
+        st.render_features = 0
+        try:
+            return self._run()
+        finally:
+            st.render_features = keep
+
+    def _run(self):
         cfg, fr = self.cfg, self.fr
         # m_v from the render at the starting pose, m_e from the target
         fr.forward(outs=self.outs)

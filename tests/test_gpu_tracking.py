@@ -160,8 +160,9 @@ def test_tracking_loop_full_frame():
     t_rgb, t_depth, _, _ = [o.clone() for o in f0.forward()]
     vm = torch.from_numpy(np.ascontiguousarray(sc.camera.viewmat, np.float32)).cuda()
     e0 = _pose_error(vm.cpu().numpy(), ident)
-    fr = Frame(d["means"], d["log_scales"], d["quats"], d["logit_opacity"], d["rgb"], None, vm,
-               spec)
+    # the frame carries its 16 feature channels; the tracker renders without
+    fr = Frame(d["means"], d["log_scales"], d["quats"], d["logit_opacity"], d["rgb"],
+               d["feat"], vm, spec)
     # the edge threshold keeps the strongest 30% of the target's gradients
     tau = float(np.percentile(otrk.edge_magnitude(t_rgb.cpu().numpy()), 70))
     tr = Tracker(fr, t_rgb, t_depth, TrackingConfig(max_iters=100, edge_threshold=tau))
@@ -176,3 +177,4 @@ def test_tracking_loop_full_frame():
     assert 0.2 * n < int(tr.mask_e.sum()) < 0.4 * n and int(tr.mask_v.sum()) > 0.5 * n
     assert last < 0.5 * first
     assert e1[0] < 0.5 * e0[0] and e1[1] < 0.5 * e0[1]
+    assert fr.settings.render_features == 1
