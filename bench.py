@@ -181,6 +181,37 @@ def tracking_rate(torch, fr, targets, K, warmup):
         vm.copy_(keep_vm)
 
 
+def keyframe_rates(torch, fr, K):
+    """Durations of the keyframe test's two passes on the frame (Sec. 3.3,
+    Eq. 6): the visibility record of the last forward and the co-visibility
+    counts of two records, from HIP events around K launches of each."""
+    from paper_2504_19409_amd import _capi
+    from paper_2504_19409_amd.rasterizer import _ptr, _stream
+    from paper_2504_19409_amd.tracking import covisibility
+    fr.forward()
+    vis = torch.empty(fr.P, dtype=torch.uint8, device="cuda")
+    other = fr.visibility(0.5).clone()
+    counts = torch.empty(2, dtype=torch.int32, device="cuda")
+    L = _capi.load()
+
+    def timed(fn):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(K):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / K * 1e3
+
+    t_vis = timed(lambda: fr.visibility(0.5, out=vis))
+    t_cov = timed(lambda: L.gsff_covisibility(_ptr(vis), _ptr(other), fr.P, _ptr(counts),
+                                              _stream()))
+    both, either = covisibility(vis, other)
+    return {"visibility_us": round(t_vis, 1), "covisibility_us": round(t_cov, 1),
+            "visible": int(vis.sum()), "iou_same_pose": round(both / max(either, 1), 4)}
+
+
 def algorithmic_work(scene, n_pairs, torch):
     """Per-stage algorithmic bytes (HBM) and the compositing evaluation counts
     from the oracle's exact work counts (pairs with support, alpha
@@ -303,6 +334,9 @@ def main():
     track = None if args.profile_run else tracking_rate(torch, fr, targets, K, args.warmup)
     if track:
         log("tracking iteration %.4f ms" % track["ms_per_iter"])
+        track["keyframe"] = keyframe_rates(torch, fr, K)
+        log("visibility %.1f us, covisibility %.1f us" % (track["keyframe"]["visibility_us"],
+                                                          track["keyframe"]["covisibility_us"]))
 
     wc, sizes = algorithmic_work(scene, n_pairs, torch)
     dom = max(ONE_KERNEL_STAGES, key=lambda s: stage_ms[s])

@@ -249,6 +249,25 @@ gsff_status gsff_backward_tracking(const gsff_gaussians* g, const gsff_camera* c
                                    const uint8_t* mask_e, float lambda_t, float* loss,
                                    float* d_pose, int32_t accumulate, void* stream);
 
+/* Visibility record of the last forward on `ws` (Sec. 3.3 keyframe
+ * selection, Eq. 6): visible [P] uint8 on the device receives 1 for every
+ * Gaussian blended at some pixel while the transmittance in front of it
+ * exceeds t_vis (the paper's 0.5), 0 for every other.  The decisions are the
+ * forward's own (same arithmetic on the walk it recorded), so call it after
+ * gsff_forward / gsff_composite_fwd with the same arguments.  Errors:
+ * GSFF_ERR_INVALID_ARGUMENT for a NULL visible (P > 0) or a non-finite t_vis. */
+gsff_status gsff_visibility(const gsff_gaussians* g, const gsff_camera* cam,
+                            const gsff_settings* st, void* ws, size_t ws_bytes,
+                            int64_t max_pairs, float t_vis, uint8_t* visible, void* stream);
+
+/* Co-visibility of two visibility records a, b [n] (uint8, non-zero =
+ * visible; Sec. 3.3): counts [2] uint32 on the device receive |a and b| and
+ * |a or b|; their ratio is the IoU that the keyframe test compares with
+ * tau_thresh.  Errors: GSFF_ERR_INVALID_ARGUMENT for a NULL pointer, n < 0
+ * or n >= 2^32. */
+gsff_status gsff_covisibility(const uint8_t* a, const uint8_t* b, int64_t n, uint32_t* counts,
+                              void* stream);
+
 /* The masks of the tracking loss (Sec. 3.3, Eq. 5), uint8 [H,W] on the
  * device, 1 = kept.  mask_e: the edge mask of the target colour image t_rgb
  * [3,H,W] f32: the Sobel gradient of the grey image (mean of the three

@@ -89,6 +89,8 @@ def lib():
         L.orc_render.restype = ctypes.c_int
         L.orc_render_pixels.argtypes = [sp, cp, stp, ctypes.c_int64, vp, vp, vp]
         L.orc_render_pixels.restype = ctypes.c_int
+        L.orc_visibility.argtypes = [sp, cp, stp, ctypes.c_double, ctypes.c_double, vp, vp]
+        L.orc_visibility.restype = ctypes.c_int
         L.orc_backward.argtypes = [sp, cp, stp] + [vp] * 12
         L.orc_backward.restype = ctypes.c_int
         L.orc_tile_lists.argtypes = [sp, cp, stp, ctypes.c_int32, vp, vp]
@@ -184,6 +186,22 @@ def render_pixels(params, camera, px, py, settings=None):
     if rc != 0:
         raise ValueError("orc_render_pixels failed")
     return dict(rgb=out[:, :3], depth=out[:, 3], alpha=out[:, 4], feat=out[:, 5:])
+
+
+def visibility(params, camera, t_vis=0.5, rel=0.0, settings=None):
+    """Visibility record of Eq. 6 (blended at some pixel with transmittance
+    above t_vis in front): (sure, possible) bool [P]; with rel = 0 both are the
+    exact FP64 record, with rel > 0 they bracket any computation whose alpha
+    and transmittance are within rel (relative) of the FP64 values."""
+    m = _Marshal(params, camera)
+    st = settings or default_settings()
+    sure = np.zeros(m.P, dtype=np.uint8)
+    possible = np.zeros(m.P, dtype=np.uint8)
+    rc = lib().orc_visibility(ctypes.byref(m.scene), ctypes.byref(m.camera), ctypes.byref(st),
+                              float(t_vis), float(rel), _ptr(sure), _ptr(possible))
+    if rc != 0:
+        raise ValueError("orc_visibility failed")
+    return sure.astype(bool), possible.astype(bool)
 
 
 def backward(params, camera, grads, settings=None):

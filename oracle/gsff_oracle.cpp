@@ -228,13 +228,18 @@ struct Eval {
   bool clamped;
 };
 
+struct NoEval {
+  void operator()(const Eval&, double) const {}
+};
+
 // Front-to-back blending at one pixel (Eqs. 2-3).  Calls on_contrib(e, T)
-// for every contributor with the transmittance in front of it; returns the
-// final transmittance.  Tracks decision margins and a decision signature.
-template <class F>
+// for every contributor with the transmittance in front of it (and, when
+// given, on_eval(e, T) for every evaluated pair before its decision); returns
+// the final transmittance.  Tracks decision margins and a decision signature.
+template <class F, class G = NoEval>
 double composite_pixel(const Prepared& pr, const orc_settings* st, long px, long py,
                        F&& on_contrib, double* margin, uint64_t* hash,
-                       int64_t* n_eval) {
+                       int64_t* n_eval, G on_eval = G{}) {
   double T = 1.0;
   double mg = INFINITY;
   for (int64_t i : pr.rows[py]) {
@@ -250,6 +255,7 @@ double composite_pixel(const Prepared& pr, const orc_settings* st, long px, long
     e.clamped = !(e.oG < st->alpha_max);
     e.alpha = e.clamped ? st->alpha_max : e.oG;
     if (n_eval) ++*n_eval;
+    on_eval(e, T);
     mg = std::min(mg, std::fabs(e.alpha - st->alpha_min) / st->alpha_min);
     mg = std::min(mg, std::fabs(e.oG - st->alpha_max) / st->alpha_max);
     int code;
@@ -347,6 +353,37 @@ extern "C" int orc_render(const orc_scene* s, const orc_camera* cam,
       if (out_n) out_n[p] = n;
       if (out_margin) out_margin[p] = mg;
     }
+  return 0;
+}
+
+// Visibility record (Sec. 3.3, Eq. 6): Gaussian i is visible when it is
+// blended at some pixel while the transmittance in front of it exceeds
+// t_vis.  sure[i] = 1 when that holds with the transmittance above
+// t_vis (1 + rel) and alpha at least alpha_min (1 + rel) at some pixel;
+// possible[i] = 1 when at some evaluated pair alpha reaches
+// alpha_min (1 - rel) with the transmittance above t_vis (1 - rel).  A
+// computation in lower precision decides every Gaussian in sure as visible
+// and none outside possible.
+extern "C" int orc_visibility(const orc_scene* s, const orc_camera* cam,
+                              const orc_settings* st, double t_vis, double rel, uint8_t* sure,
+                              uint8_t* possible) {
+  if (!check_args(s, cam, st) || (s->P > 0 && (!sure || !possible))) return -1;
+  Prepared pr;
+  prepare(s, cam, st, pr);
+  for (int64_t i = 0; i < s->P; ++i) sure[i] = possible[i] = 0;
+  for (long py = 0; py < cam->height; ++py)
+    for (long px = 0; px < cam->width; ++px)
+      composite_pixel(
+          pr, st, px, py,
+          [&](const Eval& e, double Tin) {
+            if (Tin > t_vis * (1.0 + rel) && e.alpha >= st->alpha_min * (1.0 + rel))
+              sure[e.i] = 1;
+          },
+          nullptr, nullptr, nullptr,
+          [&](const Eval& e, double Tin) {
+            if (Tin > t_vis * (1.0 - rel) && e.alpha >= st->alpha_min * (1.0 - rel))
+              possible[e.i] = 1;
+          });
   return 0;
 }
 

@@ -85,6 +85,8 @@ int orc_render(const orc_scene* s, const orc_camera* cam, const orc_settings* st
 
 /* Forward at n listed pixels only: out[k] = (r, g, b, depth, alpha,
  * feat[0..C)) of pixel (px[k], py[k]), (5 + C) doubles per pixel. */
+int orc_visibility(const orc_scene* s, const orc_camera* cam, const orc_settings* st,
+                   double t_vis, double rel, uint8_t* sure, uint8_t* possible);
 int orc_render_pixels(const orc_scene* s, const orc_camera* cam, const orc_settings* st,
                       int64_t n, const int32_t* px, const int32_t* py, double* out);
 

@@ -77,6 +77,8 @@ SIGNATURES = {
                               + [ctypes.POINTER(_f32), _vp, _R, _i32, _vp]),
     "gsff_backward_tracking": (_i32, [_G, _C, _S, _vp, _sz, _i64] + [_vp] * 6
                                + [_f32, _vp, _vp, _i32, _vp]),
+    "gsff_visibility": (_i32, [_G, _C, _S, _vp, _sz, _i64, _f32, _vp, _vp]),
+    "gsff_covisibility": (_i32, [_vp, _vp, _i64, _vp, _vp]),
     "gsff_tracking_masks": (_i32, [_vp, _vp, _i32, _i32, _f32, _f32, _vp, _vp, _vp]),
     "gsff_pose_adam_step": (_i32, [_vp, _vp, _vp, _i32, _f32, _f32, _f32, _f32, _f32, _vp,
                                    _vp]),

@@ -504,6 +504,23 @@ gsff_status gsff_backward_tracking(const gsff_gaussians* g, const gsff_camera* c
                           accumulate, stream, true, mask_v, mask_e);
 }
 
+gsff_status gsff_visibility(const gsff_gaussians* g, const gsff_camera* cam,
+                            const gsff_settings* st, void* ws, size_t ws_bytes,
+                            int64_t max_pairs, float t_vis, uint8_t* visible, void* stream) {
+  GSFF_PRELUDE
+  if (g->P > 0 && !visible) return fail(GSFF_ERR_INVALID_ARGUMENT, "NULL visible");
+  if (!std::isfinite(t_vis)) return fail(GSFF_ERR_INVALID_ARGUMENT, "t_vis not finite");
+  return hip_check(launch_visibility(c.st, c.g, c.L, c.w, t_vis, visible, c.s), "visibility");
+}
+
+gsff_status gsff_covisibility(const uint8_t* a, const uint8_t* b, int64_t n, uint32_t* counts,
+                              void* stream) {
+  if (n < 0 || !counts || (n > 0 && (!a || !b)))
+    return fail(GSFF_ERR_INVALID_ARGUMENT, "covisibility arguments");
+  if (n > (int64_t)0xFFFFFFFFu) return fail(GSFF_ERR_INVALID_ARGUMENT, "n above 2^32 - 1");
+  return hip_check(launch_covisibility(a, b, n, counts, (hipStream_t)stream), "covisibility");
+}
+
 gsff_status gsff_composite_bwd_l1(const gsff_gaussians* g, const gsff_camera* cam,
                                   const gsff_settings* st, void* ws, size_t ws_bytes,
                                   int64_t max_pairs, const float* out_rgb, const float* out_depth,

@@ -778,6 +778,119 @@ hipError_t launch_adjoint_items(const Layout& L, const WsView& w, hipStream_t s)
   return hipGetLastError();
 }
 
+// Visibility record (Sec. 3.3 keyframe selection, Eq. 6): v_i = 1 when
+// Gaussian i is blended at some pixel while the transmittance in front of it
+// exceeds t_vis.  One workgroup per tile replays the forward's walk of the
+// tile's list (the ids it recorded, up to its walk end) in batches of 64 with
+// the forward's alpha and transmittance arithmetic, so every decision is the
+// forward's; it stops once no pixel of the tile can still mark a Gaussian
+// (transmittance only falls along the list).  visible must be zero before.
+__global__ __launch_bounds__(kBlock) void k_visibility(DevSettings st, int64_t P, int W, int H,
+                                                       int tiles_x, int ntiles, WsView w,
+                                                       float t_vis,
+                                                       uint8_t* __restrict__ visible) {
+  __shared__ float4 s_r0[64], s_r1[64];
+  __shared__ uint32_t s_id[64];
+  __shared__ uint32_t s_vis[2];  // the batch's marked Gaussians: bits 0-31, 32-63
+  const int tile = blockIdx.x;
+  if (tile >= ntiles) return;  // uniform
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int tx = tile % tiles_x, ty = tile / tiles_x;
+  const int px = tx * kTile + (tid & (kTile - 1)), py = ty * kTile + tid / kTile;
+  const bool inside = px < W && py < H;
+  const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
+  const uint2 cr = w.crange[tile];
+  float T = 1.f;
+  bool done = !inside;
+  for (uint32_t b = cr.x; b < cr.y; b += 64u) {
+    const uint32_t n = min(64u, cr.y - b);
+    if (tid < 64) {
+      const uint32_t gid = (uint32_t)tid < n ? w.clist[b + (uint32_t)tid] : (uint32_t)P;
+      float4 q0, q1, q2;
+      load_record(w, gid, P, q0, q1, q2);
+      s_r0[tid] = scaled_r0(q0);
+      s_r1[tid] = scaled_r1(q1);
+      s_id[tid] = gid;
+    }
+    if (tid < 2) s_vis[tid] = 0u;
+    __syncthreads();
+    uint32_t lo = 0u, hi = 0u;
+    for (uint32_t j = 0; j < n; ++j) {
+      const AlphaEval e = eval_alpha(s_r0[j], s_r1[j], pxc, pyc, st.alpha_max);
+      const bool valid = !done && e.alpha >= st.alpha_min;
+      const float Tn = __builtin_fmaf(-e.alpha, T, T);  // as the forward
+      const bool stop = valid && Tn < st.t_min;
+      const bool use = valid && !stop;
+      if (use && T > t_vis) {
+        if (j < 32u) lo |= 1u << j;
+        else hi |= 1u << (j - 32u);
+      }
+      done = done || stop;
+      T = use ? Tn : T;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      lo |= (uint32_t)__shfl_xor((int)lo, off, 64);
+      hi |= (uint32_t)__shfl_xor((int)hi, off, 64);
+    }
+    if (lane == 0) {
+      if (lo) atomicOr(&s_vis[0], lo);
+      if (hi) atomicOr(&s_vis[1], hi);
+    }
+    // a pixel can still mark a later Gaussian only while T > t_vis
+    const int live = __syncthreads_or(!done && T > t_vis);
+    if (tid < 64 && (uint32_t)tid < n && ((s_vis[tid >> 5] >> (tid & 31)) & 1u) &&
+        s_id[tid] < (uint32_t)P)
+      visible[s_id[tid]] = 1;
+    if (!live) break;  // uniform
+    __syncthreads();   // the next batch overwrites the staged records
+  }
+}
+
+hipError_t launch_visibility(const DevSettings& st, const DevGaussians& g, const Layout& L,
+                             const WsView& w, float t_vis, uint8_t* visible, hipStream_t s) {
+  if (L.P <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_zero<uint8_t>, dim3((unsigned)((L.P + 255) / 256)), dim3(256), 0, s,
+                     visible, (int64_t)L.P);
+  if (L.ntiles > 0)
+    hipLaunchKernelGGL(k_visibility, dim3((unsigned)L.ntiles), dim3(kBlock), 0, s, st, g.P, L.W,
+                       L.H, L.tiles_x, L.ntiles, w, t_vis, visible);
+  return hipGetLastError();
+}
+
+// |a and b| and |a or b| of two visibility records (non-zero = visible), for
+// the co-visibility test; counts[2] must be zero before.
+__global__ __launch_bounds__(256) void k_covisibility(const uint8_t* __restrict__ a,
+                                                      const uint8_t* __restrict__ b, int64_t n,
+                                                      uint32_t* __restrict__ counts) {
+  uint32_t both = 0u, any = 0u;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * 256) {
+    const bool x = a[i] != 0, y = b[i] != 0;
+    both += (x && y) ? 1u : 0u;
+    any += (x || y) ? 1u : 0u;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    both += (uint32_t)__shfl_xor((int)both, off, 64);
+    any += (uint32_t)__shfl_xor((int)any, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    if (both) atomicAdd(&counts[0], both);
+    if (any) atomicAdd(&counts[1], any);
+  }
+}
+
+hipError_t launch_covisibility(const uint8_t* a, const uint8_t* b, int64_t n, uint32_t* counts,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_zero<uint32_t>, dim3(1), dim3(64), 0, s, counts, (int64_t)2);
+  if (n > 0) {
+    const int64_t blocks = (n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024;
+    hipLaunchKernelGGL(k_covisibility, dim3((unsigned)blocks), dim3(256), 0, s, a, b, n, counts);
+  }
+  return hipGetLastError();
+}
+
 template <int CP, typename FT, typename OT>
 static void launch_fwd_t(const DevSettings& st, const DevGaussians& g, const Layout& L,
                          const WsView& w, int c0, float* out_rgb, float* out_depth,

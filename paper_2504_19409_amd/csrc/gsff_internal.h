@@ -161,6 +161,10 @@ hipError_t launch_composite_fwd(const DevGaussians& g, const DevSettings& st,
 // The adjoint's work items (tile list segments, longest first) and the first
 // adjoint row of every tile, from the walks the last forward recorded.
 hipError_t launch_adjoint_items(const Layout& L, const WsView& w, hipStream_t s);
+hipError_t launch_visibility(const DevSettings& st, const DevGaussians& g, const Layout& L,
+                             const WsView& w, float t_vis, uint8_t* visible, hipStream_t s);
+hipError_t launch_covisibility(const uint8_t* a, const uint8_t* b, int64_t n, uint32_t* counts,
+                               hipStream_t s);
 hipError_t launch_composite_bwd(const DevGaussians& g, const DevSettings& st,
                                 const Layout& L, const WsView& w, const float* g_rgb,
                                 const float* g_depth, const float* g_alpha,

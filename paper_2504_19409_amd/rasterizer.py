@@ -180,6 +180,16 @@ class Frame:
                     "gsff_backward_l1")
         return grads
 
+    def visibility(self, t_vis=0.5, out=None):
+        """uint8 [P]: 1 for the Gaussians the last forward blended at a pixel
+        with transmittance above t_vis in front of them (Eq. 6)."""
+        out = out if out is not None else torch.empty(self.P, dtype=torch.uint8,
+                                                      device=self.device)
+        L = _capi.load()
+        _capi.check(L.gsff_visibility(*self._head(), float(t_vis), _ptr(out), _stream()),
+                    "gsff_visibility")
+        return out
+
     def backward_tracking(self, outs, t_rgb, t_depth, mask_v, mask_e, lambda_t, d_pose,
                           loss=None, accumulate=False):
         """Pose gradient of the tracking loss (Eq. 5) with the Gaussians frozen:

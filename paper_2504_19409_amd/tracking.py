@@ -43,6 +43,23 @@ def pose_adam_step(viewmat, d_pose, state, step: int, lr_trans: float, lr_rot: f
         float(beta1), float(beta2), float(eps), _ptr(delta), _stream()), "gsff_pose_adam_step")
 
 
+def covisibility(a, b, counts=None):
+    """(|a and b|, |a or b|) of two uint8 visibility records, read back."""
+    counts = counts if counts is not None else torch.empty(2, dtype=torch.int32,
+                                                           device=a.device)
+    _capi.check(_capi.load().gsff_covisibility(_ptr(a), _ptr(b), a.numel(), _ptr(counts),
+                                               _stream()), "gsff_covisibility")
+    both, either = (int(x) & 0xFFFFFFFF for x in counts.cpu().tolist())
+    return both, either
+
+
+def is_keyframe(vis_frame, vis_keyframe, tau_thresh: float) -> bool:
+    """Keyframe test of Sec. 3.3: the frame becomes a keyframe when the IoU
+    of its visibility record with the last keyframe's is below tau_thresh."""
+    both, either = covisibility(vis_frame, vis_keyframe)
+    return (both / either if either else 1.0) < tau_thresh
+
+
 @dataclass
 class TrackingConfig:
     lambda_t: float = 0.9          # weight of the colour term (Eq. 5)

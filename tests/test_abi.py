@@ -131,3 +131,36 @@ def test_argument_validation(capi):
     # l1 and status
     assert lib.gsff_l1_grad(None, None, 10, 1.0, None, None, None) == E
     assert lib.gsff_read_status(None, None, None, None) == E
+
+
+def test_tracking_and_visibility_argument_validation(capi):
+    """The tracking and keyframe entry points reject bad arguments on the host,
+    before anything is launched."""
+    lib = capi.load()
+    E = capi.ERR_INVALID_ARGUMENT
+    g, c, s, ws, nb, mp = _args(capi)
+    b = ctypes.byref
+    # tracking backward: NULL d_pose, non-finite lambda_t
+    assert lib.gsff_backward_tracking(b(g), b(c), b(s), ws, nb, mp, 1, 1, 1, 1, None, None,
+                                      0.9, None, None, 0, None) == E
+    assert lib.gsff_backward_tracking(b(g), b(c), b(s), ws, nb, mp, 1, 1, 1, 1, None, None,
+                                      float("nan"), None, 1, 0, None) == E
+    # masks: bad size, missing input, negative or non-finite threshold
+    assert lib.gsff_tracking_masks(1, 1, 0, 8, 0.1, 0.5, 1, 1, None) == E
+    assert lib.gsff_tracking_masks(None, 1, 8, 8, 0.1, 0.5, 1, 1, None) == E
+    assert lib.gsff_tracking_masks(1, None, 8, 8, 0.1, 0.5, 1, 1, None) == E
+    assert lib.gsff_tracking_masks(1, 1, 8, 8, -0.1, 0.5, 1, 1, None) == E
+    assert lib.gsff_tracking_masks(1, 1, 8, 8, 0.1, float("inf"), 1, 1, None) == E
+    assert lib.gsff_tracking_masks(None, None, 8, 8, 0.1, 0.5, None, None, None) == capi.OK
+    # pose step: NULL pointers, step < 1, betas, eps
+    assert lib.gsff_pose_adam_step(None, 1, 1, 1, 1e-3, 1e-3, 0.9, 0.999, 1e-8, None, None) == E
+    assert lib.gsff_pose_adam_step(1, 1, 1, 0, 1e-3, 1e-3, 0.9, 0.999, 1e-8, None, None) == E
+    assert lib.gsff_pose_adam_step(1, 1, 1, 1, 1e-3, 1e-3, 1.0, 0.999, 1e-8, None, None) == E
+    assert lib.gsff_pose_adam_step(1, 1, 1, 1, 1e-3, 1e-3, 0.9, 0.999, 0.0, None, None) == E
+    # visibility: NULL output with P > 0, non-finite threshold
+    assert lib.gsff_visibility(b(g), b(c), b(s), ws, nb, mp, 0.5, None, None) == E
+    assert lib.gsff_visibility(b(g), b(c), b(s), ws, nb, mp, float("nan"), 1, None) == E
+    # co-visibility: negative n, NULL inputs, NULL counts
+    assert lib.gsff_covisibility(1, 1, -1, 1, None) == E
+    assert lib.gsff_covisibility(None, 1, 5, 1, None) == E
+    assert lib.gsff_covisibility(1, 1, 5, None, None) == E
