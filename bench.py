@@ -212,6 +212,37 @@ def keyframe_rates(torch, fr, K):
             "visible": int(vis.sum()), "iou_same_pose": round(both / max(either, 1), 4)}
 
 
+def mapping_rates(torch, fr, K):
+    """Durations of the mapping step's two passes beyond the window's
+    forward + adjoint (Sec. 3.3, Eqs. 7-8) on the frame's Gaussians: the scale
+    regulariser and the fused Adam step over all six parameter groups, from
+    HIP events around K launches (on copies: the frame's Gaussians stay)."""
+    from paper_2504_19409_amd.mapping import adam_step, scale_reg, scale_reg_workspace
+    means, log_scales, quats, logit, rgb, feat, _ = fr.tensors
+    params = [x.clone() for x in (means, log_scales, quats, logit, rgb, feat)]
+    grads = [torch.randn_like(x) * 1e-3 for x in params]
+    groups = [(p, g, torch.zeros_like(p), torch.zeros_like(p), 1e-3)
+              for p, g in zip(params, grads)]
+    ws = scale_reg_workspace(fr.P)
+    loss = torch.zeros(1, device="cuda")
+
+    def timed(fn):
+        fn(1)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for k in range(K):
+            fn(k + 2)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / K * 1e3
+
+    t_reg = timed(lambda k: scale_reg(params[1], 0.01, grads[1], loss, True, ws))
+    t_adam = timed(lambda k: adam_step(groups, k))
+    n = sum(p.numel() for p in params)
+    return {"scale_reg_us": round(t_reg, 1), "adam_us": round(t_adam, 1), "adam_elements": n,
+            "adam_gbs": round(n * 28 / (t_adam * 1e-6) / 1e9, 1)}
+
+
 def algorithmic_work(scene, n_pairs, torch):
     """Per-stage algorithmic bytes (HBM) and the compositing evaluation counts
     from the oracle's exact work counts (pairs with support, alpha
@@ -331,12 +362,14 @@ def main():
     ms = min(eager_ms, graph_ms) if graph_ms else eager_ms
     value = 1e3 / ms
 
-    track = None if args.profile_run else tracking_rate(torch, fr, targets, K, args.warmup)
-    if track:
-        log("tracking iteration %.4f ms" % track["ms_per_iter"])
-        track["keyframe"] = keyframe_rates(torch, fr, K)
-        log("visibility %.1f us, covisibility %.1f us" % (track["keyframe"]["visibility_us"],
-                                                          track["keyframe"]["covisibility_us"]))
+    # the other SLAM passes on the same frame (Sec. 3.3): tracking iteration,
+    # keyframe test, mapping step's regulariser and optimiser
+    slam = {"tracking": tracking_rate(torch, fr, targets, K, args.warmup),
+            "keyframe": keyframe_rates(torch, fr, K), "mapping": mapping_rates(torch, fr, K)}
+    log("tracking iteration %.4f ms; visibility %.1f us, covisibility %.1f us; scale reg %.1f "
+        "us, adam %.1f us" % (slam["tracking"]["ms_per_iter"], slam["keyframe"]["visibility_us"],
+                              slam["keyframe"]["covisibility_us"],
+                              slam["mapping"]["scale_reg_us"], slam["mapping"]["adam_us"]))
 
     wc, sizes = algorithmic_work(scene, n_pairs, torch)
     dom = max(ONE_KERNEL_STAGES, key=lambda s: stage_ms[s])
@@ -353,7 +386,7 @@ def main():
                    "eager_ms": round(eager_ms, 4),
                    "graph_ms": round(graph_ms, 4) if graph_ms else None,
                    "stage_us": {s: round(v * 1e3, 1) for s, v in stage_ms.items()},
-                   "pairs": n_pairs, "work": wc, "tracking": track},
+                   "pairs": n_pairs, "work": wc, "slam": slam},
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

@@ -249,6 +249,39 @@ gsff_status gsff_backward_tracking(const gsff_gaussians* g, const gsff_camera* c
                                    const uint8_t* mask_e, float lambda_t, float* loss,
                                    float* d_pose, int32_t accumulate, void* stream);
 
+/* Scale regulariser of the mapping loss (Sec. 3.3, Eqs. 7-8):
+ *   L_reg = lambda (1/N) sum_i |s_i - sbar|_1,  s_i = exp(log_scales[:, i]),
+ * sbar the mean of the N = P scale vectors, |.|_1 over the three components.
+ * grad_log_scales [3, P] (may be NULL) receives dL/dlog_scales and loss
+ * (device, may be NULL) L: accumulate = 0 overwrites, 1 adds.  The gradient
+ * takes the mean's dependence on every s_i into account; sign(0) = 0.
+ * workspace: device scratch of gsff_scale_reg_workspace_size bytes, 8-byte
+ * aligned.  Errors: GSFF_ERR_INVALID_ARGUMENT for P <= 0, a NULL input or
+ * workspace, a small or misaligned workspace or a non-finite lambda. */
+gsff_status gsff_scale_reg(const float* log_scales, int64_t P, float lambda, float* workspace,
+                           size_t ws_bytes, float* grad_log_scales, float* loss,
+                           int32_t accumulate, void* stream);
+gsff_status gsff_scale_reg_workspace_size(int64_t P, size_t* bytes);
+
+/* One Adam step over up to 8 parameter groups in one launch (the mapping
+ * step's optimiser over the Gaussians' SoA parameters; FP32): per element
+ * m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+ * param -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).
+ * All pointers are device pointers; m and v start at zero; step counts from
+ * 1.  Errors: GSFF_ERR_INVALID_ARGUMENT for a NULL pointer in a non-empty
+ * group, 0 or more than 8 groups, step < 1, betas outside [0, 1), eps <= 0
+ * or a non-finite rate. */
+typedef struct gsff_adam_group {
+  float* param;
+  const float* grad;
+  float* m;
+  float* v;
+  int64_t n;
+  float lr;
+} gsff_adam_group;
+gsff_status gsff_adam_step(const gsff_adam_group* groups, int32_t ngroups, int32_t step,
+                           float beta1, float beta2, float eps, void* stream);
+
 /* Visibility record of the last forward on `ws` (Sec. 3.3 keyframe
  * selection, Eq. 6): visible [P] uint8 on the device receives 1 for every
  * Gaussian blended at some pixel while the transmittance in front of it

@@ -58,6 +58,11 @@ class WsLayout(ctypes.Structure):
                 ("super_x", ctypes.c_int32), ("super_y", ctypes.c_int32)]
 
 
+class AdamGroup(ctypes.Structure):
+    _fields_ = [("param", _vp), ("grad", _vp), ("m", _vp), ("v", _vp), ("n", ctypes.c_int64),
+                ("lr", ctypes.c_float)]
+
+
 _G, _C, _S, _R = (ctypes.POINTER(Gaussians), ctypes.POINTER(Camera), ctypes.POINTER(Settings),
                   ctypes.POINTER(Grads))
 _i64, _i32, _f32, _sz = ctypes.c_int64, ctypes.c_int32, ctypes.c_float, ctypes.c_size_t
@@ -79,6 +84,9 @@ SIGNATURES = {
                                + [_f32, _vp, _vp, _i32, _vp]),
     "gsff_visibility": (_i32, [_G, _C, _S, _vp, _sz, _i64, _f32, _vp, _vp]),
     "gsff_covisibility": (_i32, [_vp, _vp, _i64, _vp, _vp]),
+    "gsff_scale_reg": (_i32, [_vp, _i64, _f32, _vp, _sz, _vp, _vp, _i32, _vp]),
+    "gsff_scale_reg_workspace_size": (_i32, [_i64, ctypes.POINTER(_sz)]),
+    "gsff_adam_step": (_i32, [ctypes.POINTER(AdamGroup), _i32, _i32, _f32, _f32, _f32, _vp]),
     "gsff_tracking_masks": (_i32, [_vp, _vp, _i32, _i32, _f32, _f32, _vp, _vp, _vp]),
     "gsff_pose_adam_step": (_i32, [_vp, _vp, _vp, _i32, _f32, _f32, _f32, _f32, _f32, _vp,
                                    _vp]),

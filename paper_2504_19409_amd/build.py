@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgsff.so")
 SOURCES = ["capi.hip", "preprocess.hip", "sort.hip", "composite.hip", "decoder.hip",
-           "tracking.hip"]
+           "tracking.hip", "mapping.hip"]
 ARCH = "gfx950"
 
 

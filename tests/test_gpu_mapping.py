@@ -1,0 +1,115 @@
+"""GPU parity of the mapping support (Sec. 3.3, Eqs. 7-8) through the C ABI:
+the scale regulariser and the fused Adam step against the FP64 oracle, and the
+mapping step on a keyframe window."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import mapping as omap
+from paper_2504_19409_amd import scenegen as sg
+
+pytestmark = pytest.mark.gpu
+
+f32 = lambda x: float(np.float32(x))
+
+
+@pytest.mark.parametrize("P", [1, 3000, 1_000_000])
+def test_scale_reg_matches_oracle(P):
+    from paper_2504_19409_amd.mapping import scale_reg
+    rng = np.random.default_rng(P)
+    ls = rng.normal(-3.0, 0.5, size=(3, P)).astype(np.float32)
+    lam = f32(0.3)
+    d = torch.from_numpy(ls).cuda()
+    grad = torch.full((3, P), 1.0, device="cuda")
+    loss = torch.full((1,), 2.0, device="cuda")
+    scale_reg(d, lam, grad, loss)  # accumulate = 0 overwrites both
+    torch.cuda.synchronize()
+    L, g = omap.scale_reg(ls, lam)
+    assert loss.item() == pytest.approx(L, rel=1e-6, abs=1e-30)
+    gg = grad.cpu().numpy()
+    # compare away from ties with the mean (FP32 scales decide those signs)
+    s = np.exp(ls.astype(np.float64))
+    clear = np.abs(s - s.mean(axis=1, keepdims=True)) > 1e-6 * s.mean()
+    assert (~clear).sum() <= 4
+    np.testing.assert_allclose(gg[clear], g[clear], rtol=1e-5, atol=1e-12 / P)
+    # accumulate = 1 adds
+    scale_reg(d, lam, grad, loss, accumulate=True)
+    torch.cuda.synchronize()
+    assert loss.item() == pytest.approx(2 * L, rel=1e-6, abs=1e-30)
+    np.testing.assert_allclose(grad.cpu().numpy()[clear], 2 * g[clear], rtol=1e-5,
+                               atol=1e-12 / P)
+
+
+def _close(a, ref, scale, tol=2e-6):
+    err = np.abs(np.asarray(a, np.float64) - ref)
+    bad = err > tol * scale + 1e-30
+    assert not np.any(bad), (int(bad.sum()), float((err / (scale + 1e-30)).max()))
+
+
+def test_adam_step_matches_oracle():
+    from paper_2504_19409_amd.mapping import adam_step
+    rng = np.random.default_rng(7)
+    sizes, lrs = [600_000, 1, 0, 3_001, 257, 12_345], [1e-3, 5e-2, 1e-2, 2.5e-3, 1e-4, 3e-3]
+    P = [rng.normal(size=n).astype(np.float32) for n in sizes]
+    dev = [torch.from_numpy(p.copy()).cuda() for p in P]
+    M = [torch.zeros(n, device="cuda") for n in sizes]
+    V = [torch.zeros(n, device="cuda") for n in sizes]
+    om = [np.zeros(n) for n in sizes]
+    ov = [np.zeros(n) for n in sizes]
+    op = [p.astype(np.float64) for p in P]
+    for step in range(1, 4):
+        G = [(rng.normal(size=n) * 10.0 ** rng.uniform(-4, 1, size=n)).astype(np.float32)
+             for n in sizes]
+        gd = [torch.from_numpy(g).cuda() for g in G]
+        adam_step([(dev[q], gd[q], M[q], V[q], lrs[q]) for q in range(len(sizes))], step,
+                  0.9, 0.999, 1e-8)
+        torch.cuda.synchronize()
+        for q in range(len(sizes)):
+            # the oracle continues from the stored FP32 state with the FP32
+            # hyperparameters the C ABI passes
+            p1, m1, v1 = omap.adam(op[q].astype(np.float32), G[q], om[q].astype(np.float32),
+                                   ov[q].astype(np.float32), step, f32(lrs[q]), f32(0.9),
+                                   f32(0.999), f32(1e-8))
+            # FP32 rounding of a two-term sum is bounded relative to the terms'
+            # magnitudes (they can cancel), not to the result
+            m0, g = om[q].astype(np.float32).astype(np.float64), G[q].astype(np.float64)
+            _close(M[q].cpu().numpy(), m1, 0.9 * np.abs(m0) + 0.1 * np.abs(g))
+            _close(V[q].cpu().numpy(), v1, v1)
+            _close(dev[q].cpu().numpy(), p1, np.abs(op[q]) + lrs[q])
+            op[q], om[q], ov[q] = dev[q].cpu().numpy(), M[q].cpu().numpy(), V[q].cpu().numpy()
+
+
+def test_mapping_step_lowers_the_window_loss():
+    """Targets rendered from the reference Gaussians on two views; the mapped
+    Gaussians start perturbed, and 40 mapping steps must lower the loss."""
+    from paper_2504_19409_amd.mapping import Mapper
+    from paper_2504_19409_amd.rasterizer import CameraSpec, Frame
+    from paper_2504_19409_amd.window import KeyframeWindow
+    rng = np.random.default_rng(71)
+    sc = sg.make_scene(3000, 96, 64, 70.0, 70.0, 48.0, 32.0, 8, seed=71, rng=rng)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+    vms = [sc.camera.viewmat, sg.perturbed_viewmat(rng, sc.camera.viewmat, 0.05, 3.0)[0]]
+    cam = CameraSpec(96, 64, 70.0, 70.0, 48.0, 32.0)
+    ref = dict(means=t(sc.means), log_scales=t(sc.log_scales), quats=t(sc.quats),
+               logit_opacity=t(sc.logit_opacity), rgb=t(sc.rgb))
+    feat_ref = t(sc.feat)
+    targets = []
+    for vm in vms:
+        fr = Frame(ref["means"], ref["log_scales"], ref["quats"], ref["logit_opacity"],
+                   ref["rgb"], feat_ref, t(vm), cam)
+        o = fr.forward()
+        targets.append([o[0].clone(), o[1].clone(), None, o[3].clone()])
+    geom = dict(means=t(sc.means + 0.01 * rng.normal(size=sc.means.shape)),
+                log_scales=t(sc.log_scales), quats=t(sc.quats),
+                logit_opacity=t(sc.logit_opacity + 0.5 * rng.normal(size=sc.P)),
+                rgb=t(np.clip(sc.rgb + 0.2 * rng.normal(size=sc.rgb.shape), 0, 1)))
+    feat = t(sc.feat + 0.3 * rng.normal(size=sc.feat.shape))
+    views = [(t(vm), cam) for vm in vms]
+    win = KeyframeWindow(geom, feat, views, targets, weights=(0.9, 0.1, 0.0, 1.0))
+    mp = Mapper(win, lam_reg=0.01)
+    losses = [float(mp.step().item()) for _ in range(40)]
+    for fr in win.frames:
+        assert fr.read_status()[0] == 0
+    print("mapping loss", losses[0], "->", losses[-1])
+    assert losses[-1] < 0.7 * losses[0]
