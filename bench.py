@@ -243,6 +243,35 @@ def mapping_rates(torch, fr, K):
             "adam_gbs": round(n * 28 / (t_adam * 1e-6) / 1e9, 1)}
 
 
+def query_rates(torch, fr, K):
+    """Decode + query (Eqs. 10, 12) of the frame's rendered features (BF16)
+    against 20 query vectors, beside the plain decode to the 512-channel map,
+    from HIP events around K launches of each."""
+    from paper_2504_19409_amd import decoder as dec
+    outs = fr.forward(out_feat_dtype=torch.bfloat16)
+    X = outs[3].reshape(16, -1)
+    n = X.shape[1]
+    params = dec.init_params(0)
+    g = torch.Generator(device="cpu").manual_seed(1)
+    Q = (torch.randn(20, 512, generator=g) / 20).cuda()
+    ws_dec = dec.workspace(n)
+
+    def timed(fn):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(K):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / K * 1e3
+
+    t_query = timed(lambda: dec.query(X, params, Q))
+    t_dec = timed(lambda: dec.forward(X, params, ws_dec))
+    return {"queries": 20, "pixels": n, "decode_query_us": round(t_query, 1),
+            "decode_512_map_us": round(t_dec, 1)}
+
+
 def algorithmic_work(scene, n_pairs, torch):
     """Per-stage algorithmic bytes (HBM) and the compositing evaluation counts
     from the oracle's exact work counts (pairs with support, alpha
@@ -365,11 +394,14 @@ def main():
     # the other SLAM passes on the same frame (Sec. 3.3): tracking iteration,
     # keyframe test, mapping step's regulariser and optimiser
     slam = {"tracking": tracking_rate(torch, fr, targets, K, args.warmup),
-            "keyframe": keyframe_rates(torch, fr, K), "mapping": mapping_rates(torch, fr, K)}
+            "keyframe": keyframe_rates(torch, fr, K), "mapping": mapping_rates(torch, fr, K),
+            "query": query_rates(torch, fr, K)}
     log("tracking iteration %.4f ms; visibility %.1f us, covisibility %.1f us; scale reg %.1f "
         "us, adam %.1f us" % (slam["tracking"]["ms_per_iter"], slam["keyframe"]["visibility_us"],
                               slam["keyframe"]["covisibility_us"],
                               slam["mapping"]["scale_reg_us"], slam["mapping"]["adam_us"]))
+    log("decode + query %.1f us (decode to the 512-channel map %.1f us)"
+        % (slam["query"]["decode_query_us"], slam["query"]["decode_512_map_us"]))
 
     wc, sizes = algorithmic_work(scene, n_pairs, torch)
     dom = max(ONE_KERNEL_STAGES, key=lambda s: stage_ms[s])

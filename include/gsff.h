@@ -428,6 +428,26 @@ gsff_status gsff_decoder_train_step(const void* X, const float* W1, const float*
                                     float* dW1, float* db1, float* dW2, float* db2, void* ws,
                                     size_t ws_bytes, void* stream);
 
+/* Decode + query (Eqs. 10 and 12): the label probabilities
+ *   p(l | x) = softmax_l( o(F)(x) . q(l) ),  o(F)(x) = GELU(X W1 + b1) W2 + b2,
+ * for K query vectors Q [K, 512] f32 (1 <= K <= 64), without forming the
+ * 512-channel map (the queries fold into the second layer; FP32 arithmetic).
+ * X bf16 [16, n_px], weights as gsff_decoder_forward.  Outputs, each may be
+ * NULL: prob [K, n_px] f32; label [n_px] int32, the label of the largest
+ * logit (the first of equal ones), the prediction of Eq. 10; and, with gt
+ * [n_px] int32 given, ce_loss (device [1]) = the cross-entropy of Eq. 9,
+ * (1/n_px) sum over the pixels whose gt lies in [0, K) of -log p(gt | x)
+ * (other pixels are left out of the sum, not of n_px).  gt and ce_loss come
+ * together.  ws: device scratch of gsff_decoder_query_workspace_size bytes,
+ * 16-byte aligned.  Errors: GSFF_ERR_INVALID_ARGUMENT for K outside [1, 64],
+ * n_px < 0, a NULL input, gt without ce_loss or the reverse, or a small or
+ * misaligned workspace. */
+gsff_status gsff_decoder_query_workspace_size(int32_t K, int64_t n_px, size_t* bytes);
+gsff_status gsff_decoder_query(const void* X, const float* W1, const float* b1, const float* W2,
+                               const float* b2, const float* Q, int32_t K, int64_t n_px,
+                               float* prob, int32_t* label, const int32_t* gt, float* ce_loss,
+                               void* ws, size_t ws_bytes, void* stream);
+
 /* L1 loss of one output group (the tracking / mapping / semantic losses,
  * Eqs. 5, 8 and 11, are weighted L1 terms): grad[i] = scale * sign(x[i] - y[i])
  * (0 where equal) and, if loss != NULL, *loss += scale * sum |x - y| (FP32

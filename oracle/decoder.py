@@ -73,3 +73,26 @@ def l1_backward(X, W1, b1, W2, b2, T, scale, bf16_points=True):
     dW1 = f["Xr"].T @ dZr
     dX = dZr @ f["W1r"].T
     return dict(loss=loss, dX=dX, dW1=dW1, db1=db1, dW2=dW2, db2=db2, Y=Y)
+
+
+def query(X, W1, b1, W2, b2, Q, gt=None):
+    """Decode, then query (Eqs. 9, 10, 12), FP64 with no rounding of the
+    weights or activations: Y = o(F) for X [n, 16]; logits = Y Q^T for the
+    K query vectors Q [K, 512]; p = softmax over the labels; the label of the
+    largest logit (the first of equal ones); with gt [n], the cross-entropy
+    (1/n) sum over the pixels with gt in [0, K) of -log p(gt).
+    Returns dict(logits [n, K], prob [n, K], label [n], loss)."""
+    Y = forward(X, W1, b1, W2, b2, bf16_points=False)["Y"]
+    logits = Y @ np.asarray(Q, np.float64).T
+    m = logits.max(axis=1, keepdims=True)
+    e = np.exp(logits - m)
+    prob = e / e.sum(axis=1, keepdims=True)
+    out = dict(logits=logits, prob=prob, label=np.argmax(logits, axis=1), loss=None)
+    if gt is not None:
+        gt = np.asarray(gt)
+        K = logits.shape[1]
+        ok = (gt >= 0) & (gt < K)
+        idx = np.where(ok, gt, 0)
+        nll = -np.log(prob[np.arange(len(gt)), idx])
+        out["loss"] = float(np.where(ok, nll, 0.0).sum() / len(gt))
+    return out

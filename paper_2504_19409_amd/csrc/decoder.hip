@@ -382,6 +382,121 @@ __global__ __launch_bounds__(256) void k_dec_reduce(const float* __restrict__ pa
     db[e - nw] = scale_b * acc;
 }
 
+
+// ---- decode + query (Eqs. 10 and 12) ----------------------------------------
+//
+// p(l | x) = softmax over the K labels of o(F)(x) . q(l): the dot product with
+// the queries is linear, so it folds into the second layer,
+//   logits = GELU(X W1 + b1) (W2 Q^T) + b2 Q^T,
+// and the 512-channel map is never formed.  FP32 throughout: the folded
+// weights (128 x K, K <= 64) and W1 sit in LDS and every lane reads the same
+// word (broadcast); one thread per pixel walks the 128 hidden units, adding
+// each one's share to its K logits.  Outputs: probabilities [K, n], the label
+// of the largest logit (the first of equal ones) [n], and the cross-entropy
+// against given labels (Eq. 9), as per-block partials summed in block order.
+constexpr int kQueryMaxK = 64;
+constexpr int kQueryBlock = 256;
+
+__global__ __launch_bounds__(256) void k_query_fold(const float* __restrict__ W2,
+                                                    const float* __restrict__ b2,
+                                                    const float* __restrict__ Q, int K, int KP,
+                                                    float* __restrict__ w2q,
+                                                    float* __restrict__ b2q) {
+  // w2q [128][KP] (zero past K), b2q [KP]
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= (kHid + 1) * KP) return;
+  const int j = e / KP, k = e % KP;
+  float acc = 0.f;
+  if (k < K) {
+    const float* row = j < kHid ? W2 + (int64_t)j * kOut : b2;
+    const float* q = Q + (int64_t)k * kOut;
+    for (int c = 0; c < kOut; ++c) acc = __builtin_fmaf(row[c], q[c], acc);
+  }
+  if (j < kHid)
+    w2q[j * KP + k] = acc;
+  else
+    b2q[k] = acc;
+}
+
+template <int KP>
+__global__ __launch_bounds__(kQueryBlock) void k_query(
+    const __bf16* __restrict__ X, const float* __restrict__ W1, const float* __restrict__ b1,
+    const float* __restrict__ w2q, const float* __restrict__ b2q, int K, int64_t n,
+    float* __restrict__ prob, int32_t* __restrict__ label, const int32_t* __restrict__ gt,
+    float* __restrict__ ce_part) {
+  __shared__ float s_w1[kLat * kHid], s_b1[kHid], s_w2[kHid * KP], s_b2[KP];
+  __shared__ float s_red[kQueryBlock / 64];
+  for (int e = threadIdx.x; e < kLat * kHid; e += kQueryBlock) s_w1[e] = W1[e];
+  for (int e = threadIdx.x; e < kHid * KP; e += kQueryBlock) s_w2[e] = w2q[e];
+  if (threadIdx.x < kHid) s_b1[threadIdx.x] = b1[threadIdx.x];
+  if (threadIdx.x < KP) s_b2[threadIdx.x] = b2q[threadIdx.x];
+  __syncthreads();
+  const int64_t p = (int64_t)blockIdx.x * kQueryBlock + threadIdx.x;
+  float ce = 0.f;
+  if (p < n) {
+    float x[kLat];
+#pragma unroll
+    for (int i = 0; i < kLat; ++i) x[i] = (float)X[(int64_t)i * n + p];
+    float lg[KP];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) lg[k] = s_b2[k];
+    for (int j = 0; j < kHid; ++j) {
+      float z = s_b1[j];
+#pragma unroll
+      for (int i = 0; i < kLat; ++i) z = __builtin_fmaf(x[i], s_w1[i * kHid + j], z);
+      const float h = gelu_f(z);
+#pragma unroll
+      for (int k = 0; k < KP; ++k) lg[k] = __builtin_fmaf(h, s_w2[j * KP + k], lg[k]);
+    }
+    float m = lg[0];
+    int arg = 0;
+#pragma unroll
+    for (int k = 1; k < KP; ++k)
+      if (k < K && lg[k] > m) {
+        m = lg[k];
+        arg = k;
+      }
+    float z = 0.f;
+#pragma unroll
+    for (int k = 0; k < KP; ++k) z += k < K ? __expf(lg[k] - m) : 0.f;
+    if (prob) {
+      const float inv = 1.f / z;
+#pragma unroll
+      for (int k = 0; k < KP; ++k)
+        if (k < K) prob[(int64_t)k * n + p] = __expf(lg[k] - m) * inv;
+    }
+    if (label) label[p] = arg;
+    if (gt) {
+      const int l = gt[p];
+      float lgt = 0.f;
+#pragma unroll
+      for (int k = 0; k < KP; ++k) lgt = k == l ? lg[k] : lgt;
+      if (l >= 0 && l < K) ce = (m + __logf(z)) - lgt;  // -log p(l | x)
+    }
+  }
+  if (ce_part) {
+    float v = ce;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) ce_part[blockIdx.x] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+  }
+}
+
+// the loss: the blocks' partials in block order, over n pixels
+__global__ __launch_bounds__(256) void k_query_ce(const float* __restrict__ part, int nb,
+                                                  int64_t n, float* __restrict__ loss) {
+  __shared__ double s_red[4];
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) v += part[b];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) *loss = (float)(((s_red[0] + s_red[1]) + (s_red[2] + s_red[3])) / (double)n);
+}
+
 }  // namespace gsff
 
 using namespace gsff;
@@ -468,4 +583,53 @@ gsff_status gsff_decoder_train_step(const void* X, const float* W1, const float*
   return hipGetLastError() == hipSuccess ? GSFF_OK : GSFF_ERR_HIP;
 }
 
+
+gsff_status gsff_decoder_query_workspace_size(int32_t K, int64_t n_px, size_t* bytes) {
+  if (!bytes || K < 1 || K > kQueryMaxK || n_px < 0) return GSFF_ERR_INVALID_ARGUMENT;
+  const int64_t nb = (n_px + kQueryBlock - 1) / kQueryBlock;
+  *bytes = (size_t)(4 * ((kHid + 1) * kQueryMaxK + nb));
+  return GSFF_OK;
+}
+
+gsff_status gsff_decoder_query(const void* X, const float* W1, const float* b1, const float* W2,
+                               const float* b2, const float* Q, int32_t K, int64_t n_px,
+                               float* prob, int32_t* label, const int32_t* gt, float* ce_loss,
+                               void* ws, size_t ws_bytes, void* stream) {
+  if (K < 1 || K > kQueryMaxK || n_px < 0 || !ws || !W1 || !b1 || !W2 || !b2 || !Q ||
+      (n_px > 0 && !X) || ((gt == nullptr) != (ce_loss == nullptr)))
+    return GSFF_ERR_INVALID_ARGUMENT;
+  if (((uintptr_t)ws & 15u) != 0) return GSFF_ERR_INVALID_ARGUMENT;
+  size_t need = 0;
+  gsff_decoder_query_workspace_size(K, n_px, &need);
+  if (ws_bytes < need) return GSFF_ERR_INVALID_ARGUMENT;
+  hipStream_t s = (hipStream_t)stream;
+  const int KP = K <= 8 ? 8 : (K <= 16 ? 16 : (K <= 32 ? 32 : 64));
+  float* w2q = (float*)ws;
+  float* b2q = w2q + kHid * KP;
+  float* part = (float*)ws + (kHid + 1) * kQueryMaxK;
+  hipLaunchKernelGGL(k_query_fold, dim3((unsigned)(((kHid + 1) * KP + 255) / 256)), dim3(256), 0,
+                     s, W2, b2, Q, (int)K, KP, w2q, b2q);
+  const int64_t nb = (n_px + kQueryBlock - 1) / kQueryBlock;
+  if (nb > 0) {
+    float* cp = gt ? part : nullptr;
+#define GSFF_QUERY(KPV)                                                                         \
+  hipLaunchKernelGGL(k_query<KPV>, dim3((unsigned)nb), dim3(kQueryBlock), 0, s,                \
+                     (const __bf16*)X, W1, b1, (const float*)w2q, (const float*)b2q, (int)K, n_px, \
+                     prob, label, gt, cp)
+    if (KP == 8) GSFF_QUERY(8);
+    else if (KP == 16) GSFF_QUERY(16);
+    else if (KP == 32) GSFF_QUERY(32);
+    else GSFF_QUERY(64);
+#undef GSFF_QUERY
+  }
+  if (ce_loss) {
+    if (nb > 0)
+      hipLaunchKernelGGL(k_query_ce, dim3(1), dim3(256), 0, s, (const float*)part, (int)nb, n_px,
+                         ce_loss);
+    else
+      hipLaunchKernelGGL(k_query_ce, dim3(1), dim3(256), 0, s, (const float*)part, 0, (int64_t)1,
+                         ce_loss);
+  }
+  return hipGetLastError() == hipSuccess ? GSFF_OK : GSFF_ERR_HIP;
+}
 }  // extern "C"

@@ -47,6 +47,30 @@ def forward(X: torch.Tensor, params: dict, ws: torch.Tensor, out_dtype=torch.bfl
     return Y
 
 
+def query(X: torch.Tensor, params: dict, Q: torch.Tensor, with_prob=True, with_label=True,
+          gt: torch.Tensor | None = None, ws: torch.Tensor | None = None):
+    """Label probabilities [K, n_px] (Eq. 12), labels [n_px] (Eq. 10) and, with
+    ground-truth labels gt [n_px] int32, the cross-entropy (Eq. 9) of the
+    decoded features X bf16 [16, n_px] against queries Q [K, 512], without
+    forming the 512-channel map.  Returns (prob, label, loss); absent ones None."""
+    assert X.dtype == torch.bfloat16 and X.is_contiguous() and X.shape[0] == LATENT
+    assert Q.dtype == torch.float32 and Q.is_contiguous() and Q.shape[1] == OUT
+    n, K, dev = X.shape[1], Q.shape[0], X.device
+    if ws is None:
+        nb = ctypes.c_size_t(0)
+        _capi.check(_capi.load().gsff_decoder_query_workspace_size(K, n, ctypes.byref(nb)),
+                    "gsff_decoder_query_workspace_size")
+        ws = torch.empty(int(nb.value), dtype=torch.uint8, device=dev)
+    prob = torch.empty((K, n), device=dev) if with_prob else None
+    label = torch.empty(n, dtype=torch.int32, device=dev) if with_label else None
+    loss = torch.empty(1, device=dev) if gt is not None else None
+    _capi.check(_capi.load().gsff_decoder_query(
+        _p(X), _p(params["W1"]), _p(params["b1"]), _p(params["W2"]), _p(params["b2"]), _p(Q), K,
+        n, _p(prob), _p(label), _p(gt), _p(loss), _p(ws), ws.numel(), _stream()),
+        "gsff_decoder_query")
+    return prob, label, loss
+
+
 def train_step(X: torch.Tensor, params: dict, T: torch.Tensor, ws: torch.Tensor,
                scale: float | None = None, loss: torch.Tensor | None = None):
     """Fused forward + L1 + backward.  Returns dict(dX, dW1, db1, dW2, db2)."""

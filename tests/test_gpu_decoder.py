@@ -95,3 +95,41 @@ def test_decoder_full_frame_sampled():
     assert H.rel_l2(g["dX"].cpu().numpy()[:, pick], r["dX"].T[:, pick]) <= 1e-3
     for name in ["dW1", "db1", "dW2", "db2"]:
         assert H.rel_l2(g[name].cpu().numpy(), r[name]) <= 1e-3, name
+
+
+# ---- decode + query (Eqs. 9, 10, 12) ----------------------------------------
+
+@pytest.mark.parametrize("n,K", [(3000, 5), (1000, 20), (257, 64), (1, 1), (640 * 480, 20)])
+def test_query_matches_oracle(n, K):
+    """Probabilities to 2e-5 (FP32 vs FP64, relative L2), the cross-entropy to
+    1e-5; labels equal wherever the oracle's two largest logits are further
+    apart than the FP32 error of a logit (3e-5 of the pixel's largest
+    |logit|: a sum of 128 FP32 products through the folded weights)."""
+    from paper_2504_19409_amd import decoder as dec
+    Xb, p, npp, rng = _problem(n, 100 + K)
+    Q = (rng.normal(size=(K, 512)) / 20).astype(np.float32)
+    gt = rng.integers(-1, K, size=n).astype(np.int32)
+    prob, label, loss = dec.query(Xb, p, torch.from_numpy(Q).cuda(),
+                                  gt=torch.from_numpy(gt).cuda())
+    torch.cuda.synchronize()
+    X = Xb.float().cpu().numpy().astype(np.float64).T  # the BF16 values, exactly
+    r = ref.query(X, npp["W1"], npp["b1"], npp["W2"], npp["b2"], Q.astype(np.float64), gt=gt)
+    assert H.rel_l2(prob.cpu().numpy().T, r["prob"]) <= 2e-5
+    assert loss.item() == pytest.approx(r["loss"], rel=1e-5)
+    lg = np.sort(r["logits"], axis=1)
+    scale = np.abs(r["logits"]).max(axis=1)
+    clear = (lg[:, -1] - lg[:, -2]) > 3e-5 * scale if K > 1 else np.ones(n, bool)
+    assert (~clear).sum() <= max(2, n // 500), int((~clear).sum())
+    assert np.array_equal(label.cpu().numpy()[clear], r["label"][clear])
+
+
+def test_query_outputs_are_optional():
+    from paper_2504_19409_amd import decoder as dec
+    Xb, p, npp, rng = _problem(500, 7)
+    Q = torch.from_numpy((rng.normal(size=(3, 512)) / 20).astype(np.float32)).cuda()
+    pr, lb, ls = dec.query(Xb, p, Q)
+    pr2, lb2, ls2 = dec.query(Xb, p, Q, with_prob=False)
+    _, lb3, _ = dec.query(Xb, p, Q, with_label=True, with_prob=True)
+    torch.cuda.synchronize()
+    assert ls is None and ls2 is None and pr2 is None
+    assert torch.equal(lb, lb2) and torch.equal(lb, lb3)

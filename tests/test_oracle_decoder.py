@@ -115,3 +115,46 @@ def test_rounding_is_identity_on_bf16_inputs():
     np.testing.assert_array_equal(a["Z"], b["Z"])
     # only the hidden layer's rounding separates the two
     np.testing.assert_array_equal(a["H"], dec.bf16(b["H"]))
+
+
+# ---- decode + query (Eqs. 9, 10, 12) ----------------------------------------
+
+def _query_case(rng, n=50, K=6):
+    X = rng.normal(size=(n, 16))
+    W1, b1 = rng.normal(size=(16, 128)) / 4, rng.normal(size=128) * 0.1
+    W2, b2 = rng.normal(size=(128, 512)) / 11, rng.normal(size=512) * 0.1
+    Q = rng.normal(size=(K, 512)) / 20
+    return X, W1, b1, W2, b2, Q
+
+
+def test_query_unit_queries_read_decoder_channels():
+    """Queries that are unit vectors e_c give the decoder's channel c as the
+    logits, so the query reads the same map the decoder writes."""
+    rng = np.random.default_rng(1)
+    X, W1, b1, W2, b2, _ = _query_case(rng)
+    chans = [0, 17, 300, 511]
+    Q = np.eye(512)[chans]
+    r = dec.query(X, W1, b1, W2, b2, Q)
+    Y = dec.forward(X, W1, b1, W2, b2, bf16_points=False)["Y"]
+    np.testing.assert_allclose(r["logits"], Y[:, chans], rtol=1e-13, atol=1e-13)
+    np.testing.assert_array_equal(r["label"], np.argmax(Y[:, chans], axis=1))
+
+
+def test_query_softmax_and_cross_entropy_closed_forms():
+    rng = np.random.default_rng(2)
+    X, W1, b1, W2, b2, Q = _query_case(rng, K=7)
+    r = dec.query(X, W1, b1, W2, b2, Q)
+    np.testing.assert_allclose(r["prob"].sum(axis=1), 1.0, rtol=1e-14)
+    assert np.all(r["prob"] > 0)
+    # one label: probability 1; equal queries: uniform, cross-entropy log K
+    r1 = dec.query(X, W1, b1, W2, b2, Q[:1])
+    np.testing.assert_allclose(r1["prob"], 1.0, rtol=1e-15)
+    gt = rng.integers(0, 7, size=X.shape[0])
+    ru = dec.query(X, W1, b1, W2, b2, np.tile(Q[:1], (7, 1)), gt=gt)
+    assert ru["loss"] == pytest.approx(np.log(7.0), rel=1e-13)
+    assert np.all(ru["label"] == 0)  # ties go to the first label
+    # pixels whose label is out of range stay out of the sum, not of n
+    gt2 = gt.copy()
+    gt2[::2] = -1
+    r2 = dec.query(X, W1, b1, W2, b2, np.tile(Q[:1], (7, 1)), gt=gt2)
+    assert r2["loss"] == pytest.approx(np.log(7.0) * (gt2 >= 0).sum() / len(gt2), rel=1e-13)
