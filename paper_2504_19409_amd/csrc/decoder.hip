@@ -389,33 +389,47 @@ __global__ __launch_bounds__(256) void k_dec_reduce(const float* __restrict__ pa
 // the queries is linear, so it folds into the second layer,
 //   logits = GELU(X W1 + b1) (W2 Q^T) + b2 Q^T,
 // and the 512-channel map is never formed.  FP32 throughout: the folded
-// weights (128 x K, K <= 64) and W1 sit in LDS and every lane reads the same
-// word (broadcast); one thread per pixel walks the 128 hidden units, adding
-// each one's share to its K logits.  Outputs: probabilities [K, n], the label
+// weights (128 x K padded to 8, 16, 24, 32, 48 or 64 columns) and W1 sit in
+// LDS and every lane reads the same word (broadcast); one thread per pixel
+// walks the 128 hidden units, adding each one's share to its K logits.  Outputs: probabilities [K, n], the label
 // of the largest logit (the first of equal ones) [n], and the cross-entropy
 // against given labels (Eq. 9), as per-block partials summed in block order.
 constexpr int kQueryMaxK = 64;
 constexpr int kQueryBlock = 256;
 
+// one wave per folded weight: lanes take 8 of the 512 channels each
 __global__ __launch_bounds__(256) void k_query_fold(const float* __restrict__ W2,
                                                     const float* __restrict__ b2,
                                                     const float* __restrict__ Q, int K, int KP,
                                                     float* __restrict__ w2q,
                                                     float* __restrict__ b2q) {
   // w2q [128][KP] (zero past K), b2q [KP]
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  if (e >= (kHid + 1) * KP) return;
+  const int e = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (e >= (kHid + 1) * KP) return;  // uniform in the wave
   const int j = e / KP, k = e % KP;
   float acc = 0.f;
   if (k < K) {
     const float* row = j < kHid ? W2 + (int64_t)j * kOut : b2;
     const float* q = Q + (int64_t)k * kOut;
-    for (int c = 0; c < kOut; ++c) acc = __builtin_fmaf(row[c], q[c], acc);
+#pragma unroll
+    for (int t = 0; t < kOut / 64; ++t) acc = __builtin_fmaf(row[64 * t + lane], q[64 * t + lane], acc);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
   }
-  if (j < kHid)
-    w2q[j * KP + k] = acc;
-  else
-    b2q[k] = acc;
+  if (lane == 0) {
+    if (j < kHid)
+      w2q[j * KP + k] = acc;
+    else
+      b2q[k] = acc;
+  }
+}
+
+// GELU as the decoder's, with tanh(u) = 1 - 2 / (exp(2u) + 1) through the
+// fast divide (a few ulp; the query path is FP32 throughout)
+__device__ __forceinline__ float gelu_q(float z) {
+  const float u = 0.7978845608028654f * (z + 0.044715f * z * z * z);
+  const float t = 1.f - __fdividef(2.f, __expf(2.f * u) + 1.f);
+  return 0.5f * z * (1.f + t);
 }
 
 template <int KP>
@@ -444,7 +458,7 @@ __global__ __launch_bounds__(kQueryBlock) void k_query(
       float z = s_b1[j];
 #pragma unroll
       for (int i = 0; i < kLat; ++i) z = __builtin_fmaf(x[i], s_w1[i * kHid + j], z);
-      const float h = gelu_f(z);
+      const float h = gelu_q(z);
 #pragma unroll
       for (int k = 0; k < KP; ++k) lg[k] = __builtin_fmaf(h, s_w2[j * KP + k], lg[k]);
     }
@@ -603,12 +617,12 @@ gsff_status gsff_decoder_query(const void* X, const float* W1, const float* b1, 
   gsff_decoder_query_workspace_size(K, n_px, &need);
   if (ws_bytes < need) return GSFF_ERR_INVALID_ARGUMENT;
   hipStream_t s = (hipStream_t)stream;
-  const int KP = K <= 8 ? 8 : (K <= 16 ? 16 : (K <= 32 ? 32 : 64));
+  const int KP = K <= 8 ? 8 : (K <= 16 ? 16 : (K <= 24 ? 24 : (K <= 32 ? 32 : (K <= 48 ? 48 : 64))));
   float* w2q = (float*)ws;
   float* b2q = w2q + kHid * KP;
   float* part = (float*)ws + (kHid + 1) * kQueryMaxK;
-  hipLaunchKernelGGL(k_query_fold, dim3((unsigned)(((kHid + 1) * KP + 255) / 256)), dim3(256), 0,
-                     s, W2, b2, Q, (int)K, KP, w2q, b2q);
+  hipLaunchKernelGGL(k_query_fold, dim3((unsigned)(((kHid + 1) * KP + 3) / 4)), dim3(256), 0, s,
+                     W2, b2, Q, (int)K, KP, w2q, b2q);
   const int64_t nb = (n_px + kQueryBlock - 1) / kQueryBlock;
   if (nb > 0) {
     float* cp = gt ? part : nullptr;
@@ -618,7 +632,9 @@ gsff_status gsff_decoder_query(const void* X, const float* W1, const float* b1, 
                      prob, label, gt, cp)
     if (KP == 8) GSFF_QUERY(8);
     else if (KP == 16) GSFF_QUERY(16);
+    else if (KP == 24) GSFF_QUERY(24);
     else if (KP == 32) GSFF_QUERY(32);
+    else if (KP == 48) GSFF_QUERY(48);
     else GSFF_QUERY(64);
 #undef GSFF_QUERY
   }
