@@ -108,6 +108,7 @@ bool compute_layout(int64_t P, int32_t C, int64_t max_pairs, int32_t W, int32_t 
   l.l1_codes = take(4ull * (1 + (C + 15) / 16) * HW);
   l.loss_part = take(4ull * ((HW + 255) / 256));
   l.slot_local = take(4ull * P);
+  l.slot_cnt = take(4ull * (uint64_t)(l.pose_blocks + 1));
   l.slot_blk = take(4ull * (uint64_t)(l.pose_blocks + 1));
   l.nslot = take(4ull * P);
   // slots: a Gaussian's range is its rectangle's tile count, so all of them
@@ -160,6 +161,7 @@ WsView make_view(void* ws, const Layout& L) {
   w.tile_walk = (uint32_t*)(b + L.tile_walk);
   w.walk_off = (uint32_t*)(b + L.walk_off);
   w.slot_local = (uint32_t*)(b + L.slot_local);
+  w.slot_cnt = (uint32_t*)(b + L.slot_cnt);
   w.slot_blk = (uint32_t*)(b + L.slot_blk);
   w.nslot = (uint32_t*)(b + L.nslot);
   w.slots = (uint32_t*)(b + L.slots);

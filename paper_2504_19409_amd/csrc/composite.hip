@@ -768,13 +768,33 @@ __device__ void build_adjoint_items(const WsView& w, int ntiles, uint32_t max_pa
   if (tid == 0) w.seg_n[0] = min(sm.total, cap);
 }
 
-__global__ __launch_bounds__(1024) void k_walk_scan(WsView w, int ntiles, uint32_t max_pairs) {
+// The adjoint's slot bases: slot_blk = the exclusive scan of the preprocess's
+// per-block slot counts (one workgroup of NT threads; rerun by every adjoint,
+// so a second adjoint of the same forward finds the same bases).
+template <int NT>
+__device__ void scan_slot_blocks(const WsView& w, int nblk, uint32_t* part) {
+  uint32_t carry = 0;
+  for (int b = 0; b < nblk; b += NT) {
+    const int k = b + (int)threadIdx.x;
+    const uint32_t v = k < nblk ? w.slot_cnt[k] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_u32<NT>(v, tot, part);
+    if (k < nblk) w.slot_blk[k] = carry + ex;
+    carry += tot;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_walk_scan(WsView w, int ntiles, uint32_t max_pairs,
+                                                    int nslot_blk) {
   __shared__ ItemScratch sm;
   build_adjoint_items<1024>(w, ntiles, max_pairs, sm);
+  __syncthreads();
+  scan_slot_blocks<1024>(w, nslot_blk, sm.part);
 }
 
 hipError_t launch_adjoint_items(const Layout& L, const WsView& w, hipStream_t s) {
-  hipLaunchKernelGGL(k_walk_scan, dim3(1), dim3(1024), 0, s, w, L.ntiles, (uint32_t)L.max_pairs);
+  hipLaunchKernelGGL(k_walk_scan, dim3(1), dim3(1024), 0, s, w, L.ntiles, (uint32_t)L.max_pairs,
+                     (int)(L.P > 0 ? L.pose_blocks : 0));
   return hipGetLastError();
 }
 
@@ -1009,11 +1029,12 @@ struct L1Upstream {
 // pass also adds the loss.
 //
 // The same launch does the adjoint's other set-up, which shares no data with
-// the codes: its first workgroup builds the work items (one workgroup of
-// dependent steps, which would otherwise be a launch of its own on the
-// critical path) and, for a call that does not accumulate, sets the loss to
-// zero (loss_zero; the adjoint then adds it) while the code workgroups clear
-// the feature gradient (n_zero floats at zero).
+// the codes: its first workgroup builds the work items and its second scans
+// the slot bases (each a workgroup of dependent steps, which would otherwise
+// be a launch of its own on the critical path); for a call that does not
+// accumulate, the first sets the loss to zero (loss_zero; the adjoint then
+// adds it) while the code workgroups clear the feature gradient (n_zero
+// floats at zero).
 __device__ __forceinline__ uint32_t l1_code(float o, float t, float scale, float& l) {
   const float d = o - t;
   l += fabsf(d) * scale;
@@ -1028,7 +1049,7 @@ __global__ __launch_bounds__(256) void k_l1_codes(L1Upstream l1, int64_t HW, int
                                                   float* __restrict__ loss_part, WsView w,
                                                   int ntiles, uint32_t max_pairs,
                                                   float* __restrict__ zero, int64_t n_zero,
-                                                  float* __restrict__ loss_zero) {
+                                                  float* __restrict__ loss_zero, int nslot_blk) {
   __shared__ float s_l[4];
   __shared__ ItemScratch s_items;
   if (blockIdx.x == 0) {  // uniform
@@ -1036,7 +1057,11 @@ __global__ __launch_bounds__(256) void k_l1_codes(L1Upstream l1, int64_t HW, int
     build_adjoint_items<256>(w, ntiles, max_pairs, s_items);
     return;
   }
-  const int64_t wg = (int64_t)blockIdx.x - 1, nwg = (int64_t)gridDim.x - 1;
+  if (blockIdx.x == 1) {  // uniform
+    scan_slot_blocks<256>(w, nslot_blk, s_items.part);
+    return;
+  }
+  const int64_t wg = (int64_t)blockIdx.x - 2, nwg = (int64_t)gridDim.x - 2;
   const int64_t p = wg * 256 + threadIdx.x;
   float loss = 0.f;
   if (p < HW) {
@@ -1740,9 +1765,10 @@ hipError_t launch_composite_bwd_l1(const DevGaussians& g, const DevSettings& st,
   const int64_t n_zero = (d_feat && !accumulate && L.P > 0 && g.C > 0) ? L.P * g.C : 0;
   // (at least one code workgroup, for the clearing)
   const int64_t ncode = npx > 0 ? (npx + 255) / 256 : 1;
-  hipLaunchKernelGGL(k_l1_codes, dim3((unsigned)(1 + ncode)), dim3(256), 0, s, u,
+  hipLaunchKernelGGL(k_l1_codes, dim3((unsigned)(2 + ncode)), dim3(256), 0, s, u,
                      npx, g.C, w.l1_codes, w.loss_part, w, L.ntiles, (uint32_t)L.max_pairs,
-                     d_feat, n_zero, accumulate ? nullptr : a.loss);
+                     d_feat, n_zero, accumulate ? nullptr : a.loss,
+                     (int)(L.P > 0 ? L.pose_blocks : 0));
   return launch_composite_bwd_impl(g, st, L, w, nullptr, nullptr, nullptr, nullptr, geometry,
                                    d_feat, accumulate, &u, s);
 }

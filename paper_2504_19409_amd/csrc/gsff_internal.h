@@ -55,7 +55,7 @@ struct Layout {
            dids_b = 0, offsets = 0, pkeys_a = 0, pkeys_b = 0, tile_ranges = 0, pix_T = 0,
            pix_end = 0, grad2d = 0, hist = 0, hist_tot = 0, scan_part = 0, pose_part = 0,
            binhist = 0, tile_tot = 0, curbase = 0, rows = 0, tile_walk = 0, walk_off = 0,
-           slot_local = 0, slot_blk = 0, nslot = 0, slots = 0, item_n = 0, items = 0,
+           slot_local = 0, slot_cnt = 0, slot_blk = 0, nslot = 0, slots = 0, item_n = 0, items = 0,
            seg_order = 0, seg_n = 0, seg_state = 0, seg_final = 0, l1_codes = 0, loss_part = 0, sort_part = 0, sort_lb = 0, sort_ctr = 0, total = 0;
 };
 
@@ -109,7 +109,8 @@ struct WsView {
   uint32_t* l1_codes;    // [1 + ceil(C / 16)][H*W] the L1 upstream in 2-bit codes
   float* loss_part;      // [ceil(H*W / 256)] the L1 loss per 256 pixels
   uint32_t* slot_local;  // [P] first slot of each Gaussian inside its 256-Gaussian block
-  uint32_t* slot_blk;    // [P/256]: slot count of each block, then its first slot
+  uint32_t* slot_cnt;    // [P/256]: slot count of each 256-Gaussian block (preprocess)
+  uint32_t* slot_blk;    // [P/256]: first slot of each block (scanned by the adjoint's set-up)
   uint32_t* nslot;       // [P] slots filled per Gaussian
   uint32_t* slots;       // [slot_cap] row index per filed (tile, Gaussian) pair
   uint32_t* item_n;      // [1] work items filed

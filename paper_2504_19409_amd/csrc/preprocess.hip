@@ -74,7 +74,8 @@ __global__ __launch_bounds__(256) void k_preprocess(DevGaussians g, DevCamera ca
     ntile = (uint32_t)(rect.z - rect.x + 1) * (uint32_t)(rect.w - rect.y + 1);
   }
   // slots for the adjoint: a Gaussian gets one per tile of its rectangle;
-  // block-local exclusive offsets here, the block bases in k_slot_scan
+  // block-local exclusive offsets and the block's count here, the block bases
+  // in the adjoint's set-up (a scan of the counts, repeated by every adjoint)
   __shared__ uint32_t s_ws[4];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   uint32_t inc = ntile;
@@ -92,34 +93,7 @@ __global__ __launch_bounds__(256) void k_preprocess(DevGaussians g, DevCamera ca
     tot += s_ws[k];
   }
   if (i < P) w.slot_local[i] = pre + inc - ntile;
-  if (threadIdx.x == 0) w.slot_blk[blockIdx.x] = tot;
-}
-
-// One block: exclusive scan of the per-block slot counts into block bases.
-__global__ __launch_bounds__(1024) void k_slot_scan(WsView w, int nblk) {
-  __shared__ uint32_t s_w[16];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  uint32_t carry = 0;
-  for (int b = 0; b < nblk; b += 1024) {
-    const int k = b + threadIdx.x;
-    const uint32_t v = k < nblk ? w.slot_blk[k] : 0u;
-    uint32_t inc = v;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const uint32_t t = __shfl_up(inc, off, 64);
-      if (lane >= off) inc += t;
-    }
-    if (lane == 63) s_w[wv] = inc;
-    __syncthreads();
-    uint32_t pre = 0, tot = 0;
-    for (int q = 0; q < 16; ++q) {
-      if (q < wv) pre += s_w[q];
-      tot += s_w[q];
-    }
-    __syncthreads();
-    if (k < nblk) w.slot_blk[k] = carry + pre + inc - v;
-    carry += tot;
-  }
+  if (threadIdx.x == 0) w.slot_cnt[blockIdx.x] = tot;
 }
 
 // Sum of the adjoint rows, one wave per work item (a Gaussian and 64 of its
@@ -352,8 +326,6 @@ hipError_t launch_preprocess(const DevGaussians& g, const DevCamera& cam, const 
                              const Layout& L, const WsView& w, hipStream_t s) {
   const int64_t blocks = g.P > 0 ? (g.P + 255) / 256 : 1;
   hipLaunchKernelGGL(k_preprocess, dim3((unsigned)blocks), dim3(256), 0, s, g, cam, st, w);
-  if (g.P > 0)
-    hipLaunchKernelGGL(k_slot_scan, dim3(1), dim3(1024), 0, s, w, (int)blocks);
   return hipGetLastError();
 }
 
