@@ -438,10 +438,11 @@ gsff_status gsff_decoder_train_step(const void* X, const float* W1, const float*
  * [n_px] int32 given, ce_loss (device [1]) = the cross-entropy of Eq. 9,
  * (1/n_px) sum over the pixels whose gt lies in [0, K) of -log p(gt | x)
  * (other pixels are left out of the sum, not of n_px).  gt and ce_loss come
- * together.  ws: device scratch of gsff_decoder_query_workspace_size bytes,
- * 16-byte aligned.  Errors: GSFF_ERR_INVALID_ARGUMENT for K outside [1, 64],
- * n_px < 0, a NULL input, gt without ce_loss or the reverse, or a small or
- * misaligned workspace. */
+ * together (with n_px = 0, ce_loss alone receives 0).  ws: device scratch of
+ * gsff_decoder_query_workspace_size bytes, 16-byte aligned.  Errors:
+ * GSFF_ERR_INVALID_ARGUMENT for K outside [1, 64], n_px < 0, a NULL input,
+ * gt without ce_loss or the reverse (n_px > 0), or a small or misaligned
+ * workspace. */
 gsff_status gsff_decoder_query_workspace_size(int32_t K, int64_t n_px, size_t* bytes);
 gsff_status gsff_decoder_query(const void* X, const float* W1, const float* b1, const float* W2,
                                const float* b2, const float* Q, int32_t K, int64_t n_px,

@@ -610,7 +610,7 @@ gsff_status gsff_decoder_query(const void* X, const float* W1, const float* b1, 
                                float* prob, int32_t* label, const int32_t* gt, float* ce_loss,
                                void* ws, size_t ws_bytes, void* stream) {
   if (K < 1 || K > kQueryMaxK || n_px < 0 || !ws || !W1 || !b1 || !W2 || !b2 || !Q ||
-      (n_px > 0 && !X) || ((gt == nullptr) != (ce_loss == nullptr)))
+      (n_px > 0 && (!X || (gt == nullptr) != (ce_loss == nullptr))))
     return GSFF_ERR_INVALID_ARGUMENT;
   if (((uintptr_t)ws & 15u) != 0) return GSFF_ERR_INVALID_ARGUMENT;
   size_t need = 0;

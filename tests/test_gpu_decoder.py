@@ -133,3 +133,15 @@ def test_query_outputs_are_optional():
     torch.cuda.synchronize()
     assert ls is None and ls2 is None and pr2 is None
     assert torch.equal(lb, lb2) and torch.equal(lb, lb3)
+
+
+def test_query_without_pixels():
+    """n_px = 0: nothing to label, the cross-entropy is 0."""
+    from paper_2504_19409_amd import decoder as dec
+    p = dec.init_params(3)
+    X = torch.empty((16, 0), dtype=torch.bfloat16, device="cuda")
+    Q = torch.ones((4, 512), device="cuda")
+    gt = torch.empty(0, dtype=torch.int32, device="cuda")
+    prob, label, loss = dec.query(X, p, Q, gt=gt)
+    torch.cuda.synchronize()
+    assert prob.shape == (4, 0) and label.shape == (0,) and loss.item() == 0.0

@@ -125,3 +125,27 @@ def test_keyframe_decision_from_two_poses():
     both, either = covisibility(v0, v1)
     assert 0 < either and both < either
     assert is_keyframe(v1, v0, 0.9) == (both / either < 0.9)
+
+
+def test_slam_passes_on_an_empty_scene():
+    """No Gaussians: the visibility record is empty, the tracking gradient and
+    loss are zero against any target, and the mapping passes accept the empty
+    parameter set."""
+    from paper_2504_19409_amd.mapping import adam_step
+    sc = sg.make_scene(0, 40, 30, 40.0, 40.0, 20.0, 15.0, 3, seed=1)
+    fr, _ = H.make_frame(sc, torch)
+    outs = fr.forward()
+    vis = fr.visibility(0.5)
+    assert vis.numel() == 0
+    t_rgb = torch.full((3, 30, 40), 0.5, device="cuda")
+    t_depth = torch.full((30, 40), 2.0, device="cuda")
+    d_pose = torch.full((6,), 3.0, device="cuda")
+    loss = torch.full((1,), 3.0, device="cuda")
+    fr.backward_tracking(outs, t_rgb, t_depth, None, None, 0.9, d_pose, loss)
+    torch.cuda.synchronize()
+    assert not torch.any(d_pose)
+    # the loss still counts the empty render against the target
+    assert loss.item() == pytest.approx(0.9 * 0.5 + 0.1 * 2.0, rel=1e-6)
+    e = torch.empty(0, device="cuda")
+    adam_step([(e, e, e, e, 1e-3)], 1)
+    torch.cuda.synchronize()
