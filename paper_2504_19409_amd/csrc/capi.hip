@@ -43,10 +43,11 @@ bool compute_layout(int64_t P, int32_t C, int64_t max_pairs, int32_t W, int32_t 
   l.nsuper = l.super_x * l.super_y;
   l.rank_bits = ceil_log2((uint64_t)(P < 2 ? 2 : P));
   l.tile_bits = ceil_log2((uint64_t)l.nsuper);
-  // direct binning keeps per-wave cursors (16 B per super-tile) and coverage
-  // masks (32 B per super-tile column and row) of a block in 64 KiB of LDS
+  // direct binning keeps per-wave cursors (16 B per super-tile), the tiles'
+  // first pairs (4 B per super-tile) and coverage masks (32 B per super-tile
+  // column and row) of a block in 64 KiB of LDS
   l.direct_bin = l.nsuper <= kMaxDirectTiles &&
-                 16ll * l.nsuper + 32ll * (l.super_x + l.super_y) <= 65536;
+                 20ll * l.nsuper + 32ll * (l.super_x + l.super_y) <= 65536 - 64;
   // the fallback path packs (super-tile, rank) into 32-bit keys
   l.sort_fits = l.rank_bits + l.tile_bits <= 32;
   if (!l.direct_bin && !l.sort_fits) return false;

@@ -619,63 +619,65 @@ __global__ __launch_bounds__(256) void k_bin_colscan(WsView w, int ntiles, int n
   if (lane == 0) w.tile_tot[t] = carry;
 }
 
-// one block: tile ranges from the tile totals, pair count and overflow flag
-__global__ __launch_bounds__(1024) void k_bin_tilescan(WsView w, int ntiles, uint64_t max_pairs) {
-  __shared__ uint64_t s_w[16];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+// Stable scatter of Gaussian ids into their tiles' segments.  Every
+// workgroup first scans the tile totals itself (a few hundred words) for the
+// tiles' first pairs; workgroup (0, 0) also writes the tile ranges, the pair
+// count and the overflow flag (an overflowing frame renders empty: every
+// range collapses and nothing is written).  Wave wv owns the block's ranks
+// [64 wv, 64 wv + 64); its cursors start after the pairs of lower waves, and
+// every pair's place follows from the coverage masks, so each lane walks its
+// own rectangle with no ordering between lanes.  The rank chunk's tile rows
+// are split into gridDim.y bands, one workgroup each: the nearest chunks hold
+// the largest rectangles, and a band is a fraction of their walk.
+__global__ __launch_bounds__(256) void k_bin_scatter(WsView w, int64_t P, int ntiles,
+                                                     int tiles_x, int tiles_y, int nblk,
+                                                     uint32_t max_pairs) {
+  // [4][tiles_x + tiles_y] masks, then [4][band tiles] cursors, then [ntiles] starts
+  extern __shared__ uint64_t s_m[];
+  __shared__ uint64_t s_wsum[4];
+  const int wv = threadIdx.x >> 6, TM = tiles_x + tiles_y, lane = threadIdx.x & 63;
+  const int nband = (int)gridDim.y;
+  const int band_rows = (tiles_y + nband - 1) / nband;
+  uint32_t* s_c = reinterpret_cast<uint32_t*>(s_m + 4 * TM);
+  uint32_t* s_st = s_c + 4 * band_rows * tiles_x;
+  // the tiles' first pairs: an exclusive scan of the tile totals
   uint64_t carry = 0;
-  for (int b = 0; b < ntiles; b += 1024) {
-    const int i = b + threadIdx.x;
-    const uint64_t v = (i < ntiles) ? (uint64_t)w.tile_tot[i] : 0ull;
+  for (int b0 = 0; b0 < ntiles; b0 += 256) {
+    const int i = b0 + (int)threadIdx.x;
+    const uint64_t v = i < ntiles ? (uint64_t)w.tile_tot[i] : 0ull;
     uint64_t inc = v;
+#pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
       const uint64_t t = __shfl_up(inc, off, 64);
       if (lane >= off) inc += t;
     }
-    if (lane == 63) s_w[wv] = inc;
+    if (lane == 63) s_wsum[wv] = inc;
     __syncthreads();
     uint64_t pre = 0, tot = 0;
-    for (int k = 0; k < 16; ++k) {
-      if (k < wv) pre += s_w[k];
-      tot += s_w[k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (k < wv) pre += s_wsum[k];
+      tot += s_wsum[k];
     }
     __syncthreads();
-    if (i < ntiles) {
-      const uint64_t st = carry + pre + inc - v;
-      const uint64_t en = st + v;
-      const bool fits = en <= max_pairs;
-      w.tile_ranges[i] = fits ? make_uint2((uint32_t)st, (uint32_t)en) : make_uint2(0u, 0u);
-    }
+    if (i < ntiles) s_st[i] = (uint32_t)(carry + pre + inc - v);
     carry += tot;
   }
-  const bool over = carry > max_pairs;
-  if (over)  // the frame renders empty: every range collapses
-    for (int i = threadIdx.x; i < ntiles; i += 1024) w.tile_ranges[i] = make_uint2(0u, 0u);
-  if (threadIdx.x == 0) {
-    if (over) w.status[0] |= GSFF_FLAG_PAIR_OVERFLOW;
-    w.status[1] = (uint32_t)(carry > 0xFFFFFFFFull ? 0xFFFFFFFFull : carry);
-    w.status[2] = over ? 0u : (uint32_t)carry;
+  __syncthreads();
+  const bool over = carry > (uint64_t)max_pairs;
+  if (blockIdx.x == 0 && blockIdx.y == 0) {
+    for (int i = threadIdx.x; i < ntiles; i += 256)
+      w.tile_ranges[i] = over ? make_uint2(0u, 0u) : make_uint2(s_st[i], s_st[i] + w.tile_tot[i]);
+    if (threadIdx.x == 0) {
+      if (over) w.status[0] |= GSFF_FLAG_PAIR_OVERFLOW;
+      w.status[1] = (uint32_t)(carry > 0xFFFFFFFFull ? 0xFFFFFFFFull : carry);
+      w.status[2] = over ? 0u : (uint32_t)carry;
+    }
   }
-}
-
-// Stable scatter of Gaussian ids into their tiles' segments.  Wave wv owns
-// the block's ranks [64 wv, 64 wv + 64); its cursors start after the pairs of
-// lower waves, and every pair's place follows from the coverage masks, so each
-// lane walks its own rectangle with no ordering between lanes.  The rank
-// chunk's tile rows are split into gridDim.y bands, one workgroup each: the
-// nearest chunks hold the largest rectangles, and a band is a fraction of
-// their walk.
-__global__ __launch_bounds__(256) void k_bin_scatter(WsView w, int64_t P, int ntiles,
-                                                     int tiles_x, int tiles_y, int nblk,
-                                                     uint32_t max_pairs) {
-  extern __shared__ uint64_t s_m[];  // [4][tiles_x + tiles_y] masks, then [4][band tiles] cursors
-  if (w.status[2] == 0u) return;     // nothing to write, or overflow (uniform)
-  const int wv = threadIdx.x >> 6, TM = tiles_x + tiles_y;
-  const int nband = (int)gridDim.y;
+  if (carry == 0 || over) return;  // nothing to write, or overflow (uniform)
   const int y_lo = (int)blockIdx.y * tiles_y / nband, y_hi = ((int)blockIdx.y + 1) * tiles_y / nband;
   const int t_lo = y_lo * tiles_x, nbt = (y_hi - y_lo) * tiles_x;
   if (nbt == 0) return;  // uniform
-  uint32_t* s_c = reinterpret_cast<uint32_t*>(s_m + 4 * TM);
   uint32_t gid;
   const ushort4 trc = rank_rect(w, (int64_t)blockIdx.x * kBinBlock + threadIdx.x, P, &gid);
   const ushort4 rc = super_rect(trc);
@@ -686,7 +688,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter(WsView w, int64_t P, int nt
   for (int b = threadIdx.x; b < nbt; b += 256) {
     const int t = t_lo + b;
     const int y = t / tiles_x, x = t - y * tiles_x;
-    uint32_t cur = w.tile_ranges[t].x + w.curbase[(int64_t)blockIdx.x * ntiles + t];
+    uint32_t cur = s_st[t] + w.curbase[(int64_t)blockIdx.x * ntiles + t];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       s_c[k * nbt + b] = cur;
@@ -744,13 +746,11 @@ hipError_t launch_bin(const Layout& L, const WsView& w, hipStream_t s) {
     const int nband = L.super_y < kBinBands ? L.super_y : kBinBands;
     const int band_rows = (L.super_y + nband - 1) / nband;
     const size_t lds_m = 32ull * (L.super_x + L.super_y);
-    const size_t lds_c = lds_m + 16ull * band_rows * L.super_x;
+    const size_t lds_c = lds_m + 16ull * band_rows * L.super_x + 4ull * L.nsuper;
     hipLaunchKernelGGL(k_bin_hist, dim3((unsigned)L.bin_blocks), dim3(256), lds_m, s, w, L.P,
                        L.nsuper, L.super_x, L.super_y, (int)L.bin_blocks);
     hipLaunchKernelGGL(k_bin_colscan, dim3((unsigned)((L.nsuper + 3) / 4)), dim3(256), 0, s, w,
                        L.nsuper, (int)L.bin_blocks);
-    hipLaunchKernelGGL(k_bin_tilescan, dim3(1), dim3(1024), 0, s, w, L.nsuper,
-                       (uint64_t)L.max_pairs);
     hipLaunchKernelGGL(k_bin_scatter, dim3((unsigned)L.bin_blocks, (unsigned)nband), dim3(256),
                        lds_c, s, w, L.P, L.nsuper, L.super_x, L.super_y, (int)L.bin_blocks,
                        (uint32_t)L.max_pairs);
