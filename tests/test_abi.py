@@ -164,3 +164,18 @@ def test_tracking_and_visibility_argument_validation(capi):
     assert lib.gsff_covisibility(1, 1, -1, 1, None) == E
     assert lib.gsff_covisibility(None, 1, 5, 1, None) == E
     assert lib.gsff_covisibility(1, 1, 5, None, None) == E
+    # Adam: more than eight groups, none, or a NULL table
+    grp = (capi.AdamGroup * 9)()
+    assert lib.gsff_adam_step(grp, 9, 1, 0.9, 0.999, 1e-8, None) == E
+    assert lib.gsff_adam_step(grp, 0, 1, 0.9, 0.999, 1e-8, None) == E
+    assert lib.gsff_adam_step(None, 1, 1, 0.9, 0.999, 1e-8, None) == E
+    # regulariser: no Gaussians, no workspace
+    assert lib.gsff_scale_reg(1, 0, 0.1, 1, 1 << 20, None, None, 0, None) == E
+    assert lib.gsff_scale_reg(1, 10, 0.1, None, 1 << 20, None, None, 0, None) == E
+    # decode + query: K out of range, labels without a loss
+    assert lib.gsff_decoder_query(1, 1, 1, 1, 1, 1, 0, 10, None, None, None, None, 1 << 20,
+                                  1 << 20, None) == E
+    assert lib.gsff_decoder_query(1, 1, 1, 1, 1, 1, 65, 10, None, None, None, None, 1 << 20,
+                                  1 << 20, None) == E
+    assert lib.gsff_decoder_query(1, 1, 1, 1, 1, 1, 4, 10, None, None, 1, None, 1 << 20,
+                                  1 << 20, None) == E

@@ -113,3 +113,40 @@ def test_mapping_step_lowers_the_window_loss():
         assert fr.read_status()[0] == 0
     print("mapping loss", losses[0], "->", losses[-1])
     assert losses[-1] < 0.7 * losses[0]
+
+
+def test_scale_reg_loss_only_and_gradient_only():
+    from paper_2504_19409_amd.mapping import scale_reg
+    rng = np.random.default_rng(9)
+    ls = rng.normal(-3.0, 0.5, size=(3, 2000)).astype(np.float32)
+    d = torch.from_numpy(ls).cuda()
+    L, g = omap.scale_reg(ls, 1.0)
+    loss = torch.empty(1, device="cuda")
+    scale_reg(d, 1.0, None, loss)
+    grad = torch.empty((3, 2000), device="cuda")
+    scale_reg(d, 1.0, grad, None)
+    torch.cuda.synchronize()
+    assert loss.item() == pytest.approx(L, rel=1e-6)
+    np.testing.assert_allclose(grad.cpu().numpy(), g, rtol=1e-5, atol=1e-12)
+
+
+def test_adam_step_eight_groups():
+    """The largest group count in one launch: every group moves by its own
+    rate (first step: -lr g / (|g| + eps))."""
+    from paper_2504_19409_amd.mapping import adam_step
+    rng = np.random.default_rng(10)
+    groups, ref = [], []
+    for q in range(8):
+        n = 1000 + 37 * q
+        p0 = rng.normal(size=n).astype(np.float32)
+        g = rng.normal(size=n).astype(np.float32)
+        lr = f32(10.0 ** -(1 + q % 4))
+        t = lambda a: torch.from_numpy(a).cuda()
+        groups.append((t(p0.copy()), t(g), torch.zeros(n, device="cuda"),
+                       torch.zeros(n, device="cuda"), lr))
+        ref.append(omap.adam(p0, g, np.zeros(n), np.zeros(n), 1, lr, f32(0.9), f32(0.999),
+                             f32(1e-8))[0])
+    adam_step(groups, 1, 0.9, 0.999, 1e-8)
+    torch.cuda.synchronize()
+    for (p, *_), r in zip(groups, ref):
+        np.testing.assert_allclose(p.cpu().numpy(), r, rtol=2e-6, atol=1e-7)

@@ -178,3 +178,32 @@ def test_tracking_loop_full_frame():
     assert last < 0.5 * first
     assert e1[0] < 0.5 * e0[0] and e1[1] < 0.5 * e0[1]
     assert fr.settings.render_features == 1
+
+
+@pytest.mark.parametrize("lam,drop", [(1.0, None), (0.7, "depth"), (0.7, "rgb")])
+def test_backward_tracking_single_terms(orc, lam, drop):
+    """lambda_t = 1 leaves only the colour term; a NULL target leaves its term
+    out of the loss and the gradient."""
+    sc, (p, c, ref), t_rgb, t_depth, mv, me = _tracking_case(orc, 34)
+    fr, _ = H.make_frame(sc, torch)
+    outs = fr.forward()
+    dev = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    tr = None if drop == "rgb" else t_rgb
+    td = None if drop == "depth" else t_depth
+    d_pose = torch.empty(6, device="cuda")
+    loss = torch.empty(1, device="cuda")
+    fr.backward_tracking(outs, dev(tr), dev(td), dev(mv), dev(me), lam, d_pose, loss)
+    torch.cuda.synchronize()
+    g_c, g_d, _ = otrk.tracking_upstream(ref["rgb"], ref["depth"], t_rgb, t_depth, mv, me, lam)
+    if drop == "rgb":
+        g_c = np.zeros_like(g_c)
+    if drop == "depth" or lam == 1.0:
+        g_d = np.zeros_like(g_d)
+    ref_loss = 0.0
+    if drop != "rgb":
+        ref_loss += lam / ref["rgb"].size * ((mv * me)[None] * np.abs(ref["rgb"] - t_rgb)).sum()
+    if drop != "depth":
+        ref_loss += (1 - lam) / ref["depth"].size * (mv * np.abs(ref["depth"] - t_depth)).sum()
+    ob = orc.backward(p, c, dict(g_rgb=g_c, g_depth=g_d, g_alpha=np.zeros_like(g_d)))
+    assert loss.item() == pytest.approx(ref_loss, rel=2e-5, abs=1e-12)
+    assert H.rel_l2(d_pose.cpu().numpy(), ob["pose"]) <= H.TOL_GRAD

@@ -54,7 +54,8 @@ def _check(gpu, sure, possible, P):
 
 
 @pytest.mark.parametrize("kind,t_vis", [("tiny", 0.5), ("ragged", 0.5), ("rotated", 0.5),
-                                        ("dense", 0.5), ("tiny", 0.9), ("dense", 0.05)])
+                                        ("dense", 0.5), ("tiny", 0.9), ("dense", 0.05),
+                                        ("ragged", 0.0)])
 def test_visibility_matches_oracle(orc, kind, t_vis):
     sc = _scene(kind)
     fr, _ = H.make_frame(sc, torch)
