@@ -388,10 +388,8 @@ __global__ __launch_bounds__(256) void k_dec_reduce(const float* __restrict__ pa
 // p(l | x) = softmax over the K labels of o(F)(x) . q(l): the dot product with
 // the queries is linear, so it folds into the second layer,
 //   logits = GELU(X W1 + b1) (W2 Q^T) + b2 Q^T,
-// and the 512-channel map is never formed.  FP32 throughout: the folded
-// weights (128 x K padded to 8, 16, 24, 32, 48 or 64 columns) and W1 sit in
-// LDS and every lane reads the same word (broadcast); one thread per pixel
-// walks the 128 hidden units, adding each one's share to its K logits.  Outputs: probabilities [K, n], the label
+// and the 512-channel map is never formed.  FP32 throughout (the folded
+// weights are 128 x K padded to a multiple of 16 labels).  Outputs: probabilities [K, n], the label
 // of the largest logit (the first of equal ones) [n], and the cross-entropy
 // against given labels (Eq. 9), as per-block partials summed in block order.
 constexpr int kQueryMaxK = 64;
@@ -432,61 +430,138 @@ __device__ __forceinline__ float gelu_q(float z) {
   return 0.5f * z * (1.f + t);
 }
 
-template <int KP>
+// Both products on the FP32 matrix cores (16x16x4), transposed so that no
+// value changes lanes: Z^T = W1^T X^T (hidden x pixels) leaves lane l with
+// hidden units 16 t + 4 (l / 16) + i, i = 0..3, of pixel l % 16 in its four
+// accumulator registers; after GELU, register i of every lane is one k-step of
+// logits^T = W2q^T H^T, whose A operand takes the same hidden units, staged
+// in LDS in lane order.  Lane l ends with labels 16 u + 4 (l / 16) + i of
+// pixel l % 16.  A wave takes 16 pixels at a time.
+typedef float f32x4q __attribute__((ext_vector_type(4)));
+
+template <int NLT>  // label tiles of 16
 __global__ __launch_bounds__(kQueryBlock) void k_query(
     const __bf16* __restrict__ X, const float* __restrict__ W1, const float* __restrict__ b1,
     const float* __restrict__ w2q, const float* __restrict__ b2q, int K, int64_t n,
     float* __restrict__ prob, int32_t* __restrict__ label, const int32_t* __restrict__ gt,
     float* __restrict__ ce_part) {
-  __shared__ float s_w1[kLat * kHid], s_b1[kHid], s_w2[kHid * KP], s_b2[KP];
+  constexpr int KP = 16 * NLT, NHT = kHid / 16;
+  __shared__ float s_a1[NHT][4][64];       // W1^T operand of k-step s, lane order
+  __shared__ float s_a2[NLT][NHT][4][64];  // W2q^T operand, lane order
+  __shared__ float s_b1[kHid], s_b2[KP];
   __shared__ float s_red[kQueryBlock / 64];
-  for (int e = threadIdx.x; e < kLat * kHid; e += kQueryBlock) s_w1[e] = W1[e];
-  for (int e = threadIdx.x; e < kHid * KP; e += kQueryBlock) s_w2[e] = w2q[e];
+  const int lane = threadIdx.x & 63, r = lane & 15, c4 = lane >> 4;
+  for (int e = threadIdx.x; e < NHT * 4 * 64; e += kQueryBlock) {
+    const int t = e >> 8, k = (e >> 6) & 3, l = e & 63;
+    s_a1[t][k][l] = W1[(4 * k + (l >> 4)) * kHid + 16 * t + (l & 15)];
+  }
+  for (int e = threadIdx.x; e < NLT * NHT * 4 * 64; e += kQueryBlock) {
+    const int u = e / (NHT * 256), rem = e % (NHT * 256);
+    const int t = rem >> 8, i = (rem >> 6) & 3, l = rem & 63;
+    s_a2[u][t][i][l] = w2q[(16 * t + 4 * (l >> 4) + i) * KP + 16 * u + (l & 15)];
+  }
   if (threadIdx.x < kHid) s_b1[threadIdx.x] = b1[threadIdx.x];
   if (threadIdx.x < KP) s_b2[threadIdx.x] = b2q[threadIdx.x];
   __syncthreads();
-  const int64_t p = (int64_t)blockIdx.x * kQueryBlock + threadIdx.x;
+  const int64_t ngroups = (n + 15) / 16;
+  const int64_t nwaves = (int64_t)gridDim.x * (kQueryBlock / 64);
   float ce = 0.f;
-  if (p < n) {
-    float x[kLat];
+  // B of layer 1, k-step s: latent 4 s + l / 16 of pixel l % 16; the next
+  // group's are loaded while this one is computed
+  auto load_x = [&](int64_t g, float* x) {
+    const int64_t q = g * 16 + r;
 #pragma unroll
-    for (int i = 0; i < kLat; ++i) x[i] = (float)X[(int64_t)i * n + p];
-    float lg[KP];
+    for (int k = 0; k < 4; ++k)
+      x[k] = (g < ngroups && q < n) ? (float)X[(int64_t)(4 * k + c4) * n + q] : 0.f;
+  };
+  int64_t grp = (int64_t)blockIdx.x * (kQueryBlock / 64) + (threadIdx.x >> 6);
+  float xb[4];
+  load_x(grp, xb);
+  for (; grp < ngroups; grp += nwaves) {
+    const int64_t p = grp * 16 + r;
+    const bool ok = p < n;
+    float xn[4];
+    load_x(grp + nwaves, xn);
+    // the operands are read from LDS at every step: an empty asm keeps the
+    // compiler from holding all 32 + 32 NLT of them in registers across the
+    // loop, which would leave room for two waves per SIMD
+    int li = lane;
+    asm volatile("" : "+v"(li));
+    float h[NHT][4];
 #pragma unroll
-    for (int k = 0; k < KP; ++k) lg[k] = s_b2[k];
-    for (int j = 0; j < kHid; ++j) {
-      float z = s_b1[j];
+    for (int t = 0; t < NHT; ++t) {
+      f32x4q z = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int i = 0; i < kLat; ++i) z = __builtin_fmaf(x[i], s_w1[i * kHid + j], z);
-      const float h = gelu_q(z);
+      for (int k = 0; k < 4; ++k)
+        z = __builtin_amdgcn_mfma_f32_16x16x4f32(s_a1[t][k][li], xb[k], z, 0, 0, 0);
 #pragma unroll
-      for (int k = 0; k < KP; ++k) lg[k] = __builtin_fmaf(h, s_w2[j * KP + k], lg[k]);
+      for (int i = 0; i < 4; ++i) h[t][i] = gelu_q(z[i] + s_b1[16 * t + 4 * c4 + i]);
     }
-    float m = lg[0];
-    int arg = 0;
+    float lg[NLT][4];
 #pragma unroll
-    for (int k = 1; k < KP; ++k)
-      if (k < K && lg[k] > m) {
-        m = lg[k];
-        arg = k;
+    for (int u = 0; u < NLT; ++u) {
+      f32x4q acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int t = 0; t < NHT; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(s_a2[u][t][i][li], h[t][i], acc, 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) lg[u][i] = acc[i] + s_b2[16 * u + 4 * c4 + i];
+    }
+    // the pixel's labels are spread over lanes r, r + 16, r + 32, r + 48
+    float m = -INFINITY;
+    int arg = 0x7FFFFFFF;
+#pragma unroll
+    for (int u = 0; u < NLT; ++u)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int lab = 16 * u + 4 * c4 + i;
+        if (lab < K && (lg[u][i] > m || (lg[u][i] == m && lab < arg))) {
+          m = lg[u][i];
+          arg = lab;
+        }
       }
+#pragma unroll
+    for (int off = 16; off < 64; off <<= 1) {
+      const float mo = __shfl_xor(m, off, 64);
+      const int ao = __shfl_xor(arg, off, 64);
+      if (mo > m || (mo == m && ao < arg)) {
+        m = mo;
+        arg = ao;
+      }
+    }
     float z = 0.f;
 #pragma unroll
-    for (int k = 0; k < KP; ++k) z += k < K ? __expf(lg[k] - m) : 0.f;
-    if (prob) {
-      const float inv = 1.f / z;
+    for (int u = 0; u < NLT; ++u)
 #pragma unroll
-      for (int k = 0; k < KP; ++k)
-        if (k < K) prob[(int64_t)k * n + p] = __expf(lg[k] - m) * inv;
-    }
-    if (label) label[p] = arg;
-    if (gt) {
-      const int l = gt[p];
-      float lgt = 0.f;
+      for (int i = 0; i < 4; ++i)
+        if (16 * u + 4 * c4 + i < K) z += __expf(lg[u][i] - m);
 #pragma unroll
-      for (int k = 0; k < KP; ++k) lgt = k == l ? lg[k] : lgt;
-      if (l >= 0 && l < K) ce = (m + __logf(z)) - lgt;  // -log p(l | x)
+    for (int off = 16; off < 64; off <<= 1) z += __shfl_xor(z, off, 64);
+    if (ok) {
+      if (prob) {
+        const float inv = 1.f / z;
+#pragma unroll
+        for (int u = 0; u < NLT; ++u)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int lab = 16 * u + 4 * c4 + i;
+            if (lab < K) prob[(int64_t)lab * n + p] = __expf(lg[u][i] - m) * inv;
+          }
+      }
+      if (label && c4 == 0) label[p] = arg;
+      if (gt) {
+        const int l = gt[p];
+#pragma unroll
+        for (int u = 0; u < NLT; ++u)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (16 * u + 4 * c4 + i == l && l < K) ce += (m + __logf(z)) - lg[u][i];  // -log p
+      }
     }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) xb[k] = xn[k];
   }
   if (ce_part) {
     float v = ce;
@@ -598,10 +673,15 @@ gsff_status gsff_decoder_train_step(const void* X, const float* W1, const float*
 }
 
 
+static int64_t query_blocks(int64_t n_px) {
+  const int64_t groups = (n_px + 15) / 16;  // 16 pixels per wave step
+  const int64_t b = (groups + 15) / 16;     // about four steps per wave
+  return b < 1024 ? b : 1024;
+}
+
 gsff_status gsff_decoder_query_workspace_size(int32_t K, int64_t n_px, size_t* bytes) {
   if (!bytes || K < 1 || K > kQueryMaxK || n_px < 0) return GSFF_ERR_INVALID_ARGUMENT;
-  const int64_t nb = (n_px + kQueryBlock - 1) / kQueryBlock;
-  *bytes = (size_t)(4 * ((kHid + 1) * kQueryMaxK + nb));
+  *bytes = (size_t)(4 * ((kHid + 1) * kQueryMaxK + query_blocks(n_px) + 1));
   return GSFF_OK;
 }
 
@@ -617,35 +697,29 @@ gsff_status gsff_decoder_query(const void* X, const float* W1, const float* b1, 
   gsff_decoder_query_workspace_size(K, n_px, &need);
   if (ws_bytes < need) return GSFF_ERR_INVALID_ARGUMENT;
   hipStream_t s = (hipStream_t)stream;
-  const int KP = K <= 8 ? 8 : (K <= 16 ? 16 : (K <= 24 ? 24 : (K <= 32 ? 32 : (K <= 48 ? 48 : 64))));
+  const int NLT = (K + 15) / 16, KP = 16 * NLT;
   float* w2q = (float*)ws;
   float* b2q = w2q + kHid * KP;
   float* part = (float*)ws + (kHid + 1) * kQueryMaxK;
   hipLaunchKernelGGL(k_query_fold, dim3((unsigned)(((kHid + 1) * KP + 3) / 4)), dim3(256), 0, s,
                      W2, b2, Q, (int)K, KP, w2q, b2q);
-  const int64_t nb = (n_px + kQueryBlock - 1) / kQueryBlock;
+  const int64_t nb = n_px > 0 ? query_blocks(n_px) : 0;
   if (nb > 0) {
     float* cp = gt ? part : nullptr;
-#define GSFF_QUERY(KPV)                                                                         \
-  hipLaunchKernelGGL(k_query<KPV>, dim3((unsigned)nb), dim3(kQueryBlock), 0, s,                \
-                     (const __bf16*)X, W1, b1, (const float*)w2q, (const float*)b2q, (int)K, n_px, \
-                     prob, label, gt, cp)
-    if (KP == 8) GSFF_QUERY(8);
-    else if (KP == 16) GSFF_QUERY(16);
-    else if (KP == 24) GSFF_QUERY(24);
-    else if (KP == 32) GSFF_QUERY(32);
-    else if (KP == 48) GSFF_QUERY(48);
-    else GSFF_QUERY(64);
+#define GSFF_QUERY(NLTV)                                                                        \
+  hipLaunchKernelGGL(k_query<NLTV>, dim3((unsigned)nb), dim3(kQueryBlock), 0, s, (const __bf16*)X, \
+                     W1, b1, (const float*)w2q, (const float*)b2q, (int)K, n_px, prob, label, gt, \
+                     cp)
+    if (NLT == 1) GSFF_QUERY(1);
+    else if (NLT == 2) GSFF_QUERY(2);
+    else if (NLT == 3) GSFF_QUERY(3);
+    else GSFF_QUERY(4);
 #undef GSFF_QUERY
   }
-  if (ce_loss) {
-    if (nb > 0)
-      hipLaunchKernelGGL(k_query_ce, dim3(1), dim3(256), 0, s, (const float*)part, (int)nb, n_px,
-                         ce_loss);
-    else
-      hipLaunchKernelGGL(k_query_ce, dim3(1), dim3(256), 0, s, (const float*)part, 0, (int64_t)1,
-                         ce_loss);
-  }
+  if (ce_loss)
+    hipLaunchKernelGGL(k_query_ce, dim3(1), dim3(256), 0, s, (const float*)part, (int)nb,
+                       n_px > 0 ? n_px : (int64_t)1, ce_loss);
   return hipGetLastError() == hipSuccess ? GSFF_OK : GSFF_ERR_HIP;
 }
+
 }  // extern "C"
