@@ -350,8 +350,10 @@ gsff_status gsff_pose_adam_step(float* viewmat, const float* d_pose, float* stat
  * by one preprocess_bwd with the same `out`.  `adjoint_items` turns the walks
  * of the last composite_fwd into the adjoint's work items (each tile's walked
  * list in segments of 64 entries, at most 8 per tile, longest first; the
- * forward recorded each pixel's state at every segment end) and the first
- * adjoint row of every tile: it runs after composite_fwd and before the
+ * forward recorded each pixel's state at every segment end), the first
+ * adjoint row of every tile and the first slot of every 256-Gaussian block
+ * (from the counts preprocess wrote; repeating it gives the same result): it
+ * runs after composite_fwd and before the
  * first composite_bwd that follows it (gsff_backward runs it itself;
  * composite_bwd_l1 and gsff_backward_l1 build the same items inside their
  * L1 upstream pass and need no adjoint_items call). */
