@@ -423,10 +423,10 @@ __global__ __launch_bounds__(256) void k_query_fold(const float* __restrict__ W2
 }
 
 // GELU as the decoder's, with tanh(u) = 1 - 2 / (exp(2u) + 1) through the
-// fast divide (a few ulp; the query path is FP32 throughout)
+// hardware reciprocal (1 ulp; exact at the ends: 1 / inf = 0, 1 / 1 = 1)
 __device__ __forceinline__ float gelu_q(float z) {
   const float u = 0.7978845608028654f * (z + 0.044715f * z * z * z);
-  const float t = 1.f - __fdividef(2.f, __expf(2.f * u) + 1.f);
+  const float t = 1.f - 2.f * __builtin_amdgcn_rcpf(__expf(2.f * u) + 1.f);
   return 0.5f * z * (1.f + t);
 }
 
