@@ -68,15 +68,17 @@ static DecLayout dec_layout(int64_t npx) {
   return L;
 }
 
+// tanh(u) = 1 - 2 / (exp(2u) + 1) through the hardware reciprocal (1 ulp;
+// exact at the ends: 1 / inf = 0, 1 / 1 = 1)
 __device__ __forceinline__ float gelu_f(float z) {
   const float u = 0.7978845608028654f * (z + 0.044715f * z * z * z);
-  const float t = 1.f - 2.f / (__expf(2.f * u) + 1.f);  // tanh(u)
+  const float t = 1.f - 2.f * __builtin_amdgcn_rcpf(__expf(2.f * u) + 1.f);  // tanh(u)
   return 0.5f * z * (1.f + t);
 }
 
 __device__ __forceinline__ float gelu_grad_f(float z) {
   const float u = 0.7978845608028654f * (z + 0.044715f * z * z * z);
-  const float t = 1.f - 2.f / (__expf(2.f * u) + 1.f);
+  const float t = 1.f - 2.f * __builtin_amdgcn_rcpf(__expf(2.f * u) + 1.f);
   const float du = 0.7978845608028654f * (1.f + 3.f * 0.044715f * z * z);
   return 0.5f * (1.f + t) + 0.5f * z * (1.f - t * t) * du;
 }
@@ -422,21 +424,6 @@ __global__ __launch_bounds__(256) void k_query_fold(const float* __restrict__ W2
   }
 }
 
-// GELU as the decoder's, with tanh(u) = 1 - 2 / (exp(2u) + 1) through the
-// hardware reciprocal (1 ulp; exact at the ends: 1 / inf = 0, 1 / 1 = 1)
-__device__ __forceinline__ float gelu_q(float z) {
-  const float u = 0.7978845608028654f * (z + 0.044715f * z * z * z);
-  const float t = 1.f - 2.f * __builtin_amdgcn_rcpf(__expf(2.f * u) + 1.f);
-  return 0.5f * z * (1.f + t);
-}
-
-// Both products on the FP32 matrix cores (16x16x4), transposed so that no
-// value changes lanes: Z^T = W1^T X^T (hidden x pixels) leaves lane l with
-// hidden units 16 t + 4 (l / 16) + i, i = 0..3, of pixel l % 16 in its four
-// accumulator registers; after GELU, register i of every lane is one k-step of
-// logits^T = W2q^T H^T, whose A operand takes the same hidden units, staged
-// in LDS in lane order.  Lane l ends with labels 16 u + 4 (l / 16) + i of
-// pixel l % 16.  A wave takes 16 pixels at a time.
 typedef float f32x4q __attribute__((ext_vector_type(4)));
 
 template <int NLT>  // label tiles of 16
@@ -495,7 +482,7 @@ __global__ __launch_bounds__(kQueryBlock) void k_query(
       for (int k = 0; k < 4; ++k)
         z = __builtin_amdgcn_mfma_f32_16x16x4f32(s_a1[t][k][li], xb[k], z, 0, 0, 0);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) h[t][i] = gelu_q(z[i] + s_b1[16 * t + 4 * c4 + i]);
+      for (int i = 0; i < 4; ++i) h[t][i] = gelu_f(z[i] + s_b1[16 * t + 4 * c4 + i]);
     }
     float lg[NLT][4];
 #pragma unroll
