@@ -427,7 +427,8 @@ __global__ __launch_bounds__(256) void k_query_fold(const float* __restrict__ W2
 typedef float f32x4q __attribute__((ext_vector_type(4)));
 
 template <int NLT>  // label tiles of 16
-__global__ __launch_bounds__(kQueryBlock) void k_query(
+__global__ __attribute__((amdgpu_flat_work_group_size(kQueryBlock, kQueryBlock),
+                          amdgpu_waves_per_eu(5))) void k_query(
     const __bf16* __restrict__ X, const float* __restrict__ W1, const float* __restrict__ b1,
     const float* __restrict__ w2q, const float* __restrict__ b2q, int K, int64_t n,
     float* __restrict__ prob, int32_t* __restrict__ label, const int32_t* __restrict__ gt,
