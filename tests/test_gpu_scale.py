@@ -179,3 +179,51 @@ def test_keyframe_window_full_size(orc):
         e = H.rel_l2(g[k].cpu().numpy(), ob[k])
         print(f"view {v} grad {k}: relL2 {e:.2e}")
         assert e <= H.TOL_GRAD, k
+
+
+def test_large_frame_fused_l1(orc):
+    """1920x1088, 50k Gaussians, 16 FP32 channels: 8160 tiles (more than the
+    2048 whose ranges the fused L1 pass's item workgroup holds in registers),
+    510 super-tiles (the binning's range scan runs in two chunks) and 196
+    slot blocks.  The forward on sampled pixels against the oracle; the
+    fused-L1 adjoint against the oracle for targets 0.25 above the render at
+    sampled pixels, so the upstream is -1/numel there and zero elsewhere."""
+    rng = np.random.default_rng(81)
+    W, Hh, C = 1920, 1088, 16
+    sc = sg.make_scene(50_000, W, Hh, 1000.0, 1000.0, W / 2, Hh / 2, C, seed=81, rng=rng)
+    fr, _ = H.make_frame(sc, torch)
+    fr.forward()
+    flags, n = fr.read_status()
+    fr, _ = H.make_frame(sc, torch, max_pairs=int(n * 1.05) + 4096)
+    outs = fr.forward()
+    assert fr.read_status()[0] == 0
+    idx = rng.choice(W * Hh, 2000, replace=False)
+    py, px = np.divmod(idx, W)
+    p, c = orc.scene_dicts(sc)
+    o = orc.render_pixels(p, c, px, py)
+    g = [x.cpu().numpy() for x in outs]
+    assert H.rel_l2(g[0][:, py, px].T, o["rgb"]) <= H.TOL_FWD
+    assert H.rel_l2(g[1][py, px], o["depth"]) <= H.TOL_FWD
+    assert H.rel_l2(g[2][py, px], o["alpha"]) <= H.TOL_FWD
+    assert H.rel_l2(g[3][:, py, px].T, o["feat"]) <= H.TOL_FWD
+    tg = [outs[0].clone(), outs[1].clone(), None, outs[3].clone()]
+    tpx, tpy = torch.from_numpy(px).cuda(), torch.from_numpy(py).cuda()
+    tg[0][:, tpy, tpx] += 0.25
+    tg[1][tpy, tpx] += 0.25
+    tg[3][:, tpy, tpx] += 0.25
+    grads = fr.make_grads()
+    loss = torch.empty(1, device="cuda")
+    fr.backward_l1(outs, tg, (1.0, 1.0, 0.0, 1.0), grads, loss)
+    torch.cuda.synchronize()
+    assert fr.read_status()[0] == 0
+    ups = [np.zeros((3, Hh, W)), np.zeros((Hh, W)), np.zeros((Hh, W)), np.zeros((C, Hh, W))]
+    ups[0][:, py, px] = -1.0 / ups[0].size
+    ups[1][py, px] = -1.0 / ups[1].size
+    ups[3][:, py, px] = -1.0 / ups[3].size
+    ob = orc.backward(p, c, dict(g_rgb=ups[0], g_depth=ups[1], g_alpha=ups[2], g_feat=ups[3]))
+    for k in GRADS:
+        e = H.rel_l2(grads[k].cpu().numpy(), ob[k])
+        print(f"grad {k}: relL2 {e:.2e}")
+        assert e <= H.TOL_GRAD, k
+    # every picked element is 0.25 off in each of the three groups
+    assert loss.item() == pytest.approx(3 * 0.25 * 2000 / (W * Hh), rel=1e-4)
