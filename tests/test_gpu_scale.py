@@ -181,16 +181,20 @@ def test_keyframe_window_full_size(orc):
         assert e <= H.TOL_GRAD, k
 
 
-def test_large_frame_fused_l1(orc):
-    """1920x1088, 50k Gaussians, 16 FP32 channels: 8160 tiles (more than the
-    2048 whose ranges the fused L1 pass's item workgroup holds in registers),
-    510 super-tiles (the binning's range scan runs in two chunks) and 196
-    slot blocks.  The forward on sampled pixels against the oracle; the
-    fused-L1 adjoint against the oracle for targets 0.25 above the render at
-    sampled pixels, so the upstream is -1/numel there and zero elsewhere."""
+@pytest.mark.parametrize("W,Hh,f", [(1920, 1088, 1000.0), (3840, 2160, 2000.0)])
+def test_large_frame_fused_l1(orc, W, Hh, f):
+    """50k Gaussians, 16 FP32 channels on large frames: 1920x1088 has 8160
+    tiles (more than the 2048 whose ranges the fused L1 pass's item workgroup
+    holds in registers), 510 super-tiles (the binning's range scan runs in two
+    chunks) and 196 slot blocks; 3840x2160 has 32400 tiles (more than the 8192
+    of the explicit path's 1024-thread item kernel) and 2040 super-tiles.
+    The forward on sampled pixels against the oracle; the fused-L1 adjoint
+    against the oracle for targets 0.25 above the render at sampled pixels,
+    so the upstream is -1/numel there and zero elsewhere; and the explicit
+    adjoint given that same upstream."""
     rng = np.random.default_rng(81)
-    W, Hh, C = 1920, 1088, 16
-    sc = sg.make_scene(50_000, W, Hh, 1000.0, 1000.0, W / 2, Hh / 2, C, seed=81, rng=rng)
+    C = 16
+    sc = sg.make_scene(50_000, W, Hh, f, f, W / 2, Hh / 2, C, seed=81, rng=rng)
     fr, _ = H.make_frame(sc, torch)
     fr.forward()
     flags, n = fr.read_status()
@@ -227,3 +231,9 @@ def test_large_frame_fused_l1(orc):
         assert e <= H.TOL_GRAD, k
     # every picked element is 0.25 off in each of the three groups
     assert loss.item() == pytest.approx(3 * 0.25 * 2000 / (W * Hh), rel=1e-4)
+    # the explicit-upstream adjoint (its own item kernel) with the same upstream
+    g2 = fr.make_grads()
+    fr.backward(*[torch.from_numpy(u.astype(np.float32)).cuda() for u in ups], g2)
+    torch.cuda.synchronize()
+    for k in GRADS:
+        assert H.rel_l2(g2[k].cpu().numpy(), ob[k]) <= H.TOL_GRAD, k
