@@ -12,6 +12,13 @@ mean|rgb - t| + mean|depth - t| + mean|feat - t| (upstream formed inside the
 compositing adjoint) -> preprocess adjoint + pose reduction, all in libgsff
 kernels on one stream, inputs resident in HBM.
 
+After the timed step, the same frame also times the other SLAM passes built
+on the rasterizer, reported under config.slam: a tracking iteration (forward
+without features, pose-only adjoint of the masked tracking loss, pose step),
+the keyframe test's visibility record and co-visibility counts, the mapping
+step's scale regulariser and fused Adam, and decode + query of the rendered
+features against 20 labels.
+
 Prints one JSON line (see the keys below); ``--gpus`` above 1 is refused: this
 build runs on a single GPU.
 """
