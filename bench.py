@@ -189,7 +189,7 @@ def tracking_rate(torch, fr, targets, K, warmup):
 
 
 def keyframe_rates(torch, fr, K):
-    """Durations of the keyframe test's two passes on the frame (Sec. 3.3,
+    """Durations of the keyframe test's two passes on the frame (Sec. 3.2,
     Eq. 6): the visibility record of the last forward and the co-visibility
     counts of two records, from HIP events around K launches of each."""
     from paper_2504_19409_amd import _capi
@@ -221,7 +221,7 @@ def keyframe_rates(torch, fr, K):
 
 def mapping_rates(torch, fr, K):
     """Durations of the mapping step's two passes beyond the window's
-    forward + adjoint (Sec. 3.3, Eqs. 7-8) on the frame's Gaussians: the scale
+    forward + adjoint (Sec. 3.2, Eqs. 7-8) on the frame's Gaussians: the scale
     regulariser and the fused Adam step over all six parameter groups, from
     HIP events around K launches (on copies: the frame's Gaussians stay)."""
     from paper_2504_19409_amd.mapping import adam_step, scale_reg, scale_reg_workspace
@@ -398,7 +398,7 @@ def main():
     ms = min(eager_ms, graph_ms) if graph_ms else eager_ms
     value = 1e3 / ms
 
-    # the other SLAM passes on the same frame (Sec. 3.3): tracking iteration,
+    # the other SLAM passes on the same frame (Sec. 3.2): tracking iteration,
     # keyframe test, mapping step's regulariser and optimiser
     slam = {"tracking": tracking_rate(torch, fr, targets, K, args.warmup),
             "keyframe": keyframe_rates(torch, fr, K), "mapping": mapping_rates(torch, fr, K),

@@ -229,7 +229,7 @@ gsff_status gsff_backward_l1(const gsff_gaussians* g, const gsff_camera* cam,
                              const float* weights, float* loss, const gsff_grads* out,
                              int32_t accumulate, void* stream);
 
-/* Tracking backward (Sec. 3.3 tracking loss, Eq. 5; pose terms Eq. 4): with
+/* Tracking backward (Sec. 3.2 tracking loss, Eq. 5; pose terms Eq. 4): with
  * the Gaussians frozen, the gradient of
  *   L = lambda_t mean(m_v m_e |rgb - t_rgb|) + (1 - lambda_t) mean(m_v |depth - t_depth|)
  * with respect to the pose perturbation only (d_pose [6], rho then theta, as
@@ -249,7 +249,7 @@ gsff_status gsff_backward_tracking(const gsff_gaussians* g, const gsff_camera* c
                                    const uint8_t* mask_e, float lambda_t, float* loss,
                                    float* d_pose, int32_t accumulate, void* stream);
 
-/* Scale regulariser of the mapping loss (Sec. 3.3, Eqs. 7-8):
+/* Scale regulariser of the mapping loss (Sec. 3.2, Eqs. 7-8):
  *   L_reg = lambda (1/N) sum_i |s_i - sbar|_1,  s_i = exp(log_scales[:, i]),
  * sbar the mean of the N = P scale vectors, |.|_1 over the three components.
  * grad_log_scales [3, P] (may be NULL) receives dL/dlog_scales and loss
@@ -282,7 +282,7 @@ typedef struct gsff_adam_group {
 gsff_status gsff_adam_step(const gsff_adam_group* groups, int32_t ngroups, int32_t step,
                            float beta1, float beta2, float eps, void* stream);
 
-/* Visibility record of the last forward on `ws` (Sec. 3.3 keyframe
+/* Visibility record of the last forward on `ws` (Sec. 3.2 keyframe
  * selection, Eq. 6): visible [P] uint8 on the device receives 1 for every
  * Gaussian blended at some pixel while the transmittance in front of it
  * exceeds t_vis (the paper's 0.5), 0 for every other.  The decisions are the
@@ -294,14 +294,14 @@ gsff_status gsff_visibility(const gsff_gaussians* g, const gsff_camera* cam,
                             int64_t max_pairs, float t_vis, uint8_t* visible, void* stream);
 
 /* Co-visibility of two visibility records a, b [n] (uint8, non-zero =
- * visible; Sec. 3.3): counts [2] uint32 on the device receive |a and b| and
+ * visible; Sec. 3.2): counts [2] uint32 on the device receive |a and b| and
  * |a or b|; their ratio is the IoU that the keyframe test compares with
  * tau_thresh.  Errors: GSFF_ERR_INVALID_ARGUMENT for a NULL pointer, n < 0
  * or n >= 2^32. */
 gsff_status gsff_covisibility(const uint8_t* a, const uint8_t* b, int64_t n, uint32_t* counts,
                               void* stream);
 
-/* The masks of the tracking loss (Sec. 3.3, Eq. 5), uint8 [H,W] on the
+/* The masks of the tracking loss (Sec. 3.2, Eq. 5), uint8 [H,W] on the
  * device, 1 = kept.  mask_e: the edge mask of the target colour image t_rgb
  * [3,H,W] f32: the Sobel gradient of the grey image (mean of the three
  * channels), scaled by 1/8 so that a ramp of slope a per pixel has magnitude
@@ -315,7 +315,7 @@ gsff_status gsff_tracking_masks(const float* t_rgb, const float* alpha, int32_t 
                                 int32_t height, float edge_threshold, float vis_threshold,
                                 uint8_t* mask_v, uint8_t* mask_e, void* stream);
 
-/* One pose step of the tracking loop (Sec. 3.3; the increment is the left
+/* One pose step of the tracking loop (Sec. 3.2; the increment is the left
  * perturbation of Eq. 4).  d_pose [6] (rho, theta) is the gradient from
  * gsff_backward_tracking; state [12] holds Adam's first and second moments
  * (zero before step 1); step counts from 1.  The increment

@@ -1,7 +1,7 @@
 """FP64 numpy oracle of the mapping support (test infrastructure only; only
 ``tests/`` use it).  Shares no code with the HIP path.
 
-Sec. 3.3, mapping loss (Eqs. 7-8):
+Sec. 3.2, mapping loss (Eqs. 7-8):
 
 * ``scale_reg`` -- L_reg = (1/N) sum_i |s_i - sbar|_1 with s_i = exp(log
                    scale), sbar the mean scale vector, |.|_1 over the three

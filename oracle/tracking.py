@@ -1,7 +1,7 @@
 """FP64 numpy oracle of the tracking support (test infrastructure only; only
 ``tests/`` use it).  Shares no code with the HIP path.
 
-Sec. 3.3 (tracking loss, Eq. 5; camera pose optimisation, Eq. 4):
+Sec. 3.2 (tracking loss, Eq. 5; camera pose optimisation, Eq. 4):
 
 * ``edge_mask``         -- m_e: Sobel gradient magnitude of the grey target
                            image (mean of r, g, b), scaled by 1/8 so that a ramp

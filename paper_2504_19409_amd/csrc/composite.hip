@@ -798,7 +798,7 @@ hipError_t launch_adjoint_items(const Layout& L, const WsView& w, hipStream_t s)
   return hipGetLastError();
 }
 
-// Visibility record (Sec. 3.3 keyframe selection, Eq. 6): v_i = 1 when
+// Visibility record (Sec. 3.2 keyframe selection, Eq. 6): v_i = 1 when
 // Gaussian i is blended at some pixel while the transmittance in front of it
 // exceeds t_vis.  One workgroup per tile replays the forward's walk of the
 // tile's list (the ids it recorded, up to its walk end) in batches of 64 with

@@ -1,4 +1,4 @@
-// Mapping support (Sec. 3.3, mapping loss Eqs. 7-8): the scale regulariser
+// Mapping support (Sec. 3.2, mapping loss Eqs. 7-8): the scale regulariser
 // and a fused Adam step over the Gaussians' parameter groups.
 //
 // Regulariser.  L_reg = (1/N) sum_i |s_i - sbar|_1 with s_i = exp(log-scale

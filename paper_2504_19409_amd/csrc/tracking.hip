@@ -1,4 +1,4 @@
-// Tracking support (Sec. 3.3, camera pose optimisation and tracking loss):
+// Tracking support (Sec. 3.2, camera pose optimisation and tracking loss):
 // the two per-pixel masks of the tracking loss (Eq. 5) and the pose step that
 // turns the pose gradient of Eq. 4 into the next camera pose.
 //

@@ -1,4 +1,4 @@
-"""Mapping step on the rasterizer (Sec. 3.3, Eqs. 7-8): the keyframe window's
+"""Mapping step on the rasterizer (Sec. 3.2, Eqs. 7-8): the keyframe window's
 L1 terms (colour and depth weighted lambda_m and 1 - lambda_m, features when
 given) over its views, the scale regulariser lambda_r L_reg, and one fused
 Adam step over the Gaussians' parameters, with the camera poses frozen.

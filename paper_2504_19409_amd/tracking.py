@@ -1,4 +1,4 @@
-"""Camera tracking on the rasterizer (Sec. 3.3): the masks of the tracking
+"""Camera tracking on the rasterizer (Sec. 3.2): the masks of the tracking
 loss (Eq. 5), the pose step on the left increment of Eq. 4, and the loop that
 iterates render -> pose gradient -> pose step until the increment converges.
 
@@ -54,7 +54,7 @@ def covisibility(a, b, counts=None):
 
 
 def is_keyframe(vis_frame, vis_keyframe, tau_thresh: float) -> bool:
-    """Keyframe test of Sec. 3.3: the frame becomes a keyframe when the IoU
+    """Keyframe test of Sec. 3.2: the frame becomes a keyframe when the IoU
     of its visibility record with the last keyframe's is below tau_thresh."""
     both, either = covisibility(vis_frame, vis_keyframe)
     return (both / either if either else 1.0) < tau_thresh

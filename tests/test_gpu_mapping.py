@@ -1,4 +1,4 @@
-"""GPU parity of the mapping support (Sec. 3.3, Eqs. 7-8) through the C ABI:
+"""GPU parity of the mapping support (Sec. 3.2, Eqs. 7-8) through the C ABI:
 the scale regulariser and the fused Adam step against the FP64 oracle, and the
 mapping step on a keyframe window."""
 import numpy as np

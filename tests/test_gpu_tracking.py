@@ -1,4 +1,4 @@
-"""GPU parity of the tracking support (Sec. 3.3, Eqs. 4-5) through the C ABI:
+"""GPU parity of the tracking support (Sec. 3.2, Eqs. 4-5) through the C ABI:
 the masks, the pose gradient of the masked tracking loss and the pose step
 against the FP64 oracle, and the tracking loop on the full frame workload."""
 import numpy as np

@@ -1,5 +1,5 @@
 """GPU parity of the visibility record (Eq. 6) and the co-visibility counts of
-the keyframe test (Sec. 3.3) through the C ABI.
+the keyframe test (Sec. 3.2) through the C ABI.
 
 The record is a set decided by floating point (alpha against alpha_min, the
 transmittance against the threshold); the oracle brackets it with the FP64

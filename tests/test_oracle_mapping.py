@@ -1,4 +1,4 @@
-"""Pins of the mapping oracle (Sec. 3.3, Eqs. 7-8): the scale regulariser
+"""Pins of the mapping oracle (Sec. 3.2, Eqs. 7-8): the scale regulariser
 against closed forms and finite differences, Adam against its first-step
 closed form.  CPU only."""
 import numpy as np

@@ -1,4 +1,4 @@
-"""Pins of the tracking oracle (Sec. 3.3, Eqs. 4-5) against closed forms, a
+"""Pins of the tracking oracle (Sec. 3.2, Eqs. 4-5) against closed forms, a
 library routine and the oracle renderer itself; CPU only."""
 import numpy as np
 import pytest
