@@ -138,7 +138,7 @@ class Step:
 def tracking_rate(torch, fr, targets, K, warmup):
     """Tracking iterations per second on the same frame, from its perturbed
     pose toward the targets: forward without features, the pose-only adjoint
-    of the masked tracking loss (Eq. 5) and the pose step, replayed from a HIP
+    of the masked tracking loss (Eq. 6) and the pose step, replayed from a HIP
     graph (the captured step keeps one Adam step count; timing only)."""
     from paper_2504_19409_amd.tracking import pose_adam_step, tracking_masks
     st = fr.settings
@@ -190,7 +190,7 @@ def tracking_rate(torch, fr, targets, K, warmup):
 
 def keyframe_rates(torch, fr, K):
     """Durations of the keyframe test's two passes on the frame (Sec. 3.2,
-    Eq. 6): the visibility record of the last forward and the co-visibility
+    Eq. 5): the visibility record of the last forward and the co-visibility
     counts of two records, from HIP events around K launches of each."""
     from paper_2504_19409_amd import _capi
     from paper_2504_19409_amd.rasterizer import _ptr, _stream

@@ -208,7 +208,7 @@ gsff_status gsff_backward(const gsff_gaussians* g, const gsff_camera* cam,
                           const gsff_grads* out, int32_t accumulate, void* stream);
 
 /* Backward of the L1 losses the method optimises (the tracking, mapping and
- * feature losses, Eqs. 5, 8 and 11, are weighted sums of L1 terms):
+ * feature losses, Eqs. 6, 8 and 11, are weighted sums of L1 terms):
  *   L = w[0] mean|rgb - t_rgb| + w[1] mean|depth - t_depth|
  *     + w[2] mean|alpha - t_alpha| + w[3] mean|feat - t_feat|
  * with each mean over its group's elements (3HW, HW, HW, C*HW).  The adjoint
@@ -229,7 +229,7 @@ gsff_status gsff_backward_l1(const gsff_gaussians* g, const gsff_camera* cam,
                              const float* weights, float* loss, const gsff_grads* out,
                              int32_t accumulate, void* stream);
 
-/* Tracking backward (Sec. 3.2 tracking loss, Eq. 5; pose terms Eq. 4): with
+/* Tracking backward (Sec. 3.2 tracking loss, Eq. 6; pose terms Eq. 4): with
  * the Gaussians frozen, the gradient of
  *   L = lambda_t mean(m_v m_e |rgb - t_rgb|) + (1 - lambda_t) mean(m_v |depth - t_depth|)
  * with respect to the pose perturbation only (d_pose [6], rho then theta, as
@@ -283,7 +283,7 @@ gsff_status gsff_adam_step(const gsff_adam_group* groups, int32_t ngroups, int32
                            float beta1, float beta2, float eps, void* stream);
 
 /* Visibility record of the last forward on `ws` (Sec. 3.2 keyframe
- * selection, Eq. 6): visible [P] uint8 on the device receives 1 for every
+ * selection, Eq. 5): visible [P] uint8 on the device receives 1 for every
  * Gaussian blended at some pixel while the transmittance in front of it
  * exceeds t_vis (the paper's 0.5), 0 for every other.  The decisions are the
  * forward's own (same arithmetic on the walk it recorded), so call it after
@@ -301,7 +301,7 @@ gsff_status gsff_visibility(const gsff_gaussians* g, const gsff_camera* cam,
 gsff_status gsff_covisibility(const uint8_t* a, const uint8_t* b, int64_t n, uint32_t* counts,
                               void* stream);
 
-/* The masks of the tracking loss (Sec. 3.2, Eq. 5), uint8 [H,W] on the
+/* The masks of the tracking loss (Sec. 3.2, Eq. 6), uint8 [H,W] on the
  * device, 1 = kept.  mask_e: the edge mask of the target colour image t_rgb
  * [3,H,W] f32: the Sobel gradient of the grey image (mean of the three
  * channels), scaled by 1/8 so that a ramp of slope a per pixel has magnitude
@@ -452,7 +452,7 @@ gsff_status gsff_decoder_query(const void* X, const float* W1, const float* b1, 
                                void* ws, size_t ws_bytes, void* stream);
 
 /* L1 loss of one output group (the tracking / mapping / semantic losses,
- * Eqs. 5, 8 and 11, are weighted L1 terms): grad[i] = scale * sign(x[i] - y[i])
+ * Eqs. 6, 8 and 11, are weighted L1 terms): grad[i] = scale * sign(x[i] - y[i])
  * (0 where equal) and, if loss != NULL, *loss += scale * sum |x - y| (FP32
  * atomics).  n elements, device pointers. */
 gsff_status gsff_l1_grad(const float* x, const float* y, int64_t n, float scale,

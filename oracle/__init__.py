@@ -189,7 +189,7 @@ def render_pixels(params, camera, px, py, settings=None):
 
 
 def visibility(params, camera, t_vis=0.5, rel=0.0, settings=None):
-    """Visibility record of Eq. 6 (blended at some pixel with transmittance
+    """Visibility record of Eq. 5 (blended at some pixel with transmittance
     above t_vis in front): (sure, possible) bool [P]; with rel = 0 both are the
     exact FP64 record, with rel > 0 they bracket any computation whose alpha
     and transmittance are within rel (relative) of the FP64 values."""

@@ -356,7 +356,7 @@ extern "C" int orc_render(const orc_scene* s, const orc_camera* cam,
   return 0;
 }
 
-// Visibility record (Sec. 3.2, Eq. 6): Gaussian i is visible when it is
+// Visibility record (Sec. 3.2, Eq. 5): Gaussian i is visible when it is
 // blended at some pixel while the transmittance in front of it exceeds
 // t_vis.  sure[i] = 1 when that holds with the transmittance above
 // t_vis (1 + rel) and alpha at least alpha_min (1 + rel) at some pixel;

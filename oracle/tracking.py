@@ -1,7 +1,7 @@
 """FP64 numpy oracle of the tracking support (test infrastructure only; only
 ``tests/`` use it).  Shares no code with the HIP path.
 
-Sec. 3.2 (tracking loss, Eq. 5; camera pose optimisation, Eq. 4):
+Sec. 3.2 (tracking loss, Eq. 6; camera pose optimisation, Eq. 4):
 
 * ``edge_mask``         -- m_e: Sobel gradient magnitude of the grey target
                            image (mean of r, g, b), scaled by 1/8 so that a ramp
@@ -46,7 +46,7 @@ def visibility_mask(alpha, threshold):
 
 
 def tracking_upstream(out_rgb, out_depth, t_rgb, t_depth, mask_v, mask_e, lam):
-    """(g_rgb [3,H,W], g_depth [H,W], loss) of Eq. 5; None masks keep every
+    """(g_rgb [3,H,W], g_depth [H,W], loss) of Eq. 6; None masks keep every
     pixel.  The colour term is weighted by m_v m_e, the depth term by m_v;
     each mean runs over all of its elements (3HW, HW)."""
     o_c = np.asarray(out_rgb, np.float64)

@@ -798,7 +798,7 @@ hipError_t launch_adjoint_items(const Layout& L, const WsView& w, hipStream_t s)
   return hipGetLastError();
 }
 
-// Visibility record (Sec. 3.2 keyframe selection, Eq. 6): v_i = 1 when
+// Visibility record (Sec. 3.2 keyframe selection, Eq. 5): v_i = 1 when
 // Gaussian i is blended at some pixel while the transmittance in front of it
 // exceeds t_vis.  One workgroup per tile replays the forward's walk of the
 // tile's list (the ids it recorded, up to its walk end) in batches of 64 with
@@ -1002,7 +1002,7 @@ constexpr int kBwdMaxChannels = 64;     // feature channels of a feature-only pa
 
 
 // Upstream gradient formed inside the adjoint for the L1 losses of the
-// method (Eqs. 5, 8, 11 are weighted sums of L1 terms):
+// method (Eqs. 6, 8, 11 are weighted sums of L1 terms):
 //   L = sum_k w_k * mean|out_k - target_k|  over the groups rgb, depth, alpha,
 // feature; the per-element gradient is (w_k / numel_k) sign(out - target).
 // A group with a NULL target does not enter the loss.
@@ -1025,7 +1025,7 @@ struct L1Upstream {
 // formed once per adjoint call: plane 0 holds r, g, b, depth, alpha at bits
 // 0-9, plane 1 + k the feature channels 16 k .. 16 k + 15.  Groups without a
 // target are zero, and so are the colour and depth groups of a pixel the
-// tracking masks leave out (Eq. 5: m_v m_e on colour, m_v on depth).  The
+// tracking masks leave out (Eq. 6: m_v m_e on colour, m_v on depth).  The
 // pass also adds the loss.
 //
 // The same launch does the adjoint's other set-up, which shares no data with

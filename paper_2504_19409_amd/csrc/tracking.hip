@@ -1,5 +1,5 @@
 // Tracking support (Sec. 3.2, camera pose optimisation and tracking loss):
-// the two per-pixel masks of the tracking loss (Eq. 5) and the pose step that
+// the two per-pixel masks of the tracking loss (Eq. 6) and the pose step that
 // turns the pose gradient of Eq. 4 into the next camera pose.
 //
 // Masks.  m_e keeps the pixels where the target colour image has a strong

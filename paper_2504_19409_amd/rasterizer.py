@@ -182,7 +182,7 @@ class Frame:
 
     def visibility(self, t_vis=0.5, out=None):
         """uint8 [P]: 1 for the Gaussians the last forward blended at a pixel
-        with transmittance above t_vis in front of them (Eq. 6)."""
+        with transmittance above t_vis in front of them (Eq. 5)."""
         out = out if out is not None else torch.empty(self.P, dtype=torch.uint8,
                                                       device=self.device)
         L = _capi.load()
@@ -192,7 +192,7 @@ class Frame:
 
     def backward_tracking(self, outs, t_rgb, t_depth, mask_v, mask_e, lambda_t, d_pose,
                           loss=None, accumulate=False):
-        """Pose gradient of the tracking loss (Eq. 5) with the Gaussians frozen:
+        """Pose gradient of the tracking loss (Eq. 6) with the Gaussians frozen:
         lambda_t mean(m_v m_e |rgb - t_rgb|) + (1 - lambda_t) mean(m_v |depth -
         t_depth|).  Masks are uint8 [H, W] (None keeps every pixel); d_pose [6]
         receives (rho, theta)."""

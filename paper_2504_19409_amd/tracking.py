@@ -1,5 +1,5 @@
 """Camera tracking on the rasterizer (Sec. 3.2): the masks of the tracking
-loss (Eq. 5), the pose step on the left increment of Eq. 4, and the loop that
+loss (Eq. 6), the pose step on the left increment of Eq. 4, and the loop that
 iterates render -> pose gradient -> pose step until the increment converges.
 
 Every step runs in libgsff kernels on the current stream; the loop reads the
@@ -62,7 +62,7 @@ def is_keyframe(vis_frame, vis_keyframe, tau_thresh: float) -> bool:
 
 @dataclass
 class TrackingConfig:
-    lambda_t: float = 0.9          # weight of the colour term (Eq. 5)
+    lambda_t: float = 0.9          # weight of the colour term (Eq. 6)
     edge_threshold: float = 0.01   # m_e: grey-level gradient per pixel
     vis_threshold: float = 0.5     # m_v: accumulated opacity of the first render
     lr_trans: float = 1e-3

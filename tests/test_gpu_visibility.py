@@ -1,4 +1,4 @@
-"""GPU parity of the visibility record (Eq. 6) and the co-visibility counts of
+"""GPU parity of the visibility record (Eq. 5) and the co-visibility counts of
 the keyframe test (Sec. 3.2) through the C ABI.
 
 The record is a set decided by floating point (alpha against alpha_min, the

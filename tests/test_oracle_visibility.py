@@ -1,4 +1,4 @@
-"""Pins of the oracle's visibility record (Sec. 3.2 keyframe selection, Eq. 6):
+"""Pins of the oracle's visibility record (Sec. 3.2 keyframe selection, Eq. 5):
 a Gaussian is visible when it is blended at some pixel while the transmittance
 in front of it exceeds the threshold.  CPU only."""
 import math
