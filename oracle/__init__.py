@@ -97,6 +97,8 @@ def lib():
         L.orc_tile_lists.restype = ctypes.c_int64
         L.orc_work_counts.argtypes = [sp, cp, stp, ctypes.c_int32, vp]
         L.orc_work_counts.restype = ctypes.c_int
+        L.orc_ambiguous.argtypes = [sp, cp, stp, ctypes.c_double, ctypes.c_int64, vp, vp, vp]
+        L.orc_ambiguous.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -255,3 +257,23 @@ def work_counts(params, camera, tile=16, settings=None):
         raise ValueError("orc_work_counts failed")
     return dict(pairs=int(out[0]), evals=int(out[1]), tile_evals=int(out[2]),
                 contribs=int(out[3]))
+
+
+def ambiguous(params, camera, thr, settings=None, px=None, py=None):
+    """bool [P]: the Gaussians evaluated at a pixel with a decision within
+    relative distance ``thr`` of its threshold, and the one such a pixel would
+    blend next after its stop (see orc_ambiguous); only the listed pixels
+    when px / py are given."""
+    m = _Marshal(params, camera)
+    st = settings or default_settings()
+    flags = np.zeros(m.P, dtype=np.uint8)
+    n = 0
+    if px is not None:
+        px = np.ascontiguousarray(px, dtype=np.int32)
+        py = np.ascontiguousarray(py, dtype=np.int32)
+        n = px.size
+    rc = lib().orc_ambiguous(ctypes.byref(m.scene), ctypes.byref(m.camera), ctypes.byref(st),
+                             float(thr), n, _ptr(px), _ptr(py), _ptr(flags))
+    if rc != 0:
+        raise ValueError("orc_ambiguous failed")
+    return flags.astype(bool)

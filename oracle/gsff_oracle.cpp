@@ -36,6 +36,12 @@
 
 namespace {
 
+// Pairs just outside a Gaussian's exact support box, with alpha up to this
+// fraction below alpha_min, are evaluated for the decision margins and the
+// flag sets (visibility bracket, ambiguity) only: a lower-precision alpha can
+// reach alpha_min there.  They never change a result.
+constexpr double kWide = 1e-2;
+
 struct Proj {
   bool valid = false;
   double mc[3] = {0, 0, 0};  // camera-space mean
@@ -44,6 +50,7 @@ struct Proj {
   double A = 0, B = 0, Cc = 0;     // conic = Sigma'^-1
   double o = 0;                    // activated opacity
   double rx = 0, ry = 0;           // exact half-widths of the support box
+  double rxw = 0, ryw = 0;         // the same for alpha_min (1 - kWide)
   float key = 0;                   // depth sort key
   // kept for the backward pass
   double s[3] = {0, 0, 0};
@@ -173,6 +180,9 @@ Proj project_one(const orc_scene* s, const orc_camera* cam, const orc_settings* 
   const double k2 = 2.0 * std::log(g.o / st->alpha_min);
   g.rx = std::sqrt(k2 * g.a);
   g.ry = std::sqrt(k2 * g.c);
+  const double k2w = 2.0 * std::log(g.o / (st->alpha_min * (1.0 - kWide)));
+  g.rxw = std::sqrt(k2w * g.a);
+  g.ryw = std::sqrt(k2w * g.c);
   g.valid = true;
   return g;
 }
@@ -207,17 +217,21 @@ void prepare(const orc_scene* s, const orc_camera* cam, const orc_settings* st,
   pr.rows.assign(cam->height, {});
   for (int64_t i : pr.order) {
     const Proj& g = pr.proj[i];
-    long y0 = (long)std::floor(g.v - g.ry - 0.5) - 1;
-    long y1 = (long)std::ceil(g.v + g.ry - 0.5) + 1;
+    long y0 = (long)std::floor(g.v - g.ryw - 0.5) - 1;
+    long y1 = (long)std::ceil(g.v + g.ryw - 0.5) + 1;
     y0 = std::max(0L, y0);
     y1 = std::min((long)cam->height - 1, y1);
     for (long py = y0; py <= y1; ++py)
-      if (std::fabs(py + 0.5 - g.v) <= g.ry) pr.rows[py].push_back(i);
+      if (std::fabs(py + 0.5 - g.v) <= g.ryw) pr.rows[py].push_back(i);
   }
 }
 
 inline bool covers(const Proj& g, long px, long py) {
   return std::fabs(px + 0.5 - g.u) <= g.rx && std::fabs(py + 0.5 - g.v) <= g.ry;
+}
+
+inline bool covers_wide(const Proj& g, long px, long py) {
+  return std::fabs(px + 0.5 - g.u) <= g.rxw && std::fabs(py + 0.5 - g.v) <= g.ryw;
 }
 
 // One evaluated (pixel, Gaussian) pair.
@@ -234,8 +248,9 @@ struct NoEval {
 
 // Front-to-back blending at one pixel (Eqs. 2-3).  Calls on_contrib(e, T)
 // for every contributor with the transmittance in front of it (and, when
-// given, on_eval(e, T) for every evaluated pair before its decision); returns
-// the final transmittance.  Tracks decision margins and a decision signature.
+// given, on_eval(e, T) for every evaluated pair before its decision, the
+// pairs just outside the exact support box included); returns the final
+// transmittance.  Tracks decision margins and a decision signature.
 template <class F, class G = NoEval>
 double composite_pixel(const Prepared& pr, const orc_settings* st, long px, long py,
                        F&& on_contrib, double* margin, uint64_t* hash,
@@ -244,7 +259,7 @@ double composite_pixel(const Prepared& pr, const orc_settings* st, long px, long
   double mg = INFINITY;
   for (int64_t i : pr.rows[py]) {
     const Proj& g = pr.proj[i];
-    if (!covers(g, px, py)) continue;
+    if (!covers_wide(g, px, py)) continue;
     Eval e;
     e.i = i;
     e.dx = g.u - (px + 0.5);
@@ -254,6 +269,12 @@ double composite_pixel(const Prepared& pr, const orc_settings* st, long px, long
     e.oG = g.o * e.G;
     e.clamped = !(e.oG < st->alpha_max);
     e.alpha = e.clamped ? st->alpha_max : e.oG;
+    if (!covers(g, px, py)) {
+      // outside the exact box alpha < alpha_min: skipped, margin only
+      mg = std::min(mg, std::fabs(e.alpha - st->alpha_min) / st->alpha_min);
+      on_eval(e, T);
+      continue;
+    }
     if (n_eval) ++*n_eval;
     on_eval(e, T);
     mg = std::min(mg, std::fabs(e.alpha - st->alpha_min) / st->alpha_min);
@@ -384,6 +405,67 @@ extern "C" int orc_visibility(const orc_scene* s, const orc_camera* cam,
             if (Tin > t_vis * (1.0 - rel) && e.alpha >= st->alpha_min * (1.0 - rel))
               possible[e.i] = 1;
           });
+  return 0;
+}
+
+// Gaussians whose gradient a lower-precision computation may legitimately
+// take differently.  A pixel is ambiguous when some skip, clamp or stop
+// decision there lies within relative distance `thr` of its threshold (the
+// pixel's margin, as orc_render reports it).  Flagged: every Gaussian
+// evaluated at an ambiguous pixel, and after its stop every Gaussian the
+// pixel could still reach if decisions went the other way (taken as the
+// transmittance in front of the stopping Gaussian raised by 1%, more than two
+// skipped Gaussians at alpha_min restore, and alpha thresholds lowered by
+// thr).  Everywhere else both computations take every decision alike, so the
+// gradients agree to rounding.  flags[i] = 1 for a flagged Gaussian.
+extern "C" int orc_ambiguous(const orc_scene* s, const orc_camera* cam,
+                             const orc_settings* st, double thr, int64_t n,
+                             const int32_t* pxs, const int32_t* pys, uint8_t* flags) {
+  if (!check_args(s, cam, st) || (s->P > 0 && !flags)) return -1;
+  if ((pxs == nullptr) != (pys == nullptr) || (pxs && n < 0) || !(thr < kWide)) return -1;
+  Prepared pr;
+  prepare(s, cam, st, pr);
+  for (int64_t i = 0; i < s->P; ++i) flags[i] = 0;
+  std::vector<int64_t> walked;
+  const int64_t npx = pxs ? n : (int64_t)cam->width * cam->height;
+  for (int64_t k = 0; k < npx; ++k) {
+    const long px = pxs ? pxs[k] : (long)(k % cam->width);
+    const long py = pxs ? pys[k] : (long)(k / cam->width);
+    if (px < 0 || px >= cam->width || py < 0 || py >= cam->height) return -1;
+    walked.clear();
+    double mg, T_last = 1.0;
+    composite_pixel(
+        pr, st, px, py, [](const Eval&, double) {}, &mg, nullptr, nullptr,
+        [&](const Eval& e, double Tin) {
+          walked.push_back(e.i);
+          T_last = Tin;
+        });
+    if (!(mg < thr)) continue;
+    for (int64_t i : walked) flags[i] = 1;
+    if (walked.empty()) continue;
+    // past the last evaluated Gaussian: those the pixel could still reach
+    double Tw = T_last * 1.01;
+    bool past = false;
+    for (int64_t i : pr.rows[py]) {
+      const Proj& g = pr.proj[i];
+      if (!covers_wide(g, px, py)) continue;
+      const double dx = g.u - (px + 0.5), dy = g.v - (py + 0.5);
+      const double power = -0.5 * (g.A * dx * dx + 2.0 * g.B * dx * dy + g.Cc * dy * dy);
+      const double oG = g.o * std::exp(power);
+      const double alpha = oG < st->alpha_max ? oG : st->alpha_max;
+      if (!past) {
+        if (i == walked.back()) {
+          past = true;
+          if (alpha >= st->alpha_min * (1.0 - thr)) Tw *= 1.0 - alpha;
+        }
+        continue;
+      }
+      if (alpha < st->alpha_min * (1.0 - thr)) continue;
+      if (Tw < st->t_min * (1.0 - thr)) break;
+      flags[i] = 1;
+      Tw *= 1.0 - alpha;
+    }
+  }
   return 0;
 }
 

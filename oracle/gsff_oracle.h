@@ -90,6 +90,16 @@ int orc_visibility(const orc_scene* s, const orc_camera* cam, const orc_settings
 int orc_render_pixels(const orc_scene* s, const orc_camera* cam, const orc_settings* st,
                       int64_t n, const int32_t* px, const int32_t* py, double* out);
 
+/* flags[i] = 1 for every Gaussian evaluated at a pixel with a skip / clamp /
+ * stop decision within relative distance thr of its threshold, and for the
+ * Gaussian such a pixel would blend next after its stop; 0 for every other.
+ * Outside the flagged set a computation whose alpha and transmittance are
+ * within thr of these takes every decision alike.  px / py (n entries) list
+ * the pixels to examine; both NULL examines every pixel. */
+int orc_ambiguous(const orc_scene* s, const orc_camera* cam, const orc_settings* st,
+                  double thr, int64_t n, const int32_t* px, const int32_t* py,
+                  uint8_t* flags);
+
 /* Gradient of  sum(g_rgb*rgb) + sum(g_depth*depth) + sum(g_alpha*alpha)
  *            + sum(g_feat*feat)  with respect to every input.
  * Outputs are overwritten.  g_feat may be NULL (treated as zero).  d2d, if not

@@ -85,6 +85,7 @@ def _oracle(sc, orc, settings=None, ups=None, feat=None):
     if ups is not None:
         g = dict(g_rgb=ups[0], g_depth=ups[1], g_alpha=ups[2], g_feat=ups[3])
         o["grads"] = orc.backward(p, c, g, settings)
+        o["amb"] = orc.ambiguous(p, c, H.MARGIN, settings)
     return o
 
 
@@ -98,7 +99,7 @@ def _check_forward(res, o, tol=H.TOL_FWD, keys=("rgb", "depth", "alpha", "feat")
         assert H.rel_l2(g, r) <= tol, (k, H.rel_l2(g, r))
         # element-wise: only decision-ambiguous pixels may be off
         mask = np.broadcast_to(~amb, r.shape)
-        assert H.elementwise_outliers(g, r, 1e-3, mask) == 0, k
+        assert H.elementwise_outliers(g, r, 1e-4, mask) == 0, k
     # few pixels may be excluded: with ~80 alpha evaluations per pixel about 0.1% of
     # pixels hold a decision within MARGIN of a threshold; cap at 0.2% (or a handful
     # on small images).  The relative-L2 gate above still covers every pixel.
@@ -106,14 +107,9 @@ def _check_forward(res, o, tol=H.TOL_FWD, keys=("rgb", "depth", "alpha", "feat")
 
 
 def _check_backward(res, o, tol=H.TOL_GRAD, keys=GRAD_KEYS):
-    for k in keys:
-        if k not in res["grads"]:
-            continue
-        g, r = res["grads"][k], o["grads"][k]
-        if r.size == 0 or not np.any(r):
-            assert not np.any(g), k
-            continue
-        assert H.rel_l2(g, r) <= tol, (k, H.rel_l2(g, r))
+    """Relative L2 per group and element by element on every Gaussian the
+    oracle does not flag as decision-ambiguous (o["amb"])."""
+    H.check_grads(res["grads"], o["grads"], keys, flags=o.get("amb"), tol=tol)
 
 
 # ---------------------------------------------------------------- stages ----
@@ -335,7 +331,8 @@ def test_feature_gradient_stays_on_its_own_path(orc):
     p, c = orc.scene_dicts(sc)
     ob = orc.backward(p, c, dict(g_rgb=np.zeros((3, Hh, W)), g_depth=np.zeros((Hh, W)),
                                  g_alpha=np.zeros((Hh, W)), g_feat=gf.cpu().numpy()))
-    assert H.rel_l2(grads["feat"].cpu().numpy(), ob["feat"]) <= H.TOL_GRAD
+    H.check_grads({"feat": grads["feat"].cpu().numpy()}, ob, ["feat"],
+                  flags=orc.ambiguous(p, c, H.MARGIN))
     # geometry gradients do not depend on the feature upstream or the feature flag
     ups = [torch.from_numpy(a).cuda() for a in sg.upstream_signs(rng, W, Hh, C)]
     g1 = fr.make_grads()
@@ -531,29 +528,29 @@ def test_autograd_function(orc):
     loss.backward()
     p, c = orc.scene_dicts(sc)
     ob = orc.backward(p, c, dict(g_rgb=ups[0], g_depth=ups[1], g_alpha=ups[2], g_feat=ups[3]))
-    for k, t in leaves.items():
-        assert H.rel_l2(t.grad.cpu().numpy(), ob[k]) <= H.TOL_GRAD, k
-    assert H.rel_l2(tangent.grad.cpu().numpy(), ob["pose"]) <= H.TOL_GRAD
+    got = {k: t.grad.cpu().numpy() for k, t in leaves.items()}
+    got["pose"] = tangent.grad.cpu().numpy()
+    H.check_grads(got, ob, GRAD_KEYS, flags=orc.ambiguous(p, c, H.MARGIN))
 
 
 # ------------------------------------------------------- fused L1 adjoint ----
 
-@pytest.mark.parametrize("kind,C,weights", [("tiny", 16, (1.0, 1.0, 0.0, 1.0)),
-                                            ("ragged", 5, (0.7, 0.3, 0.2, 2.0)),
-                                            ("tiny", 80, (1.0, 0.5, 0.0, 1.0))])
-def test_backward_l1_fused_upstream(orc, kind, C, weights):
+def _l1_case(orc, sc, weights, seed=17, max_pairs=None, report=None):
     """gsff_backward_l1 forms (w_k / numel_k) sign(out - target) inside the
     adjoint; the oracle gets that same upstream explicitly, formed from its
-    own render.  Targets keep a margin from the outputs so that no sign
+    own render.  Targets keep a margin from the oracle's outputs (1e-3, and
+    0.05 at pixels with a decision near its threshold) so that no sign
     depends on the rounding of either side."""
-    sc = _scene(kind, C=C)
     p, c = orc.scene_dicts(sc)
     ref = orc.render(p, c)
     o = [ref["rgb"], ref["depth"], ref["alpha"], ref["feat"]]
-    rng = np.random.default_rng(17)
-    targets_np = [H.targets_away(rng, x) for x in o]
-    fr, _ = H.make_frame(sc, torch)
+    amb_px = ref["margin"] < H.MARGIN
+    rng = np.random.default_rng(seed)
+    margin = np.where(amb_px, 0.05, 1e-3)
+    targets_np = [H.targets_away(rng, x, margin) for x in o]
+    fr, _ = H.make_frame(sc, torch, max_pairs=max_pairs)
     outs = fr.forward()
+    assert fr.read_status()[0] == 0
     targets = [torch.from_numpy(t).cuda() for t in targets_np]
     if weights[2] == 0.0:
         targets[2] = None
@@ -561,18 +558,58 @@ def test_backward_l1_fused_upstream(orc, kind, C, weights):
     grads = fr.make_grads()
     fr.backward_l1(outs, targets, weights, grads, loss)
     torch.cuda.synchronize()
-    ups, ref_loss = [], 0.0
-    for k, (x, t) in enumerate(zip(o, targets_np)):
-        if targets[k] is None or weights[k] == 0.0:
-            ups.append(np.zeros_like(x))
-            continue
-        scale = weights[k] / x.size
-        ups.append(scale * np.sign(x - t))
-        ref_loss += scale * np.abs(x - t).sum()
+    ups, ref_loss = H.l1_upstream(o, [None if t is None else tn
+                                     for t, tn in zip(targets, targets_np)], weights)
     assert loss.item() == pytest.approx(ref_loss, rel=2e-5)
     ob = orc.backward(p, c, dict(g_rgb=ups[0], g_depth=ups[1], g_alpha=ups[2], g_feat=ups[3]))
-    for k in GRAD_KEYS:
-        assert H.rel_l2(grads[k].cpu().numpy(), ob[k]) <= H.TOL_GRAD, k
+    amb = orc.ambiguous(p, c, H.MARGIN)
+    H.check_grads({k: v.cpu().numpy() for k, v in grads.items()}, ob, GRAD_KEYS, flags=amb,
+                  report=report)
+    return fr
+
+
+@pytest.mark.parametrize("kind,C,weights", [("tiny", 16, (1.0, 1.0, 0.0, 1.0)),
+                                            ("ragged", 5, (0.7, 0.3, 0.2, 2.0)),
+                                            ("tiny", 80, (1.0, 0.5, 0.0, 1.0))])
+def test_backward_l1_fused_upstream(orc, kind, C, weights):
+    _l1_case(orc, _scene(kind, C=C), weights)
+
+
+def test_backward_l1_full_frame(orc):
+    """The benchmark's own path: 200k Gaussians, 640x480, 16-ch FP32, pose
+    perturbed 1 cm / 1 degree, the fused-L1 adjoint with dense targets and
+    the benchmark's loss weights and pair capacity, against the oracle on
+    every output and every gradient element."""
+    sc, _ = sg.workload_scene("frame")
+    fr, _ = H.make_frame(sc, torch)
+    fr.forward()
+    flags, n = fr.read_status()
+    assert flags == 0
+    rep = {}
+    _l1_case(orc, sc, (1.0, 1.0, 0.0, 1.0), seed=29, max_pairs=int(n * 1.05) + 4096,
+             report=rep)
+    print("full-frame fused-L1 gradients:", rep, flush=True)
+
+
+def test_rows_overflow_falls_back_to_atomics(orc):
+    """A few hundred large faint splats on a 320x240 image walk far more
+    (tile, Gaussian) pairs than the adjoint's partial-row capacity
+    (2P + 4096 rows): the tiles whose rows do not fit add their sums
+    directly.  Both kinds of tile in one frame, against the oracle."""
+    sc = sg.make_scene(300, 320, 240, 260.0, 260.0, 160.0, 120.0, 8, seed=41)
+    sc.log_scales += 1.8
+    sc.logit_opacity = np.full_like(sc.logit_opacity, -3.0)
+    res = _run(sc, orc)
+    fr = res["frame"]
+    lay = fr.layout
+    nt = lay.tiles_x * lay.tiles_y
+    rng = fr.ws_view("tile_list_ranges", torch.int32, 2 * nt).cpu().numpy().reshape(nt, 2)
+    walked = int((rng[:, 1] - rng[:, 0]).sum())
+    row_cap = 2 * sc.P + 4096
+    assert walked > 2 * row_cap, (walked, row_cap)  # many tiles without rows
+    o = _oracle(sc, orc, ups=res["ups"])
+    _check_forward(res, o)
+    _check_backward(res, o)
 
 
 @pytest.mark.parametrize("kind,C", [("ragged", 5), ("dense", 16)])
@@ -633,5 +670,6 @@ def test_backward_l1_feature_only(orc):
     z = np.zeros((sc.camera.height, sc.camera.width))
     ob = orc.backward(p, c, dict(g_rgb=np.zeros((3,) + z.shape), g_depth=z, g_alpha=z,
                                  g_feat=up))
-    assert H.rel_l2(grads["feat"].cpu().numpy(), ob["feat"]) <= H.TOL_GRAD
+    H.check_grads({"feat": grads["feat"].cpu().numpy()}, ob, ["feat"],
+                  flags=orc.ambiguous(p, c, H.MARGIN))
     assert loss.item() == pytest.approx(np.abs(of - t_feat).mean(), rel=2e-5)

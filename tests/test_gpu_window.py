@@ -75,12 +75,15 @@ def test_window_parity_vs_oracle():
     # sign of out - target depends on rounding; the upstream comes from the
     # oracle's render
     refs = []
+    amb = np.zeros(sc.P, dtype=bool)
     for v, cam in enumerate(cams):
         r = oracle.render(p, cam)
         o = [r["rgb"], r["depth"], r["alpha"], r["feat"]]
+        margin = np.where(r["margin"] < H.MARGIN, 0.05, 1e-3)
         for k in (0, 1, 3):
-            win.targets[v][k].copy_(torch.from_numpy(H.targets_away(rng, o[k])))
+            win.targets[v][k].copy_(torch.from_numpy(H.targets_away(rng, o[k], margin)))
         refs.append(o)
+        amb |= oracle.ambiguous(p, cam, H.MARGIN)
     win.run()
     torch.cuda.synchronize()
     total = {k: np.zeros(np.shape(p[k]) if k != "feat" else sc.feat.shape) for k in GEO}
@@ -95,6 +98,5 @@ def test_window_parity_vs_oracle():
                                           g_feat=ups[3]))
         for k in GEO:
             total[k] += ob[k]
-        assert H.rel_l2(win.pose[v].cpu().numpy(), ob["pose"]) <= H.TOL_GRAD, v
-    for k in GEO:
-        assert H.rel_l2(win.grads[k].cpu().numpy(), total[k]) <= H.TOL_GRAD, k
+        H.check_grads({"pose": win.pose[v].cpu().numpy()}, ob, ["pose"])
+    H.check_grads({k: win.grads[k].cpu().numpy() for k in GEO}, total, GEO, flags=amb)
