@@ -44,6 +44,17 @@ VALU_PEAK_TSLOTS = 256 * 4 * 16 * 2.4e9 / 1e12
 # LDS delivery peak: 128 bytes per clock per CU x 256 CUs x 2.4 GHz, in TB/s
 LDS_PEAK_TBS = 128 * 256 * 2.4e9 / 1e12
 
+# What the timed step computes in: the inputs, outputs and gradients are
+# FP32; alpha, transmittance and every decision are FP32 VALU arithmetic; the
+# blending sums (colour, depth, features) and the adjoint's per-tile
+# contraction run on BF16 matrix cores with each FP32 operand split into a
+# high and a low BF16 part (three products, FP32 accumulation: about 2^-16
+# relative per product); depth keys and the pose sum are FP64.
+DTYPE_LABEL = "f32 (blend sums: bf16x3 split MFMA, f32 accumulate)"
+ARITHMETIC = ("FP32 alpha/transmittance/decisions; colour, depth and feature blend sums and "
+              "the adjoint contraction as BF16 hi/lo split MFMA (hi*hi + lo*hi + hi*lo) with "
+              "FP32 accumulation; FP64 depth keys and pose sum")
+
 STAGES = ["preprocess", "sort_depth", "bin", "sort_tiles", "tile_ranges", "composite_fwd",
           "composite_bwd_l1", "preprocess_bwd"]
 L1_WEIGHTS = (1.0, 1.0, 0.0, 1.0)  # rgb, depth, alpha, feature
@@ -140,7 +151,7 @@ def tracking_rate(torch, fr, targets, K, warmup):
     pose toward the targets: forward without features, the pose-only adjoint
     of the masked tracking loss (Eq. 6) and the pose step, replayed from a HIP
     graph (the captured step keeps one Adam step count; timing only)."""
-    from paper_2504_19409_amd.tracking import pose_adam_step, tracking_masks
+    from paper_2504_19409_amd.tracking import pose_adam_step, pose_state, tracking_masks
     st = fr.settings
     keep_feat = st.render_features
     vm = fr.tensors[-1]
@@ -153,7 +164,7 @@ def tracking_rate(torch, fr, targets, K, warmup):
         # edge threshold: keeps about 30% of this frame's pixels
         mv, me = tracking_masks(targets[0], alpha, 0.0025, 0.5)
         dev = rgb.device
-        d_pose, state = torch.zeros(6, device=dev), torch.zeros(12, device=dev)
+        d_pose, state = torch.zeros(6, device=dev), pose_state(dev)
         delta, loss = torch.zeros(6, device=dev), torch.zeros(1, device=dev)
 
         def iteration(step):
@@ -292,10 +303,20 @@ def algorithmic_work(scene, n_pairs, torch):
     return wc, dict(P=P, C=C, HW=HW, n_pairs=n_pairs)
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(scene, budget_s):
     """The FP64 oracle (single-threaded C++) on whole frames of the same
     workload: forward + backward with an L1-shaped upstream, repeated until the
-    time budget is spent."""
+    time budget is spent, with this process pinned to one host core."""
     import oracle
     from paper_2504_19409_amd import scenegen as sg
     oracle.build(force=False)
@@ -304,18 +325,26 @@ def cpu_baseline(scene, budget_s):
     W, H, C = scene.camera.width, scene.camera.height, scene.C
     gr, gd, ga, gf = sg.upstream_signs(rng, W, H, C)
     g = dict(g_rgb=gr, g_depth=gd, g_alpha=ga, g_feat=gf)
-    n = 0
-    t0 = time.perf_counter()
-    while True:
-        oracle.render(p, c)
-        oracle.backward(p, c, g)
-        n += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s:
-            break
+    allowed = sorted(os.sched_getaffinity(0))
+    core = allowed[-1]
+    os.sched_setaffinity(0, {core})
+    try:
+        n = 0
+        t0 = time.perf_counter()
+        while True:
+            oracle.render(p, c)
+            oracle.backward(p, c, g)
+            n += 1
+            el = time.perf_counter() - t0
+            if el >= budget_s:
+                break
+    finally:
+        os.sched_setaffinity(0, set(allowed))
     return dict(value=n / el, unit="it/s", cores=1, kind="oracle",
                 sample=f"{n} full 640x480 / 200k-Gaussian / 16-ch frames, forward + backward, "
-                       f"FP64 single-threaded C++ oracle, {el:.1f} s")
+                       f"FP64 single-threaded C++ oracle pinned to core {core}, {el:.1f} s",
+                host_cores=os.cpu_count(), host_cores_allowed=len(allowed),
+                cpu_model=_cpu_model())
 
 
 def main():
@@ -359,14 +388,14 @@ def main():
         step.run(ev[k])
     torch.cuda.synchronize()
     eager_ms = (time.perf_counter() - t0) / K * 1e3
-    stage_ms = {s: float(np.mean([ev[k][i].elapsed_time(ev[k][i + 1]) for k in range(K)]))
+    stage_ms = {s: float(np.median([ev[k][i].elapsed_time(ev[k][i + 1]) for k in range(K)]))
                 for i, s in enumerate(STAGES)}
     log("eager ms/step %.4f" % eager_ms)
     for s in STAGES:
         log(f"  {s:16s} {stage_ms[s] * 1e3:9.1f} us")
 
     # the same step replayed from a HIP graph (launch overhead removed)
-    graph_ms = None
+    graph_ms, graph_dist = None, None
     if not args.no_graph:
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
@@ -388,12 +417,22 @@ def main():
         for _ in range(args.warmup):
             g.replay()
         torch.cuda.synchronize()
+        # per-replay events (median, p10, p90) inside the wall-clock bracket
+        gev = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(K):
+        gev[0].record()
+        for k in range(K):
             g.replay()
+            gev[k + 1].record()
         torch.cuda.synchronize()
         graph_ms = (time.perf_counter() - t0) / K * 1e3
-        log("graph ms/step %.4f" % graph_ms)
+        per = np.array([gev[k].elapsed_time(gev[k + 1]) for k in range(K)])
+        graph_dist = {"median_ms": round(float(np.median(per)), 4),
+                      "p10_ms": round(float(np.percentile(per, 10)), 4),
+                      "p90_ms": round(float(np.percentile(per, 90)), 4)}
+        log("graph ms/step %.4f (median %.4f, p10 %.4f, p90 %.4f)"
+            % (graph_ms, graph_dist["median_ms"], graph_dist["p10_ms"], graph_dist["p90_ms"]))
 
     ms = min(eager_ms, graph_ms) if graph_ms else eager_ms
     value = 1e3 / ms
@@ -417,13 +456,15 @@ def main():
         "metric": "fwd+bwd render iterations/sec at 640x480, 200k Gaussians, 16-ch features",
         "value": round(value, 2), "unit": "it/s", "n_gpus": 1, "steps": K,
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": DTYPE_LABEL, "data": "synthetic",
         "config": {"workload": "tracking/mapping frame: 200k Gaussians, 640x480, fx=fy=525, "
                                "RGB+depth+alpha+16-ch FP32 features, pose perturbed 1 cm/1 deg",
                    "gaussians": scene.P, "width": 640, "height": 480, "channels": 16,
+                   "arithmetic": ARITHMETIC,
                    "timing": "graph replay" if graph_ms and graph_ms < eager_ms else "eager",
                    "eager_ms": round(eager_ms, 4),
                    "graph_ms": round(graph_ms, 4) if graph_ms else None,
+                   "graph_replay_dist": graph_dist,
                    "stage_us": {s: round(v * 1e3, 1) for s, v in stage_ms.items()},
                    "pairs": n_pairs, "work": wc, "slam": slam},
         "roofline": roof,

@@ -301,6 +301,19 @@ gsff_status gsff_visibility(const gsff_gaussians* g, const gsff_camera* cam,
 gsff_status gsff_covisibility(const uint8_t* a, const uint8_t* b, int64_t n, uint32_t* counts,
                               void* stream);
 
+/* Keyframe test (Sec. 3.2 keyframe selection): the frame becomes a keyframe
+ * when the IoU of its visibility record frame_vis with the last keyframe's
+ * record keyframe_vis ([n] uint8, non-zero = visible) is below tau_thresh.
+ * counts [2] receive |a and b| and |a or b| (as gsff_covisibility) and
+ * keyframe [1] receives 1 for a keyframe, else 0; the IoU (1 when both
+ * records are empty) is formed and compared in FP64 on the device, so the
+ * decision needs no host round trip.  Device pointers.  Errors:
+ * GSFF_ERR_INVALID_ARGUMENT for a NULL counts or keyframe, a non-finite
+ * tau_thresh, or the arguments gsff_covisibility rejects. */
+gsff_status gsff_keyframe_test(const uint8_t* frame_vis, const uint8_t* keyframe_vis, int64_t n,
+                               float tau_thresh, uint32_t* counts, uint32_t* keyframe,
+                               void* stream);
+
 /* The masks of the tracking loss (Sec. 3.2, Eq. 6), uint8 [H,W] on the
  * device, 1 = kept.  mask_e: the edge mask of the target colour image t_rgb
  * [3,H,W] f32: the Sobel gradient of the grey image (mean of the three
@@ -315,20 +328,43 @@ gsff_status gsff_tracking_masks(const float* t_rgb, const float* alpha, int32_t 
                                 int32_t height, float edge_threshold, float vis_threshold,
                                 uint8_t* mask_v, uint8_t* mask_e, void* stream);
 
+/* Convergence test of the tracking loop (Sec. 3.2: the pose iterations of
+ * a frame end when the changes of the camera-frame means and of the rotation
+ * have converged).  Every `window` steps the pose step measures the net
+ * motion T_now T_start^-1 over the window (T_start: the pose when the window
+ * began): its rotation angle (radians) against tol_rot and the length of its
+ * translation (the shift of the camera-frame position of the world origin,
+ * in the units of the means) against tol_trans. */
+typedef struct gsff_pose_convergence {
+  int32_t window;   /* steps per test, >= 1 */
+  float tol_trans;  /* >= 0 */
+  float tol_rot;    /* >= 0, radians */
+} gsff_pose_convergence;
+
+/* Floats of pose-step state (Adam moments, window start, converged flag). */
+#define GSFF_POSE_STATE_FLOATS 32
+
 /* One pose step of the tracking loop (Sec. 3.2; the increment is the left
  * perturbation of Eq. 4).  d_pose [6] (rho, theta) is the gradient from
- * gsff_backward_tracking; state [12] holds Adam's first and second moments
- * (zero before step 1); step counts from 1.  The increment
- * delta_k = -lr_k mhat_k / (sqrt(vhat_k) + eps) (lr_trans for rho, lr_rot for
- * theta) is applied as viewmat <- Exp(delta) viewmat with the closed-form
- * SE(3) exponential, in FP64, and written to delta [6] if that is not NULL:
- * its two halves are the translation and rotation changes whose norms the
- * caller tests for convergence.  All pointers are device pointers; viewmat
- * is updated in place.  Errors: GSFF_ERR_INVALID_ARGUMENT for a NULL
- * pointer, step < 1, betas outside [0, 1), eps <= 0 or a non-finite rate. */
+ * gsff_backward_tracking; state [GSFF_POSE_STATE_FLOATS] holds Adam's
+ * moments, the pose at the start of the test window and the converged flag;
+ * step counts from 1, and step 1 resets the state (a new frame).  The
+ * increment delta_k = -lr_k mhat_k / (sqrt(vhat_k) + eps) (lr_trans for rho,
+ * lr_rot for theta) is applied as viewmat <- Exp(delta) viewmat with the
+ * closed-form SE(3) exponential, in FP64, and written to delta [6] if that is
+ * not NULL.  conv (HOST pointer, may be NULL = no test) sets the convergence
+ * test; converged (device, may be NULL) receives 1 when the test held at this
+ * step or an earlier one of the frame, else 0.  Once it has held, later steps
+ * of the frame leave viewmat and state unchanged and write a zero delta, so a
+ * captured loop of a fixed number of steps ends where an early exit would.
+ * All other pointers are device pointers; viewmat is updated in place.
+ * Errors: GSFF_ERR_INVALID_ARGUMENT for a NULL pointer, step < 1, betas
+ * outside [0, 1), eps <= 0, a non-finite rate, or a window < 1 or a negative
+ * or non-finite tolerance in conv. */
 gsff_status gsff_pose_adam_step(float* viewmat, const float* d_pose, float* state,
                                 int32_t step, float lr_trans, float lr_rot, float beta1,
-                                float beta2, float eps, float* delta, void* stream);
+                                float beta2, float eps, const gsff_pose_convergence* conv,
+                                float* delta, uint32_t* converged, void* stream);
 
 /* Stage entry points: the forward is exactly preprocess, sort_depth, bin,
  * sort_tiles, tile_ranges, composite_fwd in this order; the backward is

@@ -15,6 +15,9 @@ Sec. 3.2 (tracking loss, Eq. 6; camera pose optimisation, Eq. 4):
 * ``se3_exp``           -- the closed-form SE(3) exponential of (rho, theta).
 * ``pose_adam_step``    -- one Adam step on the left increment, applied as
                            T <- Exp(delta) T.
+* ``relative_motion``   -- rotation angle and translation length of
+                           T_now T_then^-1, the net pose change the tracking
+                           loop's convergence test measures over a window.
 
 The operator and thresholds of the masks, the means over all elements and
 the optimiser (Adam) are readings where the paper gives no detail.
@@ -100,3 +103,17 @@ def pose_adam_step(viewmat, grad, m, v, step, lr_trans, lr_rot, beta1=0.9, beta2
     T[:3, :] = np.asarray(viewmat, np.float64).reshape(3, 4)
     Tn = se3_exp(delta) @ T
     return Tn[:3, :], m, v, delta
+
+
+def relative_motion(T_now, T_then):
+    """(angle [rad], shift) of the motion T_now T_then^-1 between two 3x4
+    world-to-camera poses: the rotation angle of R_now R_then^T (from its
+    axis-angle logarithm, ``scipy.spatial.transform``) and the length of its
+    translation t_now - R_now R_then^T t_then."""
+    from scipy.spatial.transform import Rotation
+    A = np.asarray(T_now, np.float64).reshape(3, 4)
+    B = np.asarray(T_then, np.float64).reshape(3, 4)
+    D = A[:, :3] @ B[:, :3].T
+    angle = float(np.linalg.norm(Rotation.from_matrix(D).as_rotvec()))
+    shift = float(np.linalg.norm(A[:, 3] - D @ B[:, 3]))
+    return angle, shift

@@ -58,6 +58,14 @@ class WsLayout(ctypes.Structure):
                 ("super_x", ctypes.c_int32), ("super_y", ctypes.c_int32)]
 
 
+class PoseConvergence(ctypes.Structure):
+    _fields_ = [("window", ctypes.c_int32), ("tol_trans", ctypes.c_float),
+                ("tol_rot", ctypes.c_float)]
+
+
+POSE_STATE_FLOATS = 32
+
+
 class AdamGroup(ctypes.Structure):
     _fields_ = [("param", _vp), ("grad", _vp), ("m", _vp), ("v", _vp), ("n", ctypes.c_int64),
                 ("lr", ctypes.c_float)]
@@ -88,8 +96,9 @@ SIGNATURES = {
     "gsff_scale_reg_workspace_size": (_i32, [_i64, ctypes.POINTER(_sz)]),
     "gsff_adam_step": (_i32, [ctypes.POINTER(AdamGroup), _i32, _i32, _f32, _f32, _f32, _vp]),
     "gsff_tracking_masks": (_i32, [_vp, _vp, _i32, _i32, _f32, _f32, _vp, _vp, _vp]),
-    "gsff_pose_adam_step": (_i32, [_vp, _vp, _vp, _i32, _f32, _f32, _f32, _f32, _f32, _vp,
-                                   _vp]),
+    "gsff_pose_adam_step": (_i32, [_vp, _vp, _vp, _i32, _f32, _f32, _f32, _f32, _f32,
+                                   ctypes.POINTER(PoseConvergence), _vp, _vp, _vp]),
+    "gsff_keyframe_test": (_i32, [_vp, _vp, _i64, _f32, _vp, _vp, _vp]),
     "gsff_preprocess": (_i32, [_G, _C, _S, _vp, _sz, _i64, _vp]),
     "gsff_sort_depth": (_i32, [_G, _C, _S, _vp, _sz, _i64, _vp]),
     "gsff_bin": (_i32, [_G, _C, _S, _vp, _sz, _i64, _vp]),

@@ -524,6 +524,17 @@ gsff_status gsff_covisibility(const uint8_t* a, const uint8_t* b, int64_t n, uin
   return hip_check(launch_covisibility(a, b, n, counts, (hipStream_t)stream), "covisibility");
 }
 
+gsff_status gsff_keyframe_test(const uint8_t* frame_vis, const uint8_t* keyframe_vis, int64_t n,
+                               float tau_thresh, uint32_t* counts, uint32_t* keyframe,
+                               void* stream) {
+  if (!keyframe || !std::isfinite(tau_thresh))
+    return fail(GSFF_ERR_INVALID_ARGUMENT, "keyframe test arguments");
+  const gsff_status rc = gsff_covisibility(frame_vis, keyframe_vis, n, counts, stream);
+  if (rc != GSFF_OK) return rc;
+  return hip_check(launch_keyframe_decide(counts, tau_thresh, keyframe, (hipStream_t)stream),
+                   "keyframe decision");
+}
+
 gsff_status gsff_composite_bwd_l1(const gsff_gaussians* g, const gsff_camera* cam,
                                   const gsff_settings* st, void* ws, size_t ws_bytes,
                                   int64_t max_pairs, const float* out_rgb, const float* out_depth,

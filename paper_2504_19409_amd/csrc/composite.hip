@@ -901,6 +901,16 @@ __global__ __launch_bounds__(256) void k_covisibility(const uint8_t* __restrict_
   }
 }
 
+// Keyframe decision (Sec. 3.2): IoU = |a and b| / |a or b| of the two
+// records (1 when both are empty) below tau_thresh, compared in FP64.
+__global__ void k_keyframe_decide(const uint32_t* __restrict__ counts, float tau,
+                                  uint32_t* __restrict__ keyframe) {
+  if (threadIdx.x != 0) return;
+  const uint32_t both = counts[0], either = counts[1];
+  const double iou = either ? (double)both / (double)either : 1.0;
+  keyframe[0] = iou < (double)tau ? 1u : 0u;
+}
+
 hipError_t launch_covisibility(const uint8_t* a, const uint8_t* b, int64_t n, uint32_t* counts,
                                hipStream_t s) {
   hipLaunchKernelGGL(k_fill_zero<uint32_t>, dim3(1), dim3(64), 0, s, counts, (int64_t)2);
@@ -908,6 +918,12 @@ hipError_t launch_covisibility(const uint8_t* a, const uint8_t* b, int64_t n, ui
     const int64_t blocks = (n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024;
     hipLaunchKernelGGL(k_covisibility, dim3((unsigned)blocks), dim3(256), 0, s, a, b, n, counts);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_keyframe_decide(const uint32_t* counts, float tau, uint32_t* keyframe,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL(k_keyframe_decide, dim3(1), dim3(64), 0, s, counts, tau, keyframe);
   return hipGetLastError();
 }
 

@@ -166,6 +166,8 @@ hipError_t launch_visibility(const DevSettings& st, const DevGaussians& g, const
                              const WsView& w, float t_vis, uint8_t* visible, hipStream_t s);
 hipError_t launch_covisibility(const uint8_t* a, const uint8_t* b, int64_t n, uint32_t* counts,
                                hipStream_t s);
+hipError_t launch_keyframe_decide(const uint32_t* counts, float tau, uint32_t* keyframe,
+                                  hipStream_t s);
 hipError_t launch_composite_bwd(const DevGaussians& g, const DevSettings& st,
                                 const Layout& L, const WsView& w, const float* g_rgb,
                                 const float* g_depth, const float* g_alpha,

@@ -1,7 +1,8 @@
 """Mapping step on the rasterizer (Sec. 3.2, Eqs. 7-8): the keyframe window's
-L1 terms (colour and depth weighted lambda_m and 1 - lambda_m, features when
-given) over its views, the scale regulariser lambda_r L_reg, and one fused
-Adam step over the Gaussians' parameters, with the camera poses frozen.
+L1 terms (colour and depth weighted lambda_m and 1 - lambda_m; a feature term
+only when asked for) over its views, the scale regulariser lambda_r L_reg,
+and one fused Adam step over the Gaussians' parameters, with the camera poses
+frozen.
 
 Every step runs in libgsff kernels on the current stream.
 """
@@ -54,17 +55,26 @@ DEFAULT_LR = dict(means=1.6e-4, log_scales=5e-3, quats=1e-3, logit_opacity=5e-2,
 
 
 class Mapper:
-    """One mapping step = the window's forward + fused-L1 adjoint over its
-    views, lambda_r L_reg into the log-scale gradient and the loss, and one
-    Adam step on every FP32 parameter group (a BF16 or FP16 feature payload
-    stays fixed)."""
+    """One mapping step (Eq. 8) = the window's forward + fused-L1 adjoint over
+    its views with colour weight lambda_m and depth weight 1 - lambda_m,
+    lambda_r L_reg (Eq. 7) into the log-scale gradient and the loss, and one
+    Adam step on the geometry and colour groups, the poses frozen.  Eq. 8 has
+    no feature term (the paper optimises the feature field after the
+    geometry, Sec. 3.3): features stay out unless ``feature_weight`` > 0,
+    which adds that L1 term and the feature group (FP32 payloads only).
+    Every ``check_every`` steps the window's status is read and a view that
+    outgrew its pair capacity raises."""
 
-    def __init__(self, window: KeyframeWindow, lam_reg: float = 0.01, lr: dict | None = None,
-                 betas=(0.9, 0.999), eps: float = 1e-15):
+    def __init__(self, window: KeyframeWindow, lam_m: float = 0.5, lam_reg: float = 0.01,
+                 feature_weight: float = 0.0, lr: dict | None = None, betas=(0.9, 0.999),
+                 eps: float = 1e-15, check_every: int = 10):
         self.win, self.lam_reg, self.betas, self.eps = window, lam_reg, betas, eps
+        self.check_every = check_every
+        window.weights = (float(lam_m), 1.0 - float(lam_m), 0.0, float(feature_weight))
         rates = dict(DEFAULT_LR, **(lr or {}))
         params = dict(window.geom)
-        if window.feat is not None and window.feat.dtype == torch.float32:
+        if (feature_weight > 0 and window.feat is not None
+                and window.feat.dtype == torch.float32):
             params["feat"] = window.feat
         self.groups = []
         for name, p in params.items():
@@ -81,4 +91,6 @@ class Mapper:
                   accumulate=True, workspace=self.ws)
         self.n += 1
         adam_step(self.groups, self.n, self.betas[0], self.betas[1], self.eps)
+        if self.n % self.check_every == 0:
+            win.check()
         return win.loss

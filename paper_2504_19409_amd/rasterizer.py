@@ -256,6 +256,34 @@ def l1_grad(x: torch.Tensor, y: torch.Tensor, scale: float, grad: torch.Tensor,
     return grad
 
 
+# Status bits of every rasterize() call since the last reset, OR-ed together
+# on the device (one int32 per device), so a call never waits for the host.
+_STICKY: dict = {}
+
+
+def _sticky(device) -> torch.Tensor:
+    key = torch.device(device)
+    if key.type == "cuda" and key.index is None:
+        key = torch.device("cuda", torch.cuda.current_device())
+    t = _STICKY.get(key)
+    if t is None:
+        t = torch.zeros(1, dtype=torch.int32, device=key)
+        _STICKY[key] = t
+    return t
+
+
+def raster_status(device="cuda", reset: bool = False) -> int:
+    """The GSFF_FLAG_* bits raised by any rasterize() call on ``device`` since
+    the last reset (FLAG_PAIR_OVERFLOW: some call's pairs exceeded its
+    capacity and that view rendered empty).  This read waits for the device;
+    rasterize() itself never does unless asked to (check_overflow=True)."""
+    t = _sticky(device)
+    flags = int(t.item())
+    if reset:
+        t.zero_()
+    return flags
+
+
 class _RasterizeFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, means, log_scales, quats, logit_opacity, rgb, feat, pose_tangent, viewmat,
@@ -269,6 +297,9 @@ class _RasterizeFn(torch.autograd.Function):
                 fr = Frame(means, log_scales, quats, logit_opacity, rgb, feat, viewmat, cam,
                            settings, int(n * 1.25) + 1024)
                 outs = fr.forward()
+        else:
+            st = _sticky(fr.device)
+            torch.bitwise_or(st, fr.ws_view("status", torch.int32, 1), out=st)
         ctx.frame = fr
         ctx.has_feat = fr.C > 0
         return outs
@@ -300,12 +331,20 @@ class _RasterizeFn(torch.autograd.Function):
 
 def rasterize(means, log_scales, quats, logit_opacity, rgb, feat, viewmat, cam: CameraSpec,
               pose_tangent: torch.Tensor | None = None, settings=None, max_pairs=None,
-              check_overflow=True):
+              check_overflow=False):
     """Differentiable render of (rgb [3,H,W], depth [H,W], alpha [H,W],
     feat [C,H,W]).  ``pose_tangent`` ([6], zeros, requires_grad) receives the
     gradient with respect to the left perturbation T <- Exp(delta) T at
     delta = 0 (Eq. 4); its value is not applied -- fold each optimizer step
-    into ``viewmat``."""
+    into ``viewmat``.
+
+    The call never waits for the device: its workspace comes from torch's
+    caching allocator and its status bits are OR-ed into a device flag that
+    ``raster_status()`` reads, so forward and backward can be captured into a
+    graph.  A view whose pairs exceed ``max_pairs`` (default: 64 per
+    Gaussian) renders empty and raises FLAG_PAIR_OVERFLOW there.  With
+    ``check_overflow=True`` the call instead reads the status at once (a host
+    round trip) and renders again with the capacity the frame needed."""
     if pose_tangent is None:
         pose_tangent = torch.zeros(6, dtype=torch.float32, device=means.device)
     return _RasterizeFn.apply(means, log_scales, quats, logit_opacity, rgb, feat, pose_tangent,

@@ -153,10 +153,15 @@ def test_tracking_and_visibility_argument_validation(capi):
     assert lib.gsff_tracking_masks(1, 1, 8, 8, 0.1, float("inf"), 1, 1, None) == E
     assert lib.gsff_tracking_masks(None, None, 8, 8, 0.1, 0.5, None, None, None) == capi.OK
     # pose step: NULL pointers, step < 1, betas, eps
-    assert lib.gsff_pose_adam_step(None, 1, 1, 1, 1e-3, 1e-3, 0.9, 0.999, 1e-8, None, None) == E
-    assert lib.gsff_pose_adam_step(1, 1, 1, 0, 1e-3, 1e-3, 0.9, 0.999, 1e-8, None, None) == E
-    assert lib.gsff_pose_adam_step(1, 1, 1, 1, 1e-3, 1e-3, 1.0, 0.999, 1e-8, None, None) == E
-    assert lib.gsff_pose_adam_step(1, 1, 1, 1, 1e-3, 1e-3, 0.9, 0.999, 0.0, None, None) == E
+    step = lambda *a, conv=None: lib.gsff_pose_adam_step(*a, conv, None, None, None)
+    assert step(None, 1, 1, 1, 1e-3, 1e-3, 0.9, 0.999, 1e-8) == E
+    assert step(1, 1, 1, 0, 1e-3, 1e-3, 0.9, 0.999, 1e-8) == E
+    assert step(1, 1, 1, 1, 1e-3, 1e-3, 1.0, 0.999, 1e-8) == E
+    assert step(1, 1, 1, 1, 1e-3, 1e-3, 0.9, 0.999, 0.0) == E
+    bad = [capi.PoseConvergence(0, 1e-3, 1e-3), capi.PoseConvergence(5, -1.0, 1e-3),
+           capi.PoseConvergence(5, 1e-3, float("nan"))]
+    for cv in bad:
+        assert step(1, 1, 1, 1, 1e-3, 1e-3, 0.9, 0.999, 1e-8, conv=ctypes.byref(cv)) == E
     # visibility: NULL output with P > 0, non-finite threshold
     assert lib.gsff_visibility(b(g), b(c), b(s), ws, nb, mp, 0.5, None, None) == E
     assert lib.gsff_visibility(b(g), b(c), b(s), ws, nb, mp, float("nan"), 1, None) == E
@@ -164,6 +169,9 @@ def test_tracking_and_visibility_argument_validation(capi):
     assert lib.gsff_covisibility(1, 1, -1, 1, None) == E
     assert lib.gsff_covisibility(None, 1, 5, 1, None) == E
     assert lib.gsff_covisibility(1, 1, 5, None, None) == E
+    assert lib.gsff_keyframe_test(1, 1, 5, 0.9, 1, None, None) == E
+    assert lib.gsff_keyframe_test(1, 1, 5, float("nan"), 1, 1, None) == E
+    assert lib.gsff_keyframe_test(1, 1, -1, 0.9, 1, 1, None) == E
     # Adam: more than eight groups, none, or a NULL table
     grp = (capi.AdamGroup * 9)()
     assert lib.gsff_adam_step(grp, 9, 1, 0.9, 0.999, 1e-8, None) == E

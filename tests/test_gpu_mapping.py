@@ -106,13 +106,48 @@ def test_mapping_step_lowers_the_window_loss():
                 rgb=t(np.clip(sc.rgb + 0.2 * rng.normal(size=sc.rgb.shape), 0, 1)))
     feat = t(sc.feat + 0.3 * rng.normal(size=sc.feat.shape))
     views = [(t(vm), cam) for vm in vms]
-    win = KeyframeWindow(geom, feat, views, targets, weights=(0.9, 0.1, 0.0, 1.0))
-    mp = Mapper(win, lam_reg=0.01)
+    feat0 = feat.clone()
+    win = KeyframeWindow(geom, feat, views, targets)
+    mp = Mapper(win, lam_m=0.9, lam_reg=0.01)
+    assert win.weights == (0.9, pytest.approx(0.1), 0.0, 0.0)  # Eq. 8: no feature term
     losses = [float(mp.step().item()) for _ in range(40)]
     for fr in win.frames:
         assert fr.read_status()[0] == 0
+    assert win.check() == 0
     print("mapping loss", losses[0], "->", losses[-1])
     assert losses[-1] < 0.7 * losses[0]
+    assert torch.equal(feat, feat0)  # the feature field is not touched
+    # asked for, the feature term enters the loss and the feature group moves
+    mp2 = Mapper(win, lam_m=0.9, lam_reg=0.01, feature_weight=1.0)
+    mp2.step()
+    torch.cuda.synchronize()
+    assert not torch.equal(feat, feat0)
+
+
+def test_window_reports_pair_overflow():
+    """Gaussians that grow after the window sized its pair capacities make a
+    view overflow; the window's check() raises instead of letting the empty
+    render reach the optimiser, and resize() restores it."""
+    from paper_2504_19409_amd.rasterizer import CameraSpec
+    from paper_2504_19409_amd.window import KeyframeWindow
+    rng = np.random.default_rng(72)
+    sc = sg.make_scene(20000, 640, 480, 525.0, 525.0, 320.0, 240.0, 0, seed=72, rng=rng)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+    geom = dict(means=t(sc.means), log_scales=t(sc.log_scales), quats=t(sc.quats),
+                logit_opacity=t(sc.logit_opacity), rgb=t(sc.rgb))
+    cam = CameraSpec(640, 480, 525.0, 525.0, 320.0, 240.0)
+    tg = [torch.zeros((3, 480, 640), device="cuda"), torch.zeros((480, 640), device="cuda"),
+          None, None]
+    win = KeyframeWindow(geom, None, [(t(sc.camera.viewmat), cam)], [tg], headroom=1.0)
+    win.run()
+    assert win.check() == 0
+    geom["log_scales"] += 1.5  # every splat grows: far more pairs than the capacity
+    win.run()
+    with pytest.raises(RuntimeError, match="overflowed"):
+        win.check()
+    win.resize()
+    win.run()
+    assert win.check() == 0
 
 
 def test_scale_reg_loss_only_and_gradient_only():

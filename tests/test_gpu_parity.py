@@ -413,9 +413,10 @@ def test_pair_overflow_reported_and_recovered(orc):
     assert flags & _capi.FLAG_PAIR_OVERFLOW
     assert n > 100
     assert torch.count_nonzero(outs[2]) == 0  # empty render, no out-of-bounds work
-    # the torch wrapper re-runs with the reported size
+    # asked to check, the torch wrapper re-runs with the reported size
     outs2 = rasterize(d["means"], d["log_scales"], d["quats"], d["logit_opacity"], d["rgb"],
-                      d["feat"], d["viewmat"], H.camspec(sc), max_pairs=100)
+                      d["feat"], d["viewmat"], H.camspec(sc), max_pairs=100,
+                      check_overflow=True)
     o = _oracle(sc, orc)
     assert H.rel_l2(outs2[0].detach().cpu().numpy(), o["rgb"]) <= H.TOL_FWD
 
@@ -531,6 +532,60 @@ def test_autograd_function(orc):
     got = {k: t.grad.cpu().numpy() for k, t in leaves.items()}
     got["pose"] = tangent.grad.cpu().numpy()
     H.check_grads(got, ob, GRAD_KEYS, flags=orc.ambiguous(p, c, H.MARGIN))
+
+
+def test_autograd_function_in_a_graph(orc):
+    """rasterize() forward and backward captured into one graph (the call
+    never waits for the host): every replay gives the eager gradients, and
+    the sticky status flag stays clear; a capacity that is too small raises
+    FLAG_PAIR_OVERFLOW in that flag, again without a host round trip."""
+    from paper_2504_19409_amd import _capi
+    from paper_2504_19409_amd.rasterizer import raster_status, rasterize
+    sc = _scene("ragged", C=5)
+    d = H.scene_to_device(sc, torch)
+    leaves = {k: d[k].clone().requires_grad_(True)
+              for k in ["means", "log_scales", "quats", "logit_opacity", "rgb", "feat"]}
+    tangent = torch.zeros(6, device="cuda", requires_grad=True)
+    rng = np.random.default_rng(9)
+    ups = [torch.from_numpy(u).cuda()
+           for u in sg.upstream_signs(rng, sc.camera.width, sc.camera.height, sc.C)]
+    raster_status(reset=True)
+
+    def step():
+        outs = rasterize(leaves["means"], leaves["log_scales"], leaves["quats"],
+                         leaves["logit_opacity"], leaves["rgb"], leaves["feat"], d["viewmat"],
+                         H.camspec(sc), pose_tangent=tangent)
+        loss = sum((o * u).sum() for o, u in zip(outs, ups))
+        loss.backward()
+
+    step()
+    ref = {k: t.grad.clone() for k, t in leaves.items()}
+    ref["pose"] = tangent.grad.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for t in list(leaves.values()) + [tangent]:
+            t.grad = None
+        step()
+    torch.cuda.current_stream().wait_stream(s)
+    for t in list(leaves.values()) + [tangent]:
+        t.grad = None
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    for rep in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        got = {k: t.grad.clone() for k, t in leaves.items()}
+        got["pose"] = tangent.grad.clone()
+        for k in ref:
+            assert H.rel_l2(got[k].cpu().numpy(), ref[k].cpu().numpy()) <= 1e-5, (rep, k)
+        junk = torch.randn(1 << 20, device="cuda")  # eager work between replays
+        del junk
+    assert raster_status(reset=True) == 0
+    rasterize(d["means"], d["log_scales"], d["quats"], d["logit_opacity"], d["rgb"], d["feat"],
+              d["viewmat"], H.camspec(sc), max_pairs=64)
+    assert raster_status(reset=True) & _capi.FLAG_PAIR_OVERFLOW
 
 
 # ------------------------------------------------------- fused L1 adjoint ----

@@ -116,7 +116,7 @@ def test_pose_adam_step_matches_oracle():
     rng = np.random.default_rng(41)
     V = sg.se3_exp(rng.normal(size=6) * 0.3)[:3, :].astype(np.float32)
     vm = torch.from_numpy(V.copy()).cuda()
-    state = torch.zeros(12, device="cuda")
+    state = torch.zeros(32, device="cuda")
     delta = torch.empty(6, device="cuda")
     Vo, m, v = V.astype(np.float64), np.zeros(6), np.zeros(6)
     for step in range(1, 4):
@@ -133,7 +133,64 @@ def test_pose_adam_step_matches_oracle():
         np.testing.assert_allclose(vm.cpu().numpy(), Vo, rtol=0, atol=2e-7)
         st = state.cpu().numpy()
         np.testing.assert_allclose(st[:6], m, rtol=1e-6)
-        np.testing.assert_allclose(st[6:], v, rtol=1e-6)
+        np.testing.assert_allclose(st[6:12], v, rtol=1e-6)
+
+
+def test_pose_convergence_test():
+    """The convergence test of the pose step: every `window` steps the net
+    motion over the window (rotation angle and translation length of
+    T_now T_start^-1, measured by the oracle from its own poses) against the
+    tolerances.  Gradients of a fixed sign move the pose steadily (no
+    convergence); gradients of alternating sign make it oscillate in place
+    (convergence at the end of the next window).  Once converged the pose
+    stays, the increment reads zero, and step 1 starts afresh."""
+    from paper_2504_19409_amd.tracking import pose_adam_step, pose_state
+    f32 = lambda x: float(np.float32(x))
+    rng = np.random.default_rng(43)
+    V = sg.se3_exp(rng.normal(size=6) * 0.3)[:3, :].astype(np.float32)
+    vm = torch.from_numpy(V.copy()).cuda()
+    state = pose_state("cuda")
+    delta = torch.empty(6, device="cuda")
+    conv = torch.empty(1, dtype=torch.int32, device="cuda")
+    lr_t, lr_r, window = 1e-3, 3e-3, 5
+    tol_t, tol_r = 2e-3, 6e-3  # between an oscillation's and a steady window's motion
+    g0 = (rng.choice([-1.0, 1.0], size=6) * 10.0 ** rng.uniform(-2, 0, size=6))
+    Vo, m, v = V.astype(np.float64), np.zeros(6), np.zeros(6)
+    start = Vo.copy()
+    flags = []
+    for step in range(1, 31):
+        g = (g0 if step <= 10 else g0 * (-1.0) ** step).astype(np.float32)
+        pose_adam_step(vm, torch.from_numpy(g).cuda(), state, step, lr_t, lr_r, delta=delta,
+                       window=window, tol_trans=tol_t, tol_rot=tol_r, converged=conv)
+        torch.cuda.synchronize()
+        f = int(conv.item())
+        flags.append(f)
+        if flags.count(1) > 1:  # converged earlier: nothing moves
+            assert not torch.any(delta)
+            np.testing.assert_array_equal(vm.cpu().numpy(), frozen)
+            continue
+        Vo, m, v, d = otrk.pose_adam_step(Vo.astype(np.float32), g, m.astype(np.float32),
+                                          v.astype(np.float32), step, f32(lr_t), f32(lr_r),
+                                          f32(0.9), f32(0.999), f32(1e-8))
+        np.testing.assert_allclose(vm.cpu().numpy(), Vo, rtol=0, atol=2e-7)
+        if step % window == 0:
+            ang, sh = otrk.relative_motion(Vo.astype(np.float32), start.astype(np.float32))
+            want = int(sh < tol_t and ang < tol_r)
+            # the decision is taken away from the thresholds
+            assert min(abs(sh / tol_t - 1), abs(ang / tol_r - 1)) > 0.05 or want == 0
+            assert f == want, (step, ang, sh)
+            start = Vo.copy()
+            if f:
+                frozen = vm.cpu().numpy()
+        else:
+            assert f == 0
+    assert flags[:10] == [0] * 10 and 1 in flags
+    # step 1 resets: the pose moves again
+    before = vm.clone()
+    pose_adam_step(vm, torch.from_numpy(g0.astype(np.float32)).cuda(), state, 1, lr_t, lr_r,
+                   delta=delta, window=window, tol_trans=tol_t, tol_rot=tol_r, converged=conv)
+    torch.cuda.synchronize()
+    assert int(conv.item()) == 0 and not torch.equal(vm, before)
 
 
 def _pose_error(vm, ref):
@@ -165,19 +222,31 @@ def test_tracking_loop_full_frame():
                d["feat"], vm, spec)
     # the edge threshold keeps the strongest 30% of the target's gradients
     tau = float(np.percentile(otrk.edge_magnitude(t_rgb.cpu().numpy()), 70))
-    tr = Tracker(fr, t_rgb, t_depth, TrackingConfig(max_iters=100, edge_threshold=tau))
+    hist = []
+    cfg = TrackingConfig(max_iters=150, edge_threshold=tau)
+    tr = Tracker(fr, t_rgb, t_depth, cfg, history=hist)
     it, converged, first, last = tr.run()
     assert fr.read_status()[0] == 0
     e1 = _pose_error(vm.cpu().numpy(), ident)
-    dn = tr.delta.cpu().numpy()
+    poses = [ident.astype(np.float32)] + [h.cpu().numpy() for h in hist]
+    poses[0] = np.ascontiguousarray(sc.camera.viewmat, np.float32).reshape(3, 4)
+    nets = [otrk.relative_motion(poses[k], poses[k - cfg.window])
+            for k in range(cfg.window, len(poses), cfg.window)]
+    errs = [_pose_error(poses[k], ident) for k in range(cfg.window, len(poses), cfg.window)]
     print("pose error (m, deg)", e0, "->", e1, "iterations", it, "converged", converged,
           "loss", first, "->", last, "edge threshold", tau, "kept", int(tr.mask_e.sum()),
-          "last increment", np.linalg.norm(dn[:3]), np.linalg.norm(dn[3:]))
+          "net motion per window (rad, m)", [(round(a, 6), round(b, 6)) for a, b in nets],
+          "error per window (m, deg)", [(round(a, 6), round(b, 4)) for a, b in errs])
     n = t_depth.numel()
     assert 0.2 * n < int(tr.mask_e.sum()) < 0.4 * n and int(tr.mask_v.sum()) > 0.5 * n
     assert last < 0.5 * first
     assert e1[0] < 0.5 * e0[0] and e1[1] < 0.5 * e0[1]
     assert fr.settings.render_features == 1
+    # the loop stopped on the library's convergence test, before the limit,
+    # and the test's last window moved less than the tolerances
+    assert converged and it < cfg.max_iters
+    assert nets[-1][0] < 0.5 * cfg.lr_rot and nets[-1][1] < 0.5 * cfg.lr_trans
+    assert e1[0] < 0.1 * e0[0]  # converged near the optimum: under a tenth of the start
 
 
 @pytest.mark.parametrize("lam,drop", [(1.0, None), (0.7, "depth"), (0.7, "rgb")])

@@ -126,6 +126,12 @@ def test_keyframe_decision_from_two_poses():
     both, either = covisibility(v0, v1)
     assert 0 < either and both < either
     assert is_keyframe(v1, v0, 0.9) == (both / either < 0.9)
+    # the device decision on either side of the measured IoU, and for two
+    # empty records (IoU 1)
+    iou = both / either
+    assert is_keyframe(v1, v0, iou + 1e-3) and not is_keyframe(v1, v0, iou - 1e-3)
+    empty = torch.zeros_like(v0)
+    assert not is_keyframe(empty, empty, 1.0) and is_keyframe(empty, empty, 1.001)
 
 
 def test_slam_passes_on_an_empty_scene():
