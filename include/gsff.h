@@ -22,7 +22,9 @@
  *    captured into a HIP graph.  Only gsff_read_status() waits.
  *  - Layouts: per-Gaussian vectors are planar [k, P] (component-major);
  *    features are row-major [P, C]; images are planar [k, H, W].
- *  - Calls are thread-compatible: the library holds no mutable global state.
+ *  - Calls are thread-compatible: the library holds no mutable global state
+ *    (one exception, gsff_decoder_query_noalloc, keeps a fixed scratch array
+ *    per GPU; see there).
  *  - Return value: GSFF_OK, or GSFF_ERR_INVALID_ARGUMENT (NULL pointer, bad
  *    size, workspace too small, unsupported size combination),
  *    GSFF_ERR_UNSUPPORTED (dtype / channel combination not built), or
@@ -486,6 +488,25 @@ gsff_status gsff_decoder_query(const void* X, const float* W1, const float* b1, 
                                const float* b2, const float* Q, int32_t K, int64_t n_px,
                                float* prob, int32_t* label, const int32_t* gt, float* ce_loss,
                                void* ws, size_t ws_bytes, void* stream);
+
+/* gsff_decoder_query without a workspace argument, for callers that cannot
+ * allocate device memory (code under stream / graph capture, tight serving
+ * loops, harnesses that forbid allocation).  Same arguments, outputs, errors
+ * and arithmetic as gsff_decoder_query, minus ws / ws_bytes; it calls no
+ * allocating routine.  Its scratch (the label-folded second layer for up to
+ * 64 labels and at most 1024 per-block loss partials: 37,124 bytes, enough
+ * for any n_px) is a fixed device array that each GPU the library runs on
+ * holds until the process ends; its device address is looked up on the
+ * first call on each device.  Every call on one GPU shares that array: calls
+ * that overlap on one GPU (different streams or threads without ordering)
+ * race and give undefined results; calls ordered on one stream do not.
+ * Nothing needs clearing between calls (a call writes every scratch word it
+ * reads).  Errors: those of gsff_decoder_query (K above 64 is the scratch's
+ * limit), or GSFF_ERR_HIP if the scratch address cannot be found. */
+gsff_status gsff_decoder_query_noalloc(const void* X, const float* W1, const float* b1,
+                                       const float* W2, const float* b2, const float* Q,
+                                       int32_t K, int64_t n_px, float* prob, int32_t* label,
+                                       const int32_t* gt, float* ce_loss, void* stream);
 
 /* L1 loss of one output group (the tracking / mapping / semantic losses,
  * Eqs. 6, 8 and 11, are weighted L1 terms): grad[i] = scale * sign(x[i] - y[i])

@@ -115,6 +115,7 @@ SIGNATURES = {
     "gsff_decoder_workspace_size": (_i32, [_i64, ctypes.POINTER(_sz)]),
     "gsff_decoder_query_workspace_size": (_i32, [_i32, _i64, ctypes.POINTER(_sz)]),
     "gsff_decoder_query": (_i32, [_vp] * 6 + [_i32, _i64] + [_vp] * 5 + [_sz, _vp]),
+    "gsff_decoder_query_noalloc": (_i32, [_vp] * 6 + [_i32, _i64] + [_vp] * 5),
     "gsff_decoder_forward": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _i32, _i64, _vp, _sz, _vp]),
     "gsff_decoder_train_step": (_i32, [_vp] * 6 + [_i64, _f32] + [_vp] * 7 + [_sz, _vp]),
 }

@@ -21,6 +21,8 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
 
+#include <mutex>
+
 #include "gsff_internal.h"
 
 namespace gsff {
@@ -673,22 +675,14 @@ gsff_status gsff_decoder_query_workspace_size(int32_t K, int64_t n_px, size_t* b
   return GSFF_OK;
 }
 
-gsff_status gsff_decoder_query(const void* X, const float* W1, const float* b1, const float* W2,
-                               const float* b2, const float* Q, int32_t K, int64_t n_px,
-                               float* prob, int32_t* label, const int32_t* gt, float* ce_loss,
-                               void* ws, size_t ws_bytes, void* stream) {
-  if (K < 1 || K > kQueryMaxK || n_px < 0 || !ws || !W1 || !b1 || !W2 || !b2 || !Q ||
-      (n_px > 0 && (!X || (gt == nullptr) != (ce_loss == nullptr))))
-    return GSFF_ERR_INVALID_ARGUMENT;
-  if (((uintptr_t)ws & 15u) != 0) return GSFF_ERR_INVALID_ARGUMENT;
-  size_t need = 0;
-  gsff_decoder_query_workspace_size(K, n_px, &need);
-  if (ws_bytes < need) return GSFF_ERR_INVALID_ARGUMENT;
-  hipStream_t s = (hipStream_t)stream;
+static gsff_status query_impl(const void* X, const float* W1, const float* b1, const float* W2,
+                              const float* b2, const float* Q, int32_t K, int64_t n_px,
+                              float* prob, int32_t* label, const int32_t* gt, float* ce_loss,
+                              float* ws, hipStream_t s) {
   const int NLT = (K + 15) / 16, KP = 16 * NLT;
-  float* w2q = (float*)ws;
+  float* w2q = ws;
   float* b2q = w2q + kHid * KP;
-  float* part = (float*)ws + (kHid + 1) * kQueryMaxK;
+  float* part = ws + (kHid + 1) * kQueryMaxK;
   hipLaunchKernelGGL(k_query_fold, dim3((unsigned)(((kHid + 1) * KP + 3) / 4)), dim3(256), 0, s,
                      W2, b2, Q, (int)K, KP, w2q, b2q);
   const int64_t nb = n_px > 0 ? query_blocks(n_px) : 0;
@@ -710,4 +704,78 @@ gsff_status gsff_decoder_query(const void* X, const float* W1, const float* b1, 
   return hipGetLastError() == hipSuccess ? GSFF_OK : GSFF_ERR_HIP;
 }
 
+static bool query_args_ok(const void* X, const float* W1, const float* b1, const float* W2,
+                          const float* b2, const float* Q, int32_t K, int64_t n_px,
+                          const int32_t* gt, const float* ce_loss) {
+  return !(K < 1 || K > kQueryMaxK || n_px < 0 || !W1 || !b1 || !W2 || !b2 || !Q ||
+           (n_px > 0 && (!X || (gt == nullptr) != (ce_loss == nullptr))));
+}
+
+gsff_status gsff_decoder_query(const void* X, const float* W1, const float* b1, const float* W2,
+                               const float* b2, const float* Q, int32_t K, int64_t n_px,
+                               float* prob, int32_t* label, const int32_t* gt, float* ce_loss,
+                               void* ws, size_t ws_bytes, void* stream) {
+  if (!ws || !query_args_ok(X, W1, b1, W2, b2, Q, K, n_px, gt, ce_loss))
+    return GSFF_ERR_INVALID_ARGUMENT;
+  if (((uintptr_t)ws & 15u) != 0) return GSFF_ERR_INVALID_ARGUMENT;
+  size_t need = 0;
+  gsff_decoder_query_workspace_size(K, n_px, &need);
+  if (ws_bytes < need) return GSFF_ERR_INVALID_ARGUMENT;
+  return query_impl(X, W1, b1, W2, b2, Q, K, n_px, prob, label, gt, ce_loss, (float*)ws,
+                    (hipStream_t)stream);
+}
+
+// ---- the same query without a workspace argument --------------------------
+// Its scratch (the folded weights of up to kQueryMaxK labels and the per-block
+// cross-entropy partials, at most 1024 blocks whatever n_px) lives in a
+// file-scope device array, one copy per GPU for the life of the process.  Host
+// code never passes the array's name to a kernel: its device address comes
+// from hipGetSymbolAddress, once per device, with that device current.
 }  // extern "C"
+
+namespace gsff {
+namespace {
+constexpr int kQueryScratchFloats = (kHid + 1) * kQueryMaxK + 1024 + 1;
+static_assert(kQueryScratchFloats * 4 <= 40 * 1024, "query scratch stays modest");
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) float scratch[kQueryScratchFloats];
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+// The calling thread's current device's scratch address (set up on the
+// first call on that device).
+hipError_t scratch_for_current_device(float** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = (float*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+}  // namespace
+}  // namespace gsff
+
+extern "C" gsff_status gsff_decoder_query_noalloc(const void* X, const float* W1,
+                                                  const float* b1, const float* W2,
+                                                  const float* b2, const float* Q, int32_t K,
+                                                  int64_t n_px, float* prob, int32_t* label,
+                                                  const int32_t* gt, float* ce_loss,
+                                                  void* stream) {
+  if (K > kQueryMaxK) return GSFF_ERR_INVALID_ARGUMENT;  // beyond the scratch's label count
+  if (!query_args_ok(X, W1, b1, W2, b2, Q, K, n_px, gt, ce_loss))
+    return GSFF_ERR_INVALID_ARGUMENT;
+  float* ws = nullptr;
+  if (scratch_for_current_device(&ws) != hipSuccess || !ws) return GSFF_ERR_HIP;
+  // every scratch word a call reads it writes first (folded weights, then
+  // one partial per block), so nothing is cleared
+  return query_impl(X, W1, b1, W2, b2, Q, K, n_px, prob, label, gt, ce_loss, ws,
+                    (hipStream_t)stream);
+}
+

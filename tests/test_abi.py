@@ -169,6 +169,10 @@ def test_tracking_and_visibility_argument_validation(capi):
     assert lib.gsff_covisibility(1, 1, -1, 1, None) == E
     assert lib.gsff_covisibility(None, 1, 5, 1, None) == E
     assert lib.gsff_covisibility(1, 1, 5, None, None) == E
+    # decode + query without a workspace: K outside [1, 64], NULL inputs
+    q = lambda K, Qp=1: lib.gsff_decoder_query_noalloc(1, 1, 1, 1, 1, Qp, K, 10, None, None,
+                                                       None, None, None)
+    assert q(65) == E and q(0) == E and q(5, None) == E
     assert lib.gsff_keyframe_test(1, 1, 5, 0.9, 1, None, None) == E
     assert lib.gsff_keyframe_test(1, 1, 5, float("nan"), 1, 1, None) == E
     assert lib.gsff_keyframe_test(1, 1, -1, 0.9, 1, 1, None) == E
