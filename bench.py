@@ -41,8 +41,15 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 # lane-instructions ("slots") per second = 78.6 TFLOP/s of non-packed FP32 FMA
 # (packed FP32 is disabled on these machines).
 VALU_PEAK_TSLOTS = 256 * 4 * 16 * 2.4e9 / 1e12
-# LDS delivery peak: 128 bytes per clock per CU x 256 CUs x 2.4 GHz, in TB/s
-LDS_PEAK_TBS = 128 * 256 * 2.4e9 / 1e12
+# LDS delivery peak: 256 bytes per clock per CU x 256 CUs x 2.4 GHz, in TB/s.
+# The probe library measures it on the box (lane-delivered 16-byte reads at
+# broadcast and per-lane addresses: about 146 and 119 TB/s), which rules out
+# the 128 B/clk of the previous generation.
+LDS_PEAK_TBS = 256 * 256 * 2.4e9 / 1e12
+# LDS bytes a lane must receive per alpha evaluation: the Gaussian's image
+# position, scaled conic and opacity (six floats).  The blending payload
+# reaches the matrix cores once per wave and Gaussian, not per pixel.
+LDS_BYTES_PER_EVAL = 24
 
 # What the timed step computes in: the inputs, outputs and gradients are
 # FP32; alpha, transmittance and every decision are FP32 VALU arithmetic; the
@@ -285,9 +292,16 @@ def query_rates(torch, fr, K):
         return e0.elapsed_time(e1) / K * 1e3
 
     t_query = timed(lambda: dec.query(X, params, Q))
-    t_dec = timed(lambda: dec.forward(X, params, ws_dec))
+    Y = torch.empty((512, n), dtype=torch.bfloat16, device="cuda")
+    t_dec = timed(lambda: dec.forward(X, params, ws_dec, out=Y))
+    T = (torch.randn(512, n, generator=g) * 0.5).to(torch.bfloat16).cuda()
+    loss = torch.zeros(1, device="cuda")
+    t_train = timed(lambda: dec.train_step(X, params, T, ws_dec, None, loss))
+    map_bytes = 512 * n * 2
     return {"queries": 20, "pixels": n, "decode_query_us": round(t_query, 1),
-            "decode_512_map_us": round(t_dec, 1)}
+            "decode_512_map_us": round(t_dec, 1),
+            "decode_512_map_gbs": round(map_bytes / (t_dec * 1e-6) / 1e9, 1),
+            "decoder_train_step_us": round(t_train, 1)}
 
 
 def algorithmic_work(scene, n_pairs, torch):
@@ -311,6 +325,14 @@ def _cpu_model():
     except OSError:
         pass
     return "unknown"
+
+
+def walked_pairs(torch, fr):
+    """(tile, Gaussian) pairs the last forward walked (the adjoint's rows)."""
+    lay = fr.layout
+    nt = lay.tiles_x * lay.tiles_y
+    rg = fr.ws_view("tile_list_ranges", torch.int32, 2 * nt).view(nt, 2).cpu()
+    return int((rg[:, 1] - rg[:, 0]).sum())
 
 
 def cpu_baseline(scene, budget_s):
@@ -450,8 +472,18 @@ def main():
         % (slam["query"]["decode_query_us"], slam["query"]["decode_512_map_us"]))
 
     wc, sizes = algorithmic_work(scene, n_pairs, torch)
+    wc["walked"] = walked_pairs(torch, fr)
+    try:
+        from paper_2504_19409_amd import probe
+        peaks = probe.measure()
+    except Exception as e:  # the probe library is a measurement aid only
+        log(f"probe unavailable: {e}")
+        peaks = {}
+    log(f"measured peaks {peaks}")
     dom = max(ONE_KERNEL_STAGES, key=lambda s: stage_ms[s])
-    roof = roofline_for(dom, stage_ms[dom], wc, sizes)
+    roof = roofline_for(dom, stage_ms[dom], wc, sizes, peaks)
+    bound_us = {s: round(stage_bound_us(s, wc, sizes), 2) for s in STAGES}
+    step_bound = sum(bound_us.values())
     out = {
         "metric": "fwd+bwd render iterations/sec at 640x480, 200k Gaussians, 16-ch features",
         "value": round(value, 2), "unit": "it/s", "n_gpus": 1, "steps": K,
@@ -466,7 +498,13 @@ def main():
                    "graph_ms": round(graph_ms, 4) if graph_ms else None,
                    "graph_replay_dist": graph_dist,
                    "stage_us": {s: round(v * 1e3, 1) for s, v in stage_ms.items()},
-                   "pairs": n_pairs, "work": wc, "slam": slam},
+                   "pairs": n_pairs, "work": wc, "slam": slam,
+                   "stage_bound_us": bound_us,
+                   "step_roofline": {"bound_us": round(step_bound, 2),
+                                     "frac": round(step_bound / (ms * 1e3), 4),
+                                     "note": "sum over stages of the time at each stage's "
+                                             "limiting roofline, over the measured step"},
+                   "peaks_measured": peaks},
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
@@ -501,29 +539,66 @@ def measured_traffic(stage):
         return None
 
 
-def roofline_for(stage, ms, wc, sz):
+def _alu_slots(stage, wc):
+    """Vector-ALU lane slots of a compositing kernel (a transcendental, issued
+    at quarter rate, counts 4): alpha evaluation (per pixel and Gaussian walked
+    up to the pixel's stop) 15; forward, per contributing pair (transmittance,
+    stop test, weight, hi / lo split) 8; adjoint, per contributing pair
+    (transmittance recovery, weight, g . c, dL/dalpha, suffix sum, dL/dpower)
+    16.  The colour, depth, feature and per-Gaussian sums run on the matrix
+    cores and are not counted."""
+    per_contrib = 8 if stage == "composite_fwd" else 16
+    return wc["evals"] * 15 + wc["contribs"] * per_contrib
+
+
+def stage_bound_us(stage, wc, sz):
+    """Time of a stage at its limiting roofline (nominal peaks), microseconds,
+    from its algorithmic work: HBM bytes for the streaming stages, the larger
+    of vector-ALU slots and LDS lane bytes for the compositing kernels (plus
+    the upstream pass's HBM bytes for the adjoint)."""
+    P, C, HW, M = sz["P"], sz["C"], sz["HW"], sz["n_pairs"]
+    hbm = lambda b: b / (HBM_PEAK_GBS * 1e9) * 1e6
+    if stage in ("composite_fwd", "composite_bwd_l1"):
+        t_alu = _alu_slots(stage, wc) / (VALU_PEAK_TSLOTS * 1e12) * 1e6
+        t_lds = wc["tile_evals"] * LDS_BYTES_PER_EVAL / (LDS_PEAK_TBS * 1e12) * 1e6
+        t = max(t_alu, t_lds)
+        if stage == "composite_bwd_l1":  # outputs and targets read once, codes written
+            t += hbm(HW * (2 * (5 + C)) * 4 + HW * (1 + (C + 15) // 16) * 4)
+        return t
+    return hbm(algorithmic_bytes(stage, sz, wc))
+
+
+def algorithmic_bytes(stage, sz, wc):
+    P, C, HW, M = sz["P"], sz["C"], sz["HW"], sz["n_pairs"]
+    return {
+        "preprocess": P * (44 + 12) + P * (48 + 8 + 8),
+        # a stable sort of P 4-byte keys with 4-byte ids: one read and one
+        # write of both per 8-bit pass
+        "sort_depth": 4 * P * 8 * 2,
+        # keys read, super-tile entries (id + mask) written once
+        "bin": P * 8 * 2 + M * 6,
+        "sort_tiles": 0,
+        "tile_ranges": 0,
+        # adjoint rows (one per walked pair, 10 + C floats) read once,
+        # parameters read, gradients written
+        "preprocess_bwd": wc.get("walked", 0) * (10 + C) * 4 + P * (44 + 12) + P * (56 + 4 * C),
+    }[stage]
+
+
+def roofline_for(stage, ms, wc, sz, peaks=None):
     """Roofline entry of the dominant stage: algorithmic work per launch over the
     measured average launch time.  Work per unit is stated in the design notes.
 
     The compositing kernels have two candidate bounds; the limiting one is the
-    one whose time at peak is longer:
-      LDS lane delivery: every lane reads the record of every Gaussian its tile
-        walks (u, v, conic, opacity: 28 B; colour and depth: 12 B; C payload
-        channels at 4 B): W_tile * (40 + 4 C) bytes per launch, against
-        128 B per clock per CU.
-      vector-ALU issue, in lane slots (a transcendental, issued at quarter
-        rate, counts 4): alpha evaluation (per pixel and Gaussian walked up to
-        the pixel's stop) 15; forward, per contributing pair (transmittance,
-        stop test, weight, colour and depth sums) 8; adjoint, per contributing
-        pair (transmittance recovery, weight, g . c, dL/dalpha, suffix sum,
-        dL/dpower) 16.  The feature and per-Gaussian sums run on the matrix
-        cores and are not counted."""
-    P, C, HW, M = sz["P"], sz["C"], sz["HW"], sz["n_pairs"]
+    one whose time at peak is longer: vector-ALU issue (``_alu_slots``) and
+    LDS lane delivery (LDS_BYTES_PER_EVAL per lockstep evaluation of the
+    tile).  ``peaks`` (measured on the box by the probe library) are reported
+    beside the nominal ones."""
+    peaks = peaks or {}
     sec = ms * 1e-3
     if stage in ("composite_fwd", "composite_bwd_l1"):
-        per_contrib = 8 if stage == "composite_fwd" else 16
-        slots = wc["evals"] * 15 + wc["contribs"] * per_contrib
-        lds_bytes = wc["tile_evals"] * (40 + 4 * C)
+        slots = _alu_slots(stage, wc)
+        lds_bytes = wc["tile_evals"] * LDS_BYTES_PER_EVAL
         alu = slots / sec / 1e12
         lds = lds_bytes / sec / 1e12
         t_lds, t_alu = lds_bytes / (LDS_PEAK_TBS * 1e12), slots / (VALU_PEAK_TSLOTS * 1e12)
@@ -533,22 +608,21 @@ def roofline_for(stage, ms, wc, sz):
                  "work": int(slots)}
         main_ = {"bound": "lds", "achieved": round(lds, 3), "peak": round(LDS_PEAK_TBS, 2),
                  "unit": "TB/s", "frac": round(lds / LDS_PEAK_TBS, 4), "work": int(lds_bytes)}
+        if "lds_broadcast_tbs" in peaks:
+            main_["peak_measured"] = peaks["lds_broadcast_tbs"]
+            main_["frac_measured"] = round(lds / peaks["lds_broadcast_tbs"], 4)
         if t_alu > t_lds:
             main_, other = other, main_
         out = dict(main_)
         out.update({"traffic": traffic, "stage": stage, "other_bound": other})
         return out
-    bytes_ = {
-        "preprocess": P * (44 + 12) + P * (48 + 8 + 8),
-        "sort_depth": 4 * P * 8 * 3,
-        "bin": P * 8 * 2 + M * 4,
-        "sort_tiles": 2 * M * 4 * 3,
-        "tile_ranges": 8 * 1200,
-        "preprocess_bwd": P * (44 + 40) + P * 56,
-    }[stage]
+    bytes_ = algorithmic_bytes(stage, sz, wc)
     achieved = bytes_ / sec / 1e9
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "stage": stage}
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "stage": stage}
+    if "hbm_read_gbs" in peaks:
+        out["peak_measured"] = peaks["hbm_read_gbs"]
+    return out
 
 
 if __name__ == "__main__":

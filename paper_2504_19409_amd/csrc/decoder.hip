@@ -132,26 +132,36 @@ __device__ __forceinline__ bf16x8 regs_to_b(const f32x16& d, int half) {
 // ------------------------------------------------------------- forward -----
 
 // One wave decodes NPB blocks of 32 pixels; the weight fragments of each
-// K-step are loaded once per wave and used for all NPB blocks.
-template <int NPB, typename OT>
+// K-step are loaded once per wave and used for all NPB blocks.  The second
+// layer takes the hidden activations as the A operand (pixels along M) and
+// the weights as B, so lane (g, i) ends with output channel 32 c + i of
+// pixels 8 k + 4 g .. 8 k + 4 g + 3 (k = 0..3) of each block.  ROWS (rows of
+// Y 16-byte aligned): the wave's 32 channels x 32 NPB pixels pass through
+// LDS, and every store instruction writes 16 bytes per lane as whole
+// 128-byte row segments (eight lanes per row); otherwise one element per
+// store.
+template <int NPB, typename OT, bool ROWS>
 __global__ __launch_bounds__(256) void k_dec_forward(const __bf16* __restrict__ X,
                                                      const float* __restrict__ b1,
                                                      const float* __restrict__ b2,
                                                      const __bf16* __restrict__ w1t,
                                                      const __bf16* __restrict__ w2tp,
                                                      OT* __restrict__ Y, int64_t npx) {
-  const int lane = threadIdx.x & 63, g = lane >> 5, i = lane & 31;
-  const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  constexpr int PXW = 32 * NPB;                    // pixels per wave
+  constexpr int VEC = 16 / (int)sizeof(OT);        // elements per 16-byte store
+  constexpr int STRIDE = PXW + VEC;                  // LDS row pitch: 16-byte rows, banks staggered
+  __shared__ __attribute__((aligned(16))) OT s_y[ROWS ? 4 : 1][ROWS ? 32 : 1][ROWS ? STRIDE : 1];
+  const int lane = threadIdx.x & 63, g = lane >> 5, i = lane & 31, wv = threadIdx.x >> 6;
+  const int64_t wave = (int64_t)blockIdx.x * 4 + wv;
+  const int64_t wbase = wave * PXW;
   bf16x8 hf[NPB][8];
-  int64_t px[NPB];
-  bool ok[NPB];
 #pragma unroll
   for (int q = 0; q < NPB; ++q) {
-    px[q] = (wave * NPB + q) * 32 + i;
-    ok[q] = px[q] < npx;
+    const int64_t px = wbase + 32 * q + i;
+    const bool ok = px < npx;
     bf16x8 xb;
 #pragma unroll
-    for (int t = 0; t < 8; ++t) xb[t] = ok[q] ? X[(int64_t)(8 * g + t) * npx + px[q]] : (__bf16)0.f;
+    for (int t = 0; t < 8; ++t) xb[t] = ok ? X[(int64_t)(8 * g + t) * npx + px] : (__bf16)0.f;
 #pragma unroll
     for (int h = 0; h < 4; ++h) {
       f32x16 z = {};
@@ -163,26 +173,82 @@ __global__ __launch_bounds__(256) void k_dec_forward(const __bf16* __restrict__ 
       hf[q][2 * h + 1] = regs_to_b(z, 1);
     }
   }
-  for (int c = 0; c < kOut / 32; ++c) {
+  // output blocks in pairs with two fragment buffers: the weights and bias of
+  // the next block are loaded while the current one is multiplied and
+  // written (a whole block's work to arrive)
+  const bool full = wbase + PXW <= npx;  // uniform: every pixel of the wave in range
+  bf16x8 wa[8], wb[8];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) wa[s] = load8(w2tp + (i * 8 + s) * 16 + 8 * g);
+  float ba = b2[i], bb = 0.f;
+  auto block = [&](int c, const bf16x8 (&w)[8], float bias) {
     f32x16 acc[NPB];
 #pragma unroll
     for (int q = 0; q < NPB; ++q) acc[q] = f32x16{};
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      const bf16x8 a = load8(w2tp + ((32 * c + i) * 8 + s) * 16 + 8 * g);
+    for (int s = 0; s < 8; ++s)
 #pragma unroll
       for (int q = 0; q < NPB; ++q)
-        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, hf[q][s], acc[q], 0, 0, 0);
-    }
+        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hf[q][s], w[s], acc[q], 0, 0, 0);
+    if constexpr (ROWS) {
+      // the wave's tile: row = channel i, pixels 32 q + 8 k + 4 g .. +3
 #pragma unroll
-    for (int q = 0; q < NPB; ++q) {
-      if (!ok[q]) continue;
+      for (int q = 0; q < NPB; ++q)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int ch = 32 * c + 8 * (r / 4) + 4 * g + r % 4;
-        Y[(int64_t)ch * npx + px[q]] = (OT)(acc[q][r] + b2[ch]);
+        for (int k = 0; k < 4; ++k) {
+          OT* d = &s_y[wv][i][32 * q + 8 * k + 4 * g];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) d[t] = (OT)(acc[q][4 * k + t] + bias);
+        }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+      // lanes in groups of PXW / VEC per row, rows in turn
+      constexpr int LPR = PXW / VEC;  // lanes per row
+      constexpr int RPI = 64 / LPR;   // rows per store instruction
+#pragma unroll
+      for (int r0 = 0; r0 < 32; r0 += RPI) {
+        const int row = r0 + lane / LPR, col = (lane % LPR) * VEC;
+        const uint4 v = *reinterpret_cast<const uint4*>(&s_y[wv][row][col]);
+        const int64_t p0 = wbase + col;
+        OT* dst = Y + (int64_t)(32 * c + row) * npx + p0;
+        if (full) {
+          *reinterpret_cast<uint4*>(dst) = v;
+        } else {
+          const OT* e = reinterpret_cast<const OT*>(&v);
+#pragma unroll
+          for (int t = 0; t < VEC; ++t)
+            if (p0 + t < npx) dst[t] = e[t];
+        }
       }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+    } else {
+      OT* row = Y + (int64_t)(32 * c + i) * npx;
+#pragma unroll
+      for (int q = 0; q < NPB; ++q)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int64_t p0 = wbase + 32 * q + 8 * k + 4 * g;
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            if (p0 + t < npx) row[p0 + t] = (OT)(acc[q][4 * k + t] + bias);
+        }
     }
+  };
+#pragma unroll 1
+  for (int c = 0; c < kOut / 32; c += 2) {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) wb[s] = load8(w2tp + ((32 * (c + 1) + i) * 8 + s) * 16 + 8 * g);
+    bb = b2[32 * (c + 1) + i];
+    block(c, wa, ba);
+    if (c + 2 < kOut / 32) {
+#pragma unroll
+      for (int s = 0; s < 8; ++s) wa[s] = load8(w2tp + ((32 * (c + 2) + i) * 8 + s) * 16 + 8 * g);
+      ba = b2[32 * (c + 2) + i];
+    }
+    block(c + 1, wb, bb);
   }
 }
 
@@ -608,17 +674,23 @@ gsff_status gsff_decoder_forward(const void* X, const float* W1, const float* b1
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)ws;
   if (dec_prepare(W1, W2, w, L, s) != hipSuccess) return GSFF_ERR_HIP;
-  constexpr int NPB = 4;
+  constexpr int NPB = 2;  // two blocks per wave: 232-260 registers, two waves per SIMD
   const int64_t waves = (L.nblk + NPB - 1) / NPB;
   const unsigned grid = (unsigned)((waves + 3) / 4);
-  if (y_dtype == GSFF_DTYPE_BF16)
-    hipLaunchKernelGGL((k_dec_forward<NPB, __bf16>), dim3(grid), dim3(256), 0, s,
-                       (const __bf16*)X, b1, b2, (const __bf16*)(w + L.w1t),
-                       (const __bf16*)(w + L.w2tp), (__bf16*)Y, n_px);
-  else
-    hipLaunchKernelGGL((k_dec_forward<NPB, float>), dim3(grid), dim3(256), 0, s,
-                       (const __bf16*)X, b1, b2, (const __bf16*)(w + L.w1t),
-                       (const __bf16*)(w + L.w2tp), (float*)Y, n_px);
+  // rows of the output map 16-byte aligned: whole row segments per store
+  const bool y16 = ((uintptr_t)Y & 15u) == 0;
+#define GSFF_DEC_FWD(OTT, ROWS)                                                              \
+  hipLaunchKernelGGL((k_dec_forward<NPB, OTT, ROWS>), dim3(grid), dim3(256), 0, s,          \
+                     (const __bf16*)X, b1, b2, (const __bf16*)(w + L.w1t),                  \
+                     (const __bf16*)(w + L.w2tp), (OTT*)Y, n_px)
+  if (y_dtype == GSFF_DTYPE_BF16) {
+    if (y16 && n_px % 8 == 0) GSFF_DEC_FWD(__bf16, true);
+    else GSFF_DEC_FWD(__bf16, false);
+  } else {
+    if (y16 && n_px % 4 == 0) GSFF_DEC_FWD(float, true);
+    else GSFF_DEC_FWD(float, false);
+  }
+#undef GSFF_DEC_FWD
   return hipGetLastError() == hipSuccess ? GSFF_OK : GSFF_ERR_HIP;
 }
 

@@ -35,11 +35,15 @@ def init_params(seed: int = 0, device="cuda"):
                 W2=W2.to(device), b2=torch.zeros(OUT, device=device))
 
 
-def forward(X: torch.Tensor, params: dict, ws: torch.Tensor, out_dtype=torch.bfloat16):
-    """X: bf16 [16, n_px] -> Y [512, n_px]."""
+def forward(X: torch.Tensor, params: dict, ws: torch.Tensor, out_dtype=torch.bfloat16,
+            out: torch.Tensor | None = None):
+    """X: bf16 [16, n_px] -> Y [512, n_px] (into ``out`` when given)."""
     assert X.dtype == torch.bfloat16 and X.is_contiguous() and X.shape[0] == LATENT
     n = X.shape[1]
-    Y = torch.empty((OUT, n), dtype=out_dtype, device=X.device)
+    if out is not None:
+        assert out.shape == (OUT, n) and out.is_contiguous()
+        out_dtype = out.dtype
+    Y = out if out is not None else torch.empty((OUT, n), dtype=out_dtype, device=X.device)
     code = _capi.DTYPE_BF16 if out_dtype == torch.bfloat16 else _capi.DTYPE_F32
     _capi.check(_capi.load().gsff_decoder_forward(
         _p(X), _p(params["W1"]), _p(params["b1"]), _p(params["W2"]), _p(params["b2"]), _p(Y),

@@ -37,8 +37,11 @@ def _problem(n, seed):
     return Xb, p, npp, rng
 
 
-@pytest.mark.parametrize("n", [1000, 4096])
+@pytest.mark.parametrize("n", [1000, 1004, 1003, 4096])
 def test_decoder_forward_parity(n):
+    """Row-aligned sizes write whole 8-pixel rows (1000: a partial last
+    32-pixel block; 1004: aligned for FP32 only, its last 8-pixel group
+    partial); 1003 writes element by element."""
     from paper_2504_19409_amd import decoder as dec
     Xb, p, npp, _ = _problem(n, 1)
     ws = dec.workspace(n)

@@ -212,11 +212,15 @@ def test_stage_depth_sort_and_tile_lists(orc, kind):
     assert extra <= 0.6 * total
 
 
-@pytest.mark.parametrize("P", [1, 2047, 2048, 2049, 6145, 50_000, 262_145])
+@pytest.mark.parametrize("P", [1, 2047, 2048, 2049, 6145, 50_000, 262_145, 2_097_152,
+                               2_097_153])
 def test_depth_sort_exact_and_stable(P):
     """The depth sort against numpy's stable argsort of the keys preprocess
     wrote, at sizes around the 2048-key workgroup chunk and with many chunks
-    (the look-back between workgroups), on keys with heavy ties."""
+    (the look-back between workgroups), on keys with heavy ties, up to a
+    thousand chunks.  A second sort of the sorted keys must keep them and
+    their ids (the sort leaves its look-back words and tickets ready for the
+    next call)."""
     rng = np.random.default_rng(P)
     sc = sg.make_scene(P, 320, 240, 260.0, 260.0, 160.0, 120.0, 0, seed=P, rng=rng)
     # depths from 37 distinct values: long runs of equal keys
@@ -233,6 +237,13 @@ def test_depth_sort_exact_and_stable(P):
     order = np.argsort(keys0, kind="stable")
     assert np.array_equal(ids.astype(np.int64), order)
     assert np.array_equal(keys, keys0[order])
+    fr.call_stage("gsff_sort_depth")  # sorted keys: a stable sort keeps them in place
+    torch.cuda.synchronize()
+    assert fr.read_status()[0] == 0
+    keys2 = fr.ws_view("depth_keys", torch.int32, P).cpu().numpy().view(np.uint32)
+    ids2 = fr.ws_view("depth_ids", torch.int32, P).cpu().numpy().view(np.uint32)
+    assert np.array_equal(keys2, keys0[order])
+    assert np.array_equal(ids2.astype(np.int64), order)
 
 
 # --------------------------------------------------------- forward/backward ----
