@@ -86,6 +86,12 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="wall-clock budget of the CPU oracle sample")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches only")
+    ap.add_argument("--workload", default="frame",
+                    choices=["frame", "mixed", "decoder", "window"],
+                    help="frame (default): 200k Gaussians, 640x480, 16-ch FP32; mixed: 1M "
+                         "Gaussians, 1200x680, 64-ch BF16; decoder: 500k Gaussians, 640x480, "
+                         "16-ch latent + learned decoder vs the plain 512-ch render; window: "
+                         "8-view keyframe window, 1M Gaussians, 32-ch BF16, one graph")
     ap.add_argument("--profile-run", action="store_true",
                     help="for counter collection: eager steps only, no oracle work counts or "
                          "CPU baseline, plus one plain 256 MiB device copy whose counters "
@@ -379,6 +385,11 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(2)
+    if args.workload != "frame":
+        out = {"mixed": bench_mixed, "decoder": bench_decoder,
+               "window": bench_window}[args.workload](torch, args)
+        print(json.dumps(out), flush=True)
+        return
     scene, fr, targets, n_pairs = build_problem(torch)
     step = Step(torch, fr, targets)
     log(f"pairs {n_pairs}, workspace {fr.ws_bytes / 1e6:.1f} MB")
@@ -510,6 +521,161 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def _line(metric, value, unit, K, W, ms, config, roofline=None, dtype=DTYPE_LABEL):
+    return {"metric": metric, "value": round(value, 3), "unit": unit, "n_gpus": 1, "steps": K,
+            "warmup": W, "ms_per_step": round(ms, 4), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+            "config": config, "roofline": roofline, "cpu_baseline": None}
+
+
+def _replay_ms(torch, run, K, warmup):
+    """Capture run() into a graph and time K replays (wall clock inside
+    synchronisations, plus per-replay events for the median)."""
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        run()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        run()
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+    t0 = time.perf_counter()
+    ev[0].record()
+    for k in range(K):
+        g.replay()
+        ev[k + 1].record()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / K * 1e3
+    per = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(K)])
+    return ms, {"median_ms": round(float(np.median(per)), 4),
+                "p10_ms": round(float(np.percentile(per, 10)), 4),
+                "p90_ms": round(float(np.percentile(per, 90)), 4)}
+
+
+def bench_mixed(torch, args):
+    """Mixed-precision frame: 1M Gaussians, 1200x680, fx = fy = 600, 64-channel
+    BF16 payload with FP32 compositing; targets rendered at the scene pose,
+    the step at a pose perturbed by 1 cm / 1 degree; one step = the frame
+    step (forward + fused-L1 adjoint + preprocess adjoint with the pose)."""
+    from paper_2504_19409_amd import scenegen as sg
+    from paper_2504_19409_amd.rasterizer import CameraSpec, Frame
+    scene, _ = sg.workload_scene("mixed")
+    cam = scene.camera
+    spec = CameraSpec(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    d = dict(means=t(scene.means), log_scales=t(scene.log_scales), quats=t(scene.quats),
+             logit_opacity=t(scene.logit_opacity), rgb=t(scene.rgb),
+             feat=t(scene.feat).to(torch.bfloat16))
+    mk = lambda vm, mp=None: Frame(d["means"], d["log_scales"], d["quats"], d["logit_opacity"],
+                                   d["rgb"], d["feat"], vm, spec, max_pairs=mp)
+    f0 = mk(t(cam.viewmat))
+    targets = [o.clone() for o in f0.forward()]
+    prng = np.random.default_rng(1003)
+    vm, _ = sg.perturbed_viewmat(prng, cam.viewmat, 0.01, 1.0)
+    vmt = t(np.ascontiguousarray(vm, np.float32))
+    f1 = mk(vmt)
+    f1.forward()
+    flags, n = f1.read_status()
+    assert flags == 0, "pair overflow while sizing"
+    fr = mk(vmt, int(n * 1.05) + 4096)
+    del f0, f1
+    step = Step(torch, fr, targets)
+    for _ in range(args.warmup):
+        step.run()
+    torch.cuda.synchronize()
+    K = args.steps
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(STAGES) + 1)]
+          for _ in range(K)]
+    for k in range(K):
+        step.run(ev[k])
+    torch.cuda.synchronize()
+    stage_ms = {s: float(np.median([ev[k][i].elapsed_time(ev[k][i + 1]) for k in range(K)]))
+                for i, s in enumerate(STAGES)}
+    ms, dist = _replay_ms(torch, step.run, K, args.warmup)
+    assert fr.read_status()[0] == 0
+    log("mixed: graph ms/step %.4f; stages %s" % (ms, {k: round(v * 1e3, 1)
+                                                        for k, v in stage_ms.items()}))
+    cfg = {"workload": "mixed-precision frame: 1M Gaussians, 1200x680, fx=fy=600, RGB+depth+"
+                       "alpha+64-ch BF16 features, FP32 compositing, pose perturbed 1 cm/1 deg",
+           "gaussians": scene.P, "width": cam.width, "height": cam.height, "channels": 64,
+           "payload": "bf16", "timing": "graph replay", "graph_replay_dist": dist,
+           "stage_us": {k: round(v * 1e3, 1) for k, v in stage_ms.items()}, "pairs": n}
+    return _line("fwd+bwd render iterations/sec at 1200x680, 1M Gaussians, 64-ch BF16 features",
+                 1e3 / ms, "it/s", K, args.warmup, ms, cfg)
+
+
+def bench_decoder(torch, args):
+    """Learned decoder: 500k Gaussians at 640x480 with 512-channel class-
+    structured BF16 features; the decoded frame (16-ch latent render + the
+    1x1 MLP to 512 channels) against the plain 512-channel render, after
+    training on eight views of a 2 m arc (two held out)."""
+    from paper_2504_19409_amd.distill import decoder_experiment
+    r = decoder_experiment(steps=800)
+    ms = r["latent_render_decode_ms"]
+    n_px = r["width"] * r["height"]
+    map_bytes = 512 * n_px * 2
+    dec_s = r["decode_ms"] * 1e-3
+    roof = {"bound": "hbm", "achieved": round(map_bytes / dec_s / 1e9, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(map_bytes / dec_s / 1e9 / HBM_PEAK_GBS, 4),
+            "traffic": None, "stage": "decoder_forward",
+            "other_bound": {"bound": "mfma", "unit": "TFLOP/s", "peak": 2500.0,
+                            "achieved": round(2 * n_px * (16 * 128 + 128 * 512) / dec_s / 1e12,
+                                              1),
+                            "frac": round(2 * n_px * (16 * 128 + 128 * 512) / dec_s / 2.5e15,
+                                          4)}}
+    log("decoder: %s" % r)
+    cfg = {"workload": "learned decoder: 500k Gaussians, 640x480, 16-ch BF16 latent render + 1x1 "
+                       "MLP 16-128-512 (BF16 MFMA, FP32 accumulation) vs the plain 512-ch BF16 "
+                       "render", "result": r}
+    return _line("decoded 512-ch feature frames/sec at 640x480, 500k Gaussians", 1e3 / ms,
+                 "frames/s", 10, 2, ms, cfg, roof, dtype="bf16 (FP32 accumulation)")
+
+
+def bench_window(torch, args):
+    """Keyframe window: 1M Gaussians with 32-ch BF16 features, 8 views
+    alternating 640x480 (fx 525) and 1200x680 (fx 600) on a 2 m arc; one step =
+    every view's forward and fused-L1 adjoint with the Gaussian gradients
+    accumulated over the views, replayed from one graph."""
+    from paper_2504_19409_amd import scenegen as sg
+    from paper_2504_19409_amd.rasterizer import CameraSpec
+    from paper_2504_19409_amd.window import KeyframeWindow
+    rng = np.random.default_rng(5)
+    P, C = 1_000_000, 32
+    sc = sg.make_scene(P, 640, 480, 525.0, 525.0, 320.0, 240.0, C, seed=5, rng=rng)
+    vms = sg.arc_viewmats(rng, 8, radius=3.0, arc=2.0, jitter_deg=2.0)
+    sizes = [(640, 480, 525.0), (1200, 680, 600.0)] * 4
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    geom = dict(means=t(sc.means), log_scales=t(sc.log_scales), quats=t(sc.quats),
+                logit_opacity=t(sc.logit_opacity), rgb=t(sc.rgb))
+    feat = t(sc.feat).to(torch.bfloat16)
+    views = [(t(vm), CameraSpec(W, H, f, f, W / 2, H / 2)) for (W, H, f), vm in zip(sizes, vms)]
+    targets = []
+    for (vm, cam) in views:
+        g = torch.Generator(device="cpu").manual_seed(len(targets))
+        targets.append([torch.rand((3, cam.height, cam.width), generator=g).cuda(),
+                        (1 + 4 * torch.rand((cam.height, cam.width), generator=g)).cuda(), None,
+                        torch.randn((C, cam.height, cam.width), generator=g).cuda()])
+    win = KeyframeWindow(geom, feat, views, targets, weights=(1.0, 1.0, 0.0, 1.0))
+    win.run()
+    win.check()
+    K = max(args.steps // 10, 10)
+    ms, dist = _replay_ms(torch, win.run, K, 3)
+    assert win.check() == 0
+    log("window: graph ms/step %.3f" % ms)
+    cfg = {"workload": "keyframe window: 1M Gaussians, 32-ch BF16 features, 8 views alternating "
+                       "640x480 (fx 525) and 1200x680 (fx 600) on a 2 m arc, fwd + fused-L1 "
+                       "adjoint of every view, gradients accumulated, one graph",
+           "gaussians": P, "views": 8, "channels": C, "timing": "graph replay",
+           "graph_replay_dist": dist}
+    return _line("keyframe-window steps/sec (8 views fwd+bwd, 1M Gaussians, 32-ch BF16)",
+                 1e3 / ms, "steps/s", K, 3, ms, cfg)
 
 
 # Measured HBM traffic of the dominant kernel, from the rocprofv3 counter

@@ -84,3 +84,86 @@ def feature_errors(Y: torch.Tensor, T: torch.Tensor, alpha: torch.Tensor, querie
     lt = (queries @ t).argmax(0)
     agree = float((ly == lt).float().mean())
     return dict(rel_l1=rel_l1, rel_l2=rel_l2, argmax_agreement=agree, pixels=int(m.sum()))
+
+
+def _time_ms(fn, n=10, warm=2):
+    for _ in range(warm):
+        fn()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(n):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / n
+
+
+def decoder_experiment(P: int = 500_000, W: int = 640, H: int = 480, f: float = 525.0,
+                       n_views: int = 10, held=(3, 7), steps: int = 800, seed: int = 4,
+                       lr_latent: float = 2e-2, lr_decoder: float = 2e-3, timing: bool = True):
+    """The learned-decoder workload (Sec. 3.3, Eq. 11): P Gaussians with
+    class-structured 512-channel BF16 features (32 classes), n_views cameras on
+    a 2 m arc, the plain 512-channel render of every view as the teacher,
+    16-channel latents + decoder trained on the views not in ``held`` and
+    judged on the held-out ones.  Returns a dict: the held-out errors
+    (relative L1 / L2 on covered pixels, Eq. 12 argmax agreement), the same
+    errors of a render with every Gaussian carrying its class's mean feature
+    (what the class structure alone gives: the teacher's per-Gaussian noise is
+    beyond the latent), per-frame times of the plain render and of latent
+    render + decode, the train step time, and the feature bytes per Gaussian."""
+    import numpy as np
+
+    from . import scenegen as sg
+    rng = np.random.default_rng(seed)
+    sc = sg.make_scene(P, W, H, f, f, W / 2, H / 2, 0, seed=seed, rng=rng)
+    feat, labels, q = sg.semantic_features(rng, sc.means, 32, 512, 0.05)
+    vms = sg.arc_viewmats(rng, n_views, radius=3.0, arc=2.0, jitter_deg=2.0)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    geom = dict(means=t(sc.means), log_scales=t(sc.log_scales), quats=t(sc.quats),
+                logit_opacity=t(sc.logit_opacity), rgb=t(sc.rgb))
+    cam = CameraSpec(W, H, f, f, W / 2, H / 2)
+    views = [View(t(v), cam) for v in vms]
+    f512 = t(feat).to(torch.bfloat16)
+    # class-mean features: what a representation of the classes alone renders
+    cls = np.zeros((32, 512))
+    np.add.at(cls, labels, feat.astype(np.float64))
+    cls /= np.maximum(np.bincount(labels, minlength=32), 1)[:, None]
+    fcls = t(cls[labels].astype(np.float32)).to(torch.bfloat16)
+    del feat
+    qt = t(q)
+    teacher, alphas = [], []
+    for v in views:
+        _, outs = render_features(geom, f512, v)
+        teacher.append(outs[3].clone())
+        alphas.append(outs[2].clone())
+    train = [k for k in range(n_views) if k not in held]
+    d = Distiller(geom, [views[k] for k in train], [teacher[k] for k in train],
+                  lr_latent=lr_latent, lr_decoder=lr_decoder)
+    y0, _ = d.decode(views[held[0]])
+    init = feature_errors(y0, teacher[held[0]], alphas[held[0]], qt)
+    for it in range(steps):
+        d.step(it % len(train))
+    torch.cuda.synchronize()
+    out = dict(P=P, width=W, height=H, views=n_views, held_out=list(held), steps=steps,
+               init=init, held=[], class_mean=[])
+    for k in held:
+        y, _ = d.decode(views[k])
+        out["held"].append(feature_errors(y, teacher[k], alphas[k], qt))
+        _, oc = render_features(geom, fcls, views[k])
+        out["class_mean"].append(feature_errors(oc[3], teacher[k], alphas[k], qt))
+    out["feature_bytes_per_gaussian"] = dict(plain=512 * 2, latent=dec.LATENT * 2)
+    if timing:
+        v = views[held[0]]
+        out["plain_512_render_ms"] = round(_time_ms(lambda: render_features(geom, f512, v)), 4)
+        out["latent_render_decode_ms"] = round(_time_ms(lambda: d.decode(v)), 4)
+        lat16 = d.latent.detach().to(torch.bfloat16)
+        _, outs = render_features(geom, lat16, v)
+        X = outs[3].reshape(dec.LATENT, -1)
+        pr = {n: p.detach() for n, p in d.params.items()}
+        Y = torch.empty((dec.OUT, W * H), dtype=torch.bfloat16, device="cuda")
+        out["decode_ms"] = round(_time_ms(lambda: dec.forward(X, pr, d.ws, out=Y)), 4)
+        tg = teacher[held[0]].reshape(dec.OUT, -1)
+        out["train_step_ms"] = round(_time_ms(lambda: dec.train_step(X, pr, tg, d.ws)), 4)
+        out["distill_step_ms"] = round(_time_ms(lambda: d.step(0), n=5), 4)
+    return out

@@ -94,3 +94,24 @@ def test_decoder_distillation_gain():
     assert t_dec < t_plain
     # per-Gaussian feature storage: 16 vs 512 BF16 channels
     assert d.latent.shape[1] * 2 * 32 == f512.shape[1] * 2
+
+
+def test_decoder_gain_full_scale():
+    """The learned-decoder workload at full size: 500k Gaussians at 640x480,
+    eight training and two held-out views on a 2 m arc, 800 training steps.
+    On the held-out views the decoded map must halve the initial error and
+    beat, by 10%, a render of every Gaussian's class-mean feature (what the
+    class structure alone gives; the teacher's per-Gaussian noise is mostly
+    beyond a 16-channel latent: measured 0.30-0.32 against 0.40-0.41 relative
+    L2), keep the Eq. 12 labels of at least 97% of the covered pixels, render
+    + decode faster than the plain 512-channel render, and store 32x fewer
+    feature bytes per Gaussian."""
+    from paper_2504_19409_amd.distill import decoder_experiment
+    r = decoder_experiment()
+    print("\n", r, flush=True)
+    for e, c in zip(r["held"], r["class_mean"]):
+        assert e["rel_l2"] < 0.5 * r["init"]["rel_l2"], e
+        assert e["rel_l2"] <= 0.9 * c["rel_l2"], (e, c)
+        assert e["argmax_agreement"] >= 0.97, e
+    assert r["latent_render_decode_ms"] < r["plain_512_render_ms"]
+    assert r["feature_bytes_per_gaussian"]["plain"] == 32 * r["feature_bytes_per_gaussian"]["latent"]
