@@ -515,6 +515,74 @@ gsff_status gsff_decoder_query_noalloc(const void* X, const float* W1, const flo
 gsff_status gsff_l1_grad(const float* x, const float* y, int64_t n, float scale,
                          float* grad, float* loss, void* stream);
 
+/* ---- FP64 instantiation, for derivative checks ----------------------------
+ * The forward and adjoint above in FP64, built from the same device code for
+ * the projection (Sec. 3.1, Eq. 1 and its splat) and its adjoint with the pose
+ * terms (Sec. 3.2, Eq. 4), and for the adjoint's per-pair back-to-front step
+ * and per-tile moments-to-gradient step (Eqs. 2-3).  What the FP32 kernels sum
+ * on the matrix cores is summed by plain FP64 loops, and every Gaussian meets
+ * every pixel (the FP32 tile lists only leave out pairs below alpha_min).
+ * Central finite differences of gsff_forward_f64 check gsff_backward_f64; it
+ * is not a rendering path (slow by design).  Same layouts, conventions and
+ * settings as the FP32 entry points, with doubles; limits P <= 4096,
+ * C <= 32, 1 <= width, height <= 256.  The image is rendered from the
+ * camera's pixel centres, features are FP64 [P, C]. */
+typedef struct gsff_gaussians_f64 {
+  int64_t P;
+  int32_t C;
+  const double* means;          /* [3, P] */
+  const double* log_scales;     /* [3, P] */
+  const double* quats;          /* [4, P] */
+  const double* logit_opacity;  /* [P]    */
+  const double* rgb;            /* [3, P] */
+  const double* feat;           /* [P, C] */
+} gsff_gaussians_f64;
+
+/* viewmat: DEVICE pointer to 12 doubles, row-major [R | t] = T_CW. */
+typedef struct gsff_camera_f64 {
+  int32_t width, height;
+  double fx, fy, cx, cy;
+  const double* viewmat;
+} gsff_camera_f64;
+
+/* Every pointer but feat (NULL iff C == 0) is required; outputs are written,
+ * not accumulated.  pose [6] as in gsff_grads (rho, theta; left
+ * perturbation), summed over the Gaussians in index order. */
+typedef struct gsff_grads_f64 {
+  double* means;          /* [3, P] */
+  double* log_scales;     /* [3, P] */
+  double* quats;          /* [4, P] */
+  double* logit_opacity;  /* [P]    */
+  double* rgb;            /* [3, P] */
+  double* feat;           /* [P, C] */
+  double* pose;           /* [6]    */
+} gsff_grads_f64;
+
+/* Bytes of the FP64 workspace (256-byte aligned by the caller). */
+gsff_status gsff_f64_workspace_size(int64_t P, int32_t channels, int32_t width, int32_t height,
+                                    size_t* bytes);
+
+/* FP64 forward: out_rgb [3, H, W], out_depth [H, W] (sum of w_i z_i),
+ * out_alpha [H, W] (1 - final T), out_feat [C, H, W] (required when C > 0
+ * and features are rendered; zeros when they are not), and, if out_n is not
+ * NULL, out_n [H, W] int32: the Gaussians each pixel blended.  Leaves in ws
+ * what gsff_backward_f64 of the same inputs needs.  Errors:
+ * GSFF_ERR_INVALID_ARGUMENT for sizes past the limits, NULL pointers, bad
+ * settings or a small or misaligned workspace. */
+gsff_status gsff_forward_f64(const gsff_gaussians_f64* g, const gsff_camera_f64* cam,
+                             const gsff_settings* st, void* ws, size_t ws_bytes, double* out_rgb,
+                             double* out_depth, double* out_alpha, double* out_feat,
+                             int32_t* out_n, void* stream);
+
+/* FP64 adjoint of the last gsff_forward_f64 on ws (same inputs): upstream
+ * g_rgb [3, H, W], g_depth, g_alpha [H, W], g_feat [C, H, W] (required when
+ * C > 0).  As in the FP32 path the feature upstream reaches only out->feat.
+ * Errors as gsff_forward_f64, and for a NULL upstream or gradient output. */
+gsff_status gsff_backward_f64(const gsff_gaussians_f64* g, const gsff_camera_f64* cam,
+                              const gsff_settings* st, void* ws, size_t ws_bytes,
+                              const double* g_rgb, const double* g_depth, const double* g_alpha,
+                              const double* g_feat, const gsff_grads_f64* out, void* stream);
+
 /* Wait for `stream`, then copy the workspace status word (which starts at
  * byte 0 of every workspace) to the host: *flags receives the GSFF_FLAG_*
  * bits and *n_pairs the number of super-tile pairs the last forward needed (even

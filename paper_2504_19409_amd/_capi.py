@@ -66,6 +66,23 @@ class PoseConvergence(ctypes.Structure):
 POSE_STATE_FLOATS = 32
 
 
+class Gaussians64(ctypes.Structure):
+    _fields_ = [("P", ctypes.c_int64), ("C", ctypes.c_int32),
+                ("means", _vp), ("log_scales", _vp), ("quats", _vp), ("logit_opacity", _vp),
+                ("rgb", _vp), ("feat", _vp)]
+
+
+class Camera64(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("fx", ctypes.c_double), ("fy", ctypes.c_double),
+                ("cx", ctypes.c_double), ("cy", ctypes.c_double), ("viewmat", _vp)]
+
+
+class Grads64(ctypes.Structure):
+    _fields_ = [("means", _vp), ("log_scales", _vp), ("quats", _vp), ("logit_opacity", _vp),
+                ("rgb", _vp), ("feat", _vp), ("pose", _vp)]
+
+
 class AdamGroup(ctypes.Structure):
     _fields_ = [("param", _vp), ("grad", _vp), ("m", _vp), ("v", _vp), ("n", ctypes.c_int64),
                 ("lr", ctypes.c_float)]
@@ -116,6 +133,11 @@ SIGNATURES = {
     "gsff_decoder_query_workspace_size": (_i32, [_i32, _i64, ctypes.POINTER(_sz)]),
     "gsff_decoder_query": (_i32, [_vp] * 6 + [_i32, _i64] + [_vp] * 5 + [_sz, _vp]),
     "gsff_decoder_query_noalloc": (_i32, [_vp] * 6 + [_i32, _i64] + [_vp] * 5),
+    "gsff_f64_workspace_size": (_i32, [_i64, _i32, _i32, _i32, ctypes.POINTER(_sz)]),
+    "gsff_forward_f64": (_i32, [ctypes.POINTER(Gaussians64), ctypes.POINTER(Camera64), _S, _vp,
+                                _sz, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "gsff_backward_f64": (_i32, [ctypes.POINTER(Gaussians64), ctypes.POINTER(Camera64), _S, _vp,
+                                 _sz, _vp, _vp, _vp, _vp, ctypes.POINTER(Grads64), _vp]),
     "gsff_decoder_forward": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _i32, _i64, _vp, _sz, _vp]),
     "gsff_decoder_train_step": (_i32, [_vp] * 6 + [_i64, _f32] + [_vp] * 7 + [_sz, _vp]),
 }

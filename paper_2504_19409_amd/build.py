@@ -17,7 +17,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgsff.so")
 PROBE_LIB = os.path.join(HERE, "libgsff_probe.so")
 SOURCES = ["capi.hip", "preprocess.hip", "sort.hip", "composite.hip", "decoder.hip",
-           "tracking.hip", "mapping.hip"]
+           "tracking.hip", "mapping.hip", "f64.hip"]
 ARCH = "gfx950"
 
 

@@ -19,6 +19,8 @@ static gsff_status fail(gsff_status code, const std::string& msg) {
   return code;
 }
 
+gsff_status record_error(gsff_status code, const char* msg) { return fail(code, msg); }
+
 static gsff_status hip_check(hipError_t e, const char* what) {
   if (e == hipSuccess) return GSFF_OK;
   return fail(GSFF_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));

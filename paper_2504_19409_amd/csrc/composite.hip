@@ -22,6 +22,7 @@
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 
+#include "blend.h"
 #include "gsff_internal.h"
 
 namespace gsff {
@@ -1484,18 +1485,17 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
         // a pair the pixel does not use gets alpha 0: then 1 / (1 - alpha) is
         // exactly 1, T passes through and the weight is 0
         const float al = act ? e.alpha : 0.f;
-        const float inv = __builtin_amdgcn_rcpf(1.f - al);  // v_rcp_f32, 1 ulp; rcp(1) = 1
-        const float Tb = T * inv;  // transmittance in front of this Gaussian
-        const float wv = al * Tb;
+        float gc = 0.f;
         if constexpr (GEO) {
           const float4 r2 = s_r2[buf][jj];
-          const float gc = gr * r2.x + gg * r2.y + gb * r2.z + gd * r1.z;
-          const float dal = Tb * gc + (gaT - D) * inv;
+          gc = gr * r2.x + gg * r2.y + gb * r2.z + gd * r1.z;
+        }
+        float wv, dal;
+        back_step(al, gc, gaT, T, D, wv, dal);  // rcp(1) = 1 exactly
+        if constexpr (GEO) {
           const float og = (act && e.oG < st.alpha_max) ? e.oG : 0.f;
-          D = fmaf(wv, gc, D);
           s_DP[jj][tid] = dal * og;
         }
-        T = Tb;
         s_W[jj][tid] = wv;
       }
     } else {
@@ -1590,21 +1590,11 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
           if (gid < (uint32_t)P && (rows_ok ? (uint32_t)lane < b1 - b0 : true)) {
             const float4 r0 = s_r0[buf][lane], r1 = s_r1[buf][lane];
             const float cA = r0.z * kConAInv, cB = r0.w * kConBInv, cC = r1.x * kConAInv;
-            const float M0 = s_mom[lane][0], M1 = s_mom[lane][1], M2 = s_mom[lane][2];
-            const float M3 = s_mom[lane][3], M4 = s_mom[lane][4], M5 = s_mom[lane][5];
+            const float M[6] = {s_mom[lane][0], s_mom[lane][1], s_mom[lane][2],
+                                s_mom[lane][3], s_mom[lane][4], s_mom[lane][5]};
             const float udx = r0.x - tcx, vdy = r0.y - tcy;  // mean relative to the tile centre
-            // sums of dL/dpower times (u - x_p), (v - y_p) and their products
-            const float Sx = udx * M0 - M1, Sy = vdy * M0 - M2;
-            const float Sxx = udx * udx * M0 - 2.f * udx * M1 + M3;
-            const float Sxy = udx * vdy * M0 - udx * M2 - vdy * M1 + M4;
-            const float Syy = vdy * vdy * M0 - 2.f * vdy * M2 + M5;
             float geo[6];
-            geo[0] = -(cA * Sx + cB * Sy);
-            geo[1] = -(cB * Sx + cC * Sy);
-            geo[2] = -0.5f * Sxx;
-            geo[3] = -Sxy;
-            geo[4] = -0.5f * Syy;
-            geo[5] = r1.y > 0.f ? M0 * __builtin_amdgcn_rcpf(r1.y) : 0.f;
+            geo_from_moments(cA, cB, cC, r1.y, udx, vdy, M, geo);
             if (rows_ok) {
               float* row = w.rows + (int64_t)(rowbase + b0 + (uint32_t)lane) * RW;
 #pragma unroll

@@ -147,6 +147,9 @@ struct DevGaussians {
   const void* feat;
 };
 
+// Sets the message gsff_last_error() returns and passes the code through.
+gsff_status record_error(gsff_status code, const char* msg);
+
 // ---- host launchers (each returns the first HIP error, or hipSuccess) ----
 hipError_t launch_preprocess(const DevGaussians& g, const DevCamera& cam,
                              const DevSettings& st, const Layout& L, const WsView& w,

@@ -173,92 +173,7 @@ __global__ __launch_bounds__(kPoseBlock) void k_preprocess_bwd(DevGaussians g, D
     float dmean[3] = {0.f, 0.f, 0.f}, dls[3] = {0.f, 0.f, 0.f}, dq[4] = {0.f, 0.f, 0.f, 0.f};
     float dlogit = 0.f;
     const float drgb[3] = {d[6], d[7], d[8]};
-    if (p.valid) {
-      const float du = d[0], dv = d[1], dA = d[2], dB = d[3], dC = d[4], dop = d[5], dz = d[9];
-      dlogit = dop * p.o * (1.f - p.o);
-      // conic -> 2D covariance: G = -K Gk K with Gk = [[dA, dB/2], [dB/2, dC]]
-      const float hB = 0.5f * dB;
-      const float k00 = p.A * dA + p.B * hB, k01 = p.A * hB + p.B * dC;
-      const float k10 = p.B * dA + p.Cc * hB, k11 = p.B * hB + p.Cc * dC;
-      const float G00 = -(k00 * p.A + k01 * p.B);
-      const float G01 = -(k00 * p.B + k01 * p.Cc);
-      const float G11 = -(k10 * p.B + k11 * p.Cc);
-      // Sigma' = TM TM^T:  dTM = 2 G TM
-      float dTM[6];
-      for (int k = 0; k < 3; ++k) {
-        dTM[k] = 2.f * (G00 * p.TM[k] + G01 * p.TM[3 + k]);
-        dTM[3 + k] = 2.f * (G01 * p.TM[k] + G11 * p.TM[3 + k]);
-      }
-      // TM[r][k] = sum_l T[r][l] Rq[l][k] s_k
-      float T[6];
-      for (int k = 0; k < 3; ++k) {
-        T[k] = p.J00 * V[k] + p.J02 * V[8 + k];
-        T[3 + k] = p.J11 * V[4 + k] + p.J12 * V[8 + k];
-      }
-      float dM[9];  // d/d(Rq S)
-      for (int l = 0; l < 3; ++l)
-        for (int k = 0; k < 3; ++k) dM[3 * l + k] = T[l] * dTM[k] + T[3 + l] * dTM[3 + k];
-      float dT[6];  // d/dT = dTM (Rq S)^T
-      for (int r = 0; r < 2; ++r)
-        for (int l = 0; l < 3; ++l) {
-          float acc = 0.f;
-          for (int k = 0; k < 3; ++k) acc += dTM[3 * r + k] * p.Rq[3 * l + k] * p.s[k];
-          dT[3 * r + l] = acc;
-        }
-      float dRq[9];
-      for (int r = 0; r < 3; ++r)
-        for (int k = 0; k < 3; ++k) dRq[3 * r + k] = dM[3 * r + k] * p.s[k];
-      for (int k = 0; k < 3; ++k) {
-        const float ds = dM[k] * p.Rq[k] + dM[3 + k] * p.Rq[3 + k] + dM[6 + k] * p.Rq[6 + k];
-        dls[k] = ds * p.s[k];
-      }
-      const float qw = p.q[0], qx = p.q[1], qy = p.q[2], qz = p.q[3];
-      const float* Gq = dRq;
-      float dqn[4];
-      dqn[0] = 2.f * (-qz * Gq[1] + qy * Gq[2] + qz * Gq[3] - qx * Gq[5] - qy * Gq[6] + qx * Gq[7]);
-      dqn[1] = 2.f * (qy * Gq[1] + qz * Gq[2] + qy * Gq[3] - 2.f * qx * Gq[4] - qw * Gq[5] +
-                      qz * Gq[6] + qw * Gq[7] - 2.f * qx * Gq[8]);
-      dqn[2] = 2.f * (-2.f * qy * Gq[0] + qx * Gq[1] + qw * Gq[2] + qx * Gq[3] + qz * Gq[5] -
-                      qw * Gq[6] + qz * Gq[7] - 2.f * qy * Gq[8]);
-      dqn[3] = 2.f * (-2.f * qz * Gq[0] - qw * Gq[1] + qx * Gq[2] + qw * Gq[3] - 2.f * qz * Gq[4] +
-                      qy * Gq[5] + qx * Gq[6] + qy * Gq[7]);
-      const float qd = qw * dqn[0] + qx * dqn[1] + qy * dqn[2] + qz * dqn[3];
-      for (int k = 0; k < 4; ++k) dq[k] = (dqn[k] - p.q[k] * qd) * p.qinv;
-      // T = J R:  dJ = dT R^T (only J00, J02, J11, J12 vary),  dR = J^T dT
-      const float dJ00 = dT[0] * V[0] + dT[1] * V[1] + dT[2] * V[2];
-      const float dJ02 = dT[0] * V[8] + dT[1] * V[9] + dT[2] * V[10];
-      const float dJ11 = dT[3] * V[4] + dT[4] * V[5] + dT[5] * V[6];
-      const float dJ12 = dT[3] * V[8] + dT[4] * V[9] + dT[5] * V[10];
-      float dR[9];
-      for (int l = 0; l < 3; ++l) {
-        dR[l] = p.J00 * dT[l];
-        dR[3 + l] = p.J11 * dT[3 + l];
-        dR[6 + l] = p.J02 * dT[l] + p.J12 * dT[3 + l];
-      }
-      // camera-space mean: image position, Jacobian, blended depth
-      const float rz = 1.f / p.z, rz2 = rz * rz, rz3 = rz2 * rz;
-      float gm0 = du * cam.fx * rz + dJ02 * (-cam.fx * rz2);
-      float gm1 = dv * cam.fy * rz + dJ12 * (-cam.fy * rz2);
-      float gm2 = du * (-cam.fx * p.x * rz2) + dv * (-cam.fy * p.y * rz2) +
-                  dJ00 * (-cam.fx * rz2) + dJ02 * (2.f * cam.fx * p.x * rz3) +
-                  dJ11 * (-cam.fy * rz2) + dJ12 * (2.f * cam.fy * p.y * rz3) + dz;
-      // world mean: R^T gm
-      for (int k = 0; k < 3; ++k) dmean[k] = V[k] * gm0 + V[4 + k] * gm1 + V[8 + k] * gm2;
-      // pose, left perturbation (Eq. 4): rho += gm, theta += mc x gm + sum_k R[:,k] x dR[:,k]
-      pose[0] = gm0;
-      pose[1] = gm1;
-      pose[2] = gm2;
-      pose[3] = p.y * gm2 - p.z * gm1;
-      pose[4] = p.z * gm0 - p.x * gm2;
-      pose[5] = p.x * gm1 - p.y * gm0;
-      for (int k = 0; k < 3; ++k) {
-        const float c0 = V[k], c1 = V[4 + k], c2 = V[8 + k];
-        const float e0 = dR[k], e1 = dR[3 + k], e2 = dR[6 + k];
-        pose[3] += c1 * e2 - c2 * e1;
-        pose[4] += c2 * e0 - c0 * e2;
-        pose[5] += c0 * e1 - c1 * e0;
-      }
-    }
+    if (p.valid) project_adjoint<float>(p, V, cam.fx, cam.fy, d, dmean, dls, dq, dlogit, pose);
     if (accumulate) {
       if (out.means)
         for (int k = 0; k < 3; ++k) out.means[k * P + i] += dmean[k];

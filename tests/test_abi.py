@@ -191,3 +191,43 @@ def test_tracking_and_visibility_argument_validation(capi):
                                   1 << 20, None) == E
     assert lib.gsff_decoder_query(1, 1, 1, 1, 1, 1, 4, 10, None, None, 1, None, 1 << 20,
                                   1 << 20, None) == E
+
+
+def test_f64_argument_validation(capi):
+    """The FP64 instantiation checks its limits and pointers on the host."""
+    lib = capi.load()
+    E = capi.ERR_INVALID_ARGUMENT
+    n = ctypes.c_size_t(0)
+    assert lib.gsff_f64_workspace_size(100, 4, 64, 48, ctypes.byref(n)) == capi.OK
+    assert n.value % 256 == 0 and n.value >= 100 * 8 * 8 + 64 * 48 * 12
+    for P, C, W, H in [(4097, 0, 8, 8), (10, 33, 8, 8), (10, 0, 257, 8), (10, 0, 8, 0),
+                       (-1, 0, 8, 8)]:
+        assert lib.gsff_f64_workspace_size(P, C, W, H, ctypes.byref(n)) == E
+    assert lib.gsff_f64_workspace_size(10, 0, 8, 8, None) == E
+    s = capi.default_settings()
+    cam = capi.Camera64(8, 8, 10.0, 10.0, 4.0, 4.0, 1)
+    g = capi.Gaussians64(10, 0, 1, 1, 1, 1, 1, None)
+    b = ctypes.byref
+    ws, nb = 1 << 20, 1 << 20  # aligned stand-ins, never dereferenced
+    out = (1, 1, 1, None, None, None)
+    # too many Gaussians, missing image output, misaligned or small workspace
+    big = capi.Gaussians64(5000, 0, 1, 1, 1, 1, 1, None)
+    assert lib.gsff_forward_f64(b(big), b(cam), b(s), ws, nb, *out) == E
+    assert lib.gsff_forward_f64(b(g), b(cam), b(s), ws, nb, None, 1, 1, None, None, None) == E
+    assert lib.gsff_forward_f64(b(g), b(cam), b(s), ws + 8, nb, *out) == E
+    assert lib.gsff_forward_f64(b(g), b(cam), b(s), ws, 64, *out) == E
+    # features without a feature pointer or output
+    gf = capi.Gaussians64(10, 4, 1, 1, 1, 1, 1, None)
+    assert lib.gsff_forward_f64(b(gf), b(cam), b(s), ws, nb, *out) == E
+    # camera without a view matrix, non-positive focal length
+    assert lib.gsff_forward_f64(b(g), b(capi.Camera64(8, 8, 10.0, 10.0, 4.0, 4.0, None)), b(s),
+                                ws, nb, *out) == E
+    assert lib.gsff_forward_f64(b(g), b(capi.Camera64(8, 8, 0.0, 10.0, 4.0, 4.0, 1)), b(s),
+                                ws, nb, *out) == E
+    # backward: NULL upstream, NULL gradient outputs
+    gr = capi.Grads64(1, 1, 1, 1, 1, None, 1)
+    assert lib.gsff_backward_f64(b(g), b(cam), b(s), ws, nb, None, 1, 1, None, b(gr), None) == E
+    assert lib.gsff_backward_f64(b(g), b(cam), b(s), ws, nb, 1, 1, 1, None, None, None) == E
+    gr_nopose = capi.Grads64(1, 1, 1, 1, 1, None, None)
+    assert lib.gsff_backward_f64(b(g), b(cam), b(s), ws, nb, 1, 1, 1, None, b(gr_nopose),
+                                 None) == E
