@@ -95,7 +95,8 @@ def parse():
     ap.add_argument("--profile-run", action="store_true",
                     help="for counter collection: eager steps only, no oracle work counts or "
                          "CPU baseline, plus one plain 256 MiB device copy whose counters "
-                         "calibrate FETCH_SIZE / WRITE_SIZE")
+                         "calibrate FETCH_SIZE / WRITE_SIZE, then a few decoder launches "
+                         "(decode, decode + query, train step)")
     return ap.parse_args()
 
 
@@ -404,6 +405,9 @@ def main():
         dst.copy_(src)
         for _ in range(args.steps):
             step.run()
+        torch.cuda.synchronize()
+        # the decoder kernels of the query leg: decode, decode + query, train step
+        query_rates(torch, fr, 2)
         torch.cuda.synchronize()
         log("profile run done")
         return

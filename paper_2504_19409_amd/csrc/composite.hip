@@ -247,6 +247,17 @@ void k_composite_fwd(
   __shared__ int s_act[2][kBlock / 64];
   const int tile = xcd_tile(blockIdx.x, ntiles);
   if (tile >= ntiles) return;
+  {
+    // Issue priority from the walk this tile had in the previous forward on
+    // this workspace (a hint: any value, even of a fresh workspace, is safe).
+    // All tiles of a frame are resident at once, so the launch ends with its
+    // longest walks; their waves go first and the short tiles fill the gaps.
+    const uint2 prev = w.crange[tile];
+    const uint32_t prev_len = __builtin_amdgcn_readfirstlane(prev.y - prev.x);
+    if (prev_len >= 12u * kFwdNB) __builtin_amdgcn_s_setprio(3);
+    else if (prev_len >= 9u * kFwdNB) __builtin_amdgcn_s_setprio(2);
+    else if (prev_len >= 6u * kFwdNB) __builtin_amdgcn_s_setprio(1);
+  }
   const int tid = threadIdx.x;
   // the wave index as a scalar: the scan wave's branches and counters stay uniform
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63, lq = lane >> 4,
