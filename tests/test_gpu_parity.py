@@ -89,14 +89,17 @@ def _oracle(sc, orc, settings=None, ups=None, feat=None):
     return o
 
 
-def _check_forward(res, o, tol=H.TOL_FWD, keys=("rgb", "depth", "alpha", "feat"), amb_cap=2e-3):
+def _check_forward(res, o, tol=H.TOL_FWD, keys=("rgb", "depth", "alpha", "feat"), amb_cap=2e-3,
+                   tag=None):
     amb = o["margin"] < H.MARGIN
     HW = amb.size
+    errs = {}
     for k in keys:
         g, r = res[k], o[k]
         if r.size == 0:
             continue
-        assert H.rel_l2(g, r) <= tol, (k, H.rel_l2(g, r))
+        errs[k] = H.rel_l2(g, r)
+        assert errs[k] <= tol, (k, errs[k])
         # element-wise: only decision-ambiguous pixels may be off
         mask = np.broadcast_to(~amb, r.shape)
         assert H.elementwise_outliers(g, r, 1e-4, mask) == 0, k
@@ -104,12 +107,19 @@ def _check_forward(res, o, tol=H.TOL_FWD, keys=("rgb", "depth", "alpha", "feat")
     # pixels hold a decision within MARGIN of a threshold; cap at 0.2% (or a handful
     # on small images).  The relative-L2 gate above still covers every pixel.
     assert amb.sum() <= max(16, amb_cap * HW), int(amb.sum())
+    if tag:
+        print(f"errors[{tag}] forward relL2: " +
+              ", ".join(f"{k} {v:.2e}" for k, v in errs.items()), flush=True)
 
 
-def _check_backward(res, o, tol=H.TOL_GRAD, keys=GRAD_KEYS):
+def _check_backward(res, o, tol=H.TOL_GRAD, keys=GRAD_KEYS, tag=None):
     """Relative L2 per group and element by element on every Gaussian the
     oracle does not flag as decision-ambiguous (o["amb"])."""
-    H.check_grads(res["grads"], o["grads"], keys, flags=o.get("amb"), tol=tol)
+    rep = {}
+    H.check_grads(res["grads"], o["grads"], keys, flags=o.get("amb"), tol=tol, report=rep)
+    if tag:
+        print(f"errors[{tag}] gradient relL2: " +
+              ", ".join(f"{k} {v['rel_l2']:.2e}" for k, v in rep.items()), flush=True)
 
 
 # ---------------------------------------------------------------- stages ----
@@ -255,8 +265,8 @@ def test_forward_backward_parity(orc, kind, C):
     sc = _scene(kind, C=C)
     res = _run(sc, orc)
     o = _oracle(sc, orc, ups=res["ups"])
-    _check_forward(res, o)
-    _check_backward(res, o)
+    _check_forward(res, o, tag=f"{kind} C={C}")
+    _check_backward(res, o, tag=f"{kind} C={C}")
 
 
 @pytest.mark.parametrize("C", [16, 0])
@@ -320,8 +330,8 @@ def test_full_frame_parity(orc):
     assert flags == 0
     res = _run(sc, orc, max_pairs=int(n * 1.05) + 1024)
     o = _oracle(sc, orc, ups=res["ups"])
-    _check_forward(res, o)
-    _check_backward(res, o)
+    _check_forward(res, o, tag="frame 200k 640x480")
+    _check_backward(res, o, tag="frame 200k 640x480")
 
 
 def test_feature_gradient_stays_on_its_own_path(orc):

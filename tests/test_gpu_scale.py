@@ -75,22 +75,28 @@ def test_mixed_precision_full_size(orc):
     p_r = dict(p, feat=rounded)
     o = orc.render_pixels(p_r, c, px, py)
     g = {k: v.cpu().numpy() for k, v in zip(["rgb", "depth", "alpha", "feat"], outs)}
-    assert H.rel_l2(g["rgb"][:, py, px].T, o["rgb"]) <= H.TOL_FWD
-    assert H.rel_l2(g["depth"][py, px], o["depth"]) <= H.TOL_FWD
-    assert H.rel_l2(g["alpha"][py, px], o["alpha"]) <= H.TOL_FWD
-    assert H.rel_l2(g["feat"][:, py, px].T, o["feat"]) <= H.TOL_FWD
+    errs = dict(rgb=H.rel_l2(g["rgb"][:, py, px].T, o["rgb"]),
+                depth=H.rel_l2(g["depth"][py, px], o["depth"]),
+                alpha=H.rel_l2(g["alpha"][py, px], o["alpha"]),
+                feat=H.rel_l2(g["feat"][:, py, px].T, o["feat"]))
+    print("errors[mixed 1M 1200x680 BF16x64, 3000 pixels] forward relL2 (vs the BF16-rounded "
+          "features): " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()), flush=True)
+    for k, v in errs.items():
+        assert v <= H.TOL_FWD, (k, v)
     # error against the unrounded FP32 features, per 16-channel group
     o32 = orc.render_pixels(p, c, px, py)
     for g0 in range(0, 64, 16):
         e = H.rel_l2(g["feat"][g0:g0 + 16, py, px].T, o32["feat"][:, g0:g0 + 16])
-        print(f"channels {g0}-{g0 + 15}: relL2 vs FP32 features {e:.2e}")
+        print(f"errors[mixed 1M 1200x680 BF16x64, 3000 pixels] channels {g0}-{g0 + 15}: "
+              f"relL2 vs the FP32 features {e:.2e}", flush=True)
         assert e <= H.TOL_BF16
     ob = orc.backward(p_r, c, dict(g_rgb=ups[0], g_depth=ups[1], g_alpha=ups[2], g_feat=ups[3]))
     amb = orc.ambiguous(p_r, c, H.MARGIN, px=px, py=py)
     rep = {}
     H.check_grads({k: v.cpu().numpy() for k, v in grads.items()}, ob, GRADS, flags=amb,
                   report=rep)
-    print("gradients:", rep)
+    print("errors[mixed 1M 1200x680 BF16x64, 3000 pixels] gradient relL2: " +
+          ", ".join(f"{k} {v['rel_l2']:.2e}" for k, v in rep.items()), flush=True)
 
 
 def test_keyframe_window_full_size(orc):
@@ -179,7 +185,8 @@ def test_keyframe_window_full_size(orc):
     amb = orc.ambiguous(p, cam, H.MARGIN, px=px, py=py)
     rep = {}
     H.check_grads({k: x.cpu().numpy() for k, x in g.items()}, ob, GRADS, flags=amb, report=rep)
-    print(f"view {v} gradients:", rep)
+    print(f"errors[window view {v} 1200x680 BF16x32, 2000 pixels] gradient relL2: " +
+          ", ".join(f"{k} {x['rel_l2']:.2e}" for k, x in rep.items()), flush=True)
 
 
 @pytest.mark.parametrize("W,Hh,f", [(1920, 1088, 1000.0), (3840, 2160, 2000.0)])
