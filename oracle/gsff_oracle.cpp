@@ -733,7 +733,8 @@ extern "C" int64_t orc_tile_lists(const orc_scene* s, const orc_camera* cam,
   int64_t total = 0;
   for (long t = 0; t < tx * ty; ++t) {
     counts[t] = (int64_t)lists[t].size();
-    if (ids) std::memcpy(ids + total, lists[t].data(), lists[t].size() * sizeof(int32_t));
+    if (ids && !lists[t].empty())  // (an empty list's data() may be null)
+      std::memcpy(ids + total, lists[t].data(), lists[t].size() * sizeof(int32_t));
     total += counts[t];
   }
   return total;
