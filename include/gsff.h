@@ -74,7 +74,8 @@ typedef int32_t gsff_status;
 /* Rendering constants the paper does not print (it inherits them from the
  * 3D Gaussian splatting rasterizer it builds on, Sec. 3.1).  Defaults from
  * gsff_default_settings(): near 0.2, guard 1.3, dilation 0.3,
- * alpha_min 1/255, alpha_max 0.99, t_min 1e-4, render_features 1. */
+ * alpha_min 1/255, alpha_max 0.99, t_min 1e-4, render_features 1, bin_mode 0,
+ * deterministic 0. */
 typedef struct gsff_settings {
   float near_plane;       /* Gaussians with camera z <= near_plane are culled     */
   float guard;            /* cull |x/z| > guard*W/(2fx) or |y/z| > guard*H/(2fy)  */
@@ -86,6 +87,17 @@ typedef struct gsff_settings {
   int32_t bin_mode;       /* 0: automatic; 1: bin by sorting (super-tile, rank)
                              keys even where the direct scatter applies (same
                              lists; for testing that path)                      */
+  int32_t deterministic;  /* 1: the adjoint sums every Gaussian's per-tile
+                             partial sums in a fixed order (each tile's sum in
+                             the slot of its place in the Gaussian's rectangle,
+                             one wave per Gaussian, no float atomics), so a
+                             backward repeated on the same inputs gives the
+                             same bits; 0 (default): slots in arrival order
+                             and Gaussians of more than 64 tiles summed with
+                             atomics (faster, run-to-run differences at FP32
+                             rounding).  Holds while the adjoint's rows fit
+                             (tiles whose rows do not fit fall back to
+                             atomics in either mode).                          */
 } gsff_settings;
 
 /* Pinhole camera.  viewmat is a DEVICE pointer to 12 floats, the row-major

@@ -25,7 +25,8 @@ class Settings(ctypes.Structure):
     _fields_ = [("near_plane", ctypes.c_float), ("guard", ctypes.c_float),
                 ("dilation", ctypes.c_float), ("alpha_min", ctypes.c_float),
                 ("alpha_max", ctypes.c_float), ("t_min", ctypes.c_float),
-                ("render_features", ctypes.c_int32), ("bin_mode", ctypes.c_int32)]
+                ("render_features", ctypes.c_int32), ("bin_mode", ctypes.c_int32),
+                ("deterministic", ctypes.c_int32)]
 
 
 class Camera(ctypes.Structure):

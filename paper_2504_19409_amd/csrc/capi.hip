@@ -231,8 +231,11 @@ gsff_status check_common(const gsff_gaussians* g, const gsff_camera* cam, const 
       return fail(GSFF_ERR_INVALID_ARGUMENT, "bin_mode 1: rank + super-tile bits exceed 32");
     c->L.direct_bin = false;
   }
-  c->st = DevSettings{st->near_plane, st->guard, st->dilation, st->alpha_min,
-                      st->alpha_max, st->t_min, st->render_features ? 1 : 0};
+  if (st->deterministic != 0 && st->deterministic != 1)
+    return fail(GSFF_ERR_INVALID_ARGUMENT, "deterministic must be 0 or 1");
+  c->st = DevSettings{st->near_plane, st->guard, st->dilation,        st->alpha_min,
+                      st->alpha_max,  st->t_min,   st->render_features ? 1 : 0,
+                      st->deterministic};
   c->s = (hipStream_t)stream;
   return GSFF_OK;
 }
@@ -277,6 +280,7 @@ gsff_status gsff_default_settings(gsff_settings* st) {
   st->t_min = 1e-4f;
   st->render_features = 1;
   st->bin_mode = 0;
+  st->deterministic = 0;
   return GSFF_OK;
 }
 

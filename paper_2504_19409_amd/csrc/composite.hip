@@ -601,6 +601,18 @@ __global__ void k_fill_zero(OT* p, int64_t n) {
   if (i < n) p[i] = OT(0);
 }
 
+// Deterministic mode: every slot of the Gaussians' rectangles empty
+// (0xFFFFFFFF) before the adjoint files its rows; the slots in use end where
+// the scan of the per-block slot counts ends.
+__global__ __launch_bounds__(256) void k_fill_slots(WsView w, int nslot_blk) {
+  const uint64_t used = nslot_blk > 0 ? (uint64_t)w.slot_blk[nslot_blk - 1] +
+                                             w.slot_cnt[nslot_blk - 1]
+                                       : 0ull;
+  const uint64_t n = used < w.slot_cap ? used : w.slot_cap;
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256)
+    w.slots[i] = 0xFFFFFFFFu;
+}
+
 // The adjoint's work items and the first adjoint row of every tile, built by
 // one workgroup of NT threads (the standalone kernel below, or the first
 // workgroup of the L1 upstream pass).
@@ -1622,17 +1634,29 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
     }
     // the first pass files each valid Gaussian's row in the Gaussian's slots
     // (a Gaussian has a slot per tile of its rectangle and meets each tile once)
-    // and opens a reduction work item at every 64th slot
+    // and opens a reduction work item at every 64th slot; in the deterministic
+    // mode the row goes to the slot of this tile's place in the rectangle and
+    // the reduction visits every Gaussian's slots in order instead
     if (first_pass && rows_ok && pf_lane) {
       const uint32_t gid = s_gid[buf][pf];
       if ((uint32_t)pf < b1 - b0 && gid < (uint32_t)P) {
         const uint32_t row = rowbase + b0 + (uint32_t)pf;
-        const uint32_t k = atomicAdd(&w.nslot[gid], 1u);
-        const uint32_t sl = w.slot_blk[gid >> 8] + w.slot_local[gid] + k;
-        if (sl < w.slot_cap) w.slots[sl] = row;
-        if ((k & 63u) == 0u) {
-          const uint32_t t = atomicAdd(w.item_n, 1u);
-          if (t < w.item_cap) w.items[t] = make_uint2(gid, k);
+        const uint32_t sbase = w.slot_blk[gid >> 8] + w.slot_local[gid];
+        if (st.deterministic) {
+          const ushort4 rc = w.rects[gid];
+          if (tx >= rc.x && tx <= rc.z && ty >= rc.y && ty <= rc.w) {
+            const uint32_t sl = sbase + (uint32_t)(ty - rc.y) * (uint32_t)(rc.z - rc.x + 1) +
+                                (uint32_t)(tx - rc.x);
+            if (sl < w.slot_cap) w.slots[sl] = row;
+          }
+        } else {
+          const uint32_t k = atomicAdd(&w.nslot[gid], 1u);
+          const uint32_t sl = sbase + k;
+          if (sl < w.slot_cap) w.slots[sl] = row;
+          if ((k & 63u) == 0u) {
+            const uint32_t t = atomicAdd(w.item_n, 1u);
+            if (t < w.item_cap) w.items[t] = make_uint2(gid, k);
+          }
         }
       }
     }
@@ -1715,6 +1739,8 @@ hipError_t launch_composite_bwd_impl(const DevGaussians& g, const DevSettings& s
                        d_feat, n);
   }
   if (L.P == 0 && !l1) return hipGetLastError();
+  if (st.deterministic && L.P > 0)
+    hipLaunchKernelGGL(k_fill_slots, dim3(1024), dim3(256), 0, s, w, (int)L.pose_blocks);
   L1Upstream none{};
   const L1Upstream& u = l1 ? *l1 : none;
   const int C = feat_on ? g.C : 0;

@@ -343,7 +343,7 @@ gsff_status f64_common(const gsff_gaussians_f64* g, const gsff_camera_f64* cam,
   c->g = F64Scene{g->P, g->C, g->means, g->log_scales, g->quats, g->logit_opacity, g->rgb, g->feat};
   c->cam = F64Cam{cam->width, cam->height, cam->fx, cam->fy, cam->cx, cam->cy, cam->viewmat};
   c->st = DevSettings{st->near_plane, st->guard, st->dilation, st->alpha_min,
-                      st->alpha_max, st->t_min, st->render_features ? 1 : 0};
+                      st->alpha_max, st->t_min, st->render_features ? 1 : 0, 0};
   c->s = (hipStream_t)stream;
   return GSFF_OK;
 }

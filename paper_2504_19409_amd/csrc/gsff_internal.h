@@ -127,6 +127,7 @@ WsView make_view(void* ws, const Layout& L);
 struct DevSettings {
   float near_plane, guard, dilation, alpha_min, alpha_max, t_min;
   int32_t render_features;
+  int32_t deterministic;  // fixed-order adjoint reduction
 };
 
 struct DevCamera {

@@ -237,6 +237,54 @@ __global__ __launch_bounds__(256) void k_pose_final(const double* __restrict__ p
   }
 }
 
+// Deterministic mode: one wave per Gaussian sums the rows in the slots of
+// its rectangle in slot order (a tile's row sits in the slot of the tile's
+// place in the rectangle; empty slots hold 0xFFFFFFFF), 64 slots at a time
+// with the lane groups of k_adjoint_reduce, adding the chunks in order: the
+// same inputs give the same bits, whatever order the rows were written in.
+template <int CW>
+__global__ __launch_bounds__(256) void k_adjoint_reduce_det(WsView w, int64_t P, int C,
+                                                            float* __restrict__ d_feat) {
+  constexpr int RPI = 64 / CW;
+  const int lane = threadIdx.x & 63;
+  const int cl = lane & (CW - 1), rsub = lane / CW;
+  const int64_t gg = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (gg >= P) return;  // whole wave
+  const ushort4 rc = w.rects[gg];
+  const uint32_t ntile = (rc.x <= rc.z && rc.y <= rc.w)
+                             ? (uint32_t)(rc.z - rc.x + 1) * (uint32_t)(rc.w - rc.y + 1)
+                             : 0u;
+  if (ntile == 0u) return;  // whole wave
+  const uint32_t base = w.slot_blk[gg >> 8] + w.slot_local[gg];
+  const int RW = w.row_width;
+  const int ncol = 10 + (d_feat ? C : 0);
+  for (int c0 = 0; c0 < ncol; c0 += CW) {
+    const int col = c0 + cl;
+    float tot = 0.f;
+    for (uint32_t k0 = 0; k0 < ntile; k0 += 64) {
+      const uint32_t sl = base + k0 + (uint32_t)lane;
+      const uint32_t myrow =
+          (k0 + (uint32_t)lane < ntile && sl < w.slot_cap) ? w.slots[sl] : 0xFFFFFFFFu;
+      float acc = 0.f;
+#pragma unroll
+      for (int u = 0; u < 64 / RPI; ++u) {
+        const int j = u * RPI + rsub;
+        const uint32_t r = (uint32_t)__shfl((int)myrow, j, 64);
+        const bool ok = r < w.row_cap && col < ncol;
+        const float v = w.rows[ok ? (int64_t)r * RW + col : 0];
+        acc += ok ? v : 0.f;
+      }
+#pragma unroll
+      for (int off = CW; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
+      tot += acc;
+    }
+    if (rsub == 0 && col < ncol && tot != 0.f) {
+      float* dst = col < 10 ? w.grad2d + gg * 10 + col : d_feat + gg * C + (col - 10);
+      *dst += tot;
+    }
+  }
+}
+
 hipError_t launch_preprocess(const DevGaussians& g, const DevCamera& cam, const DevSettings& st,
                              const Layout& L, const WsView& w, hipStream_t s) {
   const int64_t blocks = g.P > 0 ? (g.P + 255) / 256 : 1;
@@ -252,7 +300,15 @@ hipError_t launch_preprocess_bwd(const DevGaussians& g, const DevCamera& cam,
     float* df = g.C > 0 ? out.feat : nullptr;
     const int ncol = 10 + (df ? g.C : 0);
     const unsigned nblk = (unsigned)std::min<int64_t>(std::max<int64_t>((waves + 3) / 4, 1), 2048);
-    if (ncol <= 16)
+    const unsigned ndet = (unsigned)((g.P + 3) / 4);  // one wave per Gaussian
+    if (st.deterministic) {
+      if (ncol <= 16)
+        hipLaunchKernelGGL(k_adjoint_reduce_det<16>, dim3(ndet), dim3(256), 0, s, w, g.P, g.C, df);
+      else if (ncol <= 32)
+        hipLaunchKernelGGL(k_adjoint_reduce_det<32>, dim3(ndet), dim3(256), 0, s, w, g.P, g.C, df);
+      else
+        hipLaunchKernelGGL(k_adjoint_reduce_det<64>, dim3(ndet), dim3(256), 0, s, w, g.P, g.C, df);
+    } else if (ncol <= 16)
       hipLaunchKernelGGL(k_adjoint_reduce<16>, dim3(nblk), dim3(256), 0, s, w, g.P, g.C, df,
                          (uint32_t)L.max_pairs);
     else if (ncol <= 32)

@@ -108,6 +108,9 @@ def test_argument_validation(capi):
     # bad settings
     s2 = capi.default_settings(alpha_min=0.0)
     assert lib.gsff_forward(b(g), b(c), b(s2), ws, nb, mp, 1, 1, 1, None, 0, None) == E
+    s3 = capi.default_settings(deterministic=2)
+    assert lib.gsff_forward(b(g), b(c), b(s3), ws, nb, mp, 1, 1, 1, None, 0, None) == E
+    assert capi.default_settings().deterministic == 0
     # features on, C > 0, but no feature output
     g2, *_ = _args(capi, C=4)
     assert lib.gsff_forward(b(g2), b(c), b(s), ws, nb, mp, 1, 1, 1, None, 0, None) == E

@@ -749,3 +749,15 @@ def test_backward_l1_feature_only(orc):
     H.check_grads({"feat": grads["feat"].cpu().numpy()}, ob, ["feat"],
                   flags=orc.ambiguous(p, c, H.MARGIN))
     assert loss.item() == pytest.approx(np.abs(of - t_feat).mean(), rel=2e-5)
+
+
+@pytest.mark.parametrize("kind,C", [("tiny", 16), ("dense", 8), ("ragged", 33)])
+def test_deterministic_mode_parity(orc, kind, C):
+    """The fixed-order reduction (settings.deterministic = 1) against the
+    oracle, including Gaussians whose rectangles span more than 64 tiles
+    (the dense scene's large splats) and a second channel pass (C = 33)."""
+    sc = _scene(kind, C=C)
+    res = _run(sc, orc, settings=_settings(deterministic=1))
+    o = _oracle(sc, orc, ups=res["ups"])
+    _check_forward(res, o)
+    _check_backward(res, o, tag=f"{kind} C={C} deterministic")
