@@ -55,6 +55,24 @@ typedef int32_t gsff_status;
 /* a depth-sort workgroup stopped waiting for an earlier one (not expected;
  * the frame's results are not valid) */
 #define GSFF_FLAG_SORT_STALL 2u
+/* checked build only (gsff_is_checked_build): an index that comes from data
+ * (a sort destination, a listed Gaussian id, a tile range, an adjoint row or
+ * slot) failed its bounds test; the access was skipped and
+ * gsff_read_checks() names the first failure.  Never raised by a correct
+ * library on any input. */
+#define GSFF_FLAG_CHECK 4u
+
+/* Sites of the checked build's bounds tests (gsff_read_checks) */
+#define GSFF_CHECK_SORT_DEST 1u   /* depth-sort destination < P                     */
+#define GSFF_CHECK_RANK_ID 2u     /* Gaussian id at a depth rank < P                */
+#define GSFF_CHECK_PAIR_DEST 3u   /* binned pair position < pairs of the frame      */
+#define GSFF_CHECK_TILE_RANGE 4u  /* super-tile list: start <= end <= pairs         */
+#define GSFF_CHECK_LIST_ID 5u     /* id in a tile list or walked list < P           */
+#define GSFF_CHECK_WALK 6u        /* walked-list entry inside the tile's segment    */
+#define GSFF_CHECK_ITEM 7u        /* adjoint item: tile, segment, list range        */
+#define GSFF_CHECK_ROW 8u         /* adjoint row < row capacity                     */
+#define GSFF_CHECK_SLOT 9u        /* adjoint slot inside the Gaussian's slot range  */
+#define GSFF_CHECK_REDUCE 10u     /* reduction item / row read from a slot          */
 
 /* payload / output element types */
 #define GSFF_DTYPE_F32 0
@@ -143,7 +161,9 @@ typedef struct gsff_grads {
 /* Where each workspace region starts (byte offsets from the workspace base)
  * and how big it is; used by tests to inspect intermediate stages. */
 typedef struct gsff_ws_layout {
-  uint64_t status;      /* uint32[4]: flags, pair count, reserved x2            */
+  uint64_t status;      /* uint32[8]: flags, pair count, pairs in use, reserved,
+                           then (checked build) the first failed check's site,
+                           index and limit, and the number of failed checks     */
   uint64_t records;     /* float4[3][P]: (u,v,A,B) (C,o,z,valid) (r,g,b,-)     */
   uint64_t rects;       /* uint16[4][P]: tile rect x0,y0,x1,y1 (inclusive); empty => x0>x1 */
   uint64_t depth_keys;  /* uint32[P]: sorted depth keys (float bits)           */
@@ -173,6 +193,13 @@ typedef struct gsff_ws_layout {
 
 /* Library version (host only, no device work). */
 gsff_status gsff_version(int32_t* major, int32_t* minor);
+
+/* *checked = 1 for the checked build of the library (libgsff_checked.so:
+ * every data-dependent index of the rasterizer's kernels is tested against
+ * the buffer it addresses, a failure skips the access and raises
+ * GSFF_FLAG_CHECK; slower, for test runs), 0 for the release build.  Host
+ * only. */
+gsff_status gsff_is_checked_build(int32_t* checked);
 
 /* Text of the last GSFF_ERR_HIP / argument error raised on this thread. */
 const char* gsff_last_error(void);
@@ -600,6 +627,14 @@ gsff_status gsff_backward_f64(const gsff_gaussians_f64* g, const gsff_camera_f64
  * bits and *n_pairs the number of super-tile pairs the last forward needed (even
  * when it exceeded max_pairs).  Host pointers; either may be NULL. */
 gsff_status gsff_read_status(const void* ws, uint32_t* flags, int64_t* n_pairs, void* stream);
+
+/* Checked build: wait for `stream`, then copy the bounds-test record of the
+ * workspace to host memory out[4] = {failed tests, site of the first failure
+ * (GSFF_CHECK_*), its index, its limit} (indices saturate at 2^32 - 1).  The
+ * record is cleared by every forward (gsff_forward / gsff_preprocess) and
+ * collects the failures of the forward and of the adjoints that follow it.
+ * The release build tests nothing and reports zeros. */
+gsff_status gsff_read_checks(const void* ws, uint32_t* out, void* stream);
 
 #ifdef __cplusplus
 }

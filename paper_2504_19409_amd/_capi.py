@@ -2,17 +2,25 @@
 only; every step of the computation runs in the HIP library)."""
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgsff.so")
+# the checked build: every data-dependent index of the rasterizer's kernels
+# tested against its buffer (see checked_library)
+CHECKED_LIB_PATH = os.path.join(_HERE, "libgsff_checked.so")
 
 OK = 0
 ERR_INVALID_ARGUMENT = -1
 ERR_UNSUPPORTED = -2
 ERR_HIP = -3
 FLAG_PAIR_OVERFLOW = 1
+FLAG_SORT_STALL = 2
+FLAG_CHECK = 4
+CHECK_SITES = {1: "sort_dest", 2: "rank_id", 3: "pair_dest", 4: "tile_range", 5: "list_id",
+               6: "walk", 7: "item", 8: "row", 9: "slot", 10: "reduce"}
 DTYPE_F32, DTYPE_BF16, DTYPE_F16 = 0, 1, 2
 TILE = 16
 SUPER = 4
@@ -97,6 +105,8 @@ _i64, _i32, _f32, _sz = ctypes.c_int64, ctypes.c_int32, ctypes.c_float, ctypes.c
 SIGNATURES = {
     "gsff_version": (_i32, [ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "gsff_last_error": (ctypes.c_char_p, []),
+    "gsff_is_checked_build": (_i32, [ctypes.POINTER(_i32)]),
+    "gsff_read_checks": (_i32, [_vp, ctypes.POINTER(ctypes.c_uint32), _vp]),
     "gsff_default_settings": (_i32, [_S]),
     "gsff_workspace_size": (_i32, [_i64, _i32, _i64, _i32, _i32, ctypes.POINTER(_sz)]),
     "gsff_workspace_layout": (_i32, [_i64, _i32, _i64, _i32, _i32, ctypes.POINTER(WsLayout)]),
@@ -143,25 +153,57 @@ SIGNATURES = {
     "gsff_decoder_train_step": (_i32, [_vp] * 6 + [_i64, _f32] + [_vp] * 7 + [_sz, _vp]),
 }
 
-_lib = None
+_libs: dict[str, ctypes.CDLL] = {}
+_active = LIB_PATH
 
 
 def load() -> ctypes.CDLL:
-    """Load libgsff.so.  Raises if it is missing: there is no fallback."""
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB_PATH):
+    """Load libgsff.so (libgsff_checked.so inside checked_library()).  Raises
+    if it is missing: there is no fallback."""
+    path = _active
+    if path not in _libs:
+        if not os.path.exists(path):
             raise RuntimeError(
-                f"{LIB_PATH} is not built; run paper_2504_19409_amd/build.py "
+                f"{path} is not built; run paper_2504_19409_amd/build.py "
                 "(or __graft_entry__.build()) first")
-        L = ctypes.CDLL(LIB_PATH)
+        L = ctypes.CDLL(path)
         for name, (res, args) in SIGNATURES.items():
             if hasattr(L, name):
                 f = getattr(L, name)
                 f.restype = res
                 f.argtypes = args
-        _lib = L
-    return _lib
+        _libs[path] = L
+    return _libs[path]
+
+
+@contextlib.contextmanager
+def checked_library():
+    """Route every library call made inside the block (by this module's
+    wrappers, the Frame class and the rest of the package) to the checked
+    build, then back to the release build.  Both can be loaded at once; a
+    workspace belongs to the build whose forward filled it."""
+    global _active
+    prev = _active
+    _active = CHECKED_LIB_PATH
+    try:
+        L = load()
+        flag = _i32(0)
+        check(L.gsff_is_checked_build(ctypes.byref(flag)), "gsff_is_checked_build")
+        if flag.value != 1:
+            raise RuntimeError(f"{CHECKED_LIB_PATH} is not the checked build")
+        yield L
+    finally:
+        _active = prev
+
+
+def read_checks(ws_ptr: int, stream: int = 0) -> dict:
+    """The workspace's bounds-test record (checked build; zeros otherwise):
+    failures, and site / index / limit of the first one."""
+    out = (ctypes.c_uint32 * 4)()
+    check(load().gsff_read_checks(ctypes.c_void_p(ws_ptr), out, ctypes.c_void_p(stream)),
+          "gsff_read_checks")
+    return {"failures": int(out[0]), "site": CHECK_SITES.get(int(out[1]), int(out[1])),
+            "index": int(out[2]), "limit": int(out[3])}
 
 
 class GsffError(RuntimeError):

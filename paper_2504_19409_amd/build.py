@@ -2,6 +2,10 @@
 
 Every translation unit is compiled for gfx950 only, with packed-FP32 VALU
 instructions disabled, then linked into ``paper_2504_19409_amd/libgsff.so``.
+The same sources compiled with ``-DGSFF_CHECKED=1`` make the checked build
+``libgsff_checked.so`` (every data-dependent index tested against its buffer,
+failures recorded in the workspace status word instead of faulting), and
+``probe.hip`` the roofline microbenchmarks ``libgsff_probe.so``.
 """
 from __future__ import annotations
 
@@ -16,6 +20,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgsff.so")
 PROBE_LIB = os.path.join(HERE, "libgsff_probe.so")
+CHECKED_LIB = os.path.join(HERE, "libgsff_checked.so")
+CHECKED_BUILD = os.path.join(BUILD, "checked")
 SOURCES = ["capi.hip", "preprocess.hip", "sort.hip", "composite.hip", "decoder.hip",
            "tracking.hip", "mapping.hip", "f64.hip"]
 ARCH = "gfx950"
@@ -35,36 +41,39 @@ def common_flags():
             "-I", os.path.join(HERE, "..", "include")]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(os.path.basename(src))[0] + ".o")
-    cmd = [hipcc(), *common_flags(), "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(src: str, checked: bool = False) -> str:
+    out = CHECKED_BUILD if checked else BUILD
+    obj = os.path.join(out, os.path.splitext(os.path.basename(src))[0] + ".o")
+    cmd = [hipcc(), *common_flags(), *(["-DGSFF_CHECKED=1"] if checked else []), "-c",
+           os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
+        raise RuntimeError(f"hipcc failed for {src}{' (checked)' if checked else ''}:\n{r.stderr}")
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
-    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
-    # the roofline microbenchmarks, a library of their own
-    pobj = _compile("probe.hip")
-    ptmp = PROBE_LIB + ".tmp"
-    r = subprocess.run([hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", ptmp, pobj],
+def _link(lib: str, objs) -> None:
+    tmp = lib + ".tmp"
+    r = subprocess.run([hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs],
                        capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(ptmp, PROBE_LIB)
+    os.replace(tmp, lib)
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(CHECKED_BUILD, exist_ok=True)
+    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    jobs = [(s, False) for s in srcs] + [(s, True) for s in srcs] + [("probe.hip", False)]
+    # the largest translation units first, so the pool drains evenly
+    jobs.sort(key=lambda j: -os.path.getsize(os.path.join(CSRC, j[0])))
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
+        objs = dict(zip(jobs, ex.map(lambda j: _compile(*j), jobs)))
+    _link(LIB, [objs[(s, False)] for s in srcs])
+    _link(CHECKED_LIB, [objs[(s, True)] for s in srcs])
+    _link(PROBE_LIB, [objs[("probe.hip", False)]])
     if verbose:
-        print("built", LIB, "and", PROBE_LIB)
+        print("built", LIB, CHECKED_LIB, "and", PROBE_LIB)
     return LIB
 
 

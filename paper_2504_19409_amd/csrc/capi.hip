@@ -66,7 +66,7 @@ bool compute_layout(int64_t P, int32_t C, int64_t max_pairs, int32_t W, int32_t 
     o = align_up(o + bytes, A);
     return at;
   };
-  l.status = take(16);
+  l.status = take(32);
   l.records = take(48ull * P);
   l.rects = take(8ull * P);
   l.dkeys_a = take(4ull * P);
@@ -265,6 +265,12 @@ gsff_status gsff_version(int32_t* major, int32_t* minor) {
   if (!major || !minor) return fail(GSFF_ERR_INVALID_ARGUMENT, "NULL version pointer");
   *major = 0;
   *minor = 1;
+  return GSFF_OK;
+}
+
+gsff_status gsff_is_checked_build(int32_t* checked) {
+  if (!checked) return fail(GSFF_ERR_INVALID_ARGUMENT, "NULL output");
+  *checked = GSFF_CHECKED ? 1 : 0;
   return GSFF_OK;
 }
 
@@ -569,6 +575,20 @@ gsff_status gsff_read_status(const void* ws, uint32_t* flags, int64_t* n_pairs, 
   if (rc != GSFF_OK) return rc;
   if (flags) *flags = h[0];
   if (n_pairs) *n_pairs = (int64_t)h[1];
+  return GSFF_OK;
+}
+
+gsff_status gsff_read_checks(const void* ws, uint32_t* out, void* stream) {
+  if (!ws || !out) return fail(GSFF_ERR_INVALID_ARGUMENT, "NULL workspace or output");
+  gsff_status rc = hip_check(hipStreamSynchronize((hipStream_t)stream), "stream sync");
+  if (rc != GSFF_OK) return rc;
+  uint32_t h[8];
+  rc = hip_check(hipMemcpy(h, ws, sizeof(h), hipMemcpyDeviceToHost), "status copy");
+  if (rc != GSFF_OK) return rc;
+  out[0] = h[kStatusChkCount];
+  out[1] = h[kStatusChkSite];
+  out[2] = h[kStatusChkIndex];
+  out[3] = h[kStatusChkLimit];
   return GSFF_OK;
 }
 

@@ -271,7 +271,12 @@ void k_composite_fwd(
   const int sx = (tiles_x + kSuper - 1) / kSuper;
   const int lsub = (ty % kSuper) * kSuper + tx % kSuper;
   const uint32_t bit = 1u << lsub;
-  const uint2 sr = clamp_range(w.tile_ranges[(ty / kSuper) * sx + tx / kSuper], max_pairs);
+  const uint2 sraw = w.tile_ranges[(ty / kSuper) * sx + tx / kSuper];
+  if (GSFF_CHECKED && tid == 0) {  // start <= end <= the frame's pairs
+    GSFF_CHECK(w.status, GSFF_CHECK_TILE_RANGE, sraw.x, (uint64_t)sraw.y + 1u);
+    GSFF_CHECK(w.status, GSFF_CHECK_TILE_RANGE, sraw.y, (uint64_t)w.status[2] + 1u);
+  }
+  const uint2 sr = clamp_range(sraw, max_pairs);
   // the tile's walked list: kSuper^2 slots of the super-tile's length per super-tile entry
   const uint32_t cbase = (uint32_t)(kSuper * kSuper) * sr.x + (uint32_t)lsub * (sr.y - sr.x);
   const int cn = CP > 0 ? min(CP, C - c0) : 0;
@@ -291,7 +296,8 @@ void k_composite_fwd(
   };
   // append the accepted ones to the queue, in list order
   auto scan_commit = [&](uint32_t gA, uint32_t mA, uint32_t gB, uint32_t mB) {
-    const bool a = (mA & bit) != 0u, b = (mB & bit) != 0u;
+    const bool a = (mA & bit) != 0u && GSFF_CHECK(w.status, GSFF_CHECK_LIST_ID, gA, (uint64_t)P);
+    const bool b = (mB & bit) != 0u && GSFF_CHECK(w.status, GSFF_CHECK_LIST_ID, gB, (uint64_t)P);
     const uint64_t ba = __ballot(a), bb = __ballot(b);
     if (a) s_q[(qt + bits_below_lane(ba)) & (kFwdQueue - 1)] = gA;
     qt += (uint32_t)__popcll(ba);
@@ -311,7 +317,8 @@ void k_composite_fwd(
     g = (uint32_t)P;
     if ((uint32_t)lane < n) {
       g = s_q[(qh + (uint32_t)lane) & (kFwdQueue - 1)];
-      if (write_geo) w.clist[cbase + qh + (uint32_t)lane] = g;
+      if (write_geo && GSFF_CHECK(w.status, GSFF_CHECK_WALK, qh + (uint32_t)lane, sr.y - sr.x))
+        w.clist[cbase + qh + (uint32_t)lane] = g;
     }
     pos = qh;
     qh += n;
@@ -831,7 +838,7 @@ hipError_t launch_adjoint_items(const Layout& L, const WsView& w, hipStream_t s)
 // (transmittance only falls along the list).  visible must be zero before.
 __global__ __launch_bounds__(kBlock) void k_visibility(DevSettings st, int64_t P, int W, int H,
                                                        int tiles_x, int ntiles, WsView w,
-                                                       float t_vis,
+                                                       float t_vis, uint32_t ccap,
                                                        uint8_t* __restrict__ visible) {
   __shared__ float4 s_r0[64], s_r1[64];
   __shared__ uint32_t s_id[64];
@@ -843,13 +850,17 @@ __global__ __launch_bounds__(kBlock) void k_visibility(DevSettings st, int64_t P
   const int px = tx * kTile + (tid & (kTile - 1)), py = ty * kTile + tid / kTile;
   const bool inside = px < W && py < H;
   const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
-  const uint2 cr = w.crange[tile];
+  // the walked range, inside the walked lists whatever the workspace holds
+  const uint2 craw = w.crange[tile];
+  if (GSFF_CHECKED && tid == 0) GSFF_CHECK(w.status, GSFF_CHECK_WALK, craw.y, (uint64_t)ccap + 1u);
+  const uint2 cr = clamp_range(craw, ccap);
   float T = 1.f;
   bool done = !inside;
   for (uint32_t b = cr.x; b < cr.y; b += 64u) {
     const uint32_t n = min(64u, cr.y - b);
     if (tid < 64) {
       const uint32_t gid = (uint32_t)tid < n ? w.clist[b + (uint32_t)tid] : (uint32_t)P;
+      if (GSFF_CHECKED && (uint32_t)tid < n) GSFF_CHECK(w.status, GSFF_CHECK_LIST_ID, gid, (uint64_t)P);
       float4 q0, q1, q2;
       load_record(w, gid, P, q0, q1, q2);
       s_r0[tid] = scaled_r0(q0);
@@ -898,7 +909,10 @@ hipError_t launch_visibility(const DevSettings& st, const DevGaussians& g, const
                      visible, (int64_t)L.P);
   if (L.ntiles > 0)
     hipLaunchKernelGGL(k_visibility, dim3((unsigned)L.ntiles), dim3(kBlock), 0, s, st, g.P, L.W,
-                       L.H, L.tiles_x, L.ntiles, w, t_vis, visible);
+                       L.H, L.tiles_x, L.ntiles, w, t_vis,
+                       (uint32_t)min((uint64_t)(kSuper * kSuper) * (uint64_t)L.max_pairs,
+                                     (uint64_t)0xFFFFFFFFu),
+                       visible);
   return hipGetLastError();
 }
 
@@ -1251,7 +1265,14 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
   const bool rows_ok = (item.x >> 31) != 0u;       // the tile's rows fit
   const uint32_t q1 = item.y, q2 = item.z;
   const uint32_t rowbase = item.w;  // row of list position p: rowbase + p
-  if (tile >= ntiles) return;
+  if (!guard(w.status, GSFF_CHECK_ITEM, tile, ntiles)) return;
+  if (GSFF_CHECKED) {  // list range inside the walked lists, a recorded state per inner segment
+    const uint64_t ccap = min((uint64_t)(kSuper * kSuper) * max_pairs, (uint64_t)0xFFFFFFFFu);
+    if (!GSFF_CHECK(w.status, GSFF_CHECK_ITEM, q1, (uint64_t)q2 + 1u) ||
+        !GSFF_CHECK(w.status, GSFF_CHECK_ITEM, q2, ccap + 1u) ||
+        (inner && !GSFF_CHECK(w.status, GSFF_CHECK_ITEM, (uint64_t)seg, (uint64_t)(kMaxSeg - 1))))
+      return;
+  }
   const int tx = tile % tiles_x, ty = tile / tiles_x;
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63, lq = lane >> 4, lj = lane & 15;
@@ -1283,6 +1304,10 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
   if (pf_lane) {
     if (b0 + pf < b1) gid0 = w.clist[b0 + pf];
     if (nb0 + pf < nb1) g_next = w.clist[nb0 + pf];
+    if (GSFF_CHECKED) {  // every walked entry is a Gaussian id
+      if (b0 + pf < b1) GSFF_CHECK(w.status, GSFF_CHECK_LIST_ID, gid0, (uint64_t)P);
+      if (nb0 + pf < nb1) GSFF_CHECK(w.status, GSFF_CHECK_LIST_ID, g_next, (uint64_t)P);
+    }
   }
 
 
@@ -1493,6 +1518,8 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
     if (pf_lane) {
       if (more) load_record(w, pgid, P, p0, p1, p2);
       g_next = (more && mb0 + pf < mb1) ? w.clist[mb0 + pf] : (uint32_t)P;
+      if (GSFF_CHECKED && more && mb0 + pf < mb1)
+        GSFF_CHECK(w.status, GSFF_CHECK_LIST_ID, g_next, (uint64_t)P);
     }
 
     // ---- phase A: per-pixel products, back to front
@@ -1570,7 +1597,8 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const uint32_t g = 4 * lq + r;
-          if (g < nb) {
+          // (the row index is formed modulo 2^32: rowbase may wrap below zero)
+          if (g < nb && GSFF_CHECK(w.status, GSFF_CHECK_ROW, rowbase + b0 + g, w.row_cap)) {
             float* row = w.rows + (int64_t)(rowbase + b0 + g) * RW;
             if (col >= 0) row[col] = acc[r] * scale;
             if (wave == 0 && first_pass) {  // columns no pass of this call writes
@@ -1619,9 +1647,11 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
             float geo[6];
             geo_from_moments(cA, cB, cC, r1.y, udx, vdy, M, geo);
             if (rows_ok) {
-              float* row = w.rows + (int64_t)(rowbase + b0 + (uint32_t)lane) * RW;
+              if (GSFF_CHECK(w.status, GSFF_CHECK_ROW, rowbase + b0 + (uint32_t)lane, w.row_cap)) {
+                float* row = w.rows + (int64_t)(rowbase + b0 + (uint32_t)lane) * RW;
 #pragma unroll
-              for (int f = 0; f < 6; ++f) row[f] = geo[f];
+                for (int f = 0; f < 6; ++f) row[f] = geo[f];
+              }
             } else {
               float* dst = w.grad2d + (int64_t)gid * 10;
 #pragma unroll
@@ -1644,18 +1674,30 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
         const uint32_t sbase = w.slot_blk[gid >> 8] + w.slot_local[gid];
         if (st.deterministic) {
           const ushort4 rc = w.rects[gid];
-          if (tx >= rc.x && tx <= rc.z && ty >= rc.y && ty <= rc.w) {
+          // the tile lies in the rectangle (its list holds the Gaussian)
+          const bool in_rect = tx >= rc.x && tx <= rc.z && ty >= rc.y && ty <= rc.w;
+          if (GSFF_CHECKED && !in_rect)
+            check_failed(w.status, GSFF_CHECK_SLOT, (uint64_t)tile, (uint64_t)gid);
+          if (in_rect) {
             const uint32_t sl = sbase + (uint32_t)(ty - rc.y) * (uint32_t)(rc.z - rc.x + 1) +
                                 (uint32_t)(tx - rc.x);
-            if (sl < w.slot_cap) w.slots[sl] = row;
+            if (guard(w.status, GSFF_CHECK_SLOT, sl, w.slot_cap)) w.slots[sl] = row;
           }
         } else {
           const uint32_t k = atomicAdd(&w.nslot[gid], 1u);
           const uint32_t sl = sbase + k;
-          if (sl < w.slot_cap) w.slots[sl] = row;
+          if (GSFF_CHECKED) {  // a Gaussian meets each tile of its rectangle once
+            const ushort4 rc = w.rects[gid];
+            const uint64_t nt = (rc.x <= rc.z && rc.y <= rc.w)
+                                    ? (uint64_t)(rc.z - rc.x + 1) * (uint64_t)(rc.w - rc.y + 1)
+                                    : 0ull;
+            GSFF_CHECK(w.status, GSFF_CHECK_SLOT, k, nt);
+          }
+          if (guard(w.status, GSFF_CHECK_SLOT, sl, w.slot_cap)) w.slots[sl] = row;
           if ((k & 63u) == 0u) {
             const uint32_t t = atomicAdd(w.item_n, 1u);
-            if (t < w.item_cap) w.items[t] = make_uint2(gid, k);
+            if (guard(w.status, GSFF_CHECK_REDUCE, t, w.item_cap))
+              w.items[t] = make_uint2(gid, k);
           }
         }
       }

@@ -30,6 +30,47 @@ constexpr int kMaxSeg = 8;                 // adjoint segments per tile (the las
 
 inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
+// ---- checked build --------------------------------------------------------
+// Compiled with -DGSFF_CHECKED=1 (libgsff_checked.so), the kernels test every
+// index that comes from data (a sort destination, a listed id, a tile range,
+// an adjoint row or slot) against what it addresses.  A failed test skips the
+// access, raises GSFF_FLAG_CHECK, counts the failure and records the first
+// one (site, index, limit) in the status words below.  `guard` tests in both
+// builds (the release build needs the test for well-formed inputs too);
+// GSFF_CHECK tests only in the checked build (the release build relies on the
+// index being in range by construction).
+#ifndef GSFF_CHECKED
+#define GSFF_CHECKED 0
+#endif
+constexpr int kStatusChkSite = 4, kStatusChkIndex = 5, kStatusChkLimit = 6, kStatusChkCount = 7;
+
+__device__ __forceinline__ void check_failed(uint32_t* status, uint32_t site, uint64_t idx,
+                                             uint64_t lim) {
+  atomicOr(&status[0], GSFF_FLAG_CHECK);
+  if (atomicAdd(&status[kStatusChkCount], 1u) == 0u) {
+    status[kStatusChkSite] = site;
+    status[kStatusChkIndex] = (uint32_t)(idx < 0xFFFFFFFFull ? idx : 0xFFFFFFFFull);
+    status[kStatusChkLimit] = (uint32_t)(lim < 0xFFFFFFFFull ? lim : 0xFFFFFFFFull);
+  }
+}
+
+// (the comparison is made in the operands' own types, as unchecked code would)
+template <typename I, typename L>
+__device__ __forceinline__ bool guard(uint32_t* status, uint32_t site, I idx, L lim) {
+  const bool ok = idx < lim;
+#if GSFF_CHECKED
+  if (!ok) check_failed(status, site, (uint64_t)idx, (uint64_t)lim);
+#else
+  (void)status;
+  (void)site;
+#endif
+  return ok;
+}
+
+// (a macro: the release build evaluates none of the arguments)
+#define GSFF_CHECK(status, site, idx, lim) \
+  (!GSFF_CHECKED || ::gsff::guard((status), (site), (idx), (lim)))
+
 inline int ceil_log2(uint64_t v) {
   int b = 0;
   while ((uint64_t(1) << b) < v) ++b;
@@ -64,7 +105,7 @@ bool compute_layout(int64_t P, int32_t C, int64_t max_pairs, int32_t W, int32_t 
 
 // Device-side view of a workspace.
 struct WsView {
-  uint32_t* status;      // [0] flags, [1] pair count
+  uint32_t* status;      // [0] flags, [1] pair count, [2] pairs in use, [4-7] checks
   float4* rec;           // [3][P]
   ushort4* rects;        // [P]
   uint32_t* dkeys_a;     // [P]  depth keys (sorted result lands here)

@@ -20,10 +20,8 @@ __global__ __launch_bounds__(256) void k_preprocess(DevGaussians g, DevCamera ca
                                                     DevSettings st, WsView w) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) {  // the whole status word: later stages read the pair count from it
-    w.status[0] = 0u;
-    w.status[1] = 0u;
-    w.status[2] = 0u;
-    w.status[3] = 0u;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) w.status[k] = 0u;
   }
   const int64_t P = g.P;
   uint32_t ntile = 0;  // tiles of the support rectangle
@@ -117,12 +115,16 @@ __global__ __launch_bounds__(256) void k_adjoint_reduce(WsView w, int64_t P, int
   for (uint32_t e = blockIdx.x * 4u + (threadIdx.x >> 6); e < cnt; e += nw) {
     const uint2 it = w.items[e];
     const uint32_t gg = it.x, k0 = it.y;
-    if (gg >= (uint64_t)P) continue;
+    if (!guard(w.status, GSFF_CHECK_REDUCE, gg, (uint64_t)P)) continue;
     const uint32_t n = w.nslot[gg];
-    if (k0 >= n) continue;
+    if (!guard(w.status, GSFF_CHECK_REDUCE, k0, n)) continue;
     const uint32_t m = n - k0 < 64u ? n - k0 : 64u;
     const uint32_t sl = w.slot_blk[gg >> 8] + w.slot_local[gg] + k0 + (uint32_t)lane;
-    const uint32_t myrow = ((uint32_t)lane < m && sl < w.slot_cap) ? w.slots[sl] : 0xFFFFFFFFu;
+    const uint32_t myrow =
+        ((uint32_t)lane < m && guard(w.status, GSFF_CHECK_SLOT, sl, w.slot_cap)) ? w.slots[sl]
+                                                                               : 0xFFFFFFFFu;
+    // every filed slot holds a row
+    if (GSFF_CHECKED && (uint32_t)lane < m) GSFF_CHECK(w.status, GSFF_CHECK_REDUCE, myrow, w.row_cap);
     const bool single = n <= 64u;
     for (int c0 = 0; c0 < ncol; c0 += CW) {
       const int col = c0 + cl;
@@ -264,7 +266,11 @@ __global__ __launch_bounds__(256) void k_adjoint_reduce_det(WsView w, int64_t P,
     for (uint32_t k0 = 0; k0 < ntile; k0 += 64) {
       const uint32_t sl = base + k0 + (uint32_t)lane;
       const uint32_t myrow =
-          (k0 + (uint32_t)lane < ntile && sl < w.slot_cap) ? w.slots[sl] : 0xFFFFFFFFu;
+          (k0 + (uint32_t)lane < ntile && guard(w.status, GSFF_CHECK_SLOT, sl, w.slot_cap))
+              ? w.slots[sl]
+              : 0xFFFFFFFFu;
+      // a slot holds a row, or nothing (a tile whose walk ended in front of the Gaussian)
+      if (GSFF_CHECKED && myrow != 0xFFFFFFFFu) GSFF_CHECK(w.status, GSFF_CHECK_REDUCE, myrow, w.row_cap);
       float acc = 0.f;
 #pragma unroll
       for (int u = 0; u < 64 / RPI; ++u) {

@@ -129,7 +129,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
     const uint32_t* __restrict__ n_dev, uint32_t n_static, int shift, int nbits,
     const uint32_t* __restrict__ hist, const uint32_t* __restrict__ hist_tot, int nchunks,
-    uint32_t cap) {
+    uint32_t cap, uint32_t* status) {
   __shared__ uint32_t s_base[256];
   __shared__ uint32_t s_cnt[4][256];
   __shared__ uint32_t s_tmp[4];
@@ -171,7 +171,8 @@ __global__ __launch_bounds__(256) void k_radix_scatter(
     }
     const uint32_t rank = (uint32_t)__popcll(peers & lt);
     const uint32_t start = s_cnt[wv][d];
-    if (valid && start + rank < cap) {  // cap: output capacity, never exceeded
+    // cap: output capacity, never exceeded
+    if (valid && guard(status, GSFF_CHECK_PAIR_DEST, start + rank, cap)) {
       keys_out[start + rank] = k[it];
       if (HasVals) vals_out[start + rank] = v[it];
     }
@@ -194,11 +195,11 @@ static hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t*
   if (vin)
     hipLaunchKernelGGL((k_radix_scatter<IPT, true>), dim3(blocks), dim3(256), 0, s, kin, vin,
                        kout, vout, n_dev, n_static, shift, nbits, w.hist, w.hist_tot, nchunks,
-                       cap);
+                       cap, w.status);
   else
     hipLaunchKernelGGL((k_radix_scatter<IPT, false>), dim3(blocks), dim3(256), 0, s, kin,
                        nullptr, kout, nullptr, n_dev, n_static, shift, nbits, w.hist, w.hist_tot,
-                       nchunks, cap);
+                       nchunks, cap, w.status);
   return hipGetLastError();
 }
 
@@ -358,7 +359,7 @@ __global__ __launch_bounds__(256) void k_sort_pass(const uint32_t* __restrict__ 
     if (base + (uint64_t)it * 64 + lane < n) {
       const uint32_t d = (k[it] >> shift) & 255u;
       const uint32_t pos = s_base[d] + s_cnt[wv][d] + rank[it];
-      if (pos < n) {
+      if (guard(w.status, GSFF_CHECK_SORT_DEST, pos, n)) {
         kout[pos] = k[it];
         vout[pos] = v[it];
       }
@@ -404,7 +405,8 @@ hipError_t launch_sort_tiles(const Layout& L, const WsView& w, hipStream_t s) {
 // rectangle of the Gaussian at depth rank r (empty if the stored id is not valid)
 __device__ __forceinline__ ushort4 ranked_rect(const WsView& w, int64_t r, int64_t P) {
   const uint32_t gid = w.dids_a[r];
-  return gid < (uint32_t)P ? w.rects[gid] : make_ushort4(1, 1, 0, 0);
+  return guard(w.status, GSFF_CHECK_RANK_ID, gid, (uint32_t)P) ? w.rects[gid]
+                                                               : make_ushort4(1, 1, 0, 0);
 }
 
 __device__ __forceinline__ uint32_t rect_count(ushort4 r) {
@@ -472,7 +474,7 @@ __global__ __launch_bounds__(1024) void k_count_top(WsView w, int nblocks, uint6
   }
   if (threadIdx.x == 0) {
     const bool over = carry > max_pairs;
-    if (over) w.status[0] |= GSFF_FLAG_PAIR_OVERFLOW;
+    if (over) atomicOr(&w.status[0], GSFF_FLAG_PAIR_OVERFLOW);
     w.status[1] = (uint32_t)(carry > 0xFFFFFFFFull ? 0xFFFFFFFFull : carry);
     w.status[2] = over ? 0u : (uint32_t)carry;  // pairs the later stages use
   }
@@ -511,7 +513,8 @@ __global__ __launch_bounds__(256) void k_emit(WsView w, int64_t P, int tiles_x, 
       const uint32_t rk = rank0 + (uint32_t)src;
       for (uint32_t j = lane; j < n; j += 64) {
         const uint32_t ty = by + j / bw, tx = bx + j % bw;
-        w.pkeys_a[o + j] = ((ty * (uint32_t)tiles_x + tx) << rank_bits) | rk;
+        if (GSFF_CHECK(w.status, GSFF_CHECK_PAIR_DEST, o + j, w.status[2]))
+          w.pkeys_a[o + j] = ((ty * (uint32_t)tiles_x + tx) << rank_bits) | rk;
       }
     }
   }
@@ -560,7 +563,7 @@ __device__ __forceinline__ ushort4 rank_rect(const WsView& w, int64_t r, int64_t
   *gid = 0u;
   if (r < P) {
     *gid = w.dids_a[r];
-    if (*gid < (uint32_t)P) rc = w.rects[*gid];
+    if (guard(w.status, GSFF_CHECK_RANK_ID, *gid, (uint32_t)P)) rc = w.rects[*gid];
   }
   return rc;
 }
@@ -669,7 +672,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter(WsView w, int64_t P, int nt
     for (int i = threadIdx.x; i < ntiles; i += 256)
       w.tile_ranges[i] = over ? make_uint2(0u, 0u) : make_uint2(s_st[i], s_st[i] + w.tile_tot[i]);
     if (threadIdx.x == 0) {
-      if (over) w.status[0] |= GSFF_FLAG_PAIR_OVERFLOW;
+      if (over) atomicOr(&w.status[0], GSFF_FLAG_PAIR_OVERFLOW);
       w.status[1] = (uint32_t)(carry > 0xFFFFFFFFull ? 0xFFFFFFFFull : carry);
       w.status[2] = over ? 0u : (uint32_t)carry;
     }
@@ -707,7 +710,8 @@ __global__ __launch_bounds__(256) void k_bin_scatter(WsView w, int64_t P, int nt
   for (uint32_t j = 0; j < cnt; ++j) {
     const uint32_t t = y * (uint32_t)tiles_x + x;
     const uint32_t pos = cw[t] + bits_below_lane(col[x] & rm);
-    if (pos < max_pairs) {
+    // (carry <= max_pairs here: the frame did not overflow)
+    if (guard(w.status, GSFF_CHECK_PAIR_DEST, pos, (uint32_t)carry)) {
       w.pkeys_a[pos] = gid;
       w.pmask[pos] = (uint16_t)super_mask(trc, x, y);
     }
@@ -727,9 +731,10 @@ __global__ __launch_bounds__(256) void k_keys_to_ids(WsView w, uint32_t rmask, i
     const uint32_t key = w.pkeys_a[i];
     const uint32_t r = key & rmask;
     const uint32_t cell = rank_bits >= 32 ? 0u : key >> rank_bits;
-    const uint32_t gid = (r < (uint32_t)P) ? w.dids_a[r] : (uint32_t)P;
+    const uint32_t gid =
+        guard(w.status, GSFF_CHECK_RANK_ID, r, (uint32_t)P) ? w.dids_a[r] : (uint32_t)P;
     uint32_t m = 0u;
-    if (gid < (uint32_t)P)
+    if (guard(w.status, GSFF_CHECK_RANK_ID, gid, (uint32_t)P))
       m = super_mask(w.rects[gid], cell % (uint32_t)super_x, cell / (uint32_t)super_x);
     w.pkeys_a[i] = gid;
     w.pmask[i] = (uint16_t)m;

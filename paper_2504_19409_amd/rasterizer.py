@@ -241,6 +241,11 @@ class Frame:
                                                   _stream()), "gsff_read_status")
         return int(flags.value), int(n.value)
 
+    def read_checks(self):
+        """The checked build's bounds-test record of this workspace (zeros in
+        the release build): failures, and site / index / limit of the first."""
+        return _capi.read_checks(self.ws.data_ptr(), _stream().value or 0)
+
     # -- workspace views (for tests and inspection) -----------------------
     def ws_view(self, field: str, dtype, count):
         off = getattr(self.layout, field)

@@ -157,6 +157,12 @@ void validation() {
   double* d = static_cast<double*>(fake());
   expect(gsff_forward_f64(&g64, &c64, &s, ws, nb, d, d, d, nullptr, nullptr, nullptr) == E,
          "f64: P");
+  int32_t kind = -1;
+  expect(gsff_is_checked_build(&kind) == GSFF_OK && (kind == 0 || kind == 1), "build kind");
+  expect(gsff_is_checked_build(nullptr) == E, "build kind: NULL");
+  uint32_t chk[4];
+  expect(gsff_read_checks(nullptr, chk, nullptr) == E, "read_checks: NULL workspace");
+  expect(gsff_read_checks(ws, nullptr, nullptr) == E, "read_checks: NULL output");
   std::printf("argument validation: done\n");
 }
 

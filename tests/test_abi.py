@@ -37,6 +37,32 @@ def test_every_declared_symbol_is_exported(capi):
     assert not [n for n in names if n not in capi.SIGNATURES]
 
 
+def test_checked_build_loads_and_exports_the_same_abi(capi):
+    """libgsff_checked.so (the sources built with GSFF_CHECKED=1) exports the
+    same entry points and says which build it is; the release build says 0.
+    gsff_read_checks validates its arguments before any device work."""
+    if not os.path.exists(capi.CHECKED_LIB_PATH):
+        from paper_2504_19409_amd import build
+        build.build()
+    flag = ctypes.c_int32(-1)
+    assert capi.load().gsff_is_checked_build(ctypes.byref(flag)) == 0 and flag.value == 0
+    with capi.checked_library() as lib:
+        missing = [n for n in _declared("gsff.h") if not hasattr(lib, n)]
+        assert not missing, missing
+        assert lib.gsff_is_checked_build(ctypes.byref(flag)) == 0 and flag.value == 1
+        assert capi.load() is lib
+        out = (ctypes.c_uint32 * 4)()
+        E = capi.ERR_INVALID_ARGUMENT
+        assert lib.gsff_read_checks(None, out, None) == E
+        assert lib.gsff_read_checks(ctypes.c_void_p(0x100000), None, None) == E
+        assert lib.gsff_is_checked_build(None) == E
+        # same workspace layout in both builds
+        a = capi.workspace_layout(2000, 5, 24000, 64, 48)
+    b = capi.workspace_layout(2000, 5, 24000, 64, 48)
+    assert a.total_bytes == b.total_bytes and a.status == b.status == 0
+    assert capi.load().gsff_is_checked_build(ctypes.byref(flag)) == 0 and flag.value == 0
+
+
 def test_version_and_defaults(capi):
     lib = capi.load()
     a, b = ctypes.c_int32(-1), ctypes.c_int32(-1)
