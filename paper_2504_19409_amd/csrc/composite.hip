@@ -3,9 +3,13 @@
 //
 // One 256-thread workgroup per 16x16 screen tile, one thread per pixel.  The
 // tile's depth-ordered Gaussian list is walked in batches staged in LDS
-// (records gathered by id, features converted to FP32 on the way in); all
-// blending and transmittance is FP32.  A workgroup stops as soon as every
-// pixel in it has saturated (T would fall below t_min).
+// (records gathered by id, features split into BF16 hi and lo parts on the
+// way in).  Alpha, transmittance, the blending weights and every skip / stop
+// decision are FP32; the colour, depth and feature sums (and the adjoint's
+// contraction over the tile's pixels) are matrix-core products of BF16 hi/lo
+// splits of both operands with FP32 accumulation, each product accurate to
+// about 2^-16 relative.  A workgroup stops as soon as every pixel in it has
+// saturated (T would fall below t_min).
 //
 // Workgroup -> tile mapping is XCD-aware: the dispatcher hands consecutive
 // workgroups to the 8 XCDs in turn, so workgroup b is sent to tile
@@ -205,11 +209,13 @@ __device__ __forceinline__ void split_value(uint16_t v, __bf16& hi, __bf16& lo) 
 // Front-to-back compositing of one tile per workgroup, one thread per pixel.
 //
 // The tile's list is walked in batches of 16 Gaussians:
-//  phase A  each thread walks the batch front to front, branch-free: alpha,
-//           the skip / stop decisions, the blending weight w, transmittance
-//           and the colour and depth sums (FP32, in list order); the 16
-//           weights go to the wave's own LDS rows.
-//  phase B  the feature sums of the wave's 64 pixels for the batch are one
+//  phase A  each thread walks the batch front to back, branch-free: alpha,
+//           the skip / stop decisions, the blending weight w and
+//           transmittance (FP32, in list order); the 16 weights go to the
+//           wave's own LDS rows as BF16 hi and lo parts.
+//  phase B  the colour and depth sums are 4x4x4 BF16 products (the weights'
+//           hi and lo parts against the batch's colour and depth, split the
+//           same way); the feature sums of the wave's 64 pixels are one
 //           16x16x32 BF16 matrix product per 16 pixels x 16 channels: K
 //           holds the 16 weights twice, as hi and as lo BF16 parts, against
 //           the BF16 features (exact for a BF16 payload; FP32 / FP16
@@ -325,7 +331,6 @@ void k_composite_fwd(
     return n;
   };
 
-  float T = 1.f;
   // colour and depth sums of pixels 4 (lane / 4) + r of the wave, channel
   // lane % 4 (r, g, b, depth): the 4x4x4 products' accumulator
   f32x4 acc_c = {0.f, 0.f, 0.f, 0.f};
@@ -339,7 +344,11 @@ void k_composite_fwd(
       s_cc[sb][1][pf >> 2][c][pf & 3] = (__bf16)(v[c] - (float)h);
     }
   };
-  bool done = !inside;
+  // T > 0 while the pixel is live.  A pixel stops by keeping -T (the same
+  // magnitude), so every later T (1 - alpha) >= t_min test fails (t_min > 0)
+  // and no separate done mask is carried; pixels outside the image start
+  // stopped.  Every decision and every value is that of the plain loop.
+  float T = inside ? 1.f : -1.f;
   uint32_t end = cbase;
   f32x4 acc[4][NCB > 0 ? NCB : 1];
 #pragma unroll
@@ -438,29 +447,29 @@ void k_composite_fwd(
     // issued: waits for those loads do not include the stores.
     if (write_geo && k > 0 && k % kSegBatches == 0 && nseg_end < kMaxSeg - 1) {
       float* q = w.seg_state + ((int64_t)tile * (kMaxSeg - 1) + nseg_end) * 5 * kBlock;
-      q[tid] = T;
+      q[tid] = __builtin_fabsf(T);
 #pragma unroll
       for (int r = 0; r < 4; ++r)
         q[(1 + (lane & 3)) * kBlock + 64 * wave + 4 * (lane >> 2) + r] = acc_c[r];
       ++nseg_end;
     }
-    const bool wave_active = __ballot(!done) != 0ull;
+    const bool wave_active = __ballot(T > 0.f) != 0ull;
     if (wave_active) {
       // ---- phase A: weights, transmittance, colour and depth, front to back
       float wv[4];
+      uint32_t last = 0u;  // 1 + batch position of the last Gaussian used here
 #pragma unroll
       for (int jj = 0; jj < NB; ++jj) {
         const float4 r0 = s_r0[buf][jj], r1 = s_r1[buf][jj];
         const AlphaEval e = eval_alpha(r0, r1, pxc, pyc, st.alpha_max);
-        const bool valid = !done && e.alpha >= st.alpha_min;
-        const float aT = e.alpha * T;
+        const bool ok = e.alpha >= st.alpha_min;          // not skipped
         const float Tn = __builtin_fmaf(-e.alpha, T, T);  // T (1 - alpha), one rounding
-        const bool stop = valid && Tn < st.t_min;
-        const bool use = valid && !stop;
-        done = done || stop;
-        const float wgt = use ? aT : 0.f;
-        T = use ? Tn : T;
-        end = use ? b0 + (uint32_t)jj + 1u : end;
+        const bool use = ok && Tn >= st.t_min;            // live and not stopping here
+        const float wgt = use ? e.alpha * T : 0.f;
+        T = use ? Tn : (ok ? -__builtin_fabsf(T) : T);    // a stop keeps -T
+        last = use ? (uint32_t)jj + 1u : last;
+        // formed here: deferred, the 16 use masks would stay live in SGPRs
+        __asm__ volatile("" : "+v"(last));
         wv[jj & 3] = wgt;
         if ((jj & 3) == 3) {  // weight = hi + lo, both BF16: the products' A operands
           const f32x4 q = {wv[0], wv[1], wv[2], wv[3]};
@@ -470,6 +479,7 @@ void k_composite_fwd(
           *reinterpret_cast<bf16x4*>(&s_w[tid][16 + jj - 3]) = l;
         }
       }
+      end = last ? b0 + last : end;
       // ---- phase B: colour and depth, and the feature sums, on the matrix cores
       // (the wave reads back only its own rows)
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
@@ -534,7 +544,7 @@ void k_composite_fwd(
         s_pos[(k + 2) & 3] = pos_after;
       }
     }
-    const bool still = __ballot(!done) != 0ull;
+    const bool still = __ballot(T > 0.f) != 0ull;
     if (lane == 0) s_act[buf][wave] = still ? 1 : 0;
     lds_barrier();
     if (!more) break;
@@ -577,8 +587,8 @@ void k_composite_fwd(
   }
   if (inside && write_geo) {
     const int64_t p = (int64_t)py * W + px;
-    out_alpha[p] = 1.f - T;
-    w.pix_T[p] = T;
+    out_alpha[p] = 1.f - __builtin_fabsf(T);
+    w.pix_T[p] = __builtin_fabsf(T);
     w.pix_end[p] = end;
   }
   if constexpr (CP > 0) {
