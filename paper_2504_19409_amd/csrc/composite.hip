@@ -90,21 +90,24 @@ constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kConA = -0.5f * kLog2e, kConB = -kLog2e;
 constexpr float kConAInv = -2.f * kLn2, kConBInv = -kLn2;
 
-// A record as staged for eval_alpha: (u, v, a, b) (c, o, z, valid).  Applied
-// where a prefetched record is written to LDS, not where it is loaded, so the
-// load stays in flight while the current batch runs.
+// A record as staged for eval_alpha: (u, v, a, b) (c, o, z, log2 o) -- the
+// stored record's last lane (its valid flag) is not needed once a Gaussian is
+// in a tile list.  Applied where a prefetched record is written to LDS, not
+// where it is loaded, so the load stays in flight while the current batch
+// runs.  A zeroed record (an id past the end) stages log2 0 = -inf: alpha 0.
 __device__ __forceinline__ float4 scaled_r0(float4 r0) {
   return make_float4(r0.x, r0.y, r0.z * kConA, r0.w * kConB);
 }
 __device__ __forceinline__ float4 scaled_r1(float4 r1) {
-  return make_float4(r1.x * kConA, r1.y, r1.z, r1.w);
+  return make_float4(r1.x * kConA, r1.y, r1.z, __builtin_amdgcn_logf(r1.y));  // v_log_f32
 }
 
 // alpha of one (pixel, Gaussian) pair from a scaled record; forward and
 // adjoint call this same code so every skip decision and weight is
-// reproduced bit for bit.
+// reproduced bit for bit.  The opacity enters the exponent as log2 o, so
+// o G = 2^(log2 o + exponent) is one exp2 with no product after it.
 struct AlphaEval {
-  float dx, dy, G, oG, alpha;
+  float dx, dy, oG, alpha;
 };
 
 __device__ __forceinline__ AlphaEval eval_alpha(const float4 r0, const float4 r1, float pxc,
@@ -114,10 +117,11 @@ __device__ __forceinline__ AlphaEval eval_alpha(const float4 r0, const float4 r1
   e.dx = r0.x - pxc;
   e.dy = r0.y - pyc;
   const float q2 = __builtin_fmaf(e.dx, __builtin_fmaf(r0.z, e.dx, r0.w * e.dy),
-                                  (r1.x * e.dy) * e.dy);
-  e.G = __builtin_amdgcn_exp2f(q2);  // v_exp_f32
-  e.oG = r1.y * e.G;
-  e.alpha = __builtin_fminf(e.oG, alpha_max);
+                                  __builtin_fmaf(r1.x * e.dy, e.dy, r1.w));
+  e.oG = __builtin_amdgcn_exp2f(q2);  // v_exp_f32
+  // min(oG, alpha_max) for oG >= 0, as one v_med3_f32 (a plain fminf of the
+  // exp2 result makes the compiler quiet a NaN first, one more instruction)
+  e.alpha = __builtin_amdgcn_fmed3f(e.oG, 0.f, alpha_max);
   return e;
 }
 
