@@ -15,7 +15,7 @@
 // workgroups to the 8 XCDs in turn, so workgroup b is sent to tile
 // (b % 8) * ceil(ntiles/8) + b / 8 -- each XCD then renders a contiguous
 // band of tiles and neighbouring tiles (which share most Gaussians) hit the
-// same L2.
+// same L2.  The adjoint takes list segments longest first.
 //
 // The adjoint walks back to front from each pixel's last contributor,
 // recovering T_i = T_{i+1} / (1 - alpha_i) instead of storing per-pixel
@@ -70,14 +70,39 @@ __device__ __forceinline__ uint2 clamp_range(uint2 r, uint32_t max_pairs) {
 __device__ __forceinline__ float4 keep4(bool ok, float4 a) {
   return make_float4(ok ? a.x : 0.f, ok ? a.y : 0.f, ok ? a.z : 0.f, ok ? a.w : 0.f);
 }
-__device__ __forceinline__ void load_record(const WsView& w, uint32_t gid, int64_t P, float4& r0,
-                                            float4& r1, float4& r2) {
+// Issue the gather only; returns whether the id is valid.
+__device__ __forceinline__ bool fetch_record(const WsView& w, uint32_t gid, int64_t P, float4& r0,
+                                             float4& r1, float4& r2) {
   const bool ok = gid < (uint32_t)P;
   const int64_t g = ok ? (int64_t)gid : 0;
-  const float4 a = w.rec[g], b = w.rec[P + g], c = w.rec[2 * P + g];
-  r0 = keep4(ok, a);
-  r1 = keep4(ok, b);
-  r2 = keep4(ok, c);
+  r0 = w.rec[g];
+  r1 = w.rec[P + g];
+  r2 = w.rec[2 * P + g];
+  return ok;
+}
+__device__ __forceinline__ void load_record(const WsView& w, uint32_t gid, int64_t P, float4& r0,
+                                            float4& r1, float4& r2) {
+  const bool ok = fetch_record(w, gid, P, r0, r1, r2);
+  r0 = keep4(ok, r0);
+  r1 = keep4(ok, r1);
+  r2 = keep4(ok, r2);
+}
+// A prefetched record, settled where it is staged.  The empty asm makes the
+// values opaque up to this point: otherwise the compiler moves their first
+// use (the zeroing, the scaling) up to the loads and waits for the loads
+// there, a memory round trip per batch instead of one hidden by the batch.
+__device__ __forceinline__ void opaque4(float4& r) {
+  float __attribute__((ext_vector_type(4))) v = {r.x, r.y, r.z, r.w};
+  __asm__ volatile("" : "+v"(v));
+  r = make_float4(v[0], v[1], v[2], v[3]);
+}
+__device__ __forceinline__ void settle_record(bool ok, float4& r0, float4& r1, float4& r2) {
+  opaque4(r0);
+  opaque4(r1);
+  opaque4(r2);
+  r0 = keep4(ok, r0);
+  r1 = keep4(ok, r1);
+  r2 = keep4(ok, r2);
 }
 
 // The Gaussian's exponent (Eq. 2's G) in base 2:
@@ -290,11 +315,14 @@ void k_composite_fwd(
   // the tile's walked list: kSuper^2 slots of the super-tile's length per super-tile entry
   const uint32_t cbase = (uint32_t)(kSuper * kSuper) * sr.x + (uint32_t)lsub * (sr.y - sr.x);
   const int cn = CP > 0 ? min(CP, C - c0) : 0;
-  // wave 2 scans the list and batches the accepted ids; the first 16 lanes of
-  // the last wave load the records
-  const int pf = tid - (kBlock - 64);
-  const bool pf_lane = pf >= 0 && pf < NB;
+  // Wave 2 scans the list, batches the accepted ids and gathers each batch's
+  // records as soon as it has taken the ids, two batches before the batch
+  // runs (record lane l < 48 loads vector l / 16 of the batch's Gaussian
+  // l % 16), staging them at the end of the batch before it; the other waves
+  // issue no record loads, and none waits for one at the top of a batch.
   const bool scan_wave = wave == kBlock / 64 - 2;
+  const bool rec_lane = scan_wave && lane < 3 * NB;
+  const int rg = lane & (NB - 1), rv = lane / NB;  // a record lane's Gaussian and vector
   uint32_t sc = sr.x, qh = 0, qt = 0;  // scan position, queue head / tail (scan wave)
   // Scan 128 list entries: lanes hold entries sc + lane and sc + 64 + lane.
   auto scan_issue = [&](uint32_t& gA, uint32_t& mA, uint32_t& gB, uint32_t& mB) {
@@ -338,14 +366,36 @@ void k_composite_fwd(
   // colour and depth sums of pixels 4 (lane / 4) + r of the wave, channel
   // lane % 4 (r, g, b, depth): the 4x4x4 products' accumulator
   f32x4 acc_c = {0.f, 0.f, 0.f, 0.f};
-  // a prefetch lane writes its Gaussian's colour and depth, split hi + lo
-  auto stage_colour = [&](int sb, float4 rec1, float4 rec2) {
-    const float v[4] = {rec2.x, rec2.y, rec2.z, rec1.z};
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const __bf16 h = (__bf16)v[c];
-      s_cc[sb][0][pf >> 2][c][pf & 3] = h;
-      s_cc[sb][1][pf >> 2][c][pf & 3] = (__bf16)(v[c] - (float)h);
+  // Record gather of a batch (called by the whole scan wave: ids holds the
+  // batch's ids in lanes 0..NB-1, P past the batch); returns whether this
+  // lane's Gaussian is valid.
+  auto fetch_vec = [&](uint32_t ids, float4& v) {
+    const uint32_t gid = __shfl(ids, rg, 64);
+    const bool ok = gid < (uint32_t)P;
+    if (rec_lane) v = w.rec[(int64_t)rv * P + (ok ? (int64_t)gid : 0)];
+    return ok;
+  };
+  // A record lane stages its vector into buffer sb: (u, v, a, b) and (c, o,
+  // z, log2 o) scaled for eval_alpha, colour and depth split hi + lo as the B
+  // operand of the colour products.  The empty asm (opaque4) keeps the
+  // compiler from using the values, and waiting for the gather, any earlier.
+  auto stage_vec = [&](int sb, bool ok, float4 v) {
+    opaque4(v);
+    v = keep4(ok, v);
+    auto colour = [&](int c, float x) {
+      const __bf16 h = (__bf16)x;
+      s_cc[sb][0][rg >> 2][c][rg & 3] = h;
+      s_cc[sb][1][rg >> 2][c][rg & 3] = (__bf16)(x - (float)h);
+    };
+    if (rv == 0) {
+      s_r0[sb][rg] = scaled_r0(v);
+    } else if (rv == 1) {
+      s_r1[sb][rg] = scaled_r1(v);
+      colour(3, v.z);
+    } else {
+      colour(0, v.x);
+      colour(1, v.y);
+      colour(2, v.z);
     }
   };
   // T > 0 while the pixel is live.  A pixel stops by keeping -T (the same
@@ -360,31 +410,31 @@ void k_composite_fwd(
 #pragma unroll
     for (int k = 0; k < (NCB > 0 ? NCB : 1); ++k) acc[rb][k] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  // ---- prologue: ids of batches 0 and 1, records and features of batch 0
+  // ---- prologue: ids of batches 0 and 1 and their record gathers (batch
+  // 0's staged here, batch 1's in flight), then batch 0's features
+  float4 rv_next = make_float4(0.f, 0.f, 0.f, 0.f);  // records of batch k + 1 (record lanes)
+  bool rok_next = false;
   if (scan_wave) {
-    uint32_t g, pos;
-    const uint32_t n0 = take_batch(g, pos);
-    if (lane < NB) s_ids[0][lane] = g;
+    uint32_t g0, g1, pos;
+    const uint32_t n0 = take_batch(g0, pos);
+    if (lane < NB) s_ids[0][lane] = g0;
     if (lane == 0) {
       s_nb[0] = n0;
       s_pos[0] = pos;
     }
-    const uint32_t n1 = take_batch(g, pos);
-    if (lane < NB) s_ids[1][lane] = g;
+    const uint32_t n1 = take_batch(g1, pos);
+    if (lane < NB) s_ids[1][lane] = g1;
     if (lane == 0) {
       s_nb[1] = n1;
       s_pos[1] = pos;
     }
+    float4 v0 = make_float4(0.f, 0.f, 0.f, 0.f);
+    const bool ok0 = fetch_vec(g0, v0);
+    rok_next = fetch_vec(g1, rv_next);
+    if (rec_lane) stage_vec(0, ok0, v0);
   }
   lds_barrier();
   if (s_nb[0] > 0u) {
-    if (pf_lane) {
-      float4 q0, q1, q2;
-      load_record(w, s_ids[0][pf], P, q0, q1, q2);
-      s_r0[0][pf] = scaled_r0(q0);
-      s_r1[0][pf] = scaled_r1(q1);
-      stage_colour(0, q1, q2);
-    }
     if constexpr (CP > 0) {
 #pragma unroll
       for (int k = 0; k < FPT; ++k) {
@@ -421,9 +471,6 @@ void k_composite_fwd(
       ahead = qt - qh < 3u * NB && sc < sr.y;
       if (ahead) scan_issue(gA, mA, gB, mB);
     }
-    // ---- records of the next batch
-    float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f), p1 = p0, p2 = p0;
-    if (more && pf_lane) load_record(w, s_ids[buf ^ 1][pf], P, p0, p1, p2);
     // features of the next batch, raw: split where they are staged, so the
     // loads stay in flight while this batch runs
     FT fraw[FPT > 0 ? FPT : 1];
@@ -444,6 +491,14 @@ void k_composite_fwd(
         }
       }
     }
+
+    // ---- record gathers of batch k + 2 (k + 1's are in flight since batch
+    // k - 1), issued after this batch's other loads: waits count loads in
+    // issue order, so the waits for those (at this batch's staging) leave
+    // these in flight
+    float4 rv_after = make_float4(0.f, 0.f, 0.f, 0.f);
+    bool rok_after = false;
+    if (scan_wave) rok_after = fetch_vec(g_after, rv_after);
 
     // ---- every kSegBatches batches, each pixel's transmittance and the
     // colour and depth blended in front of this batch: the adjoint's segments
@@ -522,11 +577,7 @@ void k_composite_fwd(
     }
     // ---- stage the next batch, report activity
     if (more) {
-      if (pf_lane) {
-        s_r0[buf ^ 1][pf] = scaled_r0(p0);
-        s_r1[buf ^ 1][pf] = scaled_r1(p1);
-        stage_colour(buf ^ 1, p1, p2);
-      }
+      if (rec_lane) stage_vec(buf ^ 1, rok_next, rv_next);
       if constexpr (CP > 0) {
 #pragma unroll
         for (int kk = 0; kk < FPT; ++kk) {
@@ -541,6 +592,8 @@ void k_composite_fwd(
         }
       }
     }
+    rv_next = rv_after;
+    rok_next = rok_after;
     if (scan_wave) {
       if (lane < NB) s_ids[buf][lane] = g_after;  // the slot of batch k + 2
       if (lane == 0) {
@@ -1528,9 +1581,10 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
     // records of the next batch, ids of the one after
     const uint32_t pgid = g_next;
     float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f), p1 = p0, p2 = p0;
+    bool pok = false;
     const uint32_t mb1 = nb0, mb0 = batch_start(mb1);
     if (pf_lane) {
-      if (more) load_record(w, pgid, P, p0, p1, p2);
+      if (more) pok = fetch_record(w, pgid, P, p0, p1, p2);
       g_next = (more && mb0 + pf < mb1) ? w.clist[mb0 + pf] : (uint32_t)P;
       if (GSFF_CHECKED && more && mb0 + pf < mb1)
         GSFF_CHECK(w.status, GSFF_CHECK_LIST_ID, g_next, (uint64_t)P);
@@ -1717,6 +1771,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kBlock, kBlock),
       }
     }
     if (more && pf_lane) {
+      settle_record(pok, p0, p1, p2);
       s_gid[buf ^ 1][pf] = pgid;
       s_r0[buf ^ 1][pf] = scaled_r0(p0);
       s_r1[buf ^ 1][pf] = scaled_r1(p1);
