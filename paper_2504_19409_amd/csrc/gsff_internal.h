@@ -20,7 +20,7 @@ constexpr int kSortHistBlocks = 64;        // workgroups of the 4-digit histogra
 constexpr int kScanBlock = 1024;           // elements per block in the count scan
 constexpr int kPoseBlock = 256;            // Gaussians per preprocess-adjoint block
 constexpr int kMaxDirectTiles = 4096;      // tile grids binned without a pair sort
-constexpr int kBinBands = 4;               // tile-row bands of the direct scatter
+constexpr int kBinBands = 2;               // tile-row bands of the direct scatter
 constexpr int kSuper = GSFF_SUPER;         // bin-grid cell: kSuper x kSuper tiles (16-bit masks)
 static_assert(kSuper == 4, "pair masks are 16 bits");
 constexpr int kBinBlock = 256;             // depth ranks per direct-binning block
