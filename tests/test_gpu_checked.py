@@ -8,8 +8,10 @@ status word (GSFF_FLAG_CHECK, gsff_read_checks).  Here:
 
 * on the scenes of the parity suite -- both binning paths, both adjoint
   reduction modes, the explicit and the fused-L1 upstream, several channel
-  passes, a BF16 payload, a pair-capacity overflow -- no test fails, and the
-  outputs and gradients are those of the release build;
+  passes, a BF16 payload, a pair-capacity overflow -- and at full size (the
+  benchmark's 200k-Gaussian frame, the adjoint's atomic fallback, 1M
+  Gaussians at 1200x680 with a BF16 payload) no test fails, and the outputs
+  and gradients are those of the release build;
 * conditions forced from the host are reported at their site, with every
   access still inside the workspace: a super-tile range that ends past the
   frame's pairs (the extra entries hold a valid id and an empty tile mask),
@@ -207,3 +209,62 @@ def test_forced_walked_id_past_p_is_reported_by_the_adjoint():
     assert chk == {"failures": 1, "site": "list_id", "index": P + 7, "limit": P}, chk
     for v in grads.values():
         assert torch.isfinite(v).all()
+
+
+def _sized_frame(sc, feat_dtype=None):
+    fr, _ = H.make_frame(sc, torch, feat_dtype=feat_dtype)
+    fr.forward()
+    n = fr.read_status()[1]
+    fr, _ = H.make_frame(sc, torch, feat_dtype=feat_dtype, max_pairs=int(n * 1.05) + 4096)
+    return fr
+
+
+def _l1_run(sc, feat_dtype=None):
+    """Forward and fused-L1 adjoint (dense seeded targets, the benchmark's loss
+    weights) on a frame sized from a first forward; images, loss, flags and
+    the check record."""
+    fr = _sized_frame(sc, feat_dtype)
+    outs = fr.forward()
+    W, Hh, C = sc.camera.width, sc.camera.height, sc.C
+    t_rgb, t_depth, t_feat = sg.make_targets(np.random.default_rng(31), W, Hh, C)
+    targets = [torch.from_numpy(t).cuda() for t in (t_rgb, t_depth)] + [None]
+    targets.append(torch.from_numpy(t_feat).cuda() if C else None)
+    grads = fr.make_grads()
+    loss = torch.zeros(1, device="cuda")
+    fr.backward_l1(outs, targets, (1.0, 1.0, 0.0, 1.0), grads, loss)
+    return dict(outs=[o.clone() for o in outs], loss=float(loss.item()),
+                flags=fr.read_status()[0], checks=fr.read_checks(),
+                grads={k: v.cpu().numpy() for k, v in grads.items()})
+
+
+@pytest.mark.parametrize("case", ["frame", "rows-overflow", "mixed-1M"])
+def test_checked_build_at_full_size(case):
+    """The benchmark's frame (200k Gaussians, 640x480, 16 FP32 channels, the
+    fused-L1 adjoint with dense targets), a frame whose walked pairs overflow
+    the adjoint's partial rows (the atomic fallback) and the 1M-Gaussian
+    1200x680 frame with a 64-channel BF16 payload: the checked build records
+    no failure and renders the release build's images bit for bit."""
+    fdt = None
+    if case == "frame":
+        sc, _ = sg.workload_scene("frame")
+    elif case == "rows-overflow":
+        sc = sg.make_scene(300, 320, 240, 260.0, 260.0, 160.0, 120.0, 8, seed=41)
+        sc.log_scales += 1.8
+        sc.logit_opacity = np.full_like(sc.logit_opacity, -3.0)
+    else:
+        cfg = dict(sg.WORKLOADS["mixed"])
+        seed = cfg.pop("seed")
+        sc = sg.make_scene(rng=np.random.default_rng(seed), seed=seed, **cfg)
+        fdt = torch.bfloat16
+    rel = _l1_run(sc, fdt)
+    with _capi().checked_library():
+        chk = _l1_run(sc, fdt)
+    assert chk["checks"]["failures"] == 0, chk["checks"]
+    assert chk["flags"] == 0 and rel["flags"] == 0
+    for a, b in zip(chk["outs"], rel["outs"]):
+        assert torch.equal(a, b)
+    assert chk["loss"] == pytest.approx(rel["loss"], rel=1e-5)
+    errs = {k: H.rel_l2(chk["grads"][k], g) for k, g in rel["grads"].items()}
+    assert max(errs.values()) <= 5e-4, errs  # order of float atomics only
+    print(f"checked vs release [{case}]: " + ", ".join(f"{k} {v:.1e}" for k, v in errs.items()),
+          flush=True)
