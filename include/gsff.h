@@ -52,9 +52,10 @@ typedef int32_t gsff_status;
 
 /* status-word bits set by the device */
 #define GSFF_FLAG_PAIR_OVERFLOW 1u
-/* a depth-sort workgroup stopped waiting for an earlier one (not expected;
- * the frame's results are not valid) */
-#define GSFF_FLAG_SORT_STALL 2u
+/* a depth-sort workgroup stopped waiting for the digit counts of the
+ * chunks before its own (see gsff_set_sort_wait_limit) and counted them
+ * from the keys itself; the frame's results are valid */
+#define GSFF_FLAG_SORT_RECOUNT 2u
 /* checked build only (gsff_is_checked_build): an index that comes from data
  * (a sort destination, a listed Gaussian id, a tile range, an adjoint row or
  * slot) failed its bounds test; the access was skipped and
@@ -200,6 +201,15 @@ gsff_status gsff_version(int32_t* major, int32_t* minor);
  * GSFF_FLAG_CHECK; slower, for test runs), 0 for the release build.  Host
  * only. */
 gsff_status gsff_is_checked_build(int32_t* checked);
+
+/* Polls a depth-sort workgroup makes for the published digit counts of the
+ * chunks before its own before it counts those chunks' digits from the keys
+ * itself (raising GSFF_FLAG_SORT_RECOUNT); either way the sort is exact and
+ * stable, and every wait ends whatever order the workgroups are dispatched
+ * in.  0 makes every workgroup count (the fallback path, for tests).
+ * Default 2048.  Process-wide; applies to frames enqueued afterwards.
+ * Host only. */
+gsff_status gsff_set_sort_wait_limit(uint32_t polls);
 
 /* Text of the last GSFF_ERR_HIP / argument error raised on this thread. */
 const char* gsff_last_error(void);

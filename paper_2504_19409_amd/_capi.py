@@ -17,7 +17,7 @@ ERR_INVALID_ARGUMENT = -1
 ERR_UNSUPPORTED = -2
 ERR_HIP = -3
 FLAG_PAIR_OVERFLOW = 1
-FLAG_SORT_STALL = 2
+FLAG_SORT_RECOUNT = 2
 FLAG_CHECK = 4
 CHECK_SITES = {1: "sort_dest", 2: "rank_id", 3: "pair_dest", 4: "tile_range", 5: "list_id",
                6: "walk", 7: "item", 8: "row", 9: "slot", 10: "reduce"}
@@ -106,6 +106,7 @@ SIGNATURES = {
     "gsff_version": (_i32, [ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "gsff_last_error": (ctypes.c_char_p, []),
     "gsff_is_checked_build": (_i32, [ctypes.POINTER(_i32)]),
+    "gsff_set_sort_wait_limit": (_i32, [ctypes.c_uint32]),
     "gsff_read_checks": (_i32, [_vp, ctypes.POINTER(ctypes.c_uint32), _vp]),
     "gsff_default_settings": (_i32, [_S]),
     "gsff_workspace_size": (_i32, [_i64, _i32, _i64, _i32, _i32, ctypes.POINTER(_sz)]),

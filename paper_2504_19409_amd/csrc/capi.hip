@@ -53,7 +53,8 @@ bool compute_layout(int64_t P, int32_t C, int64_t max_pairs, int32_t W, int32_t 
   // the fallback path packs (super-tile, rank) into 32-bit keys
   l.sort_fits = l.rank_bits + l.tile_bits <= 32;
   if (!l.direct_bin && !l.sort_fits) return false;
-  l.sort_blocks = (P + kSortBlockKeys - 1) / kSortBlockKeys;
+  l.sort_ipt = sort_ipt_for(P);
+  l.sort_blocks = (P + 256 * l.sort_ipt - 1) / (256 * l.sort_ipt);
   l.pair_chunks = (max_pairs + kRadixChunk - 1) / kRadixChunk;
   l.scan_blocks = (P + kScanBlock - 1) / kScanBlock;
   l.pose_blocks = (P + kPoseBlock - 1) / kPoseBlock;
@@ -88,8 +89,10 @@ bool compute_layout(int64_t P, int32_t C, int64_t max_pairs, int32_t W, int32_t 
   l.hist = take(4ull * 256 * (uint64_t)chunks);
   l.hist_tot = take(4ull * 256);
   l.sort_part = take(4ull * kSortHistBlocks * 1024);
-  l.sort_lb = take(4ull * 4 * 256 * (uint64_t)(l.sort_blocks > 0 ? l.sort_blocks : 1));
-  l.sort_ctr = take(16);
+  {  // per pass: a word per digit for every chunk and every group of kSortLbGroup chunks
+    const uint64_t ch = (uint64_t)(l.sort_blocks > 0 ? l.sort_blocks : 1);
+    l.sort_lb = take(4ull * 4 * 256 * (ch + (ch + kSortLbGroup - 1) / kSortLbGroup));
+  }
   l.scan_part = take(4ull * (uint64_t)(l.scan_blocks + 1));
   l.pose_part = take(8ull * 6 * (uint64_t)(l.pose_blocks + 1));
   l.binhist = take(l.direct_bin ? 4ull * l.nsuper * (uint64_t)l.bin_blocks : 0ull);
@@ -154,7 +157,6 @@ WsView make_view(void* ws, const Layout& L) {
   w.hist_tot = (uint32_t*)(b + L.hist_tot);
   w.sort_part = (uint32_t*)(b + L.sort_part);
   w.sort_lb = (uint32_t*)(b + L.sort_lb);
-  w.sort_ctr = (uint32_t*)(b + L.sort_ctr);
   w.scan_part = (uint32_t*)(b + L.scan_part);
   w.pose_part = (double*)(b + L.pose_part);
   w.binhist = (uint32_t*)(b + L.binhist);
@@ -271,6 +273,11 @@ gsff_status gsff_version(int32_t* major, int32_t* minor) {
 gsff_status gsff_is_checked_build(int32_t* checked) {
   if (!checked) return fail(GSFF_ERR_INVALID_ARGUMENT, "NULL output");
   *checked = GSFF_CHECKED ? 1 : 0;
+  return GSFF_OK;
+}
+
+gsff_status gsff_set_sort_wait_limit(uint32_t polls) {
+  set_sort_wait_limit(polls);
   return GSFF_OK;
 }
 

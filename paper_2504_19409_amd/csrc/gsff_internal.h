@@ -14,9 +14,16 @@ constexpr int kTile = GSFF_TILE;           // 16x16 pixel screen tiles
 constexpr int kBlock = kTile * kTile;      // one thread per pixel of a tile
 constexpr int kRadixIpt = 16;              // keys per lane in a pair-sort radix chunk
 constexpr int kRadixChunk = 64 * kRadixIpt;  // keys per wave chunk (pair sort)
-constexpr int kSortIpt = 8;                // depth sort: keys per lane
-constexpr int kSortBlockKeys = 256 * kSortIpt;  // keys per single-sweep workgroup
+constexpr int kSortIptMax = 16;            // depth sort: most keys per lane
+// Depth sort keys per lane (4, 8 or 16; a workgroup sorts 256 times as many):
+// the fewest that keep the chunks to about 256, so that small frames get
+// many short chunks and large ones no more chunks than the chip holds.
+inline int sort_ipt_for(int64_t P) {
+  return P <= 256 * 256 * 4 ? 4 : (P <= 256 * 256 * 8 ? 8 : kSortIptMax);
+}
 constexpr int kSortHistBlocks = 64;        // workgroups of the 4-digit histogram
+constexpr int kSortLbGroup = 8;            // depth sort: chunks per look-back group
+constexpr uint32_t kSortWaitPolls = 2048;  // depth sort: polls before a workgroup counts itself
 constexpr int kScanBlock = 1024;           // elements per block in the count scan
 constexpr int kPoseBlock = 256;            // Gaussians per preprocess-adjoint block
 constexpr int kMaxDirectTiles = 4096;      // tile grids binned without a pair sort
@@ -91,13 +98,14 @@ struct Layout {
   int32_t rank_bits = 0, tile_bits = 0;
   bool direct_bin = false;  // bin by coverage masks (else by sorting (super-tile, rank) keys)
   bool sort_fits = false;   // (super-tile, rank) keys fit 32 bits
+  int64_t sort_ipt = 0;  // depth sort keys per lane (sort_ipt_for)
   int64_t sort_blocks = 0, pair_chunks = 0, scan_blocks = 0, pose_blocks = 0, bin_blocks = 0;
   uint64_t status = 0, records = 0, rects = 0, pmask = 0, clist = 0, crange = 0, dkeys_a = 0, dkeys_b = 0, dids_a = 0,
            dids_b = 0, offsets = 0, pkeys_a = 0, pkeys_b = 0, tile_ranges = 0, pix_T = 0,
            pix_end = 0, grad2d = 0, hist = 0, hist_tot = 0, scan_part = 0, pose_part = 0,
            binhist = 0, tile_tot = 0, curbase = 0, rows = 0, tile_walk = 0, walk_off = 0,
            slot_local = 0, slot_cnt = 0, slot_blk = 0, nslot = 0, slots = 0, item_n = 0, items = 0,
-           seg_order = 0, seg_n = 0, seg_state = 0, seg_final = 0, l1_codes = 0, loss_part = 0, sort_part = 0, sort_lb = 0, sort_ctr = 0, total = 0;
+           seg_order = 0, seg_n = 0, seg_state = 0, seg_final = 0, l1_codes = 0, loss_part = 0, sort_part = 0, sort_lb = 0, total = 0;
 };
 
 // Returns false if the sizes are not representable (key bits, negative sizes).
@@ -127,8 +135,7 @@ struct WsView {
   uint32_t* hist;        // radix chunk histograms [bins][chunks]
   uint32_t* hist_tot;    // radix digit totals [256]
   uint32_t* sort_part;   // depth sort: per-workgroup 4-digit histograms [kSortHistBlocks][4][256]
-  uint32_t* sort_lb;     // depth sort look-back words [4 passes][sort_blocks][256]
-  uint32_t* sort_ctr;    // depth sort: workgroup tickets, one per pass
+  uint32_t* sort_lb;     // depth sort look-back words [4 passes][chunks + groups][256]
   uint32_t* scan_part;   // count-scan block partials
   double* pose_part;     // [pose_blocks][6]
   uint32_t* binhist;     // direct binning: per-tile counts per rank block [ntiles][blocks]
@@ -197,6 +204,7 @@ hipError_t launch_preprocess(const DevGaussians& g, const DevCamera& cam,
                              const DevSettings& st, const Layout& L, const WsView& w,
                              hipStream_t s);
 hipError_t launch_sort_depth(const Layout& L, const WsView& w, hipStream_t s);
+void set_sort_wait_limit(uint32_t polls);
 hipError_t launch_bin(const Layout& L, const WsView& w, hipStream_t s);
 hipError_t launch_sort_tiles(const Layout& L, const WsView& w, hipStream_t s);
 hipError_t launch_tile_ranges(const Layout& L, const WsView& w, hipStream_t s);

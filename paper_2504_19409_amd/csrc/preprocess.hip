@@ -160,7 +160,6 @@ __global__ __launch_bounds__(kPoseBlock) void k_preprocess_bwd(DevGaussians g, D
   for (int k = 0; k < 12; ++k) V[k] = cam.viewmat[k];
   float pose[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   if (i < P) {
-    const Proj p = project_gaussian(g, cam, st, V, i);
     // consume the image-space gradients (the adjoint reduction has added
     // the per-tile rows) and re-arm them at zero, so another adjoint of the
     // same forward starts from nothing
@@ -168,14 +167,22 @@ __global__ __launch_bounds__(kPoseBlock) void k_preprocess_bwd(DevGaussians g, D
     float d[10];
 #pragma unroll
     for (int k = 0; k < 10; ++k) d[k] = d2[k];
+    bool any = false;
 #pragma unroll
-    for (int k = 0; k < 10; ++k) d2[k] = 0.f;
+    for (int k = 0; k < 10; ++k) any |= d[k] != 0.f;
     w.nslot[i] = 0u;
     if (i == 0) *w.item_n = 0u;
     float dmean[3] = {0.f, 0.f, 0.f}, dls[3] = {0.f, 0.f, 0.f}, dq[4] = {0.f, 0.f, 0.f, 0.f};
     float dlogit = 0.f;
     const float drgb[3] = {d[6], d[7], d[8]};
-    if (p.valid) project_adjoint<float>(p, V, cam.fx, cam.fy, d, dmean, dls, dq, dlogit, pose);
+    // every term is linear in the image-space gradients: a Gaussian no tile
+    // walked (most of a frame's) has zero gradients without the projection
+    if (any) {
+#pragma unroll
+      for (int k = 0; k < 10; ++k) d2[k] = 0.f;
+      const Proj p = project_gaussian(g, cam, st, V, i);
+      if (p.valid) project_adjoint<float>(p, V, cam.fx, cam.fy, d, dmean, dls, dq, dlogit, pose);
+    }
     if (accumulate) {
       if (out.means)
         for (int k = 0; k < 3; ++k) out.means[k * P + i] += dmean[k];
@@ -302,10 +309,12 @@ hipError_t launch_preprocess_bwd(const DevGaussians& g, const DevCamera& cam,
                                  const DevSettings& st, const Layout& L, const WsView& w,
                                  const gsff_grads& out, int32_t accumulate, hipStream_t s) {
   if (g.P > 0) {
-    const int64_t waves = (g.P + 63) / 64;
     float* df = g.C > 0 ? out.feat : nullptr;
     const int ncol = 10 + (df ? g.C : 0);
-    const unsigned nblk = (unsigned)std::min<int64_t>(std::max<int64_t>((waves + 3) / 4, 1), 2048);
+    // one wave per possible item, up to 8192 waves: each item's loads are a
+    // dependent chain, so the reduction is bound by how many are in flight
+    const unsigned nblk =
+        (unsigned)std::min<int64_t>(std::max<int64_t>((L.item_cap + 3) / 4, 1), 2048);
     const unsigned ndet = (unsigned)((g.P + 3) / 4);  // one wave per Gaussian
     if (st.deterministic) {
       if (ncol <= 16)

@@ -32,6 +32,8 @@
 //             lower lanes, and write to base + running count (stable).
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include "gsff_internal.h"
 
 namespace gsff {
@@ -208,37 +210,97 @@ static hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t*
 // Single-sweep LSD radix sort of the P depth keys, four passes of 8 bits:
 //   k_sort_hist4 : all four digit histograms in one read of the keys, as
 //                  kSortHistBlocks per-workgroup partials (nothing to clear
-//                  first); it also clears the look-back words and tickets.
-//   k_sort_pass  : a workgroup draws the next ticket b, ranks the keys of
-//                  chunk b stably in LDS (one ballot per digit bit per wave,
-//                  as the radix scatter), publishes its digit counts and then
-//                  finds each digit's count in chunks 0..b-1 by decoupled
-//                  look-back: chunk b-1, b-2, ... until one whose inclusive
-//                  prefix is already published.  A workgroup only waits on
-//                  chunks with earlier tickets, whose workgroups are running
-//                  or done, so every wait ends.
-// Look-back word: bits 31-30 = 0 not yet, 1 the chunk's own count, 2 the
-// inclusive prefix through the chunk; bits 29-0 the count.
-constexpr uint32_t kLbAgg = 1u << 30, kLbInc = 2u << 30, kLbMask = (1u << 30) - 1u;
-constexpr uint32_t kLbSpinMax = 1u << 22;  // polls before giving up (flags the frame)
-constexpr int kLbWindow = 8;               // predecessors read per look-back step
+//                  first); it also clears the look-back words.
+//   k_sort_pass  : workgroup b ranks the keys of chunk b stably in LDS (one
+//                  ballot per digit bit per wave, as the radix scatter),
+//                  publishes its digit counts and then finds each digit's
+//                  count in chunks 0..b-1 in two levels: the chunks are
+//                  grouped kLbGroup at a time; b reads the counts of the
+//                  chunks of its own group before it, and the totals of the
+//                  earlier groups, to which every chunk adds its counts with
+//                  one atomic per digit (the word's top bits count the
+//                  chunks that have added).  This is the single-pass prefix
+//                  scan of Merrill and Garland (2016) with the serial
+//                  look-back chain replaced by a two-level reduction: no
+//                  chunk waits for another chunk's prefix, so every chunk
+//                  waits about one round trip after its predecessors have
+//                  ranked.  Every workgroup publishes before it waits, and
+//                  waits a bounded number of polls: a workgroup whose
+//                  predecessors have not all published by then (they may not
+//                  have been dispatched yet) counts their digits itself from
+//                  the pass's input, so every wait ends and the result does
+//                  not depend on the order workgroups are dispatched in.
+// Chunk word: bit 30 set once published, bits 29-0 the count.
+// Group word: bits 29-24 the chunks added, bits 23-0 their count.
+constexpr uint32_t kLbAgg = 1u << 30, kLbMask = (1u << 30) - 1u;
+constexpr uint32_t kLbArrive = 1u << 24, kLbGroupMask = kLbArrive - 1u;
+constexpr int kLbGroup = kSortLbGroup;
+static_assert((uint64_t)kLbGroup * 256 * kSortIptMax <= kLbGroupMask && kLbGroup < 64,
+              "a group's count and arrivals fit their fields");
+
+// Sum of the words words[k * 256], k in [lo, hi), W at a time, polling the
+// first one not yet complete: chunk words (GROUP false) once published,
+// group words once all kLbGroup chunks have added.  Stops (stalled = true)
+// once polls reaches spin.
+template <int W, bool GROUP>
+__device__ __forceinline__ uint32_t lb_sum(const uint32_t* words, int lo, int hi, uint32_t spin,
+                                           uint32_t& polls, bool& stalled) {
+  constexpr uint32_t kDone = GROUP ? (uint32_t)kLbGroup * kLbArrive : kLbAgg;
+  uint32_t s = 0;
+  int k = lo;
+  while (k < hi && !stalled) {
+    uint32_t x[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j)
+      x[j] = k + j < hi ? __hip_atomic_load(&words[(int64_t)(k + j) * 256], __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT)
+                        : kDone;
+    int used = W;  // words consumed before one that is not complete
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      if (used == W) {
+        const bool done = GROUP ? (x[j] & ~kLbGroupMask) == kDone : (x[j] & kLbAgg) != 0u;
+        if (!done) used = j;
+        else s += x[j] & (GROUP ? kLbGroupMask : kLbMask);
+      }
+    }
+    k += used;
+    if (used < W) {
+      if (++polls >= spin) stalled = true;
+      else __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  return s;
+}
 
 __global__ __launch_bounds__(256) void k_sort_hist4(const uint32_t* __restrict__ keys, uint32_t n,
                                                     WsView w, uint32_t lb_words) {
   __shared__ uint32_t s_h[1024];
   for (int j = threadIdx.x; j < 1024; j += 256) s_h[j] = 0u;
   __syncthreads();
-#pragma unroll 4
-  for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
-    const uint32_t k = keys[i];
+  // 16 keys per thread are loaded before any is counted: one round trip
+  // per 16 grid strides instead of one per stride
+  constexpr int KB = 16;
+  const uint32_t stride = gridDim.x * 256;
+  for (uint64_t i0 = blockIdx.x * 256 + threadIdx.x; i0 < n; i0 += (uint64_t)KB * stride) {
+    uint32_t k[KB];
 #pragma unroll
-    for (int p = 0; p < 4; ++p) atomicAdd(&s_h[256 * p + ((k >> (8 * p)) & 255u)], 1u);
+    for (int j = 0; j < KB; ++j) {
+      const uint64_t i = i0 + (uint64_t)j * stride;
+      k[j] = i < n ? keys[i] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      if (i0 + (uint64_t)j * stride < n) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) atomicAdd(&s_h[256 * p + ((k[j] >> (8 * p)) & 255u)], 1u);
+      }
+    }
   }
   __syncthreads();
   for (int j = threadIdx.x; j < 1024; j += 256) w.sort_part[blockIdx.x * 1024 + j] = s_h[j];
   for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < lb_words; i += gridDim.x * 256)
     w.sort_lb[i] = 0u;
-  if (blockIdx.x == 0 && threadIdx.x < 4) w.sort_ctr[threadIdx.x] = 0u;
 }
 
 template <int IPT>
@@ -246,38 +308,31 @@ __global__ __launch_bounds__(256) void k_sort_pass(const uint32_t* __restrict__ 
                                                    const uint32_t* __restrict__ vin,
                                                    uint32_t* __restrict__ kout,
                                                    uint32_t* __restrict__ vout, uint32_t n,
-                                                   int pass, WsView w) {
+                                                   int pass, uint32_t spin, WsView w) {
   __shared__ uint32_t s_cnt[4][256];  // per-wave digit counts, then per-wave digit offsets
   __shared__ uint32_t s_base[256];
   __shared__ uint32_t s_tmp[4];
-  __shared__ uint32_t s_bid;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int shift = 8 * pass;
-  uint32_t* lb = w.sort_lb + (uint64_t)pass * gridDim.x * 256;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) s_cnt[k][tid] = 0u;
-  // the keys of chunk blockIdx.x are loaded while the ticket is in flight:
-  // workgroups nearly always draw their own index, otherwise they reload
+  const int nch = (int)gridDim.x, ngr = (nch + kLbGroup - 1) / kLbGroup;
+  uint32_t* lb = w.sort_lb + (uint64_t)pass * (uint64_t)(nch + ngr) * 256;  // chunk counts
+  uint32_t* glb = lb + (uint64_t)nch * 256;                                  // group totals
+  const uint32_t b = blockIdx.x;
+  const uint64_t base = (uint64_t)b * (256 * IPT) + (uint64_t)wv * (64 * IPT);
   uint32_t k[IPT], v[IPT], rank[IPT];
-  auto load_chunk = [&](uint32_t bb) {
-    const uint64_t bs = (uint64_t)bb * (256 * IPT) + (uint64_t)wv * (64 * IPT);
 #pragma unroll
-    for (int it = 0; it < IPT; ++it) {
-      const uint64_t idx = bs + (uint64_t)it * 64 + lane;
-      k[it] = idx < n ? kin[idx] : 0u;
-      v[it] = idx < n ? vin[idx] : 0u;
-    }
-  };
-  load_chunk(blockIdx.x);
+  for (int it = 0; it < IPT; ++it) {
+    const uint64_t idx = base + (uint64_t)it * 64 + lane;
+    k[it] = idx < n ? kin[idx] : 0u;
+    v[it] = idx < n ? vin[idx] : 0u;
+  }
   // this pass's digit totals (thread = digit), from the histogram partials
   uint32_t part[kSortHistBlocks];
 #pragma unroll
   for (int g = 0; g < kSortHistBlocks; ++g) part[g] = w.sort_part[g * 1024 + 256 * pass + tid];
-  if (tid == 0) s_bid = atomicAdd(&w.sort_ctr[pass], 1u);  // after the loads are issued
-  lds_barrier();  // the ticket and the zeroed counts; the loads stay in flight
-  const uint32_t b = s_bid;
-  if (b != blockIdx.x) load_chunk(b);  // uniform
-  const uint64_t base = (uint64_t)b * (256 * IPT) + (uint64_t)wv * (64 * IPT);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) s_cnt[k][tid] = 0u;
+  lds_barrier();  // the zeroed counts; the loads stay in flight
   // stable rank of every key among the wave's keys of its digit
   const uint64_t lt = lanemask_lt(lane);
 #pragma unroll
@@ -299,49 +354,25 @@ __global__ __launch_bounds__(256) void k_sort_pass(const uint32_t* __restrict__ 
   // thread = digit: the chunk's count, published, then the earlier chunks' count
   const uint32_t c0 = s_cnt[0][tid], c1 = s_cnt[1][tid], c2 = s_cnt[2][tid], c3 = s_cnt[3][tid];
   const uint32_t cnt = c0 + c1 + c2 + c3;
-  uint32_t excl = 0;
-  if (b == 0) {
-    __hip_atomic_store(&lb[tid], kLbInc | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  } else {
-    __hip_atomic_store(&lb[b * 256 + tid], kLbAgg | cnt, __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-    // predecessors are read kLbWindow at a time (one round trip per window);
-    // chunks before chunk 0 count as an inclusive prefix of zero
-    int p = (int)b - 1;
-    uint32_t polls = 0;
-    while (true) {
-      uint32_t x[kLbWindow];
-#pragma unroll
-      for (int j = 0; j < kLbWindow; ++j)
-        x[j] = p - j >= 0 ? __hip_atomic_load(&lb[(p - j) * 256 + tid], __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT)
-                          : kLbInc;
-      int used = kLbWindow;  // words consumed before a chunk that is not ready
-      bool found = false;
-#pragma unroll
-      for (int j = 0; j < kLbWindow; ++j) {
-        if (!found && used == kLbWindow) {
-          const uint32_t f = x[j] >> 30;
-          if (f == 0u) {
-            used = j;
-          } else {
-            excl += x[j] & kLbMask;
-            found = f == 2u;
-          }
-        }
-      }
-      if (found) break;
-      p -= used;
-      if (used < kLbWindow) {  // chunk p has not published yet
-        if (++polls > kLbSpinMax) {
-          atomicOr(&w.status[0], GSFF_FLAG_SORT_STALL);
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
-    }
-    __hip_atomic_store(&lb[b * 256 + tid], kLbInc | (excl + cnt), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
+  const int grp = (int)b / kLbGroup, first = grp * kLbGroup;
+  __hip_atomic_store(&lb[b * 256 + tid], kLbAgg | cnt, __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_fetch_add(&glb[grp * 256 + tid], kLbArrive | cnt, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+  uint32_t polls = 0;
+  bool stalled = spin == 0u && b > 0u;  // (a zero limit: every workgroup counts)
+  uint32_t excl = lb_sum<kLbGroup, false>(lb + tid, first, (int)b, spin, polls, stalled);
+  excl += lb_sum<32, true>(glb + tid, 0, grp, spin, polls, stalled);
+  if (__syncthreads_or(stalled ? 1 : 0)) {  // uniform: count chunks 0..b-1 from the input
+    s_base[tid] = 0u;
+    __syncthreads();
+    const uint64_t end = (uint64_t)b * (256 * IPT);  // (those chunks are full)
+#pragma unroll 8
+    for (uint64_t i = tid; i < end; i += 256) atomicAdd(&s_base[(kin[i] >> shift) & 255u], 1u);
+    __syncthreads();
+    excl = s_base[tid];
+    __syncthreads();
+    if (tid == 0) atomicOr(&w.status[0], GSFF_FLAG_SORT_RECOUNT);
   }
   uint32_t tot = 0u;
 #pragma unroll
@@ -367,18 +398,30 @@ __global__ __launch_bounds__(256) void k_sort_pass(const uint32_t* __restrict__ 
   }
 }
 
+static std::atomic<uint32_t> g_sort_wait_limit{kSortWaitPolls};
+
+void set_sort_wait_limit(uint32_t polls) { g_sort_wait_limit.store(polls); }
+
 hipError_t launch_sort_depth(const Layout& L, const WsView& w, hipStream_t s) {
   if (L.P == 0) return hipSuccess;
+  const uint32_t spin = g_sort_wait_limit.load();
   const uint32_t n = (uint32_t)L.P;
+  const int64_t groups = (L.sort_blocks + kSortLbGroup - 1) / kSortLbGroup;
   hipLaunchKernelGGL(k_sort_hist4, dim3(kSortHistBlocks), dim3(256), 0, s, w.dkeys_a, n, w,
-                     (uint32_t)(4 * 256 * L.sort_blocks));
+                     (uint32_t)(4 * 256 * (L.sort_blocks + groups)));
   uint32_t* ka = w.dkeys_a;
   uint32_t* kb = w.dkeys_b;
   uint32_t* va = w.dids_a;
   uint32_t* vb = w.dids_b;
   for (int pass = 0; pass < 4; ++pass) {
-    hipLaunchKernelGGL(k_sort_pass<kSortIpt>, dim3((unsigned)L.sort_blocks), dim3(256), 0, s, ka,
-                       va, kb, vb, n, pass, w);
+    const dim3 grid((unsigned)L.sort_blocks);
+    if (L.sort_ipt == 4)
+      hipLaunchKernelGGL(k_sort_pass<4>, grid, dim3(256), 0, s, ka, va, kb, vb, n, pass, spin, w);
+    else if (L.sort_ipt == 8)
+      hipLaunchKernelGGL(k_sort_pass<8>, grid, dim3(256), 0, s, ka, va, kb, vb, n, pass, spin, w);
+    else
+      hipLaunchKernelGGL(k_sort_pass<kSortIptMax>, grid, dim3(256), 0, s, ka, va, kb, vb, n, pass,
+                         spin, w);
     uint32_t* t = ka;
     ka = kb;
     kb = t;
