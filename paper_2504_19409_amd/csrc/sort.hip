@@ -359,6 +359,13 @@ __global__ __launch_bounds__(256) void k_sort_pass(const uint32_t* __restrict__ 
                      __HIP_MEMORY_SCOPE_AGENT);
   __hip_atomic_fetch_add(&glb[grp * 256 + tid], kLbArrive | cnt, __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
+  // the digits' first places (independent of the earlier chunks) while the
+  // neighbours publish
+  uint32_t tot = 0u;
+#pragma unroll
+  for (int g = 0; g < kSortHistBlocks; ++g) tot += part[g];
+  uint32_t all;
+  const uint32_t dbase = block_excl_scan256(tot, s_tmp, &all);
   uint32_t polls = 0;
   bool stalled = spin == 0u && b > 0u;  // (a zero limit: every workgroup counts)
   uint32_t excl = lb_sum<kLbGroup, false>(lb + tid, first, (int)b, spin, polls, stalled);
@@ -374,11 +381,6 @@ __global__ __launch_bounds__(256) void k_sort_pass(const uint32_t* __restrict__ 
     __syncthreads();
     if (tid == 0) atomicOr(&w.status[0], GSFF_FLAG_SORT_RECOUNT);
   }
-  uint32_t tot = 0u;
-#pragma unroll
-  for (int g = 0; g < kSortHistBlocks; ++g) tot += part[g];
-  uint32_t all;
-  const uint32_t dbase = block_excl_scan256(tot, s_tmp, &all);
   s_base[tid] = dbase + excl;
   s_cnt[0][tid] = 0u;
   s_cnt[1][tid] = c0;
