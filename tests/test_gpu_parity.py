@@ -155,42 +155,54 @@ def test_stage_preprocess_records_and_keys(orc, kind):
     assert np.array_equal(keys[has_tiles], okey[has_tiles])
 
 
-def _sorted_depth(fr, P):
-    for st in ["gsff_preprocess", "gsff_sort_depth"]:
+def _sorted_and_binned(fr, P):
+    for st in ["gsff_preprocess", "gsff_sort_depth", "gsff_bin", "gsff_sort_tiles",
+               "gsff_tile_ranges"]:
         fr.call_stage(st)
     torch.cuda.synchronize()
     keys = fr.ws_view("depth_keys", torch.int32, P).cpu().numpy().view(np.uint32).copy()
     ids = fr.ws_view("depth_ids", torch.int32, P).cpu().numpy().view(np.uint32).copy()
-    return keys, ids, fr.read_status()[0]
+    flags, npairs = fr.read_status()
+    pk = fr.ws_view("pair_keys", torch.int32, npairs).cpu().numpy().view(np.uint32).copy()
+    pm = fr.ws_view("pair_masks", torch.int16, npairs).cpu().numpy().view(np.uint16).copy()
+    nr = 2 * fr.layout.super_x * fr.layout.super_y
+    rg = fr.ws_view("tile_ranges", torch.int32, nr).cpu().numpy().view(np.uint32).copy()
+    return dict(keys=keys, ids=ids, pk=pk, pm=pm, ranges=rg), flags
 
 
 @pytest.mark.parametrize("kind", ["ragged", "frame"])
 def test_depth_sort_recount_fallback(kind):
-    """A depth-sort workgroup that stops waiting for its predecessors' counts
-    counts their digits from the keys itself.  Forced from the host (a wait
-    limit of zero: every workgroup but the first counts), the sort must give
-    the same keys and ids, bit for bit, as the published-count path, be
-    sorted with ties in index order, and raise the recount flag; the normal
-    path raises no flag.  The frame case has 196 chunks in 25 groups."""
+    """A depth-sort workgroup that stops waiting for its predecessors'
+    counts counts their digits from the keys itself.  Forced from the host (a
+    wait limit of zero: every workgroup but the first counts), the sort must
+    give the same keys and ids, and the binning after it the same pairs,
+    masks and ranges, bit for bit, as the published-count path; the keys
+    are sorted with ties in index order, and the recount flag is raised;
+    the normal path raises no flag.  The frame case has 196 chunks in 25
+    groups."""
     from paper_2504_19409_amd import _capi
     sc = sg.workload_scene("frame")[0] if kind == "frame" else _scene(kind, C=4)
     fr, _ = H.make_frame(sc, torch)
     P = sc.P
-    keys, ids, flags = _sorted_depth(fr, P)
-    assert flags & _capi.FLAG_SORT_RECOUNT == 0
+    ref, flags = _sorted_and_binned(fr, P)
+    assert flags == 0
     L = _capi.load()
     try:
         _capi.check(L.gsff_set_sort_wait_limit(0), "gsff_set_sort_wait_limit")
-        keys0, ids0, flags0 = _sorted_depth(fr, P)
+        got, flags0 = _sorted_and_binned(fr, P)
     finally:
         _capi.check(L.gsff_set_sort_wait_limit(2048), "gsff_set_sort_wait_limit")
-    assert flags0 & _capi.FLAG_SORT_RECOUNT
-    assert np.array_equal(keys0, keys) and np.array_equal(ids0, ids)
+    assert flags0 == _capi.FLAG_SORT_RECOUNT
+    for k in ref:
+        assert np.array_equal(got[k], ref[k]), k
+    keys, ids = ref["keys"], ref["ids"]
     order = np.lexsort((ids.astype(np.int64), keys.astype(np.int64)))
     assert np.array_equal(order, np.arange(P))  # sorted by key, ties by index
     assert np.array_equal(np.sort(ids), np.arange(P, dtype=np.uint32))  # a permutation
-    _, _, flags1 = _sorted_depth(fr, P)  # the default limit is back
-    assert flags1 & _capi.FLAG_SORT_RECOUNT == 0
+    again, flags1 = _sorted_and_binned(fr, P)  # the default limit is back
+    assert flags1 == 0
+    for k in ref:
+        assert np.array_equal(again[k], ref[k]), k
 
 
 @pytest.mark.parametrize("kind", ["tiny", "ragged", "rotated", "dense"])
