@@ -29,6 +29,7 @@ namespace gsff {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kLat = 16, kHid = 128, kOut = 512;
 constexpr int kWgradGroups = 128;     // split-K workgroups of the weight-gradient GEMMs
@@ -209,11 +210,12 @@ __global__ __launch_bounds__(256) void k_dec_forward(const __bf16* __restrict__ 
 #pragma unroll
       for (int r0 = 0; r0 < 32; r0 += RPI) {
         const int row = r0 + lane / LPR, col = (lane % LPR) * VEC;
-        const uint4 v = *reinterpret_cast<const uint4*>(&s_y[wv][row][col]);
+        const u32x4 v = *reinterpret_cast<const u32x4*>(&s_y[wv][row][col]);
         const int64_t p0 = wbase + col;
         OT* dst = Y + (int64_t)(32 * c + row) * npx + p0;
         if (full) {
-          *reinterpret_cast<uint4*>(dst) = v;
+          // one 16-byte store, nontemporal: the map streams past the caches
+          __builtin_nontemporal_store(v, reinterpret_cast<u32x4*>(dst));
         } else {
           const OT* e = reinterpret_cast<const OT*>(&v);
 #pragma unroll
