@@ -50,7 +50,9 @@ static DecLayout dec_layout(int64_t npx) {
   DecLayout L;
   L.npx = npx;
   L.nblk = (npx + 31) / 32;
-  L.npad = L.nblk * 32;
+  // the training kernel's buffers cover every pixel its workgroups (128
+  // pixels each) are launched for, so none of its stores needs a test
+  L.npad = (npx + 127) / 128 * 128;
   uint64_t o = 0;
   auto take = [&](uint64_t b) {
     const uint64_t at = o;
@@ -272,12 +274,17 @@ __global__ __launch_bounds__(256) void k_dec_train(
   const int lane = threadIdx.x & 63, g = lane >> 5, i = lane & 31;
   const int64_t px = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 32 + i;
   const bool ok = px < npx;
-  const bool in_pad = px < npad;
+  // loads read a pixel in range and the value is dropped where !ok, so no
+  // load sits in a branch (a branch around a load makes the compiler wait
+  // for every load in flight where the paths join); every launched pixel is
+  // below npad, so the stores need no test either
+  const int64_t pxc = ok ? px : npx - 1;
   bf16x8 xb;
 #pragma unroll
   for (int t = 0; t < 8; ++t) {
-    xb[t] = ok ? X[(int64_t)(8 * g + t) * npx + px] : (__bf16)0.f;
-    if (in_pad) xbuf[(int64_t)(8 * g + t) * npad + px] = xb[t];  // zero-padded copy for dW1
+    const __bf16 v = X[(int64_t)(8 * g + t) * npx + pxc];
+    xb[t] = ok ? v : (__bf16)0.f;
+    xbuf[(int64_t)(8 * g + t) * npad + px] = xb[t];  // zero-padded copy for dW1
   }
   f32x16 z[4];
   bf16x8 hf[8];
@@ -292,7 +299,7 @@ __global__ __launch_bounds__(256) void k_dec_train(
       const int hid = 32 * h + 8 * (r / 4) + 4 * g + r % 4;
       z[h][r] += b1[hid];
       hv[r] = ok ? gelu_f(z[h][r]) : 0.f;
-      if (in_pad) hbuf[(int64_t)hid * npad + px] = (__bf16)hv[r];
+      hbuf[(int64_t)hid * npad + px] = (__bf16)hv[r];
     }
     hf[2 * h] = regs_to_b(hv, 0);
     hf[2 * h + 1] = regs_to_b(hv, 1);
@@ -311,14 +318,12 @@ __global__ __launch_bounds__(256) void k_dec_train(
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int ch = 32 * c + 8 * (r / 4) + 4 * g + r % 4;
-      float sv = 0.f;
-      if (ok) {
-        const float d = acc[r] + b2[ch] - (float)T[(int64_t)ch * npx + px];
-        lsum += fabsf(d);
-        sv = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
-      }
+      const float tv = (float)T[(int64_t)ch * npx + pxc];
+      const float d = ok ? acc[r] + b2[ch] - tv : 0.f;
+      lsum += fabsf(d);
+      const float sv = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
       sg[r] = sv;
-      if (in_pad) dys[(int64_t)ch * npad + px] = (int8_t)sv;
+      dys[(int64_t)ch * npad + px] = (int8_t)sv;
     }
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
@@ -337,7 +342,7 @@ __global__ __launch_bounds__(256) void k_dec_train(
     for (int r = 0; r < 16; ++r) {
       const int hid = 32 * h + 8 * (r / 4) + 4 * g + r % 4;
       dz[r] = ok ? scale * dh[h][r] * gelu_grad_f(z[h][r]) : 0.f;
-      if (in_pad) dzbuf[(int64_t)hid * npad + px] = (__bf16)dz[r];
+      dzbuf[(int64_t)hid * npad + px] = (__bf16)dz[r];
     }
     dzf[2 * h] = regs_to_b(dz, 0);
     dzf[2 * h + 1] = regs_to_b(dz, 1);
