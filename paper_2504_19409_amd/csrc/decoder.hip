@@ -531,11 +531,18 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kQueryBlock, kQueryBlock),
   float ce = 0.f;
   // B of layer 1, k-step s: latent 4 s + l / 16 of pixel l % 16; the next
   // group's are loaded while this one is computed
+  // (a pixel in range is read and the value dropped outside it: a load in a
+  // branch would make the compiler wait for every load in flight where the
+  // paths join)
   auto load_x = [&](int64_t g, float* x) {
     const int64_t q = g * 16 + r;
+    const bool in = g < ngroups && q < n;
+    const int64_t qc = in ? q : n - 1;
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-      x[k] = (g < ngroups && q < n) ? (float)X[(int64_t)(4 * k + c4) * n + q] : 0.f;
+    for (int k = 0; k < 4; ++k) {
+      const float v = (float)X[(int64_t)(4 * k + c4) * n + qc];
+      x[k] = in ? v : 0.f;
+    }
   };
   int64_t grp = (int64_t)blockIdx.x * (kQueryBlock / 64) + (threadIdx.x >> 6);
   float xb[4];
@@ -545,6 +552,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kQueryBlock, kQueryBlock),
     const bool ok = p < n;
     float xn[4];
     load_x(grp + nwaves, xn);
+    const int gl = gt ? gt[ok ? p : n - 1] : -1;  // (gt is uniform)
     // the operands are read from LDS at every step: an empty asm keeps the
     // compiler from holding all 32 + 32 NLT of them in registers across the
     // loop, which would leave room for two waves per SIMD
@@ -615,7 +623,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(kQueryBlock, kQueryBlock),
       }
       if (label && c4 == 0) label[p] = arg;
       if (gt) {
-        const int l = gt[p];
+        const int l = gl;
 #pragma unroll
         for (int u = 0; u < NLT; ++u)
 #pragma unroll
