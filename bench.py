@@ -86,6 +86,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="wall-clock budget of the CPU oracle sample")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches only")
+    ap.add_argument("--graph-steps", type=int, default=8,
+                    help="whole steps captured in one graph (replayed back to back; each "
+                         "step is the full forward + backward)")
     ap.add_argument("--workload", default="frame",
                     choices=["frame", "mixed", "decoder", "window"],
                     help="frame (default): 200k Gaussians, 640x480, 16-ch FP32; mixed: 1M "
@@ -441,9 +444,15 @@ def main():
         torch.cuda.current_stream().wait_stream(s)
         torch.cuda.synchronize()
         ref = [g.clone() for g in step.grads.values()]
+        # steps per graph (the launch of a graph is paid once per S): the
+        # largest divisor of K not above --graph-steps, so exactly K are timed
+        S = max(1, min(args.graph_steps, K))
+        while K % S:
+            S -= 1
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
-            step.run()
+            for _ in range(S):
+                step.run()
         torch.cuda.synchronize()
         for _ in range(3):
             g.replay()
@@ -451,20 +460,22 @@ def main():
         for a, b in zip(step.grads.values(), ref):
             d = (a - b).norm() / max(b.norm(), 1e-30)
             assert float(d) < 1e-4, "graph replay differs from eager"
-        for _ in range(args.warmup):
+        for _ in range((args.warmup + S - 1) // S):
             g.replay()
         torch.cuda.synchronize()
-        # per-replay events (median, p10, p90) inside the wall-clock bracket
-        gev = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+        # per-replay events (median, p10, p90 of a replay's time per step)
+        # inside the wall-clock bracket; K steps = R replays of S
+        R = K // S
+        gev = [torch.cuda.Event(enable_timing=True) for _ in range(R + 1)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         gev[0].record()
-        for k in range(K):
+        for k in range(R):
             g.replay()
             gev[k + 1].record()
         torch.cuda.synchronize()
-        graph_ms = (time.perf_counter() - t0) / K * 1e3
-        per = np.array([gev[k].elapsed_time(gev[k + 1]) for k in range(K)])
+        graph_ms = (time.perf_counter() - t0) / (R * S) * 1e3
+        per = np.array([gev[k].elapsed_time(gev[k + 1]) / S for k in range(R)])
         graph_dist = {"median_ms": round(float(np.median(per)), 4),
                       "p10_ms": round(float(np.percentile(per, 10)), 4),
                       "p90_ms": round(float(np.percentile(per, 90)), 4)}
@@ -508,7 +519,8 @@ def main():
                                "RGB+depth+alpha+16-ch FP32 features, pose perturbed 1 cm/1 deg",
                    "gaussians": scene.P, "width": 640, "height": 480, "channels": 16,
                    "arithmetic": ARITHMETIC,
-                   "timing": "graph replay" if graph_ms and graph_ms < eager_ms else "eager",
+                   "timing": (f"graph replay ({S} steps per graph)" if graph_ms and graph_ms < eager_ms
+                              else "eager"),
                    "eager_ms": round(eager_ms, 4),
                    "graph_ms": round(graph_ms, 4) if graph_ms else None,
                    "graph_replay_dist": graph_dist,
