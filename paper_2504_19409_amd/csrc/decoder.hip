@@ -271,6 +271,10 @@ __global__ __launch_bounds__(256) void k_dec_train(
     __bf16* __restrict__ hbuf, __bf16* __restrict__ dzbuf, int8_t* __restrict__ dys,
     float* __restrict__ dX, float* loss, float scale, int64_t npx, int64_t npad) {
   __shared__ float s_loss[4];
+  __shared__ float s_b1[kHid], s_b2[kOut];  // biases: one LDS read per element, no global
+  for (int e = threadIdx.x; e < kHid; e += 256) s_b1[e] = b1[e];
+  for (int e = threadIdx.x; e < kOut; e += 256) s_b2[e] = b2[e];
+  __syncthreads();
   const int lane = threadIdx.x & 63, g = lane >> 5, i = lane & 31;
   const int64_t px = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 32 + i;
   const bool ok = px < npx;
@@ -297,7 +301,7 @@ __global__ __launch_bounds__(256) void k_dec_train(
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int hid = 32 * h + 8 * (r / 4) + 4 * g + r % 4;
-      z[h][r] += b1[hid];
+      z[h][r] += s_b1[hid];
       hv[r] = ok ? gelu_f(z[h][r]) : 0.f;
       hbuf[(int64_t)hid * npad + px] = (__bf16)hv[r];
     }
@@ -319,7 +323,7 @@ __global__ __launch_bounds__(256) void k_dec_train(
     for (int r = 0; r < 16; ++r) {
       const int ch = 32 * c + 8 * (r / 4) + 4 * g + r % 4;
       const float tv = (float)T[(int64_t)ch * npx + pxc];
-      const float d = ok ? acc[r] + b2[ch] - tv : 0.f;
+      const float d = ok ? acc[r] + s_b2[ch] - tv : 0.f;
       lsum += fabsf(d);
       const float sv = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
       sg[r] = sv;
