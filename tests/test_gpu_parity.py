@@ -276,11 +276,11 @@ def test_stage_depth_sort_and_tile_lists(orc, kind):
                                2_097_153])
 def test_depth_sort_exact_and_stable(P):
     """The depth sort against numpy's stable argsort of the keys preprocess
-    wrote, at sizes around the 2048-key workgroup chunk and with many chunks
-    (the look-back between workgroups), on keys with heavy ties, up to a
-    thousand chunks.  A second sort of the sorted keys must keep them and
-    their ids (the sort leaves its look-back words and tickets ready for the
-    next call)."""
+    wrote, at sizes around the workgroup chunk (1024 to 4096 keys by size)
+    and with many chunks (the look-back between workgroups), on keys with
+    heavy ties, up to several hundred chunks and both chunk sizes of the
+    two-level look-back.  A second sort of the sorted keys must keep them and
+    their ids (each sort clears its look-back words for the next call)."""
     rng = np.random.default_rng(P)
     sc = sg.make_scene(P, 320, 240, 260.0, 260.0, 160.0, 120.0, 0, seed=P, rng=rng)
     # depths from 37 distinct values: long runs of equal keys
