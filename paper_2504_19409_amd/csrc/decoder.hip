@@ -272,8 +272,45 @@ __global__ __launch_bounds__(256) void k_dec_train(
     float* __restrict__ dX, float* loss, float scale, int64_t npx, int64_t npad) {
   __shared__ float s_loss[4];
   __shared__ float s_b1[kHid], s_b2[kOut];  // biases: one LDS read per element, no global
+  // the targets of one 32-channel output block for the workgroup's 128
+  // pixels, double-buffered: block c + 1's are loaded with 16-byte loads
+  // while block c is computed
+  constexpr int TP = 128 + 8;  // row pitch
+  __shared__ __attribute__((aligned(16))) __bf16 s_t[2][32][TP];
   for (int e = threadIdx.x; e < kHid; e += 256) s_b1[e] = b1[e];
   for (int e = threadIdx.x; e < kOut; e += 256) s_b2[e] = b2[e];
+  const int64_t pw = (int64_t)blockIdx.x * 128;  // the workgroup's first pixel
+  const int trow = threadIdx.x >> 3, tseg = (threadIdx.x & 7) * 16;
+  // whole 16-byte runs when every pixel of the workgroup is in range and rows
+  // are 16-byte aligned (uniform); otherwise one clamped element at a time
+  const bool tvec =
+      (npx % 8) == 0 && pw + 128 <= npx && (reinterpret_cast<uintptr_t>(T) & 15u) == 0u;
+  u32x4 tl[2];
+  auto load_tile = [&](int cc) {
+    const int64_t src = (int64_t)(32 * cc + trow) * npx + pw + tseg;
+    if (tvec) {
+      tl[0] = *reinterpret_cast<const u32x4*>(T + src);
+      tl[1] = *reinterpret_cast<const u32x4*>(T + src + 8);
+    } else {
+      uint16_t e[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int64_t p = min(pw + tseg + j, npx - 1);
+        e[j] = reinterpret_cast<const uint16_t*>(T)[(int64_t)(32 * cc + trow) * npx + p];
+      }
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          tl[q][k] = (uint32_t)e[8 * q + 2 * k] | ((uint32_t)e[8 * q + 2 * k + 1] << 16);
+    }
+  };
+  auto store_tile = [&](int buf) {
+    *reinterpret_cast<u32x4*>(&s_t[buf][trow][tseg]) = tl[0];
+    *reinterpret_cast<u32x4*>(&s_t[buf][trow][tseg + 8]) = tl[1];
+  };
+  load_tile(0);
+  store_tile(0);
   __syncthreads();
   const int lane = threadIdx.x & 63, g = lane >> 5, i = lane & 31;
   const int64_t px = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 32 + i;
@@ -312,7 +349,9 @@ __global__ __launch_bounds__(256) void k_dec_train(
 #pragma unroll
   for (int h = 0; h < 4; ++h) dh[h] = f32x16{};
   float lsum = 0.f;
+  const int wcol = (threadIdx.x >> 6) * 32 + i;  // this lane's pixel in the tile
   for (int c = 0; c < kOut / 32; ++c) {
+    load_tile(min(c + 1, kOut / 32 - 1));  // (the last block reloads itself)
     f32x16 acc = {};
 #pragma unroll
     for (int s = 0; s < 8; ++s)
@@ -322,7 +361,7 @@ __global__ __launch_bounds__(256) void k_dec_train(
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int ch = 32 * c + 8 * (r / 4) + 4 * g + r % 4;
-      const float tv = (float)T[(int64_t)ch * npx + pxc];
+      const float tv = (float)s_t[c & 1][8 * (r / 4) + 4 * g + r % 4][wcol];
       const float d = ok ? acc[r] + s_b2[ch] - tv : 0.f;
       lsum += fabsf(d);
       const float sv = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
@@ -337,6 +376,8 @@ __global__ __launch_bounds__(256) void k_dec_train(
         dh[h] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
             load8(w2p + ((32 * h + i) * 32 + 2 * c + e) * 16 + 8 * g), b, dh[h], 0, 0, 0);
     }
+    store_tile((c + 1) & 1);
+    __syncthreads();  // the next block's targets are in; this block's are read
   }
   bf16x8 dzf[8];
 #pragma unroll
