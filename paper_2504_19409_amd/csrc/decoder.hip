@@ -309,8 +309,34 @@ __global__ __launch_bounds__(256) void k_dec_train(
     *reinterpret_cast<u32x4*>(&s_t[buf][trow][tseg]) = tl[0];
     *reinterpret_cast<u32x4*>(&s_t[buf][trow][tseg + 8]) = tl[1];
   };
+  // the block's weight operands the same way: W2^T rows 32 c .. 32 c + 31 in
+  // their K-step order, and the W2 columns of K-steps 2 c, 2 c + 1 (rows
+  // padded so the lanes' 16-byte reads fall in distinct banks)
+  constexpr int WTP = 128 + 8, WP = 32 + 8;
+  __shared__ __attribute__((aligned(16))) __bf16 s_w2t[2][32 * WTP];
+  __shared__ __attribute__((aligned(16))) __bf16 s_w2[2][kHid * WP];
+  u32x4 wl[4];
+  const int wh = threadIdx.x >> 1, we = (threadIdx.x & 1) * 16;
+  auto load_w = [&](int cc) {
+    const __bf16* a = w2tp + ((int64_t)32 * cc * 128 + threadIdx.x * 16);
+    wl[0] = *reinterpret_cast<const u32x4*>(a);
+    wl[1] = *reinterpret_cast<const u32x4*>(a + 8);
+    const __bf16* bp = w2p + ((int64_t)(wh * 32 + 2 * cc) * 16 + we);
+    wl[2] = *reinterpret_cast<const u32x4*>(bp);
+    wl[3] = *reinterpret_cast<const u32x4*>(bp + 8);
+  };
+  auto store_w = [&](int buf) {
+    __bf16* a = &s_w2t[buf][trow * WTP + tseg];
+    *reinterpret_cast<u32x4*>(a) = wl[0];
+    *reinterpret_cast<u32x4*>(a + 8) = wl[1];
+    __bf16* bp = &s_w2[buf][wh * WP + we];
+    *reinterpret_cast<u32x4*>(bp) = wl[2];
+    *reinterpret_cast<u32x4*>(bp + 8) = wl[3];
+  };
   load_tile(0);
+  load_w(0);
   store_tile(0);
+  store_w(0);
   __syncthreads();
   const int lane = threadIdx.x & 63, g = lane >> 5, i = lane & 31;
   const int64_t px = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 32 + i;
@@ -327,19 +353,20 @@ __global__ __launch_bounds__(256) void k_dec_train(
     xb[t] = ok ? v : (__bf16)0.f;
     xbuf[(int64_t)(8 * g + t) * npad + px] = xb[t];  // zero-padded copy for dW1
   }
-  f32x16 z[4];
+  // (the pre-activations are computed again for the GELU derivative at the
+  // end instead of being held in 64 registers across the output blocks)
   bf16x8 hf[8];
 #pragma unroll
   for (int h = 0; h < 4; ++h) {
-    z[h] = f32x16{};
-    z[h] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load8(w1t + (32 * h + i) * kLat + 8 * g), xb,
-                                                   z[h], 0, 0, 0);
+    f32x16 z = {};
+    z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load8(w1t + (32 * h + i) * kLat + 8 * g), xb, z, 0,
+                                                0, 0);
     f32x16 hv;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int hid = 32 * h + 8 * (r / 4) + 4 * g + r % 4;
-      z[h][r] += s_b1[hid];
-      hv[r] = ok ? gelu_f(z[h][r]) : 0.f;
+      z[r] += s_b1[hid];
+      hv[r] = ok ? gelu_f(z[r]) : 0.f;
       hbuf[(int64_t)hid * npad + px] = (__bf16)hv[r];
     }
     hf[2 * h] = regs_to_b(hv, 0);
@@ -352,11 +379,13 @@ __global__ __launch_bounds__(256) void k_dec_train(
   const int wcol = (threadIdx.x >> 6) * 32 + i;  // this lane's pixel in the tile
   for (int c = 0; c < kOut / 32; ++c) {
     load_tile(min(c + 1, kOut / 32 - 1));  // (the last block reloads itself)
+    load_w(min(c + 1, kOut / 32 - 1));
+    const __bf16* wt = &s_w2t[c & 1][i * WTP + 8 * g];
     f32x16 acc = {};
 #pragma unroll
     for (int s = 0; s < 8; ++s)
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load8(w2tp + ((32 * c + i) * 8 + s) * 16 + 8 * g),
-                                                    hf[s], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+          *reinterpret_cast<const bf16x8*>(wt + 16 * s), hf[s], acc, 0, 0, 0);
     f32x16 sg;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -374,19 +403,24 @@ __global__ __launch_bounds__(256) void k_dec_train(
 #pragma unroll
       for (int h = 0; h < 4; ++h)
         dh[h] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-            load8(w2p + ((32 * h + i) * 32 + 2 * c + e) * 16 + 8 * g), b, dh[h], 0, 0, 0);
+            *reinterpret_cast<const bf16x8*>(&s_w2[c & 1][(32 * h + i) * WP + 16 * e + 8 * g]), b,
+            dh[h], 0, 0, 0);
     }
     store_tile((c + 1) & 1);
+    store_w((c + 1) & 1);
     __syncthreads();  // the next block's targets are in; this block's are read
   }
   bf16x8 dzf[8];
 #pragma unroll
   for (int h = 0; h < 4; ++h) {
+    f32x16 z = {};
+    z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load8(w1t + (32 * h + i) * kLat + 8 * g), xb, z, 0,
+                                                0, 0);
     f32x16 dz;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int hid = 32 * h + 8 * (r / 4) + 4 * g + r % 4;
-      dz[r] = ok ? scale * dh[h][r] * gelu_grad_f(z[h][r]) : 0.f;
+      dz[r] = ok ? scale * dh[h][r] * gelu_grad_f(z[r] + s_b1[hid]) : 0.f;
       dzbuf[(int64_t)hid * npad + px] = (__bf16)dz[r];
     }
     dzf[2 * h] = regs_to_b(dz, 0);
