@@ -485,14 +485,18 @@ __global__ __launch_bounds__(64 * kWgradWaves) void k_dec_wgrad(
     acc[j] = f32x16{};
     bsum[j] = 0.f;
   }
+  // this workgroup's output blocks: blockIdx.y selects kWgradWaves MAXB of them
+  const int b0 = (int)blockIdx.y * (kWgradWaves * MAXB) + wv;
   for (int64_t k = k0; k < k1; k += 16) {
 #pragma unroll
     for (int j = 0; j < MAXB; ++j) {
-      const int b = wv + kWgradWaves * j;
+      const int b = b0 + kWgradWaves * j;
       if (b >= nblocks) break;
       const int mb = b / NB, nb = b % NB;
       const int row = 32 * mb + i;
-      const bf16x8 a = row < m_valid ? load8(A + (int64_t)row * ld + k + 8 * g) : bf16x8{};
+      // (a row in range is read and dropped beyond m_valid: no load in a branch)
+      const bf16x8 av = load8(A + (int64_t)min(row, m_valid - 1) * ld + k + 8 * g);
+      const bf16x8 a = row < m_valid ? av : bf16x8{};
       const bf16x8 bb = load_b8(B + (int64_t)(32 * nb + i) * ld + k + 8 * g);
       acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb, acc[j], 0, 0, 0);
       if (mb == 0) {
@@ -506,7 +510,7 @@ __global__ __launch_bounds__(64 * kWgradWaves) void k_dec_wgrad(
   float* out = part + (int64_t)blockIdx.x * (M * N + N);
 #pragma unroll
   for (int j = 0; j < MAXB; ++j) {
-    const int b = wv + kWgradWaves * j;
+    const int b = b0 + kWgradWaves * j;
     if (b >= nblocks) break;
     const int mb = b / NB, nb = b % NB;
 #pragma unroll
@@ -813,11 +817,13 @@ gsff_status gsff_decoder_train_step(const void* X, const float* W1, const float*
   kchunk = (kchunk + 15) / 16 * 16;
   const int64_t groups = (L.npad + kchunk - 1) / kchunk;
   // dW2[h][c] = scale sum_p H[h][p] sign[c][p];  db2[c] = scale sum_p sign[c][p]
-  hipLaunchKernelGGL((k_dec_wgrad<int8_t, 8>), dim3((unsigned)groups), dim3(64 * kWgradWaves), 0,
+  // (W2: 64 output blocks in four workgroups of 16 per K range, so the GEMM
+  // has four waves per SIMD to hide its loads)
+  hipLaunchKernelGGL((k_dec_wgrad<int8_t, 2>), dim3((unsigned)groups, 4u), dim3(64 * kWgradWaves), 0,
                      s, (const __bf16*)(w + L.hbuf), kHid, kHid / 32, (const int8_t*)(w + L.dys),
                      kOut / 32, L.npad, kchunk, (float*)(w + L.part2));
   // dW1[k][h] = sum_p X[k][p] dZ[h][p];  db1[h] = sum_p dZ[h][p]  (dZ carries the scale)
-  hipLaunchKernelGGL((k_dec_wgrad<__bf16, 1>), dim3((unsigned)groups), dim3(64 * kWgradWaves), 0,
+  hipLaunchKernelGGL((k_dec_wgrad<__bf16, 1>), dim3((unsigned)groups, 1u), dim3(64 * kWgradWaves), 0,
                      s, (const __bf16*)(w + L.xbuf), kLat, 1, (const __bf16*)(w + L.dzbuf),
                      kHid / 32, L.npad, kchunk, (float*)(w + L.part1));
   hipLaunchKernelGGL(k_dec_reduce, dim3((kHid * kOut + kOut + 255) / 256), dim3(256), 0, s,
