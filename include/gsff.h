@@ -202,7 +202,9 @@ gsff_status gsff_version(int32_t* major, int32_t* minor);
  * only. */
 gsff_status gsff_is_checked_build(int32_t* checked);
 
-/* Polls a depth-sort workgroup makes for the published digit counts of the
+/* The depth sort (Sec. 3.1: Gaussians blended in depth order) runs one
+ * workgroup per chunk of keys.  Polls a depth-sort workgroup makes for the
+ * published digit counts of the
  * chunks before its own before it counts those chunks' digits from the keys
  * itself (raising GSFF_FLAG_SORT_RECOUNT); either way the sort is exact and
  * stable, and every wait ends whatever order the workgroups are dispatched
