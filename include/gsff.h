@@ -203,14 +203,13 @@ gsff_status gsff_version(int32_t* major, int32_t* minor);
 gsff_status gsff_is_checked_build(int32_t* checked);
 
 /* The depth sort (Sec. 3.1: Gaussians blended in depth order) runs one
- * workgroup per chunk of keys.  Polls a depth-sort workgroup makes for the
- * published digit counts of the
- * chunks before its own before it counts those chunks' digits from the keys
- * itself (raising GSFF_FLAG_SORT_RECOUNT); either way the sort is exact and
- * stable, and every wait ends whatever order the workgroups are dispatched
- * in.  0 makes every workgroup count (the fallback path, for tests).
- * Default 2048.  Process-wide; applies to frames enqueued afterwards.
- * Host only. */
+ * workgroup per chunk of keys.  This sets how many polls a workgroup makes
+ * for the published digit counts of the chunks before its own before it
+ * counts those chunks' digits from the keys itself (raising
+ * GSFF_FLAG_SORT_RECOUNT); either way the sort is exact and stable, and
+ * every wait ends whatever order the workgroups are dispatched in.  0 makes
+ * every workgroup count (the fallback path, for tests).  Default 2048.
+ * Process-wide; applies to frames enqueued afterwards.  Host only. */
 gsff_status gsff_set_sort_wait_limit(uint32_t polls);
 
 /* Text of the last GSFF_ERR_HIP / argument error raised on this thread. */
