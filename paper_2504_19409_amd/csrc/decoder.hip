@@ -474,7 +474,6 @@ __global__ __launch_bounds__(64 * kWgradWaves) void k_dec_wgrad(
     int64_t ld, int64_t kchunk, float* __restrict__ part) {
   const int lane = threadIdx.x & 63, g = lane >> 5, i = lane & 31;
   const int wv = threadIdx.x >> 6;
-  const int nblocks = MB * NB;
   const int M = 32 * MB, N = 32 * NB;
   const int64_t k0 = (int64_t)blockIdx.x * kchunk;
   const int64_t k1 = min(k0 + kchunk, ld);
@@ -485,14 +484,17 @@ __global__ __launch_bounds__(64 * kWgradWaves) void k_dec_wgrad(
     acc[j] = f32x16{};
     bsum[j] = 0.f;
   }
-  // this workgroup's output blocks: blockIdx.y selects kWgradWaves MAXB of them
-  const int b0 = (int)blockIdx.y * (kWgradWaves * MAXB) + wv;
+  // this workgroup's output blocks: every row block of the columns
+  // blockIdx.y nbq .. blockIdx.y nbq + nbq - 1, so each workgroup reads only
+  // its share of B and every workgroup of a K range all of A (the smaller)
+  const int nbq = NB / (int)gridDim.y;
+  const int nloc = MB * nbq;
   for (int64_t k = k0; k < k1; k += 16) {
 #pragma unroll
     for (int j = 0; j < MAXB; ++j) {
-      const int b = b0 + kWgradWaves * j;
-      if (b >= nblocks) break;
-      const int mb = b / NB, nb = b % NB;
+      const int l = wv + kWgradWaves * j;
+      if (l >= nloc) break;
+      const int mb = l / nbq, nb = (int)blockIdx.y * nbq + l % nbq;
       const int row = 32 * mb + i;
       // (a row in range is read and dropped beyond m_valid: no load in a branch)
       const bf16x8 av = load8(A + (int64_t)min(row, m_valid - 1) * ld + k + 8 * g);
@@ -510,9 +512,9 @@ __global__ __launch_bounds__(64 * kWgradWaves) void k_dec_wgrad(
   float* out = part + (int64_t)blockIdx.x * (M * N + N);
 #pragma unroll
   for (int j = 0; j < MAXB; ++j) {
-    const int b = b0 + kWgradWaves * j;
-    if (b >= nblocks) break;
-    const int mb = b / NB, nb = b % NB;
+    const int l = wv + kWgradWaves * j;
+    if (l >= nloc) break;
+    const int mb = l / nbq, nb = (int)blockIdx.y * nbq + l % nbq;
 #pragma unroll
     for (int r = 0; r < 16; ++r)
       out[(32 * mb + 8 * (r / 4) + 4 * g + r % 4) * N + 32 * nb + i] = acc[j][r];
@@ -817,8 +819,9 @@ gsff_status gsff_decoder_train_step(const void* X, const float* W1, const float*
   kchunk = (kchunk + 15) / 16 * 16;
   const int64_t groups = (L.npad + kchunk - 1) / kchunk;
   // dW2[h][c] = scale sum_p H[h][p] sign[c][p];  db2[c] = scale sum_p sign[c][p]
-  // (W2: 64 output blocks in four workgroups of 16 per K range, so the GEMM
-  // has four waves per SIMD to hide its loads)
+  // (W2: 64 output blocks in four workgroups of 16 per K range, each with
+  // all four row blocks of four column blocks, so the GEMM has four waves per
+  // SIMD to hide its loads and reads the signs once)
   hipLaunchKernelGGL((k_dec_wgrad<int8_t, 2>), dim3((unsigned)groups, 4u), dim3(64 * kWgradWaves), 0,
                      s, (const __bf16*)(w + L.hbuf), kHid, kHid / 32, (const int8_t*)(w + L.dys),
                      kOut / 32, L.npad, kchunk, (float*)(w + L.part2));
