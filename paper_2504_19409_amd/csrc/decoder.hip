@@ -73,14 +73,17 @@ static DecLayout dec_layout(int64_t npx) {
   return L;
 }
 
-// tanh(u) = 1 - 2 / (exp(2u) + 1) through the hardware reciprocal (1 ulp;
-// exact at the ends: 1 / inf = 0, 1 / 1 = 1)
+// GELU in its tanh form, 0.5 z (1 + tanh(u)) with u = sqrt(2/pi) (z + 0.044715 z^3),
+// evaluated as the equal z / (1 + exp(-2u)): one exp2 and one hardware
+// reciprocal (1 ulp each) with the constants folded into the polynomial; at
+// the ends 1 / inf = 0 and 1 / 1 = 1, so the limits -0 and z are exact
 __device__ __forceinline__ float gelu_f(float z) {
-  const float u = 0.7978845608028654f * (z + 0.044715f * z * z * z);
-  const float t = 1.f - 2.f * __builtin_amdgcn_rcpf(__expf(2.f * u) + 1.f);  // tanh(u)
-  return 0.5f * z * (1.f + t);
+  const float a = z * fmaf(z * z, -2.f * 1.4426950408889634f * 0.7978845608028654f * 0.044715f,
+                           -2.f * 1.4426950408889634f * 0.7978845608028654f);  // -2u log2(e)
+  return z * __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(a));
 }
 
+// derivative of the tanh form; tanh(u) = 1 - 2 / (exp(2u) + 1)
 __device__ __forceinline__ float gelu_grad_f(float z) {
   const float u = 0.7978845608028654f * (z + 0.044715f * z * z * z);
   const float t = 1.f - 2.f * __builtin_amdgcn_rcpf(__expf(2.f * u) + 1.f);
@@ -134,29 +137,49 @@ __device__ __forceinline__ bf16x8 regs_to_b(const f32x16& d, int half) {
 
 // ------------------------------------------------------------- forward -----
 
-// One wave decodes NPB blocks of 32 pixels; the weight fragments of each
-// K-step are loaded once per wave and used for all NPB blocks.  The second
-// layer takes the hidden activations as the A operand (pixels along M) and
-// the weights as B, so lane (g, i) ends with output channel 32 c + i of
-// pixels 8 k + 4 g .. 8 k + 4 g + 3 (k = 0..3) of each block.  ROWS (rows of
-// Y 16-byte aligned): the wave's 32 channels x 32 NPB pixels pass through
-// LDS, and every store instruction writes 16 bytes per lane as whole
-// 128-byte row segments (eight lanes per row); otherwise one element per
-// store.
+// One wave decodes NPB blocks of 32 pixels.  The second layer takes the
+// hidden activations as the A operand (pixels along M) and the weights as B,
+// so lane (g, i) ends with output channel 32 c + i of pixels
+// 8 k + 4 g .. 8 k + 4 g + 3 (k = 0..3) of each block.  The weights of output
+// block c (32 channels x 128 hidden, 8 KB) are copied once per workgroup into
+// a padded LDS tile, one block ahead (each thread 32 bytes, loaded while the
+// current block is multiplied), and all four waves read their fragments from
+// it: a quarter of the cache traffic of per-wave loads, and no register
+// double buffer, so three waves fit on a SIMD.  ROWS (rows of Y 16-byte
+// aligned): the wave's 32 channels x 32 NPB pixels pass through LDS, and every
+// store instruction writes 16 bytes per lane as whole row segments (eight
+// lanes per row); otherwise one element per store.
 template <int NPB, typename OT, bool ROWS>
-__global__ __launch_bounds__(256) void k_dec_forward(const __bf16* __restrict__ X,
-                                                     const float* __restrict__ b1,
-                                                     const float* __restrict__ b2,
-                                                     const __bf16* __restrict__ w1t,
-                                                     const __bf16* __restrict__ w2tp,
-                                                     OT* __restrict__ Y, int64_t npx) {
+__global__ __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(3)))
+void k_dec_forward(const __bf16* __restrict__ X, const float* __restrict__ b1,
+                   const float* __restrict__ b2, const __bf16* __restrict__ w1t,
+                   const __bf16* __restrict__ w2tp, OT* __restrict__ Y, int64_t npx) {
   constexpr int PXW = 32 * NPB;                    // pixels per wave
   constexpr int VEC = 16 / (int)sizeof(OT);        // elements per 16-byte store
-  constexpr int STRIDE = PXW + VEC;                  // LDS row pitch: 16-byte rows, banks staggered
+  constexpr int STRIDE = PXW + VEC;                // LDS row pitch: 16-byte rows, banks staggered
+  constexpr int WP = kHid + 8;                     // weight row pitch (272 bytes): 16 lanes, 16 bank groups
   __shared__ __attribute__((aligned(16))) OT s_y[ROWS ? 4 : 1][ROWS ? 32 : 1][ROWS ? STRIDE : 1];
-  const int lane = threadIdx.x & 63, g = lane >> 5, i = lane & 31, wv = threadIdx.x >> 6;
+  __shared__ __attribute__((aligned(16))) __bf16 s_w[2][32 * WP];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, g = lane >> 5, i = lane & 31, wv = tid >> 6;
   const int64_t wave = (int64_t)blockIdx.x * 4 + wv;
   const int64_t wbase = wave * PXW;
+  __shared__ __attribute__((aligned(16))) float s_b1[kHid];
+  if (tid < kHid) s_b1[tid] = b1[tid];
+  __syncthreads();
+  // weight tile copy: thread tid moves bytes 32 (tid % 8) .. + 31 of row tid / 8
+  const int wr = tid >> 3, wc = (tid & 7) * 16;
+  u32x4 wt0, wt1;
+  auto wload = [&](int c) {
+    const __bf16* src = w2tp + (int64_t)(32 * c + wr) * kHid + wc;
+    wt0 = *reinterpret_cast<const u32x4*>(src);
+    wt1 = *reinterpret_cast<const u32x4*>(src + 8);
+  };
+  auto wstore = [&](int buf) {
+    __bf16* d = &s_w[buf][wr * WP + wc];
+    *reinterpret_cast<u32x4*>(d) = wt0;
+    *reinterpret_cast<u32x4*>(d + 8) = wt1;
+  };
   bf16x8 hf[NPB][8];
 #pragma unroll
   for (int q = 0; q < NPB; ++q) {
@@ -171,28 +194,30 @@ __global__ __launch_bounds__(256) void k_dec_forward(const __bf16* __restrict__ 
       z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load8(w1t + (32 * h + i) * kLat + 8 * g), xb, z,
                                                   0, 0, 0);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) z[r] = gelu_f(z[r] + b1[32 * h + 8 * (r / 4) + 4 * g + r % 4]);
+      for (int r = 0; r < 16; ++r) z[r] = gelu_f(z[r] + s_b1[32 * h + 8 * (r / 4) + 4 * g + r % 4]);
       hf[q][2 * h] = regs_to_b(z, 0);
       hf[q][2 * h + 1] = regs_to_b(z, 1);
     }
   }
-  // output blocks in pairs with two fragment buffers: the weights and bias of
-  // the next block are loaded while the current one is multiplied and
-  // written (a whole block's work to arrive)
+  wload(0);
+  wstore(0);
+  __syncthreads();
   const bool full = wbase + PXW <= npx;  // uniform: every pixel of the wave in range
-  bf16x8 wa[8], wb[8];
-#pragma unroll
-  for (int s = 0; s < 8; ++s) wa[s] = load8(w2tp + (i * 8 + s) * 16 + 8 * g);
-  float ba = b2[i], bb = 0.f;
-  auto block = [&](int c, const bf16x8 (&w)[8], float bias) {
+#pragma unroll 1
+  for (int c = 0; c < kOut / 32; ++c) {
+    if (c + 1 < kOut / 32) wload(c + 1);
+    const float bias = b2[32 * c + i];
+    const __bf16* wrow = &s_w[c & 1][i * WP + 8 * g];
     f32x16 acc[NPB];
 #pragma unroll
     for (int q = 0; q < NPB; ++q) acc[q] = f32x16{};
 #pragma unroll
-    for (int s = 0; s < 8; ++s)
+    for (int s = 0; s < 8; ++s) {
+      const bf16x8 w = *reinterpret_cast<const bf16x8*>(wrow + 16 * s);
 #pragma unroll
       for (int q = 0; q < NPB; ++q)
-        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hf[q][s], w[s], acc[q], 0, 0, 0);
+        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hf[q][s], w, acc[q], 0, 0, 0);
+    }
     if constexpr (ROWS) {
       // the wave's tile: row = channel i, pixels 32 q + 8 k + 4 g .. +3
 #pragma unroll
@@ -225,9 +250,6 @@ __global__ __launch_bounds__(256) void k_dec_forward(const __bf16* __restrict__ 
             if (p0 + t < npx) dst[t] = e[t];
         }
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
     } else {
       OT* row = Y + (int64_t)(32 * c + i) * npx;
 #pragma unroll
@@ -240,19 +262,10 @@ __global__ __launch_bounds__(256) void k_dec_forward(const __bf16* __restrict__ 
             if (p0 + t < npx) row[p0 + t] = (OT)(acc[q][4 * k + t] + bias);
         }
     }
-  };
-#pragma unroll 1
-  for (int c = 0; c < kOut / 32; c += 2) {
-#pragma unroll
-    for (int s = 0; s < 8; ++s) wb[s] = load8(w2tp + ((32 * (c + 1) + i) * 8 + s) * 16 + 8 * g);
-    bb = b2[32 * (c + 1) + i];
-    block(c, wa, ba);
-    if (c + 2 < kOut / 32) {
-#pragma unroll
-      for (int s = 0; s < 8; ++s) wa[s] = load8(w2tp + ((32 * (c + 2) + i) * 8 + s) * 16 + 8 * g);
-      ba = b2[32 * (c + 2) + i];
-    }
-    block(c + 1, wb, bb);
+    // the other weight buffer was last read before the previous barrier; the
+    // barrier below also orders this wave's tile reads before the next writes
+    if (c + 1 < kOut / 32) wstore((c + 1) & 1);
+    __syncthreads();
   }
 }
 
@@ -774,7 +787,7 @@ gsff_status gsff_decoder_forward(const void* X, const float* W1, const float* b1
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)ws;
   if (dec_prepare(W1, W2, w, L, s) != hipSuccess) return GSFF_ERR_HIP;
-  constexpr int NPB = 2;  // two blocks per wave: 232-260 registers, two waves per SIMD
+  constexpr int NPB = 2;  // two blocks per wave: 156 registers, three waves per SIMD
   const int64_t waves = (L.nblk + NPB - 1) / NPB;
   const unsigned grid = (unsigned)((waves + 3) / 4);
   // rows of the output map 16-byte aligned: whole row segments per store
