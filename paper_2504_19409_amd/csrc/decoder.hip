@@ -540,21 +540,43 @@ __global__ __launch_bounds__(64 * kWgradWaves) void k_dec_wgrad(
 
 // out[e] = scale * sum_wg part[wg][src(e)]; rows >= m_valid of the M x N
 // block are dropped, the N bias sums follow the m_valid x N gradient.
+// Sum of the split-K partials in a fixed order: 32 outputs per workgroup,
+// the groups of each output split into 8 slices of at most 16 consecutive
+// groups, whose loads are all in flight at once (a clamped group index, the
+// value dropped), then the slice sums added in slice order.
+constexpr int kRedCols = 32, kRedSlices = 8, kRedPerSlice = 16;
+static_assert(kWgradGroups <= kRedSlices * kRedPerSlice, "split-K groups exceed the reduction");
 __global__ __launch_bounds__(256) void k_dec_reduce(const float* __restrict__ part, int groups,
                                                     int M, int N, int m_valid, float scale_w,
                                                     float scale_b, float* __restrict__ dW,
                                                     float* __restrict__ db) {
-  const int e = blockIdx.x * 256 + threadIdx.x;
+  __shared__ float s_sum[kRedSlices][kRedCols];
+  const int c = threadIdx.x % kRedCols, sl = threadIdx.x / kRedCols;
+  const int e = blockIdx.x * kRedCols + c;
   const int nw = m_valid * N;
-  if (e >= nw + N) return;
-  const int src = e < nw ? e : M * N + (e - nw);
+  const bool ok = e < nw + N;
+  const int src = !ok ? 0 : (e < nw ? e : M * N + (e - nw));
   const int64_t stride = (int64_t)M * N + N;
+  const int per = (groups + kRedSlices - 1) / kRedSlices;
+  const int w0 = sl * per, w1 = min(groups, w0 + per);
+  float v[kRedPerSlice];
+#pragma unroll
+  for (int k = 0; k < kRedPerSlice; ++k)
+    v[k] = part[(int64_t)min(w0 + k, groups - 1) * stride + src];
   float acc = 0.f;
-  for (int w = 0; w < groups; ++w) acc += part[w * stride + src];
-  if (e < nw)
-    dW[e] = scale_w * acc;
-  else
-    db[e - nw] = scale_b * acc;
+#pragma unroll
+  for (int k = 0; k < kRedPerSlice; ++k) acc += w0 + k < w1 ? v[k] : 0.f;
+  s_sum[sl][c] = acc;
+  __syncthreads();
+  if (sl == 0 && ok) {
+    float t = 0.f;
+#pragma unroll
+    for (int k = 0; k < kRedSlices; ++k) t += s_sum[k][c];
+    if (e < nw)
+      dW[e] = scale_w * t;
+    else
+      db[e - nw] = scale_b * t;
+  }
 }
 
 
@@ -842,11 +864,11 @@ gsff_status gsff_decoder_train_step(const void* X, const float* W1, const float*
   hipLaunchKernelGGL((k_dec_wgrad<__bf16, 1>), dim3((unsigned)groups, 1u), dim3(64 * kWgradWaves), 0,
                      s, (const __bf16*)(w + L.xbuf), kLat, 1, (const __bf16*)(w + L.dzbuf),
                      kHid / 32, L.npad, kchunk, (float*)(w + L.part1));
-  hipLaunchKernelGGL(k_dec_reduce, dim3((kHid * kOut + kOut + 255) / 256), dim3(256), 0, s,
-                     (const float*)(w + L.part2), (int)groups, kHid, kOut, kHid, scale, scale,
+  hipLaunchKernelGGL(k_dec_reduce, dim3((kHid * kOut + kOut + kRedCols - 1) / kRedCols), dim3(256),
+                     0, s, (const float*)(w + L.part2), (int)groups, kHid, kOut, kHid, scale, scale,
                      dW2, db2);
-  hipLaunchKernelGGL(k_dec_reduce, dim3((kLat * kHid + kHid + 255) / 256), dim3(256), 0, s,
-                     (const float*)(w + L.part1), (int)groups, 32, kHid, kLat, 1.f, 1.f, dW1, db1);
+  hipLaunchKernelGGL(k_dec_reduce, dim3((kLat * kHid + kHid + kRedCols - 1) / kRedCols), dim3(256),
+                     0, s, (const float*)(w + L.part1), (int)groups, 32, kHid, kLat, 1.f, 1.f, dW1, db1);
   return hipGetLastError() == hipSuccess ? GSFF_OK : GSFF_ERR_HIP;
 }
 
