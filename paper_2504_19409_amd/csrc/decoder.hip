@@ -34,6 +34,9 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 constexpr int kLat = 16, kHid = 128, kOut = 512;
 constexpr int kWgradGroups = 128;     // split-K workgroups of the weight-gradient GEMMs
 constexpr int kWgradWaves = 8;
+// column blocks per workgroup of the two weight-gradient GEMMs, W2 (16 in
+// four workgroups) and W1 (4 in one), divide the wave count
+static_assert(kWgradWaves % ((kOut / 32) / 4) == 0 && kWgradWaves % (kHid / 32) == 0, "");
 
 __host__ __device__ inline int dec_pi(int s, int g, int t) {
   return 32 * (s / 2) + 16 * (s % 2) + 8 * (t / 4) + 4 * g + (t % 4);
@@ -491,35 +494,38 @@ __global__ __launch_bounds__(64 * kWgradWaves) void k_dec_wgrad(
   const int64_t k0 = (int64_t)blockIdx.x * kchunk;
   const int64_t k1 = min(k0 + kchunk, ld);
   f32x16 acc[MAXB];
-  float bsum[MAXB];
 #pragma unroll
-  for (int j = 0; j < MAXB; ++j) {
-    acc[j] = f32x16{};
-    bsum[j] = 0.f;
-  }
+  for (int j = 0; j < MAXB; ++j) acc[j] = f32x16{};
+  float bsum = 0.f;
   // this workgroup's output blocks: every row block of the columns
   // blockIdx.y nbq .. blockIdx.y nbq + nbq - 1, so each workgroup reads only
-  // its share of B and every workgroup of a K range all of A (the smaller)
+  // its share of B and every workgroup of a K range all of A (the smaller).
+  // nbq divides the wave count, so all of a wave's blocks lie in one column
+  // block: its B operand is loaded and converted once per K step, and the
+  // wave holds row block 0 (whose column sums give the bias gradient) when
+  // wv < nbq
   const int nbq = NB / (int)gridDim.y;
   const int nloc = MB * nbq;
-  for (int64_t k = k0; k < k1; k += 16) {
+  const int nb = (int)blockIdx.y * nbq + wv % nbq;
+  const BT* brow = B + (int64_t)(32 * nb + i) * ld + 8 * g;
+  // (waves beyond the workgroup's blocks, W1 only, skip the loop)
+  for (int64_t k = wv < nloc ? k0 : k1; k < k1; k += 16) {
+    const bf16x8 bb = load_b8(brow + k);
 #pragma unroll
     for (int j = 0; j < MAXB; ++j) {
       const int l = wv + kWgradWaves * j;
       if (l >= nloc) break;
-      const int mb = l / nbq, nb = (int)blockIdx.y * nbq + l % nbq;
-      const int row = 32 * mb + i;
+      const int row = 32 * (l / nbq) + i;
       // (a row in range is read and dropped beyond m_valid: no load in a branch)
       const bf16x8 av = load8(A + (int64_t)min(row, m_valid - 1) * ld + k + 8 * g);
       const bf16x8 a = row < m_valid ? av : bf16x8{};
-      const bf16x8 bb = load_b8(B + (int64_t)(32 * nb + i) * ld + k + 8 * g);
       acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb, acc[j], 0, 0, 0);
-      if (mb == 0) {
-        float sacc = 0.f;
+    }
+    if (wv < nbq) {
+      float sacc = 0.f;
 #pragma unroll
-        for (int t = 0; t < 8; ++t) sacc += (float)bb[t];
-        bsum[j] += sacc;
-      }
+      for (int t = 0; t < 8; ++t) sacc += (float)bb[t];
+      bsum += sacc;
     }
   }
   float* out = part + (int64_t)blockIdx.x * (M * N + N);
@@ -527,12 +533,12 @@ __global__ __launch_bounds__(64 * kWgradWaves) void k_dec_wgrad(
   for (int j = 0; j < MAXB; ++j) {
     const int l = wv + kWgradWaves * j;
     if (l >= nloc) break;
-    const int mb = l / nbq, nb = (int)blockIdx.y * nbq + l % nbq;
+    const int mb = l / nbq;
 #pragma unroll
     for (int r = 0; r < 16; ++r)
       out[(32 * mb + 8 * (r / 4) + 4 * g + r % 4) * N + 32 * nb + i] = acc[j][r];
     if (mb == 0) {
-      const float v = bsum[j] + __shfl_xor(bsum[j], 32, 64);
+      const float v = bsum + __shfl_xor(bsum, 32, 64);
       if (g == 0) out[M * N + 32 * nb + i] = v;
     }
   }
